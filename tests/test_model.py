@@ -1,0 +1,162 @@
+"""Pins for the NumPy model of the paper's algorithms (oracle/sbr_model.py).
+
+Identities of Eq. (4.1), Eq. (4.2) and Corollary 3.7, the Ensure clauses of
+Algorithms 3.2, 4.1 and 4.2 (exact band structure, spectrum preserved), and the
+chase-ordering rule used by the GPU pipeline.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import sbr_inputs as si
+from oracle import sbr_model as M
+
+EPS = np.finfo(np.float64).eps
+
+
+def _random_wy(m, c, seed):
+    rng = np.random.default_rng(seed)
+    U, tau, _ = M.householder_qr(rng.standard_normal((m, c)))
+    return U, M.larft(U, tau)
+
+
+@pytest.mark.parametrize("m,c", [(12, 3), (40, 8), (33, 16)])
+def test_eq_4_1_two_sided_update(m, c):
+    U, T = _random_wy(m, c, m + c)
+    X = si.gaussian_symmetric(m, np.random.default_rng(m))
+    Q = np.eye(m) - U @ T @ U.T
+    lhs = Q.T @ X @ Q
+    rhs = M.two_sided_update(X, U, T)
+    assert np.max(np.abs(lhs - rhs)) <= 50 * m * EPS * np.max(np.abs(X))
+    # Q is orthogonal and U^T U = T^{-1} + T^{-T} (Corollary 3.7)
+    assert np.max(np.abs(Q.T @ Q - np.eye(m))) <= 50 * m * EPS
+    Ti = np.linalg.inv(T)
+    assert np.max(np.abs(U.T @ U - Ti - Ti.T)) <= 100 * m * EPS * np.max(np.abs(Ti))
+
+
+def test_eq_4_2_deferred_application():
+    m, c = 30, 6
+    U, T = _random_wy(m, c, 3)
+    X = si.gaussian_symmetric(m, np.random.default_rng(4))
+    Y = np.random.default_rng(5).standard_normal((m, 5))
+    Q = np.eye(m) - U @ T @ U.T
+    V = M.two_sided_v(X, U, T)
+    assert np.allclose(Q.T @ X @ Q @ Y, X @ Y + U @ (V.T @ Y) + V @ (U.T @ Y), atol=1e-12)
+
+
+@pytest.mark.parametrize("m,c,p", [(64, 8, 1), (64, 8, 4), (200, 16, 8), (130, 16, 4), (48, 16, 2)])
+def test_rect_qr(oracle_mod, m, c, p):
+    A = np.random.default_rng(m * c + p).standard_normal((m, c))
+    Q, R = M.rect_qr(A, p)
+    assert Q.shape == (m, c) and R.shape == (c, c)
+    assert np.max(np.abs(np.tril(R, -1))) == 0.0
+    assert np.max(np.abs(Q @ R - A)) <= 100 * m * EPS * np.max(np.abs(A))
+    assert np.max(np.abs(Q.T @ Q - np.eye(c))) <= 100 * m * EPS
+    s = np.sign(np.diag(R))
+    assert np.allclose(s[:, None] * R, oracle_mod.qr_r(A), atol=1e-12 * np.max(np.abs(A)))
+
+
+@pytest.mark.parametrize("m,c", [(16, 4), (96, 16), (64, 32)])
+def test_householder_reconstruction(m, c):
+    P = np.random.default_rng(m + 7 * c).standard_normal((m, c))
+    Q, R = M.rect_qr(P, 4)
+    U, T, S = M.householder_reconstruct(Q)
+    U1 = U[:c]
+    assert np.allclose(np.diag(U1), 1.0) and np.max(np.abs(np.triu(U1, 1))) == 0.0
+    assert np.max(np.abs(np.tril(T, -1))) <= 1e-14
+    H = np.eye(m) - U @ T @ U.T
+    assert np.allclose(H[:, :c], Q * S[None, :], atol=1e-13)
+    top = np.zeros((m, c))
+    top[:c] = S[:, None] * R
+    assert np.allclose(H.T @ P, top, atol=1e-12)
+    assert np.max(np.abs(H.T @ H - np.eye(m))) <= 1e-13
+    Ti = np.linalg.inv(T)
+    assert np.allclose(U.T @ U, Ti + Ti.T, atol=1e-11 * np.max(np.abs(Ti)))
+
+
+@pytest.mark.parametrize("n,b", [(64, 8), (67, 8), (100, 16), (33, 4), (40, 2), (129, 32), (20, 16)])
+def test_full_to_band_and_halvings(oracle_mod, n, b):
+    A = si.gaussian_symmetric(n, si.make_rng(si.CFG_SMALL, 0))
+    ref = oracle_mod.eigvalsh(A)
+    fro = math.sqrt(float(np.sum(A * A)))
+    B = M.full_to_band(A, b)
+    assert M.bandwidth(B) <= b
+    assert np.max(np.abs(B - B.T)) <= 1e-13 * fro
+    assert abs(np.trace(B) - np.trace(A)) <= 1e-12 * fro
+    assert abs(math.sqrt(float(np.sum(B * B))) - fro) <= 1e-13 * fro * n
+    assert np.max(np.abs(oracle_mod.eigvalsh(B) - ref)) <= 1e-12 * np.max(np.abs(ref))
+    h = b
+    while h > 1:
+        B = M.band_to_band(B, h)     # also asserts the window reading per chase
+        h //= 2
+        assert M.bandwidth(B) <= h
+        assert np.max(np.abs(oracle_mod.eigvalsh(B) - ref)) <= 1e-12 * np.max(np.abs(ref))
+    d, e = np.diag(B), np.diag(B, -1)
+    assert np.max(np.abs(oracle_mod.tridiag_eigvals(d, e) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_model_pipeline_prescribed_spectrum(oracle_mod):
+    rng = np.random.default_rng(11)
+    lam = si.geometric_spectrum(96, rng)
+    A = si.spectrum_matrix(lam, rng)
+    d, e = M.sbr_eigvals(A, 16)
+    w = oracle_mod.tridiag_eigvals(d, e)
+    assert np.max(np.abs(w - np.sort(lam))) <= 1e-13
+
+
+def _ancestors(chases, lag):
+    last = {}
+    for c in chases:
+        last[c["i"]] = max(last.get(c["i"], 0), c["j"])
+    anc = {}
+    for c in chases:
+        i, j = c["i"], c["j"]
+        s = set()
+        preds = []
+        if j > 1:
+            preds.append((i, j - 1))
+        if i > 1 and (i - 1) in last:
+            preds.append((i - 1, min(j + lag - 1, last[i - 1])))
+        for p in preds:
+            s |= anc[p]
+            s.add(p)
+        anc[(i, j)] = s
+    return anc
+
+
+def _conflicts_not_ordered(n, b, lag):
+    chases = M.chase_list(n, b)
+    touched = [M.chase_touched(c) for c in chases]
+    anc = _ancestors(chases, lag)
+    bad = 0
+    for a, c in itertools.combinations(range(len(chases)), 2):
+        if touched[a] & touched[c]:
+            ka = (chases[a]["i"], chases[a]["j"])
+            kc = (chases[c]["i"], chases[c]["j"])
+            bad += ka not in anc[kc]
+    return bad
+
+
+@pytest.mark.parametrize("n,b", [(64, 8), (67, 4), (128, 16), (60, 2), (45, 8)])
+def test_chase_schedule_lag3_orders_every_conflict(n, b):
+    # chase (i, j) waits for (i, j-1) and (i-1, j+2): every pair of chases
+    # that write a common entry is ordered as in the sequential loop nest.
+    assert _conflicts_not_ordered(n, b, 3) == 0
+
+
+def test_chase_schedule_lag2_is_not_enough():
+    # Running (i, j) beside (i-1, j+2) (a new panel after the previous bulge
+    # moved twice) lets two chases write the same entries.
+    assert _conflicts_not_ordered(64, 8, 2) > 0
+
+
+def test_chase_list_bounds():
+    # n not a multiple of b: the last sweeps still get their chases (reading G4)
+    ch = M.chase_list(21, 4)
+    sweeps = sorted({c["i"] for c in ch})
+    assert sweeps == list(range(1, (21 - 2) // 2 + 1))
+    for c in ch:
+        r0, r1 = c["qr_rows"]
+        assert r1 - r0 >= 2 and r1 <= 21
