@@ -1,0 +1,121 @@
+/*
+ * sbr.h -- C ABI of the MI355X (gfx950) successive-band-reduction symmetric
+ * eigenvalue solver.
+ *
+ * Method: Solomonik, Ballard, Demmel, Hoefler, "A communication-avoiding
+ * parallel algorithm for the symmetric eigenvalue problem".  A dense symmetric
+ * matrix is reduced to band form (Algorithm 4.1: panel QR by a TSQR tree,
+ * Algorithm 3.2, Householder reconstruction, Corollary 3.7, and the two-sided
+ * rank-2b trailing update of Eq. (4.1)); the band is then halved b -> b/2 by
+ * bulge chasing (Algorithm 4.2 with k = 2) down to tridiagonal form; the
+ * eigenvalues come from Sturm-sequence bisection (the final step of
+ * Algorithm 4.3: "compute the eigenvalues of the thin band").
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are column-major FP64 in DEVICE memory; element (i, j) of A is
+ *    A[i + j * lda].  Only the lower triangle (i >= j) is read.
+ *  - Calls are asynchronous on the given HIP stream (NULL = legacy default
+ *    stream).  Argument errors are detected on the host before anything is
+ *    enqueued.  A fault inside a kernel surfaces at the caller's next
+ *    synchronisation.
+ *  - Return value: 0 on success; -i if the i-th argument is invalid (LAPACK
+ *    convention); a positive SBR_E* code otherwise.  sbr_last_hip_error()
+ *    returns the hipError_t behind SBR_EHIP.
+ *  - Eigenvalues are written to a caller-owned device array in ascending
+ *    order.
+ */
+#ifndef SBR_H
+#define SBR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* sbr_stream_t;     /* same object as hipStream_t */
+typedef struct sbr_plan_s* sbr_plan_t;         /* opaque: workspace + tuning */
+
+typedef enum {
+    SBR_FP64 = 0,        /* every step in FP64 */
+    SBR_FP32_MFMA = 1    /* trailing updates and WY applications on FP32 MFMA
+                            with FP32 accumulation; storage, Householder norms,
+                            the TSQR R factor and the Sturm counts stay FP64 */
+} sbr_precision;
+
+enum {
+    SBR_OK = 0,
+    SBR_ENOMEM = 1,      /* device workspace could not be allocated */
+    SBR_EHIP = 2,        /* a HIP runtime call failed */
+    SBR_ENOTSUP = 3,     /* valid but unsupported parameter combination */
+    SBR_ENONFINITE = 4   /* reserved: non-finite input detected */
+};
+
+/*
+ * Eigenvalues of a dense symmetric matrix (Algorithm 4.3's problem: A in,
+ * the eigenvalue vector D out), plain FP64 form.
+ *   n      order of A, n >= 0.
+ *   A      device pointer, n x n, lda >= max(1, n); lower triangle read.
+ *          OVERWRITTEN: on return it holds no meaningful values.
+ *   lda    leading dimension of A.
+ *   b0     band width of the full-to-band stage: a power of two with
+ *          2 <= b0 <= 128, or 0 to pick it from n.  Any n is allowed (no
+ *          divisibility by b0 is required).
+ *   stream HIP stream all work is enqueued on.
+ *   w      device pointer, n doubles: the eigenvalues, ascending.
+ * Uses an internal plan cached per device (allocates on first use and when
+ * n or b0 grows).
+ */
+int sbr_syev_eigvals(int64_t n, double* A, int64_t lda, int32_t b0,
+                     sbr_stream_t stream, double* w);
+
+/* As sbr_syev_eigvals, with an explicit plan and precision form. */
+int sbr_syev_eigvals_ex(sbr_plan_t plan, int64_t n, double* A, int64_t lda,
+                        int32_t b0, sbr_precision prec, sbr_stream_t stream,
+                        double* w);
+
+/*
+ * Eigenvalues of `batch` independent symmetric matrices of different orders
+ * (the sequence of matrices of a self-consistent-field loop, Section 1).
+ *   n, lda   HOST arrays of length batch (n[k] >= 1, lda[k] >= n[k]).
+ *   A        HOST array of batch DEVICE pointers (each overwritten).
+ *   b0       band width for every matrix, or 0 for the tuned choice per size.
+ *   w        HOST array of batch DEVICE pointers, w[k] holds n[k] doubles.
+ * The plan must have been created with batch_max >= batch and
+ * n_max >= max n[k].
+ */
+int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n,
+                             double* const* A, const int64_t* lda, int32_t b0,
+                             sbr_precision prec, sbr_stream_t stream,
+                             double* const* w);
+
+/*
+ * Eigenvalues of the symmetric tridiagonal matrix with diagonal d[0..n-1]
+ * and off-diagonal e[0..n-2] (device pointers; e may be NULL when n == 1),
+ * by Sturm-sequence bisection; w (device, n doubles) ascending.
+ */
+int sbr_tridiag_eigvals(int64_t n, const double* d, const double* e,
+                        sbr_stream_t stream, double* w);
+
+/* Plan owning the device workspace for problems up to n_max (and batches up
+ * to batch_max matrices).  Creating a plan allocates; calls made through an
+ * existing plan within its limits do not. */
+int sbr_plan_create(sbr_plan_t* plan, int64_t n_max, int32_t batch_max,
+                    sbr_precision prec);
+int sbr_plan_destroy(sbr_plan_t plan);
+
+/* Device workspace bytes sbr_syev_eigvals_ex needs for (n, b0, prec). */
+int sbr_workspace_size(int64_t n, int32_t b0, sbr_precision prec, size_t* bytes);
+
+/* Band width chosen for order n when b0 = 0 is passed. */
+int32_t sbr_default_band(int64_t n);
+
+/* hipError_t of the last SBR_EHIP failure on the calling thread. */
+int sbr_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBR_H */

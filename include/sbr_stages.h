@@ -1,0 +1,112 @@
+/*
+ * sbr_stages.h -- stage-level entry points of the SBR eigensolver library.
+ *
+ * These expose the individual steps of the hot path (for component tests and
+ * per-phase measurement).  Conventions are those of sbr.h: FP64 device
+ * buffers, column-major, asynchronous on `stream`, 0 / -i / SBR_E* returns.
+ */
+#ifndef SBR_STAGES_H
+#define SBR_STAGES_H
+
+#include "sbr.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/*
+ * Full-to-band reduction (Algorithm 4.1, right-looking: every panel's
+ * two-sided update, Eq. (4.1), is applied to the whole trailing matrix).
+ * A (n x n, lower triangle) is overwritten: on return A[i + j*lda] for
+ * 0 <= i - j <= b holds the band matrix with the eigenvalues of the input,
+ * and A[i + j*lda] = 0 for i - j > b.  The strict upper triangle is scratch.
+ * b: power of two, 2 <= b <= 128.
+ */
+int sbr_full_to_band(sbr_plan_t plan, int64_t n, double* A, int64_t lda,
+                     int32_t b, sbr_precision prec, sbr_stream_t stream);
+
+/*
+ * Copy the lower band of a dense matrix into band storage:
+ * band[d + j*ldband] = A[(j+d) + j*lda] for 0 <= d <= b and j + d < n,
+ * and 0 for every other d < ldband.  Requires ldband >= b + 1.
+ */
+int sbr_dense_to_band(int64_t n, const double* A, int64_t lda, int32_t b,
+                      double* band, int64_t ldband, sbr_stream_t stream);
+
+/*
+ * One band-to-band halving (Algorithm 4.2 with k = 2): the symmetric band
+ * matrix of bandwidth b held in `band` (lower band storage as above, with
+ * ldband >= 2b + 1 because the chase fills up to distance 2b - 1) is reduced
+ * in place to bandwidth b/2.  On return the entries at distance > b/2 are
+ * exactly zero.  b: power of two, 2 <= b <= 128.  `prec` selects FP64 or the
+ * FP32 WY form for b >= 16.
+ */
+int sbr_band_halve(sbr_plan_t plan, int64_t n, double* band, int64_t ldband,
+                   int32_t b, sbr_precision prec, sbr_stream_t stream);
+
+/*
+ * Panel QR of the m x b panel P (m >= b) by the TSQR tree of Algorithm 3.2
+ * followed by Householder reconstruction (Corollary 3.7).  Outputs (device):
+ *   Q  m x b explicit orthonormal factor (ld = m), P = Q R,
+ *   R  b x b upper triangular (ld = b),
+ *   U  m x b, unit lower trapezoidal (ld = m), T b x b upper (ld = b),
+ *   S  b signs with (I - U T U^T)[:, :b] = Q diag(S).
+ * P is left unchanged.
+ */
+int sbr_panel_qr(sbr_plan_t plan, int64_t m, int32_t b, const double* P,
+                 int64_t ldp, double* Q, double* R, double* U, double* T,
+                 double* S, sbr_stream_t stream);
+
+/* C = alpha op(A) op(B) + beta C on the MFMA tile engine (transa/transb:
+ * 0 = N, 1 = T); prec chooses FP64 or FP32-MFMA arithmetic. */
+int sbr_gemm(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k,
+             double alpha, const double* A, int64_t lda, const double* B,
+             int64_t ldb, double beta, double* C, int64_t ldc,
+             sbr_precision prec, sbr_stream_t stream);
+
+/* Lower triangle of C += U V^T + V U^T (C m x m, U and V m x k). */
+int sbr_syr2k_lower(int64_t m, int64_t k, const double* U, int64_t ldu,
+                    const double* V, int64_t ldv, double* C, int64_t ldc,
+                    sbr_precision prec, sbr_stream_t stream);
+
+/* W = A Y with A symmetric (m x m, lower triangle read), Y m x k. */
+int sbr_symm_lower(int64_t m, int64_t k, const double* A, int64_t lda,
+                   const double* Y, int64_t ldy, double* W, int64_t ldw,
+                   sbr_precision prec, sbr_stream_t stream);
+
+/* Per-phase timing of the last call made through `plan` with timing enabled
+ * (hipEvents recorded on the call's stream; reading them synchronises). */
+typedef struct {
+    double ms_total;          /* whole call */
+    double ms_f2b;            /* full-to-band */
+    double ms_band;           /* all band-to-band halvings */
+    double ms_bisect;         /* tridiagonal extraction + bisection */
+    double ms_update_kernels; /* sum over launches of the SYMM + SYR2K kernels */
+    int64_t update_launches;  /* number of those launches */
+    double ms_syr2k;          /* SYR2K launches only */
+    int64_t syr2k_launches;
+    double ms_symm;           /* SYMM launches only */
+    int64_t symm_launches;
+    double ms_stage[8];       /* per halving stage (b0, b0/2, ...) */
+    int32_t n_stages;
+} sbr_timing;
+
+int sbr_plan_set_timing(sbr_plan_t plan, int enable);
+
+/* Cap on the number of work-groups of the pipelined band-to-band kernel
+ * (0 = automatic).  With 1 the chases run one at a time in the sequential
+ * (sweep-major) order of Algorithm 4.2; the pipelined result is bitwise the
+ * same because every chase does the same arithmetic on the same data. */
+int sbr_plan_set_chase_blocks(sbr_plan_t plan, int32_t max_blocks);
+
+/* Blocking: copies the plan's device status word.  Nonzero means a pipelined
+ * band-to-band kernel stopped waiting for the previous sweep (after 10 s)
+ * and abandoned the stage; results of that call are then invalid. */
+int sbr_plan_status(sbr_plan_t plan, int32_t* status);
+int sbr_plan_get_timing(sbr_plan_t plan, sbr_timing* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBR_STAGES_H */

@@ -1,0 +1,276 @@
+"""MI355X-native successive-band-reduction symmetric eigensolver.
+
+Thin ctypes binding over ``lib/libsbr.so`` (the C ABI declared in
+``include/sbr.h`` and ``include/sbr_stages.h``).  Every step of the method runs
+in the library's HIP kernels; this module only marshals arguments: device
+pointers from torch tensors and the current torch stream.  There is no CPU
+fallback -- if the library is missing, importing the binding raises.
+
+Layout note: the library works on column-major matrices.  A row-major torch
+tensor ``A`` of shape (n, n) is the column-major matrix ``A^T``; for the
+symmetric inputs of the eigensolver this is the same matrix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libsbr.so")
+
+FP64 = 0
+FP32_MFMA = 1
+_PREC = {"fp64": FP64, "fp32": FP32_MFMA, "fp32_mfma": FP32_MFMA, FP64: FP64, FP32_MFMA: FP32_MFMA}
+
+_i64, _i32, _dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+_vp = ctypes.c_void_p
+
+
+class SbrError(RuntimeError):
+    pass
+
+
+class _Timing(ctypes.Structure):
+    _fields_ = [
+        ("ms_total", _dbl), ("ms_f2b", _dbl), ("ms_band", _dbl), ("ms_bisect", _dbl),
+        ("ms_update_kernels", _dbl), ("update_launches", _i64),
+        ("ms_syr2k", _dbl), ("syr2k_launches", _i64),
+        ("ms_symm", _dbl), ("symm_launches", _i64),
+        ("ms_stage", _dbl * 8), ("n_stages", _i32),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsbr.so not built (run paper_1604_03703_amd.build.build() or "
+                          "__graft_entry__.build()); there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "sbr_syev_eigvals": ([_i64, _vp, _i64, _i32, _vp, _vp], ctypes.c_int),
+        "sbr_syev_eigvals_ex": ([_vp, _i64, _vp, _i64, _i32, ctypes.c_int, _vp, _vp], ctypes.c_int),
+        "sbr_syev_eigvals_batched": ([_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_vp),
+                                      ctypes.POINTER(_i64), _i32, ctypes.c_int, _vp,
+                                      ctypes.POINTER(_vp)], ctypes.c_int),
+        "sbr_tridiag_eigvals": ([_i64, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "sbr_plan_create": ([ctypes.POINTER(_vp), _i64, _i32, ctypes.c_int], ctypes.c_int),
+        "sbr_plan_destroy": ([_vp], ctypes.c_int),
+        "sbr_workspace_size": ([_i64, _i32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "sbr_default_band": ([_i64], _i32),
+        "sbr_last_hip_error": ([], ctypes.c_int),
+        "sbr_full_to_band": ([_vp, _i64, _vp, _i64, _i32, ctypes.c_int, _vp], ctypes.c_int),
+        "sbr_dense_to_band": ([_i64, _vp, _i64, _i32, _vp, _i64, _vp], ctypes.c_int),
+        "sbr_band_halve": ([_vp, _i64, _vp, _i64, _i32, ctypes.c_int, _vp], ctypes.c_int),
+        "sbr_panel_qr": ([_vp, _i64, _i32, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "sbr_gemm": ([_i32, _i32, _i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64, _dbl, _vp, _i64,
+                      ctypes.c_int, _vp], ctypes.c_int),
+        "sbr_syr2k_lower": ([_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _vp], ctypes.c_int),
+        "sbr_symm_lower": ([_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _vp], ctypes.c_int),
+        "sbr_plan_set_timing": ([_vp, ctypes.c_int], ctypes.c_int),
+        "sbr_plan_get_timing": ([_vp, ctypes.POINTER(_Timing)], ctypes.c_int),
+        "sbr_plan_set_chase_blocks": ([_vp, _i32], ctypes.c_int),
+        "sbr_plan_status": ([_vp, ctypes.POINTER(_i32)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+EXPORTED = (
+    "sbr_syev_eigvals", "sbr_syev_eigvals_ex", "sbr_syev_eigvals_batched", "sbr_tridiag_eigvals",
+    "sbr_plan_create", "sbr_plan_destroy", "sbr_workspace_size", "sbr_default_band",
+    "sbr_last_hip_error", "sbr_full_to_band", "sbr_dense_to_band", "sbr_band_halve", "sbr_panel_qr",
+    "sbr_gemm", "sbr_syr2k_lower", "sbr_symm_lower", "sbr_plan_set_timing", "sbr_plan_get_timing",
+    "sbr_plan_set_chase_blocks", "sbr_plan_status",
+)
+
+
+def lib():
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        extra = ""
+        if rc == 2:
+            extra = " (hipError %d)" % _lib.sbr_last_hip_error()
+        raise SbrError("%s failed with code %d%s" % (what, rc, extra))
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError("%s must be a CUDA float64 tensor" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(p):
+    try:
+        return _PREC[p]
+    except KeyError:
+        raise ValueError("precision must be 'fp64' or 'fp32_mfma'") from None
+
+
+def default_band(n: int) -> int:
+    return int(_lib.sbr_default_band(int(n)))
+
+
+class Plan:
+    """Device workspace for problems up to ``n_max`` (grows on demand)."""
+
+    def __init__(self, n_max: int = 0, batch_max: int = 0, precision="fp64"):
+        h = ctypes.c_void_p()
+        _check(_lib.sbr_plan_create(ctypes.byref(h), int(n_max), int(batch_max), _prec(precision)),
+               "sbr_plan_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_timing(self, on: bool = True):
+        _check(_lib.sbr_plan_set_timing(self._h, 1 if on else 0), "sbr_plan_set_timing")
+
+    def timing(self) -> dict:
+        t = _Timing()
+        _check(_lib.sbr_plan_get_timing(self._h, ctypes.byref(t)), "sbr_plan_get_timing")
+        out = {f: getattr(t, f) for f, _ in _Timing._fields_ if f != "ms_stage"}
+        out["ms_stage"] = [t.ms_stage[i] for i in range(t.n_stages)]
+        return out
+
+    def set_chase_blocks(self, max_blocks: int):
+        _check(_lib.sbr_plan_set_chase_blocks(self._h, int(max_blocks)), "sbr_plan_set_chase_blocks")
+
+    def status(self) -> int:
+        v = _i32()
+        _check(_lib.sbr_plan_status(self._h, ctypes.byref(v)), "sbr_plan_status")
+        return int(v.value)
+
+    def close(self):
+        if self._h:
+            _lib.sbr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eigvalsh(A: torch.Tensor, b0: int = 0, precision="fp64", plan: Plan | None = None,
+             overwrite: bool = False, stream=None) -> torch.Tensor:
+    """Ascending eigenvalues of the symmetric CUDA float64 matrix ``A``."""
+    n = A.shape[0]
+    if A.dim() != 2 or A.shape[1] != n:
+        raise ValueError("A must be square")
+    work = A if (overwrite and A.is_contiguous()) else A.contiguous().clone()
+    w = torch.empty(n, dtype=torch.float64, device=A.device)
+    if plan is None and _prec(precision) == FP64:
+        rc = _lib.sbr_syev_eigvals(n, _dev_f64(work, "A"), max(n, 1), int(b0), _stream(stream),
+                                   _dev_f64(w, "w"))
+        _check(rc, "sbr_syev_eigvals")
+    else:
+        if plan is None:
+            plan = Plan(n, 0, precision)
+        rc = _lib.sbr_syev_eigvals_ex(plan.handle, n, _dev_f64(work, "A"), max(n, 1), int(b0),
+                                      _prec(precision), _stream(stream), _dev_f64(w, "w"))
+        _check(rc, "sbr_syev_eigvals_ex")
+    return w
+
+
+def eigvalsh_batched(mats, b0: int = 0, precision="fp64", plan: Plan | None = None, stream=None):
+    """Eigenvalues of a list of symmetric CUDA float64 matrices (overwritten)."""
+    k = len(mats)
+    ns = (_i64 * k)(*[int(m.shape[0]) for m in mats])
+    ldas = (_i64 * k)(*[int(m.shape[0]) for m in mats])
+    ws = [torch.empty(int(m.shape[0]), dtype=torch.float64, device=m.device) for m in mats]
+    aps = (_vp * k)(*[_dev_f64(m, "A").value for m in mats])
+    wps = (_vp * k)(*[_dev_f64(x, "w").value for x in ws])
+    if plan is None:
+        plan = Plan(max(int(m.shape[0]) for m in mats) if k else 0, k, precision)
+    rc = _lib.sbr_syev_eigvals_batched(plan.handle, k, ns, aps, ldas, int(b0), _prec(precision),
+                                       _stream(stream), wps)
+    _check(rc, "sbr_syev_eigvals_batched")
+    return ws
+
+
+def tridiag_eigvals(d: torch.Tensor, e: torch.Tensor | None, stream=None) -> torch.Tensor:
+    n = d.shape[0]
+    w = torch.empty(n, dtype=torch.float64, device=d.device)
+    ep = _dev_f64(e, "e") if (e is not None and n > 1) else ctypes.c_void_p(0)
+    _check(_lib.sbr_tridiag_eigvals(n, _dev_f64(d, "d"), ep, _stream(stream), _dev_f64(w, "w")),
+           "sbr_tridiag_eigvals")
+    return w
+
+
+def full_to_band(A: torch.Tensor, b: int, plan: Plan, precision="fp64", stream=None) -> torch.Tensor:
+    """Reduce the symmetric A (in place, column-major view) to bandwidth b.
+
+    Returns A; its column-major lower band (= the row-major upper band of the
+    torch tensor) holds the band matrix, the rest of that triangle is zero.
+    """
+    n = A.shape[0]
+    _check(_lib.sbr_full_to_band(plan.handle, n, _dev_f64(A, "A"), max(n, 1), int(b), _prec(precision),
+                                 _stream(stream)), "sbr_full_to_band")
+    return A
+
+
+def dense_to_band(A: torch.Tensor, b: int, ldband: int, stream=None) -> torch.Tensor:
+    """Band storage (torch shape (n, ldband): row j holds B(j + d, j) at column d)."""
+    n = A.shape[0]
+    band = torch.empty((n, ldband), dtype=torch.float64, device=A.device)
+    _check(_lib.sbr_dense_to_band(n, _dev_f64(A, "A"), max(n, 1), int(b), _dev_f64(band, "band"),
+                                  int(ldband), _stream(stream)), "sbr_dense_to_band")
+    return band
+
+
+def band_halve(band: torch.Tensor, b: int, plan: Plan, precision="fp64", stream=None) -> torch.Tensor:
+    n, ld = band.shape
+    _check(_lib.sbr_band_halve(plan.handle, n, _dev_f64(band, "band"), ld, int(b), _prec(precision),
+                               _stream(stream)), "sbr_band_halve")
+    return band
+
+
+def panel_qr(P_colmajor: torch.Tensor, b: int, plan: Plan, stream=None):
+    """TSQR + Householder reconstruction of the m x b panel given column-major
+    as a torch tensor of shape (b, m).  Returns column-major (Q, R, U, T, S)."""
+    bb, m = P_colmajor.shape
+    assert bb == b
+    dev = P_colmajor.device
+    Q = torch.empty((b, m), dtype=torch.float64, device=dev)
+    U = torch.empty((b, m), dtype=torch.float64, device=dev)
+    R = torch.empty((b, b), dtype=torch.float64, device=dev)
+    T = torch.empty((b, b), dtype=torch.float64, device=dev)
+    S = torch.empty(b, dtype=torch.float64, device=dev)
+    _check(_lib.sbr_panel_qr(plan.handle, m, b, _dev_f64(P_colmajor, "P"), m, _dev_f64(Q, "Q"),
+                             _dev_f64(R, "R"), _dev_f64(U, "U"), _dev_f64(T, "T"), _dev_f64(S, "S"),
+                             _stream(stream)), "sbr_panel_qr")
+    return Q, R, U, T, S
+
+
+def gemm(transa: int, transb: int, m: int, n: int, k: int, alpha: float, A, lda: int, B, ldb: int,
+         beta: float, C, ldc: int, precision="fp64", stream=None):
+    _check(_lib.sbr_gemm(transa, transb, m, n, k, alpha, _dev_f64(A, "A"), lda, _dev_f64(B, "B"), ldb, beta,
+                         _dev_f64(C, "C"), ldc, _prec(precision), _stream(stream)), "sbr_gemm")
+    return C
+
+
+def syr2k_lower(m: int, k: int, U, ldu: int, V, ldv: int, C, ldc: int, precision="fp64", stream=None):
+    _check(_lib.sbr_syr2k_lower(m, k, _dev_f64(U, "U"), ldu, _dev_f64(V, "V"), ldv, _dev_f64(C, "C"), ldc,
+                                _prec(precision), _stream(stream)), "sbr_syr2k_lower")
+    return C
+
+
+def symm_lower(m: int, k: int, A, lda: int, Y, ldy: int, W, ldw: int, precision="fp64", stream=None):
+    _check(_lib.sbr_symm_lower(m, k, _dev_f64(A, "A"), lda, _dev_f64(Y, "Y"), ldy, _dev_f64(W, "W"), ldw,
+                               _prec(precision), _stream(stream)), "sbr_symm_lower")
+    return W

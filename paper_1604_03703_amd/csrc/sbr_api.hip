@@ -1,0 +1,647 @@
+// sbr_api.hip -- C ABI of the SBR eigensolver: argument checking, the plan
+// (device workspace + per-call timing), and the sequencing of the stages of
+// Algorithm 4.3 on one GPU:
+//   full-to-band (Algorithm 4.1, right-looking; per panel: TSQR, Householder
+//   reconstruction, Y = U T, W = A22 Y, V = 1/2 U T^T U^T W - W,
+//   A22 += U V^T + V U^T), then band halvings b -> b/2 (Algorithm 4.2, k = 2)
+//   down to bandwidth 1, then Sturm bisection on the tridiagonal.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/sbr.h"
+#include "../../include/sbr_stages.h"
+#include "sbr_internal.h"
+
+using namespace sbr;
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+int hip_fail(hipError_t e) {
+    g_last_hip_error = (int)e;
+    return SBR_EHIP;
+}
+
+#define SBR_CHECK_LAUNCH()                                  \
+    do {                                                    \
+        hipError_t _e = hipGetLastError();                  \
+        if (_e != hipSuccess) return hip_fail(_e);          \
+    } while (0)
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace
+
+struct sbr_plan_s {
+    int device = 0;
+    int64_t n_cap = 0;
+    int b_cap = 0;
+    sbr_precision prec = SBR_FP64;
+    int32_t batch_max = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    // carved pointers
+    double *Q = nullptr, *U = nullptr, *Y = nullptr, *W = nullptr, *V = nullptr;
+    double *part = nullptr;
+    int64_t part_doubles = 0;
+    double *T = nullptr, *W1inv = nullptr, *Mm = nullptr, *Zm = nullptr, *S = nullptr;
+    double* tsqr_ws = nullptr;
+    double *bandA = nullptr, *bandB = nullptr;
+    double* chase_scratch = nullptr;
+    int* flags = nullptr;
+    int* status = nullptr;     // device word: nonzero if a pipelined kernel gave up waiting
+    int chase_max_grid = 0;
+    double *d = nullptr, *e = nullptr, *e2p = nullptr;
+    BisectSetup* setup = nullptr;
+    double* pcopy = nullptr;   // panel copy for sbr_panel_qr
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    EventPair ev_total, ev_f2b, ev_band, ev_bis;
+    std::vector<EventPair> ev_syr2k, ev_symm, ev_stage;
+
+    hipEvent_t ev() {
+        if (pool_used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[pool_used++];
+    }
+    void reset_timing() {
+        pool_used = 0;
+        ev_total = ev_f2b = ev_band = ev_bis = EventPair{};
+        ev_syr2k.clear();
+        ev_symm.clear();
+        ev_stage.clear();
+    }
+    void mark(hipEvent_t e, hipStream_t s) {
+        if (e) (void)hipEventRecord(e, s);
+    }
+};
+
+namespace {
+
+struct Layout {
+    size_t bytes = 0;
+    size_t off_Q, off_U, off_Y, off_W, off_V, off_part, off_T, off_W1inv, off_Mm, off_Zm, off_S, off_tsqr,
+        off_bandA, off_bandB, off_chase, off_flags, off_status, off_d, off_e, off_e2p, off_setup, off_pcopy;
+    int64_t part_doubles = 0;
+};
+
+size_t take(size_t& cur, size_t bytes) {
+    const size_t off = (cur + 255) & ~(size_t)255;
+    cur = off + bytes;
+    return off;
+}
+
+Layout make_layout(int64_t n, int b) {
+    Layout L;
+    const size_t D = sizeof(double);
+    const int64_t nb = n * (int64_t)b;
+    // split-K partials: the largest of the SYMM and U^T W reductions over panels
+    int64_t part = 1;
+    for (int bb = 2; bb <= b; bb *= 2)
+        for (int64_t m = n - bb; m >= bb; m -= bb) {
+            const int ss = symm_splits(m, bb);
+            if (ss > 1) part = std::max(part, (int64_t)ss * m * bb);
+            const int gs = gemm_splits(bb, bb, m);
+            if (gs > 1) part = std::max(part, (int64_t)gs * bb * bb);
+        }
+    L.part_doubles = part;
+    size_t cur = 0;
+    L.off_Q = take(cur, nb * D);
+    L.off_U = take(cur, nb * D);
+    L.off_Y = take(cur, nb * D);
+    L.off_W = take(cur, nb * D);
+    L.off_V = take(cur, nb * D);
+    L.off_part = take(cur, part * D);
+    L.off_T = take(cur, (size_t)b * b * D);
+    L.off_W1inv = take(cur, (size_t)b * b * D);
+    L.off_Mm = take(cur, (size_t)b * b * D);
+    L.off_Zm = take(cur, (size_t)b * b * D);
+    L.off_S = take(cur, (size_t)b * D);
+    L.off_tsqr = take(cur, (size_t)tsqr_workspace_doubles(n > b ? n - b : b, b) * D);
+    L.off_bandA = take(cur, (size_t)n * (2 * b + 1) * D);
+    L.off_bandB = take(cur, (size_t)n * (b + 1) * D);
+    int grid = 0;
+    L.off_chase = take(cur, (size_t)chase_workspace_doubles(n, b, &grid) * D);
+    L.off_flags = take(cur, (size_t)(n + 4) * sizeof(int));
+    L.off_status = take(cur, sizeof(int));
+    L.off_d = take(cur, (size_t)n * D);
+    L.off_e = take(cur, (size_t)n * D);
+    L.off_e2p = take(cur, (size_t)n * D);
+    L.off_setup = take(cur, sizeof(BisectSetup));
+    L.off_pcopy = take(cur, nb * D);
+    L.bytes = cur + 256;
+    return L;
+}
+
+int ensure_workspace(sbr_plan_t p, int64_t n, int b) {
+    if (p->ws && n <= p->n_cap && b <= p->b_cap) return 0;
+    const int64_t nn = std::max(n, p->n_cap);
+    const int bb = std::max(b, p->b_cap);
+    const Layout L = make_layout(nn, bb);
+    if (p->ws) {
+        hipError_t e = hipFree(p->ws);
+        p->ws = nullptr;
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    void* ws = nullptr;
+    hipError_t e = hipMalloc(&ws, L.bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return SBR_ENOMEM;
+    }
+    p->ws = ws;
+    p->ws_bytes = L.bytes;
+    p->n_cap = nn;
+    p->b_cap = bb;
+    char* base = (char*)ws;
+    p->Q = (double*)(base + L.off_Q);
+    p->U = (double*)(base + L.off_U);
+    p->Y = (double*)(base + L.off_Y);
+    p->W = (double*)(base + L.off_W);
+    p->V = (double*)(base + L.off_V);
+    p->part = (double*)(base + L.off_part);
+    p->part_doubles = L.part_doubles;
+    p->T = (double*)(base + L.off_T);
+    p->W1inv = (double*)(base + L.off_W1inv);
+    p->Mm = (double*)(base + L.off_Mm);
+    p->Zm = (double*)(base + L.off_Zm);
+    p->S = (double*)(base + L.off_S);
+    p->tsqr_ws = (double*)(base + L.off_tsqr);
+    p->bandA = (double*)(base + L.off_bandA);
+    p->bandB = (double*)(base + L.off_bandB);
+    p->chase_scratch = (double*)(base + L.off_chase);
+    p->flags = (int*)(base + L.off_flags);
+    p->status = (int*)(base + L.off_status);
+    {
+        hipError_t ez = hipMemset(p->status, 0, sizeof(int));
+        if (ez != hipSuccess) return hip_fail(ez);
+    }
+    p->d = (double*)(base + L.off_d);
+    p->e = (double*)(base + L.off_e);
+    p->e2p = (double*)(base + L.off_e2p);
+    p->setup = (BisectSetup*)(base + L.off_setup);
+    p->pcopy = (double*)(base + L.off_pcopy);
+    return 0;
+}
+
+int check_band(int32_t b) { return (is_pow2(b) && b >= 2 && b <= 128) ? 0 : 1; }
+
+int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, bool f32, hipStream_t s) {
+    const int64_t ldq = p->n_cap;
+    int64_t k = 0;
+    TsqrTree tr;
+    for (;; ++k) {
+        const int64_t c0 = k * b, r0 = c0 + b, m = n - r0;
+        if (m < b) break;
+        double* P = A + r0 + c0 * lda;
+        double* A22 = A + r0 + r0 * lda;
+        tsqr_plan(tr, m, b, p->tsqr_ws);
+        launch_tsqr(tr, P, lda, p->Q, ldq, s);
+        launch_reconstruct(b, p->Q, ldq, p->U, ldq, p->T, p->W1inv, p->S, s);
+        if (m > b)
+            launch_gemm(false, false, false, m - b, b, b, 1.0, p->Q + b, ldq, p->W1inv, b, 0.0, nullptr, 0,
+                        p->U + b, ldq, s);
+        launch_panel_writeback(m, b, P, lda, tsqr_root_r(tr), p->S, s);
+        // Y = U T
+        launch_gemm(false, false, false, m, b, b, 1.0, p->U, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, s);
+        // W = A22 Y
+        EventPair ep;
+        if (p->timing) { ep.a = p->ev(); p->mark(ep.a, s); }
+        const int ss = symm_splits(m, b);
+        launch_symm_lower(f32, m, b, A22, lda, p->Y, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
+        if (p->timing) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_symm.push_back(ep); }
+        // Z = U^T W ; M = T^T Z ; V = 1/2 U M - W
+        const int gs = gemm_splits(b, b, m);
+        launch_gemm_splitk(false, true, false, b, b, m, 1.0, p->U, ldq, p->W, ldq, 0.0, nullptr, 0, p->Zm, b,
+                           p->part, gs, s);
+        launch_gemm(false, true, false, b, b, b, 1.0, p->T, b, p->Zm, b, 0.0, nullptr, 0, p->Mm, b, s);
+        launch_gemm(false, false, false, m, b, b, 0.5, p->U, ldq, p->Mm, b, -1.0, p->W, ldq, p->V, ldq, s);
+        // A22 += U V^T + V U^T
+        EventPair eq;
+        if (p->timing) { eq.a = p->ev(); p->mark(eq.a, s); }
+        launch_syr2k_lower(f32, m, b, p->U, ldq, p->V, ldq, A22, lda, s);
+        if (p->timing) { eq.b = p->ev(); p->mark(eq.b, s); p->ev_syr2k.push_back(eq); }
+        SBR_CHECK_LAUNCH();
+    }
+    const int64_t c0 = k * b, r0 = c0 + b, m = n - r0;
+    if (m >= 2) {
+        launch_f2b_tail(m, b, A + r0 + c0 * lda, lda, A + r0 + r0 * lda, lda, s);
+        SBR_CHECK_LAUNCH();
+    }
+    return 0;
+}
+
+// Band halvings from b0 to 1 starting from the lower band of the dense A.
+int run_band_stages(sbr_plan_t p, int64_t n, const double* A, int64_t lda, int b0, bool f32, hipStream_t s) {
+    double* cur = p->bandA;
+    int64_t ld = 2 * b0 + 1;
+    launch_dense_to_band(n, A, lda, b0, cur, ld, s);
+    int b = b0;
+    while (b > 1) {
+        EventPair ep;
+        if (p->timing) { ep.a = p->ev(); p->mark(ep.a, s); }
+        launch_band_halve(n, cur, ld, b, f32, p->chase_scratch, p->flags, p->status, p->chase_max_grid, s);
+        if (p->timing) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_stage.push_back(ep); }
+        const int h = b / 2;
+        double* nxt = (cur == p->bandA) ? p->bandB : p->bandA;
+        const int64_t ldn = 2 * h + 1;
+        launch_band_copy(n, cur, ld, h, nxt, ldn, s);
+        cur = nxt;
+        ld = ldn;
+        b = h;
+        SBR_CHECK_LAUNCH();
+    }
+    launch_band_to_tridiag(n, cur, ld, p->d, p->e, s);
+    SBR_CHECK_LAUNCH();
+    return 0;
+}
+
+std::mutex g_plan_mutex;
+std::map<int, sbr_plan_t> g_plans;
+
+int init_attributes() {
+    int rc = init_tsqr_attributes();
+    rc |= init_band_attributes();
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sbr_last_hip_error(void) { return g_last_hip_error; }
+
+int32_t sbr_default_band(int64_t n) {
+    if (n < 512) return 16;
+    if (n < 16384) return 64;
+    return 128;
+}
+
+int sbr_plan_create(sbr_plan_t* plan, int64_t n_max, int32_t batch_max, sbr_precision prec) {
+    if (!plan) return -1;
+    if (n_max < 0) return -2;
+    if (batch_max < 0) return -3;
+    if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -4;
+    sbr_plan_t p = new (std::nothrow) sbr_plan_s();
+    if (!p) return SBR_ENOMEM;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e);
+    }
+    if (init_attributes() != 0) {
+        delete p;
+        return hip_fail(hipErrorInvalidValue);
+    }
+    p->prec = prec;
+    p->batch_max = batch_max;
+    if (n_max > 0) {
+        int b = sbr_default_band(n_max);
+        if (b >= n_max) b = 2;
+        const int rc = ensure_workspace(p, n_max, std::max(b, 2));
+        if (rc) {
+            delete p;
+            return rc;
+        }
+    }
+    *plan = p;
+    return 0;
+}
+
+int sbr_plan_destroy(sbr_plan_t plan) {
+    if (!plan) return -1;
+    for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
+    if (plan->ws) (void)hipFree(plan->ws);
+    delete plan;
+    return 0;
+}
+
+int sbr_workspace_size(int64_t n, int32_t b0, sbr_precision prec, size_t* bytes) {
+    if (n < 0) return -1;
+    if (b0 == 0) b0 = sbr_default_band(n);
+    if (check_band(b0)) return -2;
+    if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -3;
+    if (!bytes) return -4;
+    *bytes = make_layout(std::max<int64_t>(n, 1), b0).bytes;
+    return 0;
+}
+
+int sbr_plan_set_chase_blocks(sbr_plan_t plan, int32_t max_blocks) {
+    if (!plan) return -1;
+    if (max_blocks < 0) return -2;
+    plan->chase_max_grid = max_blocks;
+    return 0;
+}
+
+int sbr_plan_status(sbr_plan_t plan, int32_t* status) {
+    if (!plan) return -1;
+    if (!status) return -2;
+    *status = 0;
+    if (!plan->status) return 0;
+    int v = 0;
+    hipError_t e = hipMemcpy(&v, plan->status, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    *status = v;
+    return 0;
+}
+
+int sbr_plan_set_timing(sbr_plan_t plan, int enable) {
+    if (!plan) return -1;
+    plan->timing = enable != 0;
+    return 0;
+}
+
+static double pair_ms(const EventPair& p) {
+    if (!p.a || !p.b) return 0.0;
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) != hipSuccess) return 0.0;
+    if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) return 0.0;
+    return (double)ms;
+}
+
+int sbr_plan_get_timing(sbr_plan_t plan, sbr_timing* out) {
+    if (!plan) return -1;
+    if (!out) return -2;
+    memset(out, 0, sizeof(*out));
+    out->ms_total = pair_ms(plan->ev_total);
+    out->ms_f2b = pair_ms(plan->ev_f2b);
+    out->ms_band = pair_ms(plan->ev_band);
+    out->ms_bisect = pair_ms(plan->ev_bis);
+    for (auto& e : plan->ev_syr2k) { out->ms_syr2k += pair_ms(e); out->syr2k_launches++; }
+    for (auto& e : plan->ev_symm) { out->ms_symm += pair_ms(e); out->symm_launches++; }
+    out->ms_update_kernels = out->ms_syr2k + out->ms_symm;
+    out->update_launches = out->syr2k_launches + out->symm_launches;
+    out->n_stages = (int32_t)std::min<size_t>(plan->ev_stage.size(), 8);
+    for (int i = 0; i < out->n_stages; ++i) out->ms_stage[i] = pair_ms(plan->ev_stage[i]);
+    return 0;
+}
+
+int sbr_syev_eigvals_ex(sbr_plan_t plan, int64_t n, double* A, int64_t lda, int32_t b0, sbr_precision prec,
+                        sbr_stream_t stream, double* w) {
+    if (!plan) return -1;
+    if (n < 0) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < std::max<int64_t>(1, n)) return -4;
+    if (b0 != 0 && check_band(b0)) return -5;
+    if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -6;
+    if (n > 0 && !w) return -8;
+    if (n == 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    if (b0 == 0) b0 = sbr_default_band(n);
+    // a band at least as wide as the matrix needs no full-to-band step
+    int b = b0;
+    while (b > 1 && b / 2 >= n - 1) b /= 2;
+    int rc = ensure_workspace(plan, n, std::max(b0, 2));
+    if (rc) return rc;
+    const bool f32 = (prec == SBR_FP32_MFMA);
+    if (plan->timing) {
+        plan->reset_timing();
+        plan->ev_total.a = plan->ev();
+        plan->mark(plan->ev_total.a, s);
+        plan->ev_f2b.a = plan->ev();
+        plan->mark(plan->ev_f2b.a, s);
+    }
+    if (b >= 2 && b < n - 1) {
+        rc = run_full_to_band(plan, n, A, lda, b, f32, s);
+        if (rc) return rc;
+    }
+    if (plan->timing) {
+        plan->ev_f2b.b = plan->ev();
+        plan->mark(plan->ev_f2b.b, s);
+        plan->ev_band.a = plan->ev();
+        plan->mark(plan->ev_band.a, s);
+    }
+    rc = run_band_stages(plan, n, A, lda, std::max(b, 1), f32, s);
+    if (rc) return rc;
+    if (plan->timing) {
+        plan->ev_band.b = plan->ev();
+        plan->mark(plan->ev_band.b, s);
+        plan->ev_bis.a = plan->ev();
+        plan->mark(plan->ev_bis.a, s);
+    }
+    launch_tridiag_eigvals(n, plan->d, plan->e, plan->e2p, plan->setup, w, s);
+    SBR_CHECK_LAUNCH();
+    if (plan->timing) {
+        plan->ev_bis.b = plan->ev();
+        plan->mark(plan->ev_bis.b, s);
+        plan->ev_total.b = plan->ev();
+        plan->mark(plan->ev_total.b, s);
+    }
+    return 0;
+}
+
+int sbr_syev_eigvals(int64_t n, double* A, int64_t lda, int32_t b0, sbr_stream_t stream, double* w) {
+    if (n < 0) return -1;
+    if (n > 0 && !A) return -2;
+    if (lda < std::max<int64_t>(1, n)) return -3;
+    if (b0 != 0 && check_band(b0)) return -4;
+    if (n > 0 && !w) return -6;
+    if (n == 0) return 0;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    sbr_plan_t p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mutex);
+        auto it = g_plans.find(dev);
+        if (it == g_plans.end()) {
+            const int rc = sbr_plan_create(&p, 0, 0, SBR_FP64);
+            if (rc) return rc;
+            g_plans[dev] = p;
+        } else {
+            p = it->second;
+        }
+        return sbr_syev_eigvals_ex(p, n, A, lda, b0, SBR_FP64, stream, w);
+    }
+}
+
+int sbr_tridiag_eigvals(int64_t n, const double* d, const double* e, sbr_stream_t stream, double* w) {
+    if (n < 0) return -1;
+    if (n > 0 && !d) return -2;
+    if (n > 1 && !e) return -3;
+    if (n > 0 && !w) return -5;
+    if (n == 0) return 0;
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return hip_fail(he);
+    std::lock_guard<std::mutex> lk(g_plan_mutex);
+    sbr_plan_t p = nullptr;
+    auto it = g_plans.find(dev);
+    if (it == g_plans.end()) {
+        const int rc = sbr_plan_create(&p, 0, 0, SBR_FP64);
+        if (rc) return rc;
+        g_plans[dev] = p;
+    } else {
+        p = it->second;
+    }
+    const int rc = ensure_workspace(p, n, 2);
+    if (rc) return rc;
+    launch_tridiag_eigvals(n, d, e, p->e2p, p->setup, w, (hipStream_t)stream);
+    SBR_CHECK_LAUNCH();
+    return 0;
+}
+
+int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n, double* const* A,
+                             const int64_t* lda, int32_t b0, sbr_precision prec, sbr_stream_t stream,
+                             double* const* w) {
+    if (!plan) return -1;
+    if (batch < 0) return -2;
+    if (batch > 0 && !n) return -3;
+    if (batch > 0 && !A) return -4;
+    if (batch > 0 && !lda) return -5;
+    if (b0 != 0 && check_band(b0)) return -6;
+    if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -7;
+    if (batch > 0 && !w) return -9;
+    for (int32_t k = 0; k < batch; ++k) {
+        if (n[k] < 1 || lda[k] < n[k] || !A[k] || !w[k]) return -3;
+    }
+    for (int32_t k = 0; k < batch; ++k) {
+        int bk = b0 ? b0 : (n[k] <= 64 ? 8 : (n[k] <= 256 ? 16 : 32));
+        const int rc = sbr_syev_eigvals_ex(plan, n[k], A[k], lda[k], bk, prec, stream, w[k]);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+int sbr_full_to_band(sbr_plan_t plan, int64_t n, double* A, int64_t lda, int32_t b, sbr_precision prec,
+                     sbr_stream_t stream) {
+    if (!plan) return -1;
+    if (n < 0) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < std::max<int64_t>(1, n)) return -4;
+    if (check_band(b)) return -5;
+    if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -6;
+    if (n < 3 || b >= n - 1) return 0;
+    int rc = ensure_workspace(plan, n, b);
+    if (rc) return rc;
+    return run_full_to_band(plan, n, A, lda, b, prec == SBR_FP32_MFMA, (hipStream_t)stream);
+}
+
+int sbr_dense_to_band(int64_t n, const double* A, int64_t lda, int32_t b, double* band, int64_t ldband,
+                      sbr_stream_t stream) {
+    if (n < 0) return -1;
+    if (n > 0 && !A) return -2;
+    if (lda < std::max<int64_t>(1, n)) return -3;
+    if (b < 0) return -4;
+    if (n > 0 && !band) return -5;
+    if (ldband < b + 1) return -6;
+    launch_dense_to_band(n, A, lda, b, band, ldband, (hipStream_t)stream);
+    SBR_CHECK_LAUNCH();
+    return 0;
+}
+
+int sbr_band_halve(sbr_plan_t plan, int64_t n, double* band, int64_t ldband, int32_t b, sbr_precision prec,
+                   sbr_stream_t stream) {
+    if (!plan) return -1;
+    if (n < 0) return -2;
+    if (n > 0 && !band) return -3;
+    if (ldband < 2 * (int64_t)b + 1) return -4;
+    if (check_band(b)) return -5;
+    if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -6;
+    if (n < 3) return 0;
+    int rc = ensure_workspace(plan, n, b);
+    if (rc) return rc;
+    launch_band_halve(n, band, ldband, b, prec == SBR_FP32_MFMA, plan->chase_scratch, plan->flags,
+                      plan->status, plan->chase_max_grid, (hipStream_t)stream);
+    SBR_CHECK_LAUNCH();
+    return 0;
+}
+
+int sbr_panel_qr(sbr_plan_t plan, int64_t m, int32_t b, const double* P, int64_t ldp, double* Q, double* R,
+                 double* U, double* T, double* S, sbr_stream_t stream) {
+    if (!plan) return -1;
+    if (m < b) return -2;
+    if (!tsqr_supported(b)) return -3;
+    if (!P) return -4;
+    if (ldp < m) return -5;
+    if (!Q) return -6;
+    if (!R) return -7;
+    if (!U) return -8;
+    if (!T) return -9;
+    if (!S) return -10;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ensure_workspace(plan, m + b, b);
+    if (rc) return rc;
+    hipError_t e = hipMemcpy2DAsync(plan->pcopy, (size_t)m * sizeof(double), P, (size_t)ldp * sizeof(double),
+                                    (size_t)m * sizeof(double), (size_t)b, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+    TsqrTree tr;
+    tsqr_plan(tr, m, b, plan->tsqr_ws);
+    launch_tsqr(tr, plan->pcopy, m, Q, m, s);
+    launch_reconstruct(b, Q, m, U, m, T, plan->W1inv, S, s);
+    if (m > b) launch_gemm(false, false, false, m - b, b, b, 1.0, Q + b, m, plan->W1inv, b, 0.0, nullptr, 0, U + b, m, s);
+    e = hipMemcpyAsync(R, tsqr_root_r(tr), (size_t)b * b * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+    SBR_CHECK_LAUNCH();
+    return 0;
+}
+
+int sbr_gemm(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+             int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, sbr_precision prec,
+             sbr_stream_t stream) {
+    if (transa != 0 && transa != 1) return -1;
+    if (transb != 0 && transb != 1) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    if (m > 0 && n > 0 && k > 0 && !A) return -7;
+    if (lda < std::max<int64_t>(1, transa ? k : m)) return -8;
+    if (m > 0 && n > 0 && k > 0 && !B) return -9;
+    if (ldb < std::max<int64_t>(1, transb ? n : k)) return -10;
+    if (m > 0 && n > 0 && !C) return -12;
+    if (ldc < std::max<int64_t>(1, m)) return -13;
+    if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -14;
+    launch_gemm(prec == SBR_FP32_MFMA, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, C, ldc,
+                (hipStream_t)stream);
+    SBR_CHECK_LAUNCH();
+    return 0;
+}
+
+int sbr_syr2k_lower(int64_t m, int64_t k, const double* U, int64_t ldu, const double* V, int64_t ldv, double* C,
+                    int64_t ldc, sbr_precision prec, sbr_stream_t stream) {
+    if (m < 0) return -1;
+    if (k < 0) return -2;
+    if (m > 0 && k > 0 && !U) return -3;
+    if (ldu < std::max<int64_t>(1, m)) return -4;
+    if (m > 0 && k > 0 && !V) return -5;
+    if (ldv < std::max<int64_t>(1, m)) return -6;
+    if (m > 0 && !C) return -7;
+    if (ldc < std::max<int64_t>(1, m)) return -8;
+    if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -9;
+    launch_syr2k_lower(prec == SBR_FP32_MFMA, m, k, U, ldu, V, ldv, C, ldc, (hipStream_t)stream);
+    SBR_CHECK_LAUNCH();
+    return 0;
+}
+
+int sbr_symm_lower(int64_t m, int64_t k, const double* A, int64_t lda, const double* Y, int64_t ldy, double* W,
+                   int64_t ldw, sbr_precision prec, sbr_stream_t stream) {
+    if (m < 0) return -1;
+    if (k < 0) return -2;
+    if (m > 0 && !A) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -4;
+    if (m > 0 && k > 0 && !Y) return -5;
+    if (ldy < std::max<int64_t>(1, m)) return -6;
+    if (m > 0 && k > 0 && !W) return -7;
+    if (ldw < std::max<int64_t>(1, m)) return -8;
+    if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -9;
+    launch_symm_lower(prec == SBR_FP32_MFMA, m, k, A, lda, Y, ldy, W, ldw, nullptr, 1, (hipStream_t)stream);
+    SBR_CHECK_LAUNCH();
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// sbr_bisect.hip -- eigenvalues of the final tridiagonal by Sturm-sequence
+// bisection (the last step of Algorithm 4.3, "compute the eigenvalues of the
+// thin band", done here on the tridiagonal reached by the halvings).
+//
+// Sturm count of T - x I: q_0 = d_0 - x, q_i = (d_i - x) - e_{i-1}^2 / q_{i-1};
+// a pivot with |q| < pivmin is replaced by -pivmin (Kahan's guard, keeps the
+// count monotone); the count is the number of negative pivots.  The interval
+// is the Gershgorin interval widened by 2.1 (n eps |T| + 2 pivmin), and every
+// index runs the same fixed number of halvings
+// I = ceil(log2((hi - lo) / (eps max(|lo|, |hi|)))) + 2, stopping early when
+// the midpoint equals an end point.
+//
+// One thread per eigenvalue index; d and e^2 are streamed through LDS in
+// chunks that every thread of the block reads at the same address (broadcast).
+#include <float.h>
+
+#include "sbr_device.h"
+#include "sbr_internal.h"
+
+namespace {
+
+constexpr int PREP_NT = 256;
+
+__global__ __launch_bounds__(PREP_NT) void bisect_prep_kernel(int64_t n, const double* __restrict__ d,
+                                                               const double* __restrict__ e,
+                                                               double* __restrict__ e2p,
+                                                               sbr::BisectSetup* setup) {
+    __shared__ double s_lo[PREP_NT], s_hi[PREP_NT], s_e2[PREP_NT];
+    const int t = threadIdx.x;
+    double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 1.0;
+    for (int64_t i = t; i < n; i += PREP_NT) {
+        const double em = (i > 0) ? e[i - 1] : 0.0;
+        const double ep = (i + 1 < n) ? e[i] : 0.0;
+        const double r = fabs(em) + fabs(ep);
+        lo = fmin(lo, d[i] - r);
+        hi = fmax(hi, d[i] + r);
+        e2p[i] = em * em;
+        emax2 = fmax(emax2, em * em);
+    }
+    s_lo[t] = lo;
+    s_hi[t] = hi;
+    s_e2[t] = emax2;
+    __syncthreads();
+    for (int o = PREP_NT / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            s_lo[t] = fmin(s_lo[t], s_lo[t + o]);
+            s_hi[t] = fmax(s_hi[t], s_hi[t + o]);
+            s_e2[t] = fmax(s_e2[t], s_e2[t + o]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double pivmin = DBL_MIN * s_e2[0];
+        double l = s_lo[0], h = s_hi[0];
+        const double eps = DBL_EPSILON * 0.5;
+        double tnorm = fmax(fabs(l), fabs(h));
+        const double widen = 2.1 * ((double)n * eps * tnorm + 2.0 * pivmin);
+        l -= widen;
+        h += widen;
+        tnorm = fmax(fabs(l), fabs(h));
+        int iters = 0;
+        if (h > l && tnorm > 0.0) {
+            iters = (int)ceil(log2((h - l) / (eps * tnorm))) + 2;
+            if (iters < 0) iters = 0;
+        }
+        setup->lo = l;
+        setup->hi = h;
+        setup->pivmin = pivmin;
+        setup->iters = iters;
+    }
+}
+
+template <int NT, int CH>
+__global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __restrict__ d,
+                                                    const double* __restrict__ e2p,
+                                                    const sbr::BisectSetup* __restrict__ setup,
+                                                    double* __restrict__ w) {
+    __shared__ double sd[CH], se[CH];
+    const int t = threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * NT + t;   // 0-based index: the (k+1)-th smallest
+    const double lo = setup->lo, hi = setup->hi, piv = setup->pivmin;
+    const int iters = setup->iters;
+    double a = lo, c = hi;
+    bool live = (k < n);
+    for (int it = 0; it < iters; ++it) {
+        const double x = a + 0.5 * (c - a);
+        const bool act = live && (x != a) && (x != c);
+        if (!__syncthreads_or(act)) break;
+        int64_t cnt = 0;
+        double q = 1.0;
+        for (int64_t s0 = 0; s0 < n; s0 += CH) {
+            const int len = (int)((n - s0 < CH) ? (n - s0) : CH);
+            __syncthreads();
+            for (int i = t; i < len; i += NT) {
+                sd[i] = d[s0 + i];
+                se[i] = e2p[s0 + i];
+            }
+            __syncthreads();
+            for (int i = 0; i < len; ++i) {
+                q = (sd[i] - x) - se[i] / q;
+                if (fabs(q) < piv) q = -piv;
+                cnt += (q < 0.0);
+            }
+        }
+        if (act) {
+            if (cnt >= k + 1) c = x;
+            else a = x;
+        } else {
+            live = false;
+        }
+    }
+    if (k < n) w[k] = a + 0.5 * (c - a);
+}
+
+}  // namespace
+
+namespace sbr {
+
+void launch_tridiag_eigvals(int64_t n, const double* d, const double* e, double* e2p, BisectSetup* setup,
+                            double* w, hipStream_t s) {
+    if (n <= 0) return;
+    bisect_prep_kernel<<<1, PREP_NT, 0, s>>>(n, d, e, e2p, setup);
+    constexpr int NT = 128, CH = 2048;
+    const unsigned blocks = (unsigned)((n + NT - 1) / NT);
+    bisect_kernel<NT, CH><<<blocks, NT, 0, s>>>(n, d, e2p, setup, w);
+}
+
+}  // namespace sbr

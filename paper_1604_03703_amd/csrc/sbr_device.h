@@ -1,0 +1,107 @@
+// sbr_device.h -- device-side building blocks shared by the SBR kernels
+// (gfx950 / CDNA4, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double sbr_d4 __attribute__((ext_vector_type(4)));
+typedef float sbr_f4 __attribute__((ext_vector_type(4)));
+
+// Compute-type traits: FP64 tiles use v_mfma_f64_16x16x4_f64, the FP32 form
+// uses v_mfma_f32_16x16x4_f32 (operands rounded to FP32 when staged, FP32
+// accumulation, the result added into FP64 storage by the caller).
+//
+// Operand / result lane layout of the 16x16x4 single-block instructions
+// (measured on gfx950):
+//   A operand (16 x 4): lane l holds A[l % 16][l / 16]
+//   B operand (4 x 16): lane l holds B[l / 16][l % 16]
+//   D (16 x 16):        lane l, element r holds D[out_row(l, r)][l % 16] with
+//                       out_row = 4 r + l / 16 for f64, 4 (l / 16) + r for f32.
+template <typename CT> struct Mfma;
+template <> struct Mfma<double> {
+    typedef sbr_d4 acc_t;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+    typedef sbr_f4 acc_t;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int SBR_BK = 16;   // K extent of one LDS-staged chunk
+
+// Which of (row, k) is the fastest-varying index when a thread block copies an
+// (ROWS x SBR_BK) operand tile from global memory: pick the one that is
+// contiguous in memory so the loads coalesce.
+template <int ROWS, int NT, bool KFAST>
+struct TileMap {
+    static constexpr int E = ROWS * SBR_BK / NT;   // elements per thread
+    static_assert(E >= 1 && E * NT == ROWS * SBR_BK, "tile / thread mismatch");
+    static __device__ __forceinline__ void coords(int t, int e, int& row, int& k) {
+        const int idx = t + e * NT;
+        if (KFAST) { k = idx % SBR_BK; row = idx / SBR_BK; }
+        else       { row = idx % ROWS; k = idx / ROWS; }
+    }
+};
+
+// Block-level MFMA tile engine: C tile (BM x BN) += op(A) tile (BM x K) *
+// op(B) tile (K x BN), K streamed through LDS in SBR_BK chunks.
+//   LDS operand layouts: As[k * LDA + i] = op(A)(i, k), Bs[k * LDB + j] = op(B)(k, j).
+// The MFMA "A" operand is taken from op(B) and the "B" operand from op(A), so
+// the instruction computes C^T tiles: a lane's accumulator elements then lie
+// along one column of C with consecutive lanes on consecutive rows, which
+// makes column-major stores of C coalesce.
+// Waves are arranged WM x WN; wave (wm, wn) owns C rows [wm*WTM, +WTM) and
+// columns [wn*WTN, +WTN).  Accumulator acc[tn][tm][r] holds
+//   C(wm*WTM + tm*16 + (lane & 15), wn*WTN + tn*16 + Mfma<CT>::out_row(lane, r)).
+template <typename CT, int BM, int BN, int WM, int WN>
+struct TileEngine {
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int WTM = BM / WM, WTN = BN / WN;
+    static constexpr int TM = WTM / 16, TN = WTN / 16;
+    static constexpr int LDA = BM + 2, LDB = BN + 2;
+    static_assert(TM >= 1 && TN >= 1 && TM * 16 * WM == BM && TN * 16 * WN == BN, "bad tile shape");
+    typedef typename Mfma<CT>::acc_t acc_t;
+    acc_t acc[TN][TM];
+
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int a = 0; a < TN; ++a)
+#pragma unroll
+            for (int b = 0; b < TM; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+    }
+
+    __device__ __forceinline__ void chunk(const CT* As, const CT* Bs, int wm, int wn, int lane) {
+        const int kr = lane >> 4, c = lane & 15;
+#pragma unroll
+        for (int kk = 0; kk < SBR_BK; kk += 4) {
+            CT p[TN], q[TM];
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) p[tn] = Bs[(kk + kr) * LDB + wn * WTN + tn * 16 + c];
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) q[tm] = As[(kk + kr) * LDA + wm * WTM + tm * 16 + c];
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+                for (int tm = 0; tm < TM; ++tm) acc[tn][tm] = Mfma<CT>::mma(p[tn], q[tm], acc[tn][tm]);
+        }
+    }
+
+    static __device__ __forceinline__ int row_of(int wm, int tm, int lane) { return wm * WTM + tm * 16 + (lane & 15); }
+    static __device__ __forceinline__ int col_of(int wn, int tn, int lane, int r) {
+        return wn * WTN + tn * 16 + Mfma<CT>::out_row(lane, r);
+    }
+};
+
+// Agent-scope flag helpers for the pipelined chase schedule.
+__device__ __forceinline__ int sbr_load_acquire(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void sbr_store_release(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}

@@ -1,0 +1,409 @@
+// sbr_gemm.hip -- MFMA tile kernels for the dense contractions of the
+// full-to-band stage (Algorithm 4.1 with the update of Eq. (4.1)):
+//   * symm_lower : W = A22 * Y, A22 symmetric with only its lower triangle
+//                  stored (the X U T product of Eq. (4.1));
+//   * syr2k_lower: A22 += U V^T + V U^T on lower-triangle tiles only
+//                  (the rank-2b trailing update of Eq. (4.1));
+//   * gemm       : C = alpha op(A) op(B) + beta C for the skinny products
+//                  (U T, Q2 W1^{-1}, T^T (U^T W), 1/2 U M - W) and a split-K
+//                  form for the tall reductions U^T W.
+// CT = double uses v_mfma_f64_16x16x4_f64; CT = float is the precision form
+// (operands rounded to FP32 in LDS, FP32 accumulation, FP64 result).
+#include "sbr_device.h"
+#include "sbr_internal.h"
+
+namespace {
+
+template <typename CT, bool TA, bool TB, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(
+    int64_t M, int64_t N, int64_t K, int64_t kchunk, double alpha,
+    const double* __restrict__ A, int64_t lda, const double* __restrict__ B, int64_t ldb,
+    double beta, const double* Cin, int64_t ldci, double* Cout, int64_t ldco, int64_t slice_stride) {
+    typedef TileEngine<CT, BM, BN, WM, WN> E;
+    typedef TileMap<BM, E::NT, TA> MA;      // op(A)(i,k): k contiguous iff TA
+    typedef TileMap<BN, E::NT, !TB> MB;     // op(B)(k,j): k contiguous iff !TB
+    __shared__ CT As[SBR_BK * E::LDA];
+    __shared__ CT Bs[SBR_BK * E::LDB];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int64_t i0 = (int64_t)blockIdx.x * BM, j0 = (int64_t)blockIdx.y * BN;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+    E eng;
+    eng.zero();
+    CT ra[MA::E], rb[MB::E];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < MA::E; ++e) {
+            int i, k;
+            MA::coords(t, e, i, k);
+            const int64_t gi = i0 + i, gk = k0 + k;
+            double v = 0.0;
+            if (gi < M && gk < kend) v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
+            ra[e] = (CT)v;
+        }
+#pragma unroll
+        for (int e = 0; e < MB::E; ++e) {
+            int j, k;
+            MB::coords(t, e, j, k);
+            const int64_t gj = j0 + j, gk = k0 + k;
+            double v = 0.0;
+            if (gj < N && gk < kend) v = TB ? B[gj + gk * ldb] : B[gk + gj * ldb];
+            rb[e] = (CT)v;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int e = 0; e < MA::E; ++e) {
+            int i, k;
+            MA::coords(t, e, i, k);
+            As[k * E::LDA + i] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < MB::E; ++e) {
+            int j, k;
+            MB::coords(t, e, j, k);
+            Bs[k * E::LDB + j] = rb[e];
+        }
+    };
+    if (kbeg < kend) {
+        load(kbeg);
+        store();
+        __syncthreads();
+        for (int64_t k0 = kbeg; k0 < kend; k0 += SBR_BK) {
+            const bool more = k0 + SBR_BK < kend;
+            if (more) load(k0 + SBR_BK);
+            eng.chunk(As, Bs, wm, wn, lane);
+            __syncthreads();
+            if (more) {
+                store();
+                __syncthreads();
+            }
+        }
+    }
+    double* Co = Cout + (int64_t)blockIdx.z * slice_stride;
+#pragma unroll
+    for (int tn = 0; tn < E::TN; ++tn)
+#pragma unroll
+        for (int tm = 0; tm < E::TM; ++tm)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + E::row_of(wm, tm, lane);
+                const int64_t j = j0 + E::col_of(wn, tn, lane, r);
+                if (i < M && j < N) {
+                    double v = alpha * (double)eng.acc[tn][tm][r];
+                    if (beta != 0.0) v += beta * Cin[i + j * ldci];
+                    Co[i + j * ldco] = v;
+                }
+            }
+}
+
+// out = alpha * sum_s part[s] + beta * Cin (part[s] is M x N with ld M).
+__global__ void reduce_slices_kernel(int64_t M, int64_t N, int splits, const double* __restrict__ part,
+                                     double alpha, double beta, const double* Cin, int64_t ldci,
+                                     double* Cout, int64_t ldco) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * N) return;
+    const int64_t i = idx % M, j = idx / M;
+    double s = 0.0;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + idx];
+    double v = alpha * s;
+    if (beta != 0.0) v += beta * Cin[i + j * ldci];
+    Cout[i + j * ldco] = v;
+}
+
+// Lower triangle of C (m x m) += U V^T + V U^T; one block per lower tile pair
+// (I >= J).  The two products are one GEMM with K' = 2K:
+// [U_I, V_I] * [V_J, U_J]^T.
+template <typename CT, int BM, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
+    int64_t m, int64_t K, const double* __restrict__ U, int64_t ldu,
+    const double* __restrict__ V, int64_t ldv, double* C, int64_t ldc) {
+    typedef TileEngine<CT, BM, BM, WM, WN> E;
+    typedef TileMap<BM, E::NT, false> MA;   // row fastest (column-major U, V)
+    typedef TileMap<BM, E::NT, false> MB;
+    __shared__ CT As[SBR_BK * E::LDA];
+    __shared__ CT Bs[SBR_BK * E::LDB];
+    const int64_t x = blockIdx.x;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > x) --I;
+    while ((I + 1) * (I + 2) / 2 <= x) ++I;
+    const int64_t J = x - I * (I + 1) / 2;
+    const int64_t i0 = I * BM, j0 = J * BM;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int64_t K2 = 2 * K;
+    E eng;
+    eng.zero();
+    CT ra[MA::E], rb[MB::E];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < MA::E; ++e) {
+            int i, k;
+            MA::coords(t, e, i, k);
+            const int64_t gi = i0 + i, gk = k0 + k;
+            double v = 0.0;
+            if (gi < m && gk < K2) v = (gk < K) ? U[gi + gk * ldu] : V[gi + (gk - K) * ldv];
+            ra[e] = (CT)v;
+        }
+#pragma unroll
+        for (int e = 0; e < MB::E; ++e) {
+            int j, k;
+            MB::coords(t, e, j, k);
+            const int64_t gj = j0 + j, gk = k0 + k;
+            double v = 0.0;
+            if (gj < m && gk < K2) v = (gk < K) ? V[gj + gk * ldv] : U[gj + (gk - K) * ldu];
+            rb[e] = (CT)v;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int e = 0; e < MA::E; ++e) {
+            int i, k;
+            MA::coords(t, e, i, k);
+            As[k * E::LDA + i] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < MB::E; ++e) {
+            int j, k;
+            MB::coords(t, e, j, k);
+            Bs[k * E::LDB + j] = rb[e];
+        }
+    };
+    load(0);
+    store();
+    __syncthreads();
+    for (int64_t k0 = 0; k0 < K2; k0 += SBR_BK) {
+        const bool more = k0 + SBR_BK < K2;
+        if (more) load(k0 + SBR_BK);
+        eng.chunk(As, Bs, wm, wn, lane);
+        __syncthreads();
+        if (more) {
+            store();
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int tn = 0; tn < E::TN; ++tn)
+#pragma unroll
+        for (int tm = 0; tm < E::TM; ++tm)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + E::row_of(wm, tm, lane);
+                const int64_t j = j0 + E::col_of(wn, tn, lane, r);
+                if (i < m && j <= i) C[i + j * ldc] += (double)eng.acc[tn][tm][r];
+            }
+}
+
+// W (m x nb) = A Y with A symmetric, lower triangle stored.  A K-chunk of
+// the A tile lies entirely below the diagonal (read A[i + k lda], rows
+// contiguous), entirely above it (read the mirror A[k + i lda], k
+// contiguous) or straddles it (element-wise choice).
+template <typename CT, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void symm_lower_kernel(
+    int64_t m, int64_t nb, int64_t kchunk, const double* __restrict__ A, int64_t lda,
+    const double* __restrict__ Y, int64_t ldy, double* W, int64_t ldw, int64_t slice_stride) {
+    typedef TileEngine<CT, BM, BN, WM, WN> E;
+    typedef TileMap<BM, E::NT, false> MAi;   // row fastest
+    typedef TileMap<BM, E::NT, true> MAk;    // k fastest
+    typedef TileMap<BN, E::NT, true> MB;     // Y[k + j ldy]: k contiguous
+    static_assert(MAi::E == MAk::E, "maps");
+    __shared__ CT As[SBR_BK * E::LDA];
+    __shared__ CT Bs[SBR_BK * E::LDB];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int64_t i0 = (int64_t)blockIdx.x * BM, j0 = (int64_t)blockIdx.y * BN;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = (kbeg + kchunk < m) ? kbeg + kchunk : m;
+    E eng;
+    eng.zero();
+    CT ra[MAi::E], rb[MB::E];
+    bool kfast = false;
+    auto load = [&](int64_t k0) {
+        kfast = (k0 >= i0 + BM - 1);           // whole chunk at or above the diagonal
+#pragma unroll
+        for (int e = 0; e < MAi::E; ++e) {
+            int i, k;
+            if (kfast) MAk::coords(t, e, i, k); else MAi::coords(t, e, i, k);
+            const int64_t gi = i0 + i, gk = k0 + k;
+            double v = 0.0;
+            if (gi < m && gk < kend) v = (gi >= gk) ? A[gi + gk * lda] : A[gk + gi * lda];
+            ra[e] = (CT)v;
+        }
+#pragma unroll
+        for (int e = 0; e < MB::E; ++e) {
+            int j, k;
+            MB::coords(t, e, j, k);
+            const int64_t gj = j0 + j, gk = k0 + k;
+            double v = 0.0;
+            if (gj < nb && gk < kend) v = Y[gk + gj * ldy];
+            rb[e] = (CT)v;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int e = 0; e < MAi::E; ++e) {
+            int i, k;
+            if (kfast) MAk::coords(t, e, i, k); else MAi::coords(t, e, i, k);
+            As[k * E::LDA + i] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < MB::E; ++e) {
+            int j, k;
+            MB::coords(t, e, j, k);
+            Bs[k * E::LDB + j] = rb[e];
+        }
+    };
+    if (kbeg < kend) {
+        load(kbeg);
+        store();
+        __syncthreads();
+        for (int64_t k0 = kbeg; k0 < kend; k0 += SBR_BK) {
+            const bool more = k0 + SBR_BK < kend;
+            if (more) load(k0 + SBR_BK);     // sets the map the registers are stored with
+            eng.chunk(As, Bs, wm, wn, lane);
+            __syncthreads();
+            if (more) {
+                store();
+                __syncthreads();
+            }
+        }
+    }
+    double* Wo = W + (int64_t)blockIdx.z * slice_stride;
+#pragma unroll
+    for (int tn = 0; tn < E::TN; ++tn)
+#pragma unroll
+        for (int tm = 0; tm < E::TM; ++tm)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + E::row_of(wm, tm, lane);
+                const int64_t j = j0 + E::col_of(wn, tn, lane, r);
+                if (i < m && j < nb) Wo[i + j * ldw] = (double)eng.acc[tn][tm][r];
+            }
+}
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+template <typename CT, bool TA, bool TB>
+void gemm_dispatch(int64_t M, int64_t N, int64_t K, int64_t kchunk, int splits, double alpha,
+                   const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                   const double* Cin, int64_t ldci, double* Cout, int64_t ldco, int64_t slice_stride,
+                   hipStream_t s) {
+    if (N > 32) {
+        dim3 g(cdiv(M, 64), cdiv(N, 64), splits);
+        gemm_kernel<CT, TA, TB, 64, 64, 2, 2><<<g, 256, 0, s>>>(M, N, K, kchunk, alpha, A, lda, B, ldb, beta,
+                                                                 Cin, ldci, Cout, ldco, slice_stride);
+    } else if (N > 16) {
+        dim3 g(cdiv(M, 64), cdiv(N, 32), splits);
+        gemm_kernel<CT, TA, TB, 64, 32, 4, 1><<<g, 256, 0, s>>>(M, N, K, kchunk, alpha, A, lda, B, ldb, beta,
+                                                                 Cin, ldci, Cout, ldco, slice_stride);
+    } else {
+        dim3 g(cdiv(M, 64), cdiv(N, 16), splits);
+        gemm_kernel<CT, TA, TB, 64, 16, 4, 1><<<g, 256, 0, s>>>(M, N, K, kchunk, alpha, A, lda, B, ldb, beta,
+                                                                 Cin, ldci, Cout, ldco, slice_stride);
+    }
+}
+
+template <typename CT>
+void gemm_dispatch_t(bool ta, bool tb, int64_t M, int64_t N, int64_t K, int64_t kchunk, int splits,
+                     double alpha, const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                     const double* Cin, int64_t ldci, double* Cout, int64_t ldco, int64_t slice_stride,
+                     hipStream_t s) {
+    if (!ta && !tb) gemm_dispatch<CT, false, false>(M, N, K, kchunk, splits, alpha, A, lda, B, ldb, beta, Cin, ldci, Cout, ldco, slice_stride, s);
+    else if (ta && !tb) gemm_dispatch<CT, true, false>(M, N, K, kchunk, splits, alpha, A, lda, B, ldb, beta, Cin, ldci, Cout, ldco, slice_stride, s);
+    else if (!ta && tb) gemm_dispatch<CT, false, true>(M, N, K, kchunk, splits, alpha, A, lda, B, ldb, beta, Cin, ldci, Cout, ldco, slice_stride, s);
+    else gemm_dispatch<CT, true, true>(M, N, K, kchunk, splits, alpha, A, lda, B, ldb, beta, Cin, ldci, Cout, ldco, slice_stride, s);
+}
+
+template <typename CT>
+void symm_dispatch(int64_t m, int64_t nb, int64_t kchunk, int splits, const double* A, int64_t lda,
+                   const double* Y, int64_t ldy, double* W, int64_t ldw, int64_t slice_stride, hipStream_t s) {
+    if (nb > 64) {
+        dim3 g(cdiv(m, 64), cdiv(nb, 128), splits);
+        symm_lower_kernel<CT, 64, 128, 2, 2><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+    } else if (nb > 32) {
+        dim3 g(cdiv(m, 64), cdiv(nb, 64), splits);
+        symm_lower_kernel<CT, 64, 64, 2, 2><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+    } else if (nb > 16) {
+        dim3 g(cdiv(m, 64), cdiv(nb, 32), splits);
+        symm_lower_kernel<CT, 64, 32, 4, 1><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+    } else {
+        dim3 g(cdiv(m, 64), cdiv(nb, 16), splits);
+        symm_lower_kernel<CT, 64, 16, 4, 1><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+    }
+}
+
+void reduce_slices(int64_t M, int64_t N, int splits, const double* part, double alpha, double beta,
+                   const double* Cin, int64_t ldci, double* Cout, int64_t ldco, hipStream_t s) {
+    const int64_t tot = M * N;
+    reduce_slices_kernel<<<cdiv(tot, 256), 256, 0, s>>>(M, N, splits, part, alpha, beta, Cin, ldci, Cout, ldco);
+}
+
+}  // namespace
+
+namespace sbr {
+
+void launch_gemm(bool f32, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                 const double* Cin, int64_t ldci, double* Cout, int64_t ldco, hipStream_t s) {
+    if (M <= 0 || N <= 0) return;
+    const int64_t kc = K > 0 ? K : 1;
+    if (f32) gemm_dispatch_t<float>(ta, tb, M, N, K, kc, 1, alpha, A, lda, B, ldb, beta, Cin, ldci, Cout, ldco, 0, s);
+    else gemm_dispatch_t<double>(ta, tb, M, N, K, kc, 1, alpha, A, lda, B, ldb, beta, Cin, ldci, Cout, ldco, 0, s);
+}
+
+int gemm_splits(int64_t M, int64_t N, int64_t K) {
+    const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    int64_t splits = 1;
+    while (tiles * splits < 512 && K / (splits * 2) >= 256) splits *= 2;
+    return (int)splits;
+}
+
+void launch_gemm_splitk(bool f32, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                        const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                        const double* Cin, int64_t ldci, double* Cout, int64_t ldco, double* part,
+                        int splits, hipStream_t s) {
+    if (M <= 0 || N <= 0) return;
+    if (splits <= 1) {
+        launch_gemm(f32, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, Cin, ldci, Cout, ldco, s);
+        return;
+    }
+    int64_t kchunk = (K + splits - 1) / splits;
+    kchunk = (kchunk + SBR_BK - 1) / SBR_BK * SBR_BK;
+    if (f32) gemm_dispatch_t<float>(ta, tb, M, N, K, kchunk, splits, 1.0, A, lda, B, ldb, 0.0, nullptr, 0, part, M, M * N, s);
+    else gemm_dispatch_t<double>(ta, tb, M, N, K, kchunk, splits, 1.0, A, lda, B, ldb, 0.0, nullptr, 0, part, M, M * N, s);
+    reduce_slices(M, N, splits, part, alpha, beta, Cin, ldci, Cout, ldco, s);
+}
+
+void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t ldu, const double* V,
+                        int64_t ldv, double* C, int64_t ldc, hipStream_t s) {
+    if (m <= 0 || K <= 0) return;
+    const int64_t T = (m + 63) / 64;
+    const int64_t blocks = T * (T + 1) / 2;
+    if (f32) syr2k_lower_kernel<float, 64, 2, 2><<<(unsigned)blocks, 256, 0, s>>>(m, K, U, ldu, V, ldv, C, ldc);
+    else syr2k_lower_kernel<double, 64, 2, 2><<<(unsigned)blocks, 256, 0, s>>>(m, K, U, ldu, V, ldv, C, ldc);
+}
+
+int symm_splits(int64_t m, int64_t nb) {
+    const int64_t tiles = ((m + 63) / 64) * ((nb + 127) / 128);
+    int64_t splits = 1;
+    while (tiles * splits < 1024 && m / (splits * 2) >= 1024) splits *= 2;
+    return (int)splits;
+}
+
+void launch_symm_lower(bool f32, int64_t m, int64_t nb, const double* A, int64_t lda, const double* Y,
+                       int64_t ldy, double* W, int64_t ldw, double* part, int splits, hipStream_t s) {
+    if (m <= 0 || nb <= 0) return;
+    if (splits <= 1 || part == nullptr) {
+        if (f32) symm_dispatch<float>(m, nb, m, 1, A, lda, Y, ldy, W, ldw, 0, s);
+        else symm_dispatch<double>(m, nb, m, 1, A, lda, Y, ldy, W, ldw, 0, s);
+        return;
+    }
+    int64_t kchunk = (m + splits - 1) / splits;
+    kchunk = (kchunk + SBR_BK - 1) / SBR_BK * SBR_BK;
+    if (f32) symm_dispatch<float>(m, nb, kchunk, splits, A, lda, Y, ldy, part, m, m * nb, s);
+    else symm_dispatch<double>(m, nb, kchunk, splits, A, lda, Y, ldy, part, m, m * nb, s);
+    reduce_slices(m, nb, splits, part, 1.0, 0.0, nullptr, 0, W, ldw, s);
+}
+
+}  // namespace sbr

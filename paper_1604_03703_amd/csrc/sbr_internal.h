@@ -1,0 +1,85 @@
+// sbr_internal.h -- host-side launchers shared between the translation units
+// of the SBR library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sbr {
+
+// ---- sbr_gemm.hip ---------------------------------------------------------
+void launch_gemm(bool f32, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                 const double* Cin, int64_t ldci, double* Cout, int64_t ldco, hipStream_t s);
+int gemm_splits(int64_t M, int64_t N, int64_t K);
+void launch_gemm_splitk(bool f32, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                        const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                        const double* Cin, int64_t ldci, double* Cout, int64_t ldco, double* part,
+                        int splits, hipStream_t s);
+void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t ldu, const double* V,
+                        int64_t ldv, double* C, int64_t ldc, hipStream_t s);
+int symm_splits(int64_t m, int64_t nb);
+void launch_symm_lower(bool f32, int64_t m, int64_t nb, const double* A, int64_t lda, const double* Y,
+                       int64_t ldy, double* W, int64_t ldw, double* part, int splits, hipStream_t s);
+
+// ---- sbr_tsqr.hip ---------------------------------------------------------
+// TSQR tree over an m x b panel (m >= b): leaves of b rows (the last one takes
+// the remainder, < 2b rows), binary tree of stacked b x b R factors.
+struct TsqrTree {
+    int b = 0;
+    int64_t m = 0;
+    int levels = 0;               // number of levels; level 0 = leaves
+    int count[40];                // nodes per level
+    double* slots[40];            // R slots per level, b x b each (ld b)
+    double* tau[40];              // b Householder scalars per node
+};
+// Host-side sizing: doubles needed for the slots and taus of a panel of m rows.
+int64_t tsqr_workspace_doubles(int64_t m, int b);
+void tsqr_plan(TsqrTree& tr, int64_t m, int b, double* ws);
+// Factor the panel P (m x b, ld ldp; overwritten by the leaf reflectors) and
+// write the explicit thin Q (m x b, ld ldq).  The R factor is left in
+// tsqr_root_r(tr).
+bool tsqr_supported(int b);
+void launch_tsqr(const TsqrTree& tr, double* P, int64_t ldp, double* Q, int64_t ldq, hipStream_t s);
+const double* tsqr_root_r(const TsqrTree& tr);
+// Householder reconstruction (single work-group): from Q1 = Q[0:b, 0:b]
+// writes U1 (unit lower, into U rows 0..b-1, ld ldu), T (b x b), W1^{-1}
+// (b x b) and S (b signs).
+void launch_reconstruct(int b, const double* Q, int64_t ldq, double* U, int64_t ldu, double* T,
+                        double* W1inv, double* S, hipStream_t s);
+// Band block of the panel: P[0:b, :] = diag(S) R (upper), P[b:m, :] = 0.
+void launch_panel_writeback(int64_t m, int b, double* P, int64_t ldp, const double* R, const double* S,
+                            hipStream_t s);
+// Ragged last panel (m < b rows below the band): unblocked Householder on the
+// panel and two-sided application to the trailing m x m block.
+void launch_f2b_tail(int64_t m, int b, double* P, int64_t ldp, double* A22, int64_t lda, hipStream_t s);
+int init_tsqr_attributes();
+
+// ---- sbr_band.hip ---------------------------------------------------------
+void launch_dense_to_band(int64_t n, const double* A, int64_t lda, int b, double* band, int64_t ldband,
+                          hipStream_t s);
+void launch_band_copy(int64_t n, const double* src, int64_t ldsrc, int keep, double* dst, int64_t lddst,
+                      hipStream_t s);
+// Workspace (doubles) of one halving stage for bandwidth b and n.
+int64_t chase_workspace_doubles(int64_t n, int b, int* grid_out);
+// Ints of flag/counter storage for one halving stage.
+int64_t chase_flag_ints(int64_t n, int b);
+// `error` is a device int set to 1 if a pipeline wait gave up; max_grid > 0
+// caps the number of chase blocks (1 = the sequential sweep order).
+void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch,
+                       int* flags, int* error, int max_grid, hipStream_t s);
+void launch_fill_int(int* p, int64_t count, int v, hipStream_t s);
+void launch_band_to_tridiag(int64_t n, const double* band, int64_t ldband, double* d, double* e,
+                            hipStream_t s);
+int init_band_attributes();
+
+// ---- sbr_bisect.hip -------------------------------------------------------
+struct BisectSetup {
+    double lo, hi, pivmin;
+    int iters;
+    int pad;
+};
+// e may be null when n == 1.  e2p (n doubles) and setup are workspace.
+void launch_tridiag_eigvals(int64_t n, const double* d, const double* e, double* e2p, BisectSetup* setup,
+                            double* w, hipStream_t s);
+
+}  // namespace sbr

@@ -1,0 +1,540 @@
+// sbr_tsqr.hip -- panel QR of the full-to-band stage.
+//
+// * TSQR (Algorithm 3.2, rect-QR, on one GPU): the m x b panel is split into
+//   row blocks of b rows (the last block takes the remainder, < 2b rows); each
+//   block is factored by Householder QR (Lemma 3.4), then pairs of b x b R
+//   factors are stacked and factored level by level up a binary tree (after
+//   the first level every tree node is two stacked upper triangles).  The
+//   explicit thin Q is formed top-down: the root applies its reflectors to
+//   [I; 0], each node applies its reflectors to [Z; 0] with Z handed down by
+//   its parent, and the leaves write their rows of Q (Q_i = W_i Z_i).
+// * Householder reconstruction (Corollary 3.7): [U1, W1] = LU(Q1 - S) without
+//   pivoting, S_ii = -sgn of the current pivot so |pivot| >= 1; U2 = Q2 W1^{-1}
+//   (a GEMM with the explicit inverse); T = -W1 S U1^{-T}.  Then
+//   (I - U T U^T)[:, :b] = Q S and (I - U T U^T)^T P = [S R; 0].
+// * Ragged tail: when fewer than b rows remain below the band, the last panel
+//   is reduced by unblocked Householder with the two-sided update applied one
+//   reflector at a time.
+//
+// Register layout of the QR / apply kernels: NT threads, TPC = NT / b threads
+// per column; thread t owns column t / TPC, rows (t % TPC) + TPC * r for
+// r < 2b / TPC.  Column reductions are shuffles inside the TPC-lane group.
+#include <math.h>
+
+#include "sbr_device.h"
+#include "sbr_internal.h"
+
+namespace {
+
+struct TsqrLevelArgs {
+    int b;
+    int is_leaf;
+    int is_root;
+    // leaves
+    double* P;
+    int64_t ldp;
+    int64_t m;
+    int nleaves;
+    // nodes
+    double* child_slots;   // level below (b x b slots, ld b)
+    int nchild;
+    double* own_slots;     // this level's slots (R out for QR; Z in for apply)
+    double* tau;           // this level's taus (b per node)
+    // apply output for leaves
+    double* Q;
+    int64_t ldq;
+};
+
+struct Seg {
+    double* p0;
+    int64_t ld0;
+    int rows0;
+    double* p1;
+    int64_t ld1;
+    int rows1;
+};
+
+__device__ __forceinline__ Seg node_segments(const TsqrLevelArgs& a, int q) {
+    Seg s;
+    const int b = a.b;
+    if (a.is_leaf) {
+        const int64_t r0 = (int64_t)q * b;
+        const int64_t rows = (q == a.nleaves - 1) ? (a.m - r0) : b;
+        s.p0 = a.P + r0;
+        s.ld0 = a.ldp;
+        s.rows0 = (int)rows;
+        s.p1 = nullptr;
+        s.ld1 = 0;
+        s.rows1 = 0;
+    } else {
+        s.p0 = a.child_slots + (int64_t)(2 * q) * b * b;
+        s.ld0 = b;
+        s.rows0 = b;
+        if (2 * q + 1 < a.nchild) {
+            s.p1 = a.child_slots + (int64_t)(2 * q + 1) * b * b;
+            s.ld1 = b;
+            s.rows1 = b;
+        } else {
+            s.p1 = nullptr;
+            s.ld1 = 0;
+            s.rows1 = 0;
+        }
+    }
+    return s;
+}
+
+template <int B, int NT>
+__global__ __launch_bounds__(NT) void tsqr_qr_kernel(TsqrLevelArgs a) {
+    constexpr int TPC = NT / B;
+    constexpr int RPT = 2 * B / TPC;
+    static_assert(TPC >= 2 && TPC <= 64 && (TPC & (TPC - 1)) == 0 && RPT >= 1, "layout");
+    __shared__ double vsh[2][2 * B];
+    __shared__ double tsh[B];
+    const int t = threadIdx.x, c = t / TPC, s = t % TPC;
+    const int q = blockIdx.x;
+    const Seg g = node_segments(a, q);
+    const int rows = g.rows0 + g.rows1;
+    double x[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int row = s + TPC * r;
+        double v = 0.0;
+        if (row < g.rows0) v = g.p0[row + (int64_t)c * g.ld0];
+        else if (row < rows) v = g.p1[(row - g.rows0) + (int64_t)c * g.ld1];
+        x[r] = v;
+    }
+    for (int k = 0; k < B; ++k) {
+        double* v = vsh[k & 1];
+        if (c == k) {
+            double ss = 0.0, xk = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int row = s + TPC * r;
+                if (row > k) ss += x[r] * x[r];
+                else if (row == k) xk = x[r];
+            }
+#pragma unroll
+            for (int o = 1; o < TPC; o <<= 1) {
+                ss += __shfl_xor(ss, o);
+                xk += __shfl_xor(xk, o);
+            }
+            double beta, tau, scal;
+            if (ss == 0.0) {
+                beta = xk;
+                tau = 0.0;
+                scal = 0.0;
+            } else {
+                const double nrm = sqrt(xk * xk + ss);
+                beta = (xk >= 0.0) ? -nrm : nrm;
+                tau = (beta - xk) / beta;
+                scal = 1.0 / (xk - beta);
+            }
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int row = s + TPC * r;
+                const double vv = (row < k) ? 0.0 : ((row == k) ? 1.0 : x[r] * scal);
+                v[row] = vv;
+                if (row == k) x[r] = beta;
+                else if (row > k) x[r] = vv;
+            }
+            if (s == 0) tsh[k] = tau;
+        }
+        __syncthreads();
+        if (c > k) {
+            const double tau = tsh[k];
+            if (tau != 0.0) {
+                double dot = 0.0;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) dot += v[s + TPC * r] * x[r];
+#pragma unroll
+                for (int o = 1; o < TPC; o <<= 1) dot += __shfl_xor(dot, o);
+                const double f = tau * dot;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) x[r] -= f * v[s + TPC * r];
+            }
+        }
+    }
+    // reflectors (below the diagonal) and R (on and above it) back in place
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int row = s + TPC * r;
+        if (row < g.rows0) g.p0[row + (int64_t)c * g.ld0] = x[r];
+        else if (row < rows) g.p1[(row - g.rows0) + (int64_t)c * g.ld1] = x[r];
+    }
+    double* R = a.own_slots + (int64_t)q * B * B;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int row = s + TPC * r;
+        if (row < B) R[row + c * B] = (row <= c) ? x[r] : 0.0;
+    }
+    __syncthreads();
+    if (t < B) a.tau[(int64_t)q * B + t] = tsh[t];
+}
+
+// X = H_0 ... H_{B-1} [Z; 0]: the node's explicit Q block times Z.
+template <int B, int NT>
+__global__ __launch_bounds__(NT) void tsqr_apply_kernel(TsqrLevelArgs a) {
+    constexpr int TPC = NT / B;
+    constexpr int RPT = 2 * B / TPC;
+    __shared__ double vsh[2][2 * B];
+    __shared__ double tsh[B];
+    const int t = threadIdx.x, c = t / TPC, s = t % TPC;
+    const int q = blockIdx.x;
+    const Seg g = node_segments(a, q);
+    const int rows = g.rows0 + g.rows1;
+    const double* Z = a.own_slots + (int64_t)q * B * B;
+    double x[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int row = s + TPC * r;
+        double v = 0.0;
+        if (row < B) v = a.is_root ? (row == c ? 1.0 : 0.0) : Z[row + c * B];
+        x[r] = v;
+    }
+    if (t < B) tsh[t] = a.tau[(int64_t)q * B + t];
+    // reflector k, element `row`: 0 above k, 1 at k, stored value below
+    auto fetchv = [&](int row, int k) -> double {
+        if (row > k && row < rows)
+            return (row < g.rows0) ? g.p0[row + (int64_t)k * g.ld0] : g.p1[(row - g.rows0) + (int64_t)k * g.ld1];
+        return (row == k) ? 1.0 : 0.0;
+    };
+    double vnext = (t < 2 * B) ? fetchv(t, B - 1) : 0.0;
+    for (int k = B - 1; k >= 0; --k) {
+        double* v = vsh[k & 1];
+        if (t < 2 * B) v[t] = vnext;
+        __syncthreads();
+        if (k > 0 && t < 2 * B) vnext = fetchv(t, k - 1);
+        const double tau = tsh[k];
+        if (tau != 0.0) {
+            double dot = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) dot += v[s + TPC * r] * x[r];
+#pragma unroll
+            for (int o = 1; o < TPC; o <<= 1) dot += __shfl_xor(dot, o);
+            const double f = tau * dot;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) x[r] -= f * v[s + TPC * r];
+        }
+    }
+    __syncthreads();   // every read of the reflectors is done before they are overwritten
+    if (a.is_leaf) {
+        double* Qo = a.Q + (int64_t)q * B;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int row = s + TPC * r;
+            if (row < g.rows0) Qo[row + (int64_t)c * a.ldq] = x[r];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int row = s + TPC * r;
+            if (row < g.rows0) g.p0[row + (int64_t)c * g.ld0] = x[r];
+            else if (row < rows) g.p1[(row - g.rows0) + (int64_t)c * g.ld1] = x[r];
+        }
+    }
+}
+
+// Householder reconstruction for a b x b top block, one work-group.
+// LDS: F (b x (b+1)) holds Q1 - S, then U1 \ W1, then U1^{-1} \ W1, then
+// U1^{-1} \ W1^{-1}.
+constexpr int REC_NT = 512;
+
+__global__ __launch_bounds__(REC_NT) void reconstruct_kernel(int b, const double* __restrict__ Q, int64_t ldq,
+                                                             double* U, int64_t ldu, double* T, double* W1inv,
+                                                             double* S) {
+    extern __shared__ double F[];
+    __shared__ double col[128];
+    __shared__ double sv[128];
+    const int t = threadIdx.x;
+    const int ld = b + 1;
+    for (int idx = t; idx < b * b; idx += REC_NT) {
+        const int i = idx % b, j = idx / b;
+        F[i + j * ld] = Q[i + (int64_t)j * ldq];
+    }
+    __syncthreads();
+    // LU of Q1 - S without pivoting
+    for (int i = 0; i < b; ++i) {
+        if (t == 0) {
+            const double aii = F[i + i * ld];
+            const double si = (aii >= 0.0) ? -1.0 : 1.0;
+            sv[i] = si;
+            F[i + i * ld] = aii - si;
+        }
+        __syncthreads();
+        const double piv = F[i + i * ld];
+        for (int r = i + 1 + t; r < b; r += REC_NT) F[r + i * ld] /= piv;
+        __syncthreads();
+        const int w = b - i - 1;
+        for (int idx = t; idx < w * w; idx += REC_NT) {
+            const int r = i + 1 + idx % w, cc = i + 1 + idx / w;
+            F[r + cc * ld] -= F[r + i * ld] * F[i + cc * ld];
+        }
+        __syncthreads();
+    }
+    // U1 (unit lower) out, S out
+    for (int idx = t; idx < b * b; idx += REC_NT) {
+        const int i = idx % b, j = idx / b;
+        U[i + (int64_t)j * ldu] = (i > j) ? F[i + j * ld] : (i == j ? 1.0 : 0.0);
+    }
+    if (t < b) S[t] = sv[t];
+    __syncthreads();
+    // U1^{-1} in place (strict lower part), columns right to left:
+    // X[j+1:, j] = -X[j+1:, j+1:] L[j+1:, j]
+    for (int j = b - 2; j >= 0; --j) {
+        for (int r = j + 1 + t; r < b; r += REC_NT) col[r] = F[r + j * ld];
+        __syncthreads();
+        for (int r = j + 1 + t; r < b; r += REC_NT) {
+            double acc = col[r];
+            for (int k = j + 1; k < r; ++k) acc += F[r + k * ld] * col[k];
+            F[r + j * ld] = -acc;
+        }
+        __syncthreads();
+    }
+    // T = -W1 S U1^{-T}: T[i][j] = -sum_{k=i..j} W1[i][k] s_k U1inv[j][k]
+    for (int idx = t; idx < b * b; idx += REC_NT) {
+        const int i = idx % b, j = idx / b;
+        double acc = 0.0;
+        if (i <= j) {
+            for (int k = i; k <= j; ++k) {
+                const double linv = (k == j) ? 1.0 : F[j + k * ld];
+                acc += F[i + k * ld] * sv[k] * linv;
+            }
+        }
+        T[i + j * b] = -acc;
+    }
+    __syncthreads();
+    // W1^{-1} in place (upper part), columns left to right:
+    // X[j, j] = 1 / W[j, j]; X[0:j, j] = -X[0:j, 0:j] W[0:j, j] / W[j, j]
+    for (int j = 0; j < b; ++j) {
+        for (int r = t; r <= j; r += REC_NT) col[r] = F[r + j * ld];
+        __syncthreads();
+        const double wjj = col[j];
+        for (int r = t; r <= j; r += REC_NT) {
+            if (r == j) {
+                F[j + j * ld] = 1.0 / wjj;
+            } else {
+                double acc = 0.0;
+                for (int k = r; k < j; ++k) acc += F[r + k * ld] * col[k];
+                F[r + j * ld] = -acc / wjj;
+            }
+        }
+        __syncthreads();
+    }
+    for (int idx = t; idx < b * b; idx += REC_NT) {
+        const int i = idx % b, j = idx / b;
+        W1inv[i + j * b] = (i <= j) ? F[i + j * ld] : 0.0;
+    }
+}
+
+__global__ void panel_writeback_kernel(int64_t m, int b, double* P, int64_t ldp, const double* __restrict__ R,
+                                       const double* __restrict__ S) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * b) return;
+    const int64_t i = idx % m;
+    const int j = (int)(idx / m);
+    double v = 0.0;
+    if (i < b && i <= j) v = S[i] * R[i + (int64_t)j * b];
+    P[i + j * ldp] = v;
+}
+
+// Ragged tail, one work-group: P (m x b, m < b) panel rows, A22 (m x m).
+constexpr int TAIL_NT = 256;
+
+__global__ __launch_bounds__(TAIL_NT) void f2b_tail_kernel(int m, int b, double* P, int64_t ldp, double* A,
+                                                           int64_t lda) {
+    __shared__ double v[128];
+    __shared__ double p[128];
+    __shared__ double red[TAIL_NT];
+    __shared__ double sc[4];
+    const int t = threadIdx.x;
+    for (int k = 0; k + 1 < m; ++k) {
+        // norm of P[k+1:m, k]
+        double ss = 0.0;
+        for (int r = k + 1 + t; r < m; r += TAIL_NT) ss += P[r + k * ldp] * P[r + k * ldp];
+        red[t] = ss;
+        __syncthreads();
+        for (int o = TAIL_NT / 2; o > 0; o >>= 1) {
+            if (t < o) red[t] += red[t + o];
+            __syncthreads();
+        }
+        if (t == 0) {
+            const double xk = P[k + k * ldp];
+            const double s2 = red[0];
+            double beta, tau, scal;
+            if (s2 == 0.0) {
+                beta = xk; tau = 0.0; scal = 0.0;
+            } else {
+                const double nrm = sqrt(xk * xk + s2);
+                beta = (xk >= 0.0) ? -nrm : nrm;
+                tau = (beta - xk) / beta;
+                scal = 1.0 / (xk - beta);
+            }
+            sc[0] = beta; sc[1] = tau; sc[2] = scal;
+        }
+        __syncthreads();
+        const double beta = sc[0], tau = sc[1], scal = sc[2];
+        for (int r = t; r < m; r += TAIL_NT) v[r] = (r < k) ? 0.0 : (r == k ? 1.0 : P[r + k * ldp] * scal);
+        __syncthreads();
+        if (tau == 0.0) continue;   // uniform
+        for (int r = k + t; r < m; r += TAIL_NT) P[r + k * ldp] = (r == k) ? beta : 0.0;
+        // remaining panel columns: P[k:, c] -= tau v (v^T P[k:, c])
+        for (int cc = k + 1 + t; cc < b; cc += TAIL_NT) {
+            double dot = 0.0;
+            for (int r = k; r < m; ++r) dot += v[r] * P[r + cc * ldp];
+            const double f = tau * dot;
+            for (int r = k; r < m; ++r) P[r + cc * ldp] -= f * v[r];
+        }
+        // two-sided on all of A22 (v is zero above row k): p = tau A v (lower
+        // storage), w = p - (tau/2)(p^T v) v, A -= v w^T + w v^T
+        for (int r = t; r < m; r += TAIL_NT) {
+            double acc = 0.0;
+            for (int kk = k; kk < m; ++kk) {
+                const double arr = (r >= kk) ? A[r + kk * lda] : A[kk + r * lda];
+                acc += arr * v[kk];
+            }
+            p[r] = tau * acc;
+        }
+        __syncthreads();
+        double pv = 0.0;
+        for (int r = t; r < m; r += TAIL_NT) pv += p[r] * v[r];
+        red[t] = pv;
+        __syncthreads();
+        for (int o = TAIL_NT / 2; o > 0; o >>= 1) {
+            if (t < o) red[t] += red[t + o];
+            __syncthreads();
+        }
+        const double cfac = 0.5 * tau * red[0];
+        __syncthreads();
+        for (int r = t; r < m; r += TAIL_NT) p[r] -= cfac * v[r];
+        __syncthreads();
+        for (int idx = t; idx < m * m; idx += TAIL_NT) {
+            const int r = idx % m, cc = idx / m;
+            if (r >= cc) A[r + cc * lda] -= v[r] * p[cc] + p[r] * v[cc];
+        }
+        __syncthreads();
+    }
+}
+
+// threads per column: at least 2 and at most 2b (one row per thread)
+template <int B>
+constexpr int tsqr_tpc() { return B == 128 ? 8 : (B == 64 ? 4 : (B == 32 ? 8 : (B == 16 ? 16 : (2 * B < 8 ? 2 * B : 8)))); }
+
+template <int B>
+void launch_level(bool qr, const TsqrLevelArgs& a, int blocks, hipStream_t s) {
+    constexpr int NT = B * tsqr_tpc<B>();
+    if (qr) tsqr_qr_kernel<B, NT><<<blocks, NT, 0, s>>>(a);
+    else tsqr_apply_kernel<B, NT><<<blocks, NT, 0, s>>>(a);
+}
+
+void launch_level_b(int b, bool qr, const TsqrLevelArgs& a, int blocks, hipStream_t s) {
+    switch (b) {
+        case 2: launch_level<2>(qr, a, blocks, s); break;
+        case 4: launch_level<4>(qr, a, blocks, s); break;
+        case 8: launch_level<8>(qr, a, blocks, s); break;
+        case 16: launch_level<16>(qr, a, blocks, s); break;
+        case 32: launch_level<32>(qr, a, blocks, s); break;
+        case 64: launch_level<64>(qr, a, blocks, s); break;
+        case 128: launch_level<128>(qr, a, blocks, s); break;
+        default: break;
+    }
+}
+
+}  // namespace
+
+namespace sbr {
+
+bool tsqr_supported(int b) {
+    return b == 2 || b == 4 || b == 8 || b == 16 || b == 32 || b == 64 || b == 128;
+}
+
+int64_t tsqr_workspace_doubles(int64_t m, int b) {
+    int64_t count = m / b;
+    if (count < 1) count = 1;
+    int64_t tot = 0;
+    while (true) {
+        tot += count * ((int64_t)b * b + b);
+        if (count == 1) break;
+        count = (count + 1) / 2;
+    }
+    return tot;
+}
+
+void tsqr_plan(TsqrTree& tr, int64_t m, int b, double* ws) {
+    tr.b = b;
+    tr.m = m;
+    int64_t count = m / b;
+    if (count < 1) count = 1;
+    int lv = 0;
+    double* p = ws;
+    while (true) {
+        tr.count[lv] = (int)count;
+        tr.slots[lv] = p;
+        p += count * (int64_t)b * b;
+        tr.tau[lv] = p;
+        p += count * (int64_t)b;
+        ++lv;
+        if (count == 1) break;
+        count = (count + 1) / 2;
+    }
+    tr.levels = lv;
+}
+
+const double* tsqr_root_r(const TsqrTree& tr) { return tr.slots[tr.levels - 1]; }
+
+void launch_tsqr(const TsqrTree& tr, double* P, int64_t ldp, double* Q, int64_t ldq, hipStream_t s) {
+    const int b = tr.b;
+    TsqrLevelArgs a{};
+    a.b = b;
+    a.P = P;
+    a.ldp = ldp;
+    a.m = tr.m;
+    a.nleaves = tr.count[0];
+    a.Q = Q;
+    a.ldq = ldq;
+    // up-sweep
+    for (int lv = 0; lv < tr.levels; ++lv) {
+        a.is_leaf = (lv == 0);
+        a.is_root = (lv == tr.levels - 1);
+        a.child_slots = lv ? tr.slots[lv - 1] : nullptr;
+        a.nchild = lv ? tr.count[lv - 1] : 0;
+        a.own_slots = tr.slots[lv];
+        a.tau = tr.tau[lv];
+        launch_level_b(b, true, a, tr.count[lv], s);
+    }
+    // down-sweep: explicit Q
+    for (int lv = tr.levels - 1; lv >= 0; --lv) {
+        a.is_leaf = (lv == 0);
+        a.is_root = (lv == tr.levels - 1);
+        a.child_slots = lv ? tr.slots[lv - 1] : nullptr;
+        a.nchild = lv ? tr.count[lv - 1] : 0;
+        a.own_slots = tr.slots[lv];
+        a.tau = tr.tau[lv];
+        launch_level_b(b, false, a, tr.count[lv], s);
+    }
+}
+
+int init_tsqr_attributes() {
+    const int bytes = 128 * 129 * (int)sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void*)reconstruct_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       bytes);
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+void launch_reconstruct(int b, const double* Q, int64_t ldq, double* U, int64_t ldu, double* T, double* W1inv,
+                        double* S, hipStream_t s) {
+    const size_t shm = (size_t)b * (b + 1) * sizeof(double);
+    reconstruct_kernel<<<1, REC_NT, shm, s>>>(b, Q, ldq, U, ldu, T, W1inv, S);
+}
+
+void launch_panel_writeback(int64_t m, int b, double* P, int64_t ldp, const double* R, const double* S,
+                            hipStream_t s) {
+    const int64_t tot = m * b;
+    panel_writeback_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(m, b, P, ldp, R, S);
+}
+
+void launch_f2b_tail(int64_t m, int b, double* P, int64_t ldp, double* A22, int64_t lda, hipStream_t s) {
+    if (m < 2) return;
+    f2b_tail_kernel<<<1, TAIL_NT, 0, s>>>((int)m, b, P, ldp, A22, lda);
+}
+
+}  // namespace sbr
