@@ -1,0 +1,240 @@
+"""Benchmark of the SBR symmetric eigensolver on one MI355X.
+
+One step = one whole solve of the hot path on one synthetic input already in
+HBM: full-to-band (b0), band halvings b0 -> 1, Sturm bisection of all n
+eigenvalues.  The input is restored from a pristine device copy before every
+step (the solve overwrites it); that copy is outside the timed region, every
+timed step is bracketed by device synchronisations.
+
+Default workload: n = 32768, (G + G^T)/2 Gaussian, b0 = 128, FP64 form, then
+the same input in the FP32-MFMA form.  The headline `value` is the
+full-to-band rate (4/3 n^3 flops over the full-to-band time) of the FP64 form.
+
+Prints ONE JSON line (rank 0).  `--gpus N` with N > 1 is refused: this
+benchmark measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("full-to-band TFLOP/s (4/3·n³) + s/solve at n=32768 FP64 vs FP32; batch solves/s")
+PEAK_FP64_MFMA = 78.6     # TFLOP/s, MI355X dense FP64 matrix
+PEAK_FP32_MFMA = 157.3    # TFLOP/s, MI355X dense FP32 matrix
+PEAK_HBM = 8000.0         # GB/s
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def band_stage_bytes(n: int, b: int) -> float:
+    """Algorithmic bytes of one halving b -> b/2 (FP64): every chase reads and
+    writes the entries it touches once (QR block, left block, lower half of
+    the diagonal block, below block), summed over all chases."""
+    import numpy as np
+    h = b // 2
+    total = 0
+    for i in range(1, (n - 2) // h + 1):
+        o = i * h + b * np.arange(0, (n - 2 - i * h) // b + 1, dtype=np.int64)
+        nr = np.minimum(n - o, b)
+        nbr = np.maximum(0, np.minimum(n, o + 2 * b) - (o + b))
+        ent = nr * h + nr * (nr + 1) // 2 + nbr * b
+        ent[1:] += nr[1:] * h            # left block for j > 1
+        total += int(ent.sum())
+    return 16.0 * total   # 8 B read + 8 B written per entry
+
+
+def f2b_update_flops(n: int, b: int):
+    """Per-panel algorithmic flops of the two dominant kernels:
+    SYMM W = A22 Y (2 m^2 b) and the lower-triangle SYR2K (2 b m (m+1))."""
+    symm, syr2k = [], []
+    k = 0
+    while True:
+        m = n - (k + 1) * b
+        if m < b:
+            break
+        symm.append(2.0 * m * m * b)
+        syr2k.append(2.0 * b * m * (m + 1))
+        k += 1
+    return symm, syr2k
+
+
+def run_form(sbr, torch, A0, n, b0, precision, steps, warmup, plan):
+    A = torch.empty_like(A0)
+    w = torch.empty(n, dtype=torch.float64, device=A0.device)
+    stream = torch.cuda.current_stream()
+    times, tims = [], []
+    for it in range(warmup + steps):
+        A.copy_(A0)
+        torch.cuda.synchronize()
+        plan.set_timing(True)
+        t0 = time.perf_counter()
+        rc = sbr.lib().sbr_syev_eigvals_ex(plan.handle, n, sbr._dev_f64(A, "A"), n, b0, sbr._prec(precision),
+                                           sbr._stream(stream), sbr._dev_f64(w, "w"))
+        sbr._check(rc, "sbr_syev_eigvals_ex")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tm = plan.timing()
+        log("%s step %d: %.1f ms (f2b %.1f, band %.1f, bisect %.1f) stages %s" % (
+            precision, it, (t1 - t0) * 1e3, tm["ms_f2b"], tm["ms_band"], tm["ms_bisect"],
+            ["%.1f" % x for x in tm["ms_stage"]]))
+        st = plan.status()
+        if st != 0:
+            raise RuntimeError("band-to-band pipeline reported a stalled wait (stage b=%d)" % st)
+        if it >= warmup:
+            times.append(t1 - t0)
+            tims.append(tm)
+    return times, tims, w
+
+
+def mean(xs):
+    return sum(xs) / max(1, len(xs))
+
+
+def cpu_baseline(A_host, n_sample: int):
+    import oracle
+    oracle.build()
+    S = A_host[:n_sample, :n_sample].copy()
+    t0 = time.perf_counter()
+    d, e = oracle.tridiagonalize(S)
+    t1 = time.perf_counter()
+    oracle.tridiag_eigvals(d, e)
+    t2 = time.perf_counter()
+    tflops = (4.0 / 3.0) * n_sample ** 3 / (t1 - t0) / 1e12
+    return {
+        "value": tflops,
+        "unit": "TFLOP/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": ("Householder tridiagonalisation (4/3 n^3 flops) of the leading %dx%d block of the "
+                   "same input; %.2f s, plus %.2f s of bisection for its %d eigenvalues; host %s"
+                   % (n_sample, n_sample, t1 - t0, t2 - t1, n_sample, platform.processor() or platform.machine())),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--b0", type=int, default=128)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the eigensolver here runs on a single device "
+              "(no sharding, no collectives); run it with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import sbr_inputs as si
+    import paper_1604_03703_amd as sbr
+
+    n, b0 = args.n, args.b0
+    cfg = si.CFG_LARGE if n == 32768 else si.CFG_MEDIUM
+    log("generating n=%d Gaussian input (seeded)" % n)
+    t0 = time.perf_counter()
+    A_host = si.gaussian_symmetric(n, si.make_rng(cfg, 0))
+    log("generated in %.1f s" % (time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    A0 = torch.from_numpy(A_host).to(dev)
+    trace = float(np.trace(A_host))
+    fro2 = float(np.sum(A_host * A_host))
+
+    plan = sbr.Plan(n, 0, "fp64")
+    times, tims, w = run_form(sbr, torch, A0, n, b0, "fp64", args.steps, args.warmup, plan)
+    wh = w.cpu().numpy()
+    # properties that hold at any size: sum of eigenvalues = trace, sum of squares = ||A||_F^2
+    tr_err = abs(wh.sum() - trace) / math.sqrt(fro2)
+    fr_err = abs(float(np.sum(wh * wh)) - fro2) / fro2
+    f2b_ms = mean([t["ms_f2b"] for t in tims])
+    band_ms = mean([t["ms_band"] for t in tims])
+    bis_ms = mean([t["ms_bisect"] for t in tims])
+    ms_per_step = 1e3 * mean(times)
+    f2b_flops = (4.0 / 3.0) * n ** 3
+    value = f2b_flops / (f2b_ms * 1e-3) / 1e12
+
+    # dominant kernel roofline: whichever of SYMM / SYR2K took longer in total
+    symm_f, syr2k_f = f2b_update_flops(n, b0)
+    syr2k_ms = mean([t["ms_syr2k"] for t in tims])
+    symm_ms = mean([t["ms_symm"] for t in tims])
+    if syr2k_ms >= symm_ms:
+        kname, kflops, kms, klaunch = "syr2k_lower_kernel<double,64,2,2>", sum(syr2k_f), syr2k_ms, len(syr2k_f)
+    else:
+        kname, kflops, kms, klaunch = "symm_lower_kernel<double,64,128,2,2>", sum(symm_f), symm_ms, len(symm_f)
+    achieved = kflops / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
+    stage_ms = [mean([t["ms_stage"][i] for t in tims]) for i in range(len(tims[0]["ms_stage"]))]
+    stages = []
+    b = b0
+    for sms in stage_ms:
+        by = band_stage_bytes(n, b)
+        stages.append({"b": b, "ms": round(sms, 3), "alg_GB": round(by / 1e9, 3),
+                       "GBps": round(by / (sms * 1e-3) / 1e9, 1) if sms > 0 else None})
+        b //= 2
+    band_bytes = sum(band_stage_bytes(n, 2 ** k) for k in range(1, int(math.log2(b0)) + 1))
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "symmetric eigenvalues, n=%d (G+G^T)/2 Gaussian, full-to-band b0=%d, "
+                               "halvings %d->1, Sturm bisection (all n), FP64" % (n, b0, b0),
+                   "n": n, "b0": b0},
+        "s_per_solve": round(ms_per_step / 1e3, 4),
+        "phases_ms": {"f2b": round(f2b_ms, 3), "band": round(band_ms, 3), "bisect": round(bis_ms, 3)},
+        "band_stages": stages,
+        "band_GBps_alg": round(band_bytes / (band_ms * 1e-3) / 1e9, 1) if band_ms > 0 else None,
+        "checks": {"trace_rel": tr_err, "frobenius_rel": fr_err},
+        "roofline": {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3),
+                     "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA, 4),
+                     "traffic": None, "launches": klaunch, "avg_launch_ms": round(kms / max(1, klaunch), 4)},
+    }
+
+    if not args.no_fp32:
+        plan32 = sbr.Plan(n, 0, "fp32_mfma")
+        t32, tim32, w32 = run_form(sbr, torch, A0, n, b0, "fp32_mfma", args.steps, args.warmup, plan32)
+        f2b32 = mean([t["ms_f2b"] for t in tim32])
+        d = np.abs(w32.cpu().numpy() - wh)
+        norm2 = float(np.max(np.abs(wh)))
+        result["fp32_mfma"] = {
+            "f2b_TFLOPs": round(f2b_flops / (f2b32 * 1e-3) / 1e12, 4),
+            "s_per_solve": round(mean(t32) , 4),
+            "phases_ms": {"f2b": round(f2b32, 3), "band": round(mean([t["ms_band"] for t in tim32]), 3),
+                          "bisect": round(mean([t["ms_bisect"] for t in tim32]), 3)},
+            "err_vs_fp64_max_rel": float(d.max() / norm2),
+            "err_vs_fp64_rms_rel": float(math.sqrt(float(np.mean(d * d))) / norm2),
+            "speedup_f2b": round(f2b_ms / f2b32, 3) if f2b32 > 0 else None,
+        }
+        del plan32
+
+    if not args.no_cpu:
+        log("timing the CPU oracle on a %d sample" % args.cpu_sample)
+        result["cpu_baseline"] = cpu_baseline(A_host, min(args.cpu_sample, n))
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

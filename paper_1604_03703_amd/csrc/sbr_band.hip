@@ -157,14 +157,17 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
                 if (t == 0) {
                     const int need = (int)(j + 2);
                     const uint64_t t0 = wall_clock64();
-                    while (sbr_load_acquire(&a.progress[i - 1]) < need) {
+                    // spin on relaxed loads (an acquire per poll would invalidate
+                    // the L2 each time); one acquire fence once the flag is seen
+                    while (__hip_atomic_load(&a.progress[i - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                           need) {
                         __builtin_amdgcn_s_sleep(2);
                         if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                             abort_sh = 1;
                             break;
                         }
                         if (wall_clock64() - t0 > WAIT_LIMIT_TICKS) {
-                            atomicExch(a.error, 1);
+                            atomicExch(a.error, 2 * H);   // the stage (its bandwidth b) that stalled
                             abort_sh = 1;
                             break;
                         }
