@@ -201,22 +201,63 @@ int ensure_workspace(sbr_plan_t p, int64_t n, int b) {
 
 int check_band(int32_t b) { return (is_pow2(b) && b >= 2 && b <= 128) ? 0 : 1; }
 
+// Panel QR of P (m x b, m >= b) in Householder form: writes U (m x b, ld
+// n_cap) and T (b x b, ld b) into the plan and the band block [S R; 0] into
+// P.  Up to TSQR_MAX_B columns: one TSQR tree + reconstruction.  Wider:
+// factor the left half, apply its block reflector to the right half, factor
+// the lower right half, and merge T = [T_L, -T_L (U_L^T U_R) T_R; 0, T_R].
+void factor_block(sbr_plan_t p, int64_t m, int bw, double* P, int64_t ldp, double* U, double* T, int64_t ldt,
+                  double* S, hipStream_t s) {
+    const int64_t ldq = p->n_cap;
+    TsqrTree tr;
+    tsqr_plan(tr, m, bw, p->tsqr_ws);
+    launch_tsqr(tr, P, ldp, p->Q, ldq, s);
+    launch_reconstruct(bw, p->Q, ldq, U, ldq, T, ldt, p->W1inv, S, s);
+    if (m > bw)
+        launch_gemm(false, false, false, m - bw, bw, bw, 1.0, p->Q + bw, ldq, p->W1inv, bw, 0.0, nullptr, 0,
+                    U + bw, ldq, s);
+    launch_panel_writeback(m, bw, P, ldp, tsqr_root_r(tr), S, s);
+}
+
+void factor_panel(sbr_plan_t p, int64_t m, int b, double* P, int64_t ldp, hipStream_t s) {
+    const int64_t ldq = p->n_cap;
+    if (b <= TSQR_MAX_B) {
+        factor_block(p, m, b, P, ldp, p->U, p->T, b, p->S, s);
+        return;
+    }
+    const int h = b / 2;
+    double* UL = p->U;
+    double* UR = p->U + (int64_t)h * ldq;
+    double* C = P + (int64_t)h * ldp;                 // right half of the panel
+    // left half
+    factor_block(p, m, h, P, ldp, UL, p->T, b, p->S, s);
+    // C <- (I - U_L T_L U_L^T)^T C = C - U_L (T_L^T (U_L^T C))
+    const int gs = gemm_splits(h, h, m);
+    launch_gemm_splitk(false, true, false, h, h, m, 1.0, UL, ldq, C, ldp, 0.0, nullptr, 0, p->Zm, h, p->part, gs, s);
+    launch_gemm(false, true, false, h, h, h, 1.0, p->T, b, p->Zm, h, 0.0, nullptr, 0, p->Mm, h, s);
+    launch_gemm(false, false, false, m, h, h, -1.0, UL, ldq, p->Mm, h, 1.0, C, ldp, C, ldp, s);
+    // lower right half (rows h .. m-1 of C)
+    launch_zero_block(h, h, UR, ldq, s);
+    factor_block(p, m - h, h, C + h, ldp, UR + h, p->T + (int64_t)h * b + h, b, p->S + h, s);
+    // T12 = -T_L (U_L^T U_R) T_R (U_R is zero in its first h rows)
+    const int gs2 = gemm_splits(h, h, m - h);
+    launch_gemm_splitk(false, true, false, h, h, m - h, 1.0, UL + h, ldq, UR + h, ldq, 0.0, nullptr, 0, p->Zm, h,
+                       p->part, gs2, s);
+    launch_gemm(false, false, false, h, h, h, 1.0, p->T, b, p->Zm, h, 0.0, nullptr, 0, p->Mm, h, s);
+    launch_gemm(false, false, false, h, h, h, -1.0, p->Mm, h, p->T + (int64_t)h * b + h, b, 0.0, nullptr, 0,
+                p->T + (int64_t)h * b, b, s);
+    launch_zero_block(h, h, p->T + h, b, s);          // T21 = 0
+}
+
 int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, bool f32, hipStream_t s) {
     const int64_t ldq = p->n_cap;
     int64_t k = 0;
-    TsqrTree tr;
     for (;; ++k) {
         const int64_t c0 = k * b, r0 = c0 + b, m = n - r0;
         if (m < b) break;
         double* P = A + r0 + c0 * lda;
         double* A22 = A + r0 + r0 * lda;
-        tsqr_plan(tr, m, b, p->tsqr_ws);
-        launch_tsqr(tr, P, lda, p->Q, ldq, s);
-        launch_reconstruct(b, p->Q, ldq, p->U, ldq, p->T, p->W1inv, p->S, s);
-        if (m > b)
-            launch_gemm(false, false, false, m - b, b, b, 1.0, p->Q + b, ldq, p->W1inv, b, 0.0, nullptr, 0,
-                        p->U + b, ldq, s);
-        launch_panel_writeback(m, b, P, lda, tsqr_root_r(tr), p->S, s);
+        factor_panel(p, m, b, P, lda, s);
         // Y = U T
         launch_gemm(false, false, false, m, b, b, 1.0, p->U, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, s);
         // W = A22 Y
@@ -583,7 +624,7 @@ int sbr_panel_qr(sbr_plan_t plan, int64_t m, int32_t b, const double* P, int64_t
     TsqrTree tr;
     tsqr_plan(tr, m, b, plan->tsqr_ws);
     launch_tsqr(tr, plan->pcopy, m, Q, m, s);
-    launch_reconstruct(b, Q, m, U, m, T, plan->W1inv, S, s);
+    launch_reconstruct(b, Q, m, U, m, T, b, plan->W1inv, S, s);
     if (m > b) launch_gemm(false, false, false, m - b, b, b, 1.0, Q + b, m, plan->W1inv, b, 0.0, nullptr, 0, U + b, m, s);
     e = hipMemcpyAsync(R, tsqr_root_r(tr), (size_t)b * b * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e);

@@ -44,8 +44,13 @@ const double* tsqr_root_r(const TsqrTree& tr);
 // Householder reconstruction (single work-group): from Q1 = Q[0:b, 0:b]
 // writes U1 (unit lower, into U rows 0..b-1, ld ldu), T (b x b), W1^{-1}
 // (b x b) and S (b signs).
-void launch_reconstruct(int b, const double* Q, int64_t ldq, double* U, int64_t ldu, double* T,
+void launch_reconstruct(int b, const double* Q, int64_t ldq, double* U, int64_t ldu, double* T, int64_t ldt,
                         double* W1inv, double* S, hipStream_t s);
+void launch_zero_block(int64_t m, int64_t nc, double* X, int64_t ldx, hipStream_t s);
+// Largest panel width factored by one TSQR tree; wider panels are factored
+// recursively (left half, block-reflector update of the right half, lower
+// right half, then the merged T).
+constexpr int TSQR_MAX_B = 64;
 // Band block of the panel: P[0:b, :] = diag(S) R (upper), P[b:m, :] = 0.
 void launch_panel_writeback(int64_t m, int b, double* P, int64_t ldp, const double* R, const double* S,
                             hipStream_t s);

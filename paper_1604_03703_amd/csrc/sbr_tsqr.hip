@@ -16,9 +16,6 @@
 //   is reduced by unblocked Householder with the two-sided update applied one
 //   reflector at a time.
 //
-// Register layout of the QR / apply kernels: NT threads, TPC = NT / b threads
-// per column; thread t owns column t / TPC, rows (t % TPC) + TPC * r for
-// r < 2b / TPC.  Column reductions are shuffles inside the TPC-lane group.
 #include <math.h>
 
 #include "sbr_device.h"
@@ -83,11 +80,55 @@ __device__ __forceinline__ Seg node_segments(const TsqrLevelArgs& a, int q) {
     return s;
 }
 
-template <int B, int NT>
-__global__ __launch_bounds__(NT) void tsqr_qr_kernel(TsqrLevelArgs a) {
-    constexpr int TPC = NT / B;
-    constexpr int RPT = 2 * B / TPC;
-    static_assert(TPC >= 2 && TPC <= 64 && (TPC & (TPC - 1)) == 0 && RPT >= 1, "layout");
+// Register layout of the QR / apply kernels: TPC consecutive lanes own one
+// column (TPC = 8, or 2b when b < 4), lane s of the group holds the rows
+// s + TPC r (r < RPT = 2b / TPC).  Column sums are DPP exchanges inside the
+// group (no LDS traffic); one barrier per Householder step hands the
+// reflector from its owner group to the others through LDS.
+template <int B>
+struct GroupQR {
+    static constexpr int TPC = (2 * B < 8) ? 2 * B : 8;
+    static constexpr int RPT = 2 * B / TPC;
+    static constexpr int NT = B * TPC;
+    static constexpr int NACC = RPT >= 4 ? 4 : RPT;   // independent partial sums
+};
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the TPC lanes of a group (TPC in {2, 4, 8}, groups aligned):
+// quad_perm(1,0,3,2) = lane ^ 1, quad_perm(2,3,0,1) = lane ^ 2,
+// row_half_mirror = lane i <-> 7 - i inside each 8-lane half row.
+template <int TPC>
+__device__ __forceinline__ double group_sum(double v) {
+    static_assert(TPC == 2 || TPC == 4 || TPC == 8, "group size");
+    v += dpp_d<0xB1>(v);
+    if (TPC >= 4) v += dpp_d<0x4E>(v);
+    if (TPC >= 8) v += dpp_d<0x141>(v);
+    return v;
+}
+
+template <int RPT, int NACC>
+__device__ __forceinline__ double dot_rows(const double* x, const double* v, int s, int tpc) {
+    double acc[NACC];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) acc[a] = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) acc[r % NACC] += v[s + tpc * r] * x[r];
+    double d = acc[0];
+#pragma unroll
+    for (int a = 1; a < NACC; ++a) d += acc[a];
+    return d;
+}
+
+template <int B>
+__global__ __launch_bounds__(GroupQR<B>::NT) void tsqr_qr_kernel(TsqrLevelArgs a) {
+    typedef GroupQR<B> L;
+    constexpr int TPC = L::TPC, RPT = L::RPT, NACC = L::NACC;
     __shared__ double vsh[2][2 * B];
     __shared__ double tsh[B];
     const int t = threadIdx.x, c = t / TPC, s = t % TPC;
@@ -106,23 +147,24 @@ __global__ __launch_bounds__(NT) void tsqr_qr_kernel(TsqrLevelArgs a) {
     for (int k = 0; k < B; ++k) {
         double* v = vsh[k & 1];
         if (c == k) {
-            double ss = 0.0, xk = 0.0;
+            double sacc[NACC];
+#pragma unroll
+            for (int u = 0; u < NACC; ++u) sacc[u] = 0.0;
+            double xk = 0.0;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 const int row = s + TPC * r;
-                if (row > k) ss += x[r] * x[r];
+                if (row > k) sacc[r % NACC] += x[r] * x[r];
                 else if (row == k) xk = x[r];
             }
+            double ss = sacc[0];
 #pragma unroll
-            for (int o = 1; o < TPC; o <<= 1) {
-                ss += __shfl_xor(ss, o);
-                xk += __shfl_xor(xk, o);
-            }
+            for (int u = 1; u < NACC; ++u) ss += sacc[u];
+            ss = group_sum<TPC>(ss);
+            xk = group_sum<TPC>(xk);
             double beta, tau, scal;
             if (ss == 0.0) {
-                beta = xk;
-                tau = 0.0;
-                scal = 0.0;
+                beta = xk; tau = 0.0; scal = 0.0;
             } else {
                 const double nrm = sqrt(xk * xk + ss);
                 beta = (xk >= 0.0) ? -nrm : nrm;
@@ -143,28 +185,20 @@ __global__ __launch_bounds__(NT) void tsqr_qr_kernel(TsqrLevelArgs a) {
         if (c > k) {
             const double tau = tsh[k];
             if (tau != 0.0) {
-                double dot = 0.0;
-#pragma unroll
-                for (int r = 0; r < RPT; ++r) dot += v[s + TPC * r] * x[r];
-#pragma unroll
-                for (int o = 1; o < TPC; o <<= 1) dot += __shfl_xor(dot, o);
-                const double f = tau * dot;
+                const double d = group_sum<TPC>(dot_rows<RPT, NACC>(x, v, s, TPC));
+                const double f = tau * d;
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) x[r] -= f * v[s + TPC * r];
             }
         }
     }
     // reflectors (below the diagonal) and R (on and above it) back in place
+    double* R = a.own_slots + (int64_t)q * B * B;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int row = s + TPC * r;
         if (row < g.rows0) g.p0[row + (int64_t)c * g.ld0] = x[r];
         else if (row < rows) g.p1[(row - g.rows0) + (int64_t)c * g.ld1] = x[r];
-    }
-    double* R = a.own_slots + (int64_t)q * B * B;
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        const int row = s + TPC * r;
         if (row < B) R[row + c * B] = (row <= c) ? x[r] : 0.0;
     }
     __syncthreads();
@@ -172,10 +206,10 @@ __global__ __launch_bounds__(NT) void tsqr_qr_kernel(TsqrLevelArgs a) {
 }
 
 // X = H_0 ... H_{B-1} [Z; 0]: the node's explicit Q block times Z.
-template <int B, int NT>
-__global__ __launch_bounds__(NT) void tsqr_apply_kernel(TsqrLevelArgs a) {
-    constexpr int TPC = NT / B;
-    constexpr int RPT = 2 * B / TPC;
+template <int B>
+__global__ __launch_bounds__(GroupQR<B>::NT) void tsqr_apply_kernel(TsqrLevelArgs a) {
+    typedef GroupQR<B> L;
+    constexpr int TPC = L::TPC, RPT = L::RPT, NACC = L::NACC;
     __shared__ double vsh[2][2 * B];
     __shared__ double tsh[B];
     const int t = threadIdx.x, c = t / TPC, s = t % TPC;
@@ -206,28 +240,19 @@ __global__ __launch_bounds__(NT) void tsqr_apply_kernel(TsqrLevelArgs a) {
         if (k > 0 && t < 2 * B) vnext = fetchv(t, k - 1);
         const double tau = tsh[k];
         if (tau != 0.0) {
-            double dot = 0.0;
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) dot += v[s + TPC * r] * x[r];
-#pragma unroll
-            for (int o = 1; o < TPC; o <<= 1) dot += __shfl_xor(dot, o);
-            const double f = tau * dot;
+            const double d = group_sum<TPC>(dot_rows<RPT, NACC>(x, v, s, TPC));
+            const double f = tau * d;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) x[r] -= f * v[s + TPC * r];
         }
     }
     __syncthreads();   // every read of the reflectors is done before they are overwritten
-    if (a.is_leaf) {
-        double* Qo = a.Q + (int64_t)q * B;
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int row = s + TPC * r;
-            if (row < g.rows0) Qo[row + (int64_t)c * a.ldq] = x[r];
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int row = s + TPC * r;
+    for (int r = 0; r < RPT; ++r) {
+        const int row = s + TPC * r;
+        if (a.is_leaf) {
+            if (row < g.rows0) a.Q[(int64_t)q * B + row + (int64_t)c * a.ldq] = x[r];
+        } else {
             if (row < g.rows0) g.p0[row + (int64_t)c * g.ld0] = x[r];
             else if (row < rows) g.p1[(row - g.rows0) + (int64_t)c * g.ld1] = x[r];
         }
@@ -235,16 +260,18 @@ __global__ __launch_bounds__(NT) void tsqr_apply_kernel(TsqrLevelArgs a) {
 }
 
 // Householder reconstruction for a b x b top block, one work-group.
-// LDS: F (b x (b+1)) holds Q1 - S, then U1 \ W1, then U1^{-1} \ W1, then
-// U1^{-1} \ W1^{-1}.
+// LDS F (b x (b+1)): Q1, then the LU factors (U1 strictly below the diagonal,
+// W1 above it, the pivots of W1 kept in pv), then T (upper part, computed
+// from T U1^T = -W1 S), then W1^{-1} (upper part, after W1 is reloaded).
 constexpr int REC_NT = 512;
 
 __global__ __launch_bounds__(REC_NT) void reconstruct_kernel(int b, const double* __restrict__ Q, int64_t ldq,
-                                                             double* U, int64_t ldu, double* T, double* W1inv,
-                                                             double* S) {
+                                                             double* U, int64_t ldu, double* T, int64_t ldt,
+                                                             double* W1inv, double* S) {
     extern __shared__ double F[];
     __shared__ double col[128];
     __shared__ double sv[128];
+    __shared__ double pv[128];
     const int t = threadIdx.x;
     const int ld = b + 1;
     for (int idx = t; idx < b * b; idx += REC_NT) {
@@ -252,71 +279,76 @@ __global__ __launch_bounds__(REC_NT) void reconstruct_kernel(int b, const double
         F[i + j * ld] = Q[i + (int64_t)j * ldq];
     }
     __syncthreads();
-    // LU of Q1 - S without pivoting
+    // ---- LU of Q1 - S without pivoting.  The TPR threads of a row are
+    // consecutive lanes of one wave, each owning the columns = s (mod TPR).
+    // Every thread derives the pivot from the unmodified diagonal entry, so
+    // one barrier per step is enough.
+    // threads per row: at most one wave, so a row's lanes run in lock step
+    const int tpr = (REC_NT / b < 64) ? REC_NT / b : 64;
+    const int row = t / tpr, sub = t % tpr;
     for (int i = 0; i < b; ++i) {
+        const double aii = F[i + i * ld];
+        const double si = (aii >= 0.0) ? -1.0 : 1.0;
+        const double piv = aii - si;
         if (t == 0) {
-            const double aii = F[i + i * ld];
-            const double si = (aii >= 0.0) ? -1.0 : 1.0;
             sv[i] = si;
-            F[i + i * ld] = aii - si;
+            pv[i] = piv;
         }
-        __syncthreads();
-        const double piv = F[i + i * ld];
-        for (int r = i + 1 + t; r < b; r += REC_NT) F[r + i * ld] /= piv;
-        __syncthreads();
-        const int w = b - i - 1;
-        for (int idx = t; idx < w * w; idx += REC_NT) {
-            const int r = i + 1 + idx % w, cc = i + 1 + idx / w;
-            F[r + cc * ld] -= F[r + i * ld] * F[i + cc * ld];
+        if (row > i && row < b) {
+            const double l = F[row + i * ld] / piv;       // read by all lanes of the row first
+            for (int c = i + 1 + ((sub - (i + 1)) % tpr + tpr) % tpr; c < b; c += tpr)
+                F[row + c * ld] -= l * F[i + c * ld];
+            if (sub == i % tpr) F[row + i * ld] = l;
         }
         __syncthreads();
     }
-    // U1 (unit lower) out, S out
+    // ---- U1 (unit lower) and W1 (upper, to T as scratch) out
     for (int idx = t; idx < b * b; idx += REC_NT) {
         const int i = idx % b, j = idx / b;
         U[i + (int64_t)j * ldu] = (i > j) ? F[i + j * ld] : (i == j ? 1.0 : 0.0);
+        W1inv[i + j * b] = (i < j) ? F[i + j * ld] : (i == j ? pv[i] : 0.0);
     }
     if (t < b) S[t] = sv[t];
     __syncthreads();
-    // U1^{-1} in place (strict lower part), columns right to left:
-    // X[j+1:, j] = -X[j+1:, j+1:] L[j+1:, j]
-    for (int j = b - 2; j >= 0; --j) {
-        for (int r = j + 1 + t; r < b; r += REC_NT) col[r] = F[r + j * ld];
-        __syncthreads();
-        for (int r = j + 1 + t; r < b; r += REC_NT) {
-            double acc = col[r];
-            for (int k = j + 1; k < r; ++k) acc += F[r + k * ld] * col[k];
-            F[r + j * ld] = -acc;
-        }
-        __syncthreads();
-    }
-    // T = -W1 S U1^{-T}: T[i][j] = -sum_{k=i..j} W1[i][k] s_k U1inv[j][k]
+    // ---- T from T U1^T = M, M = -W1 S (upper): right-looking over columns j:
+    // T[:, j] = M[:, j]; M[i][j'] -= T[i][j] U1[j'][j] for i <= j < j'
     for (int idx = t; idx < b * b; idx += REC_NT) {
         const int i = idx % b, j = idx / b;
-        double acc = 0.0;
-        if (i <= j) {
-            for (int k = i; k <= j; ++k) {
-                const double linv = (k == j) ? 1.0 : F[j + k * ld];
-                acc += F[i + k * ld] * sv[k] * linv;
-            }
-        }
-        T[i + j * b] = -acc;
+        if (i <= j) F[i + j * ld] = -((i == j) ? pv[i] : F[i + j * ld]) * sv[j];
     }
     __syncthreads();
-    // W1^{-1} in place (upper part), columns left to right:
-    // X[j, j] = 1 / W[j, j]; X[0:j, j] = -X[0:j, 0:j] W[0:j, j] / W[j, j]
-    for (int j = 0; j < b; ++j) {
-        for (int r = t; r <= j; r += REC_NT) col[r] = F[r + j * ld];
+    for (int j = 0; j + 1 < b; ++j) {
+        const int w = b - 1 - j;                 // columns j+1 .. b-1
+        for (int idx = t; idx < (j + 1) * w; idx += REC_NT) {
+            const int i = idx % (j + 1), jp = j + 1 + idx / (j + 1);
+            F[i + jp * ld] -= F[i + j * ld] * F[jp + j * ld];
+        }
         __syncthreads();
-        const double wjj = col[j];
-        for (int r = t; r <= j; r += REC_NT) {
-            if (r == j) {
-                F[j + j * ld] = 1.0 / wjj;
-            } else {
-                double acc = 0.0;
-                for (int k = r; k < j; ++k) acc += F[r + k * ld] * col[k];
-                F[r + j * ld] = -acc / wjj;
-            }
+    }
+    for (int idx = t; idx < b * b; idx += REC_NT) {
+        const int i = idx % b, j = idx / b;
+        T[i + j * ldt] = (i <= j) ? F[i + j * ld] : 0.0;
+    }
+    __syncthreads();
+    // ---- W1^{-1} (upper): reload W1 (strict upper into F, diagonal in pv),
+    // then rows bottom-up: X[i][j] = R[i][j] / W1[i][i] (j >= i, R[i][i] = 1),
+    // R[r][j] -= W1[r][i] X[i][j] for r < i (column i of W1 snapshotted first)
+    for (int idx = t; idx < b * b; idx += REC_NT) {
+        const int i = idx % b, j = idx / b;
+        if (i < j) F[i + j * ld] = W1inv[i + j * b];
+        else if (i == j) F[i + j * ld] = 1.0;
+    }
+    __syncthreads();
+    for (int i = b - 1; i >= 0; --i) {
+        const double inv = 1.0 / pv[i];
+        for (int r = t; r < i; r += REC_NT) col[r] = F[r + i * ld];
+        for (int j = i + t; j < b; j += REC_NT) F[i + j * ld] *= inv;
+        __syncthreads();
+        const int w = b - i;                     // columns i .. b-1
+        for (int idx = t; idx < i * w; idx += REC_NT) {
+            const int r = idx % i, j = i + idx / i;
+            const double base = (j == i) ? 0.0 : F[r + j * ld];
+            F[r + j * ld] = base - col[r] * F[i + j * ld];
         }
         __syncthreads();
     }
@@ -324,6 +356,12 @@ __global__ __launch_bounds__(REC_NT) void reconstruct_kernel(int b, const double
         const int i = idx % b, j = idx / b;
         W1inv[i + j * b] = (i <= j) ? F[i + j * ld] : 0.0;
     }
+}
+
+__global__ void zero_block_kernel(int64_t m, int64_t nc, double* X, int64_t ldx) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * nc) return;
+    X[idx % m + (idx / m) * ldx] = 0.0;
 }
 
 __global__ void panel_writeback_kernel(int64_t m, int b, double* P, int64_t ldp, const double* __restrict__ R,
@@ -415,15 +453,11 @@ __global__ __launch_bounds__(TAIL_NT) void f2b_tail_kernel(int m, int b, double*
     }
 }
 
-// threads per column: at least 2 and at most 2b (one row per thread)
-template <int B>
-constexpr int tsqr_tpc() { return B == 128 ? 8 : (B == 64 ? 4 : (B == 32 ? 8 : (B == 16 ? 16 : (2 * B < 8 ? 2 * B : 8)))); }
-
 template <int B>
 void launch_level(bool qr, const TsqrLevelArgs& a, int blocks, hipStream_t s) {
-    constexpr int NT = B * tsqr_tpc<B>();
-    if (qr) tsqr_qr_kernel<B, NT><<<blocks, NT, 0, s>>>(a);
-    else tsqr_apply_kernel<B, NT><<<blocks, NT, 0, s>>>(a);
+    constexpr int NT = GroupQR<B>::NT;
+    if (qr) tsqr_qr_kernel<B><<<blocks, NT, 0, s>>>(a);
+    else tsqr_apply_kernel<B><<<blocks, NT, 0, s>>>(a);
 }
 
 void launch_level_b(int b, bool qr, const TsqrLevelArgs& a, int blocks, hipStream_t s) {
@@ -520,10 +554,16 @@ int init_tsqr_attributes() {
     return e == hipSuccess ? 0 : (int)e;
 }
 
-void launch_reconstruct(int b, const double* Q, int64_t ldq, double* U, int64_t ldu, double* T, double* W1inv,
-                        double* S, hipStream_t s) {
+void launch_reconstruct(int b, const double* Q, int64_t ldq, double* U, int64_t ldu, double* T, int64_t ldt,
+                        double* W1inv, double* S, hipStream_t s) {
     const size_t shm = (size_t)b * (b + 1) * sizeof(double);
-    reconstruct_kernel<<<1, REC_NT, shm, s>>>(b, Q, ldq, U, ldu, T, W1inv, S);
+    reconstruct_kernel<<<1, REC_NT, shm, s>>>(b, Q, ldq, U, ldu, T, ldt, W1inv, S);
+}
+
+void launch_zero_block(int64_t m, int64_t nc, double* X, int64_t ldx, hipStream_t s) {
+    const int64_t tot = m * nc;
+    if (tot <= 0) return;
+    zero_block_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(m, nc, X, ldx);
 }
 
 void launch_panel_writeback(int64_t m, int b, double* P, int64_t ldp, const double* R, const double* S,
