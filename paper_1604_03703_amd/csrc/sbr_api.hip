@@ -318,6 +318,7 @@ std::map<int, sbr_plan_t> g_plans;
 int init_attributes() {
     int rc = init_tsqr_attributes();
     rc |= init_band_attributes();
+    rc |= init_band_group_attributes();
     return rc;
 }
 

@@ -110,8 +110,26 @@ struct ChaseLayout {
     static constexpr int TOTAL = VB + 2 * H2;
 };
 
+// lanes per column in the chase QR: at most 8 (DPP group sums), at most 2h
 template <int H, int NT>
-constexpr int chase_tpcq() { return (NT / H < 2 * H) ? NT / H : 2 * H; }
+constexpr int chase_tpcq() {
+    return (NT / H < 2 * H) ? ((NT / H < 8) ? NT / H : 8) : ((2 * H < 8) ? 2 * H : 8);
+}
+
+// Register blocks of the chase's small products: MH = 2h x h outputs,
+// HH = h x h, MM = 2h x 2h (256 threads).
+template <int H> struct ChaseTiles {
+    static constexpr int MH_M = 1, MH_N = 1, HH_M = 1, HH_N = 1, MM_M = 1, MM_N = 1;
+};
+template <> struct ChaseTiles<64> {
+    static constexpr int MH_M = 4, MH_N = 4, HH_M = 4, HH_N = 4, MM_M = 4, MM_N = 4;
+};
+template <> struct ChaseTiles<32> {
+    static constexpr int MH_M = 2, MH_N = 4, HH_M = 2, HH_N = 2, MM_M = 4, MM_N = 4;
+};
+template <> struct ChaseTiles<16> {
+    static constexpr int MH_M = 1, MH_N = 2, HH_M = 1, HH_N = 1, MM_M = 2, MM_N = 2;
+};
 
 template <int H, int NT, bool LDS>
 __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
@@ -184,10 +202,14 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
             if (nb64 > H2) nb64 = H2;
             const int nbr = nb64 > 0 ? (int)nb64 : 0;
 
-            // ---- load the QR block and the diagonal block
-            for (int idx = t; idx < H2 * H; idx += NT) {
-                const int r = idx % H2, c = idx / H2;
-                Qb[idx] = (r < nr) ? bget(band, ldb, o + r, cq + c) : 0.0;
+            // ---- QR block straight into registers (column groups), diagonal block into Db
+            double x[RPT];
+            if (t < NQ) {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const int row = qs + TPCQ * r;
+                    x[r] = (row < nr) ? bget(band, ldb, o + row, cq + qc) : 0.0;
+                }
             }
             for (int idx = t; idx < H2 * H2; idx += NT) {
                 const int r = idx % H2, c = idx / H2;
@@ -195,14 +217,9 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
                 if (r < nr && c < nr) v = (r >= c) ? bget(band, ldb, o + r, o + c) : bget(band, ldb, o + c, o + r);
                 Db[idx] = v;
             }
-            __syncthreads();
 
-            // ---- Householder QR of the block (register layout, NQ threads)
-            double x[RPT];
-            if (t < NQ) {
-#pragma unroll
-                for (int r = 0; r < RPT; ++r) x[r] = Qb[(qs + TPCQ * r) + qc * H2];
-            }
+            // ---- Householder QR of the block: one barrier per reflector, column
+            // sums inside each TPCQ-lane group
             for (int k = 0; k < H; ++k) {
                 double* v = vbuf + (k & 1) * H2;
                 if (t < NQ && qc == k) {
@@ -213,11 +230,8 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
                         if (row > k) ss += x[r] * x[r];
                         else if (row == k) xk = x[r];
                     }
-#pragma unroll
-                    for (int off = 1; off < TPCQ; off <<= 1) {
-                        ss += __shfl_xor(ss, off);
-                        xk += __shfl_xor(xk, off);
-                    }
+                    ss = group_sum<TPCQ>(ss);
+                    xk = group_sum<TPCQ>(xk);
                     double beta, tk, scal;
                     if (ss == 0.0) {
                         beta = xk; tk = 0.0; scal = 0.0;
@@ -241,12 +255,11 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
                 if (t < NQ && qc > k) {
                     const double tk = tau[k];
                     if (tk != 0.0) {
-                        double dot = 0.0;
+                        double d = 0.0;
 #pragma unroll
-                        for (int r = 0; r < RPT; ++r) dot += v[qs + TPCQ * r] * x[r];
-#pragma unroll
-                        for (int off = 1; off < TPCQ; off <<= 1) dot += __shfl_xor(dot, off);
-                        const double f = tk * dot;
+                        for (int r = 0; r < RPT; ++r) d += v[qs + TPCQ * r] * x[r];
+                        d = group_sum<TPCQ>(d);
+                        const double f = tk * d;
 #pragma unroll
                         for (int r = 0; r < RPT; ++r) x[r] -= f * v[qs + TPCQ * r];
                     }
@@ -267,16 +280,16 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
             }
             __syncthreads();
 
-            // ---- T (forward, columnwise): T[c][c] = tau_c,
-            // T[0:c, c] = -tau_c T[0:c, 0:c] (U^T U)[0:c, c]
-            for (int idx = t; idx < H * H; idx += NT) {
-                const int ra = idx % H, c = idx / H;
-                double acc = 0.0;
-                if (ra < c)
-                    for (int r = 0; r < H2; ++r) acc += Qb[r + ra * H2] * Qb[r + c * H2];
-                Gm[idx] = acc;
-                Tm[idx] = 0.0;
-            }
+            typedef ChaseTiles<H> TL;
+            auto U = [&](int i, int k) -> double { return Qb[i + k * H2]; };
+            auto Ut = [&](int i, int k) -> double { return Qb[k + i * H2]; };
+            // ---- T (forward, columnwise): G = U^T U (strict upper), then
+            // T[c][c] = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] G[0:c, c]
+            block_gemm<H, H, H2, TL::HH_M, TL::HH_N, NT>(
+                t, Ut, U, [&](int i, int jj, double v) {
+                    Gm[i + jj * H] = (i < jj) ? v : 0.0;
+                    Tm[i + jj * H] = 0.0;
+                });
             __syncthreads();
             for (int c = 0; c < H; ++c) {
                 const double tc = tau[c];
@@ -292,100 +305,75 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
                 __syncthreads();
             }
             // ---- Y = U T
-            for (int idx = t; idx < H2 * H; idx += NT) {
-                const int r = idx % H2, c = idx / H2;
-                double acc = 0.0;
-                for (int k = 0; k <= c; ++k) acc += Qb[r + k * H2] * Tm[k + c * H];
-                Yb[idx] = acc;
-            }
+            block_gemm<H2, H, H, TL::MH_M, TL::MH_N, NT>(
+                t, U, [&](int k, int jj) -> double { return Tm[k + jj * H]; },
+                [&](int i, int jj, double v) { Yb[i + jj * H2] = v; });
             __syncthreads();
-            // ---- W_R = Db Y
-            for (int idx = t; idx < H2 * H; idx += NT) {
-                const int r = idx % H2, c = idx / H2;
-                double acc = 0.0;
-                for (int k = 0; k < H2; ++k) acc += Db[r + k * H2] * Yb[k + c * H2];
-                Wr[idx] = acc;
-            }
+            // ---- W_R = D Y
+            block_gemm<H2, H, H2, TL::MH_M, TL::MH_N, NT>(
+                t, [&](int i, int k) -> double { return Db[i + k * H2]; },
+                [&](int k, int jj) -> double { return Yb[k + jj * H2]; },
+                [&](int i, int jj, double v) { Wr[i + jj * H2] = v; });
             __syncthreads();
-            // ---- G = U^T W_R, M = T^T G, V_R = 1/2 U M - W_R
-            for (int idx = t; idx < H * H; idx += NT) {
-                const int ra = idx % H, c = idx / H;
-                double acc = 0.0;
-                for (int r = 0; r < H2; ++r) acc += Qb[r + ra * H2] * Wr[r + c * H2];
-                Gm[idx] = acc;
-            }
+            // ---- G = U^T W_R ; M = T^T G ; V_R = 1/2 U M - W_R
+            block_gemm<H, H, H2, TL::HH_M, TL::HH_N, NT>(
+                t, Ut, [&](int k, int jj) -> double { return Wr[k + jj * H2]; },
+                [&](int i, int jj, double v) { Gm[i + jj * H] = v; });
             __syncthreads();
-            for (int idx = t; idx < H * H; idx += NT) {
-                const int ra = idx % H, c = idx / H;
-                double acc = 0.0;
-                for (int k = 0; k <= ra; ++k) acc += Tm[k + ra * H] * Gm[k + c * H];
-                Mm[idx] = acc;
-            }
+            block_gemm<H, H, H, TL::HH_M, TL::HH_N, NT>(
+                t, [&](int i, int k) -> double { return Tm[k + i * H]; },
+                [&](int k, int jj) -> double { return Gm[k + jj * H]; },
+                [&](int i, int jj, double v) { Mm[i + jj * H] = v; });
             __syncthreads();
-            for (int idx = t; idx < H2 * H; idx += NT) {
-                const int r = idx % H2, c = idx / H2;
-                double acc = 0.0;
-                for (int k = 0; k < H; ++k) acc += Qb[r + k * H2] * Mm[k + c * H];
-                Wr[idx] = 0.5 * acc - Wr[idx];
-            }
+            block_gemm<H2, H, H, TL::MH_M, TL::MH_N, NT>(
+                t, U, [&](int k, int jj) -> double { return Mm[k + jj * H]; },
+                [&](int i, int jj, double v) { Wr[i + jj * H2] = 0.5 * v - Wr[i + jj * H2]; });
             __syncthreads();
-            // ---- diagonal block: B += U V_R^T + V_R U^T (lower part)
-            for (int idx = t; idx < H2 * H2; idx += NT) {
-                const int r = idx % H2, c = idx / H2;
-                if (r >= c && r < nr) {
-                    double acc = Db[idx];
-                    for (int k = 0; k < H; ++k)
-                        acc += Qb[r + k * H2] * Wr[c + k * H2] + Wr[r + k * H2] * Qb[c + k * H2];
-                    bput(band, ldb, o + r, o + c, acc);
-                }
-            }
+            // ---- diagonal block: B += [U, V_R] [V_R, U]^T (lower part)
+            block_gemm<H2, H2, H2, TL::MM_M, TL::MM_N, NT>(
+                t, [&](int i, int k) -> double { return (k < H) ? Qb[i + k * H2] : Wr[i + (k - H) * H2]; },
+                [&](int k, int jj) -> double { return (k < H) ? Wr[jj + k * H2] : Qb[jj + (k - H) * H2]; },
+                [&](int i, int jj, double v) {
+                    if (i >= jj && i < nr) bput(band, ldb, o + i, o + jj, Db[i + jj * H2] + v);
+                });
             __syncthreads();
-            // ---- left block (j > 1): B[qr, o-h:o] -= U (X^T Y)^T
+            // ---- left block (j > 1): X -= U (X^T Y)^T
             if (j > 1) {
                 for (int idx = t; idx < H2 * H; idx += NT) {
                     const int r = idx % H2, c = idx / H2;
                     Xb[idx] = (r < nr) ? bget(band, ldb, o + r, o - H + c) : 0.0;
                 }
                 __syncthreads();
-                for (int idx = t; idx < H * H; idx += NT) {
-                    const int c = idx % H, k = idx / H;   // W_L[c][k]
-                    double acc = 0.0;
-                    for (int r = 0; r < H2; ++r) acc += Xb[r + c * H2] * Yb[r + k * H2];
-                    Mm[c + k * H] = acc;
-                }
+                block_gemm<H, H, H2, TL::HH_M, TL::HH_N, NT>(
+                    t, [&](int c, int r) -> double { return Xb[r + c * H2]; },
+                    [&](int r, int k) -> double { return Yb[r + k * H2]; },
+                    [&](int c, int k, double v) { Mm[c + k * H] = v; });
                 __syncthreads();
-                for (int idx = t; idx < H2 * H; idx += NT) {
-                    const int r = idx % H2, c = idx / H2;
-                    if (r < nr) {
-                        double acc = Xb[idx];
-                        for (int k = 0; k < H; ++k) acc -= Qb[r + k * H2] * Mm[c + k * H];
-                        bput(band, ldb, o + r, o - H + c, acc);
-                    }
-                }
+                block_gemm<H2, H, H, TL::MH_M, TL::MH_N, NT>(
+                    t, U, [&](int k, int c) -> double { return Mm[c + k * H]; },
+                    [&](int i, int c, double v) {
+                        if (i < nr) bput(band, ldb, o + i, o - H + c, Xb[i + c * H2] - v);
+                    });
                 __syncthreads();
             }
-            // ---- below block: B[o+b:o+2b, qr] -= (X Y) U^T
+            // ---- below block: X -= (X Y) U^T
             if (nbr > 0) {
                 for (int idx = t; idx < H2 * H2; idx += NT) {
                     const int r = idx % H2, c = idx / H2;
                     Xb[idx] = (r < nbr) ? bget(band, ldb, o + H2 + r, o + c) : 0.0;
                 }
                 __syncthreads();
-                for (int idx = t; idx < H2 * H; idx += NT) {
-                    const int r = idx % H2, k = idx / H2;
-                    double acc = 0.0;
-                    for (int c = 0; c < H2; ++c) acc += Xb[r + c * H2] * Yb[c + k * H2];
-                    Wr[idx] = acc;
-                }
+                block_gemm<H2, H, H2, TL::MH_M, TL::MH_N, NT>(
+                    t, [&](int i, int c) -> double { return Xb[i + c * H2]; },
+                    [&](int c, int k) -> double { return Yb[c + k * H2]; },
+                    [&](int i, int k, double v) { Wr[i + k * H2] = v; });
                 __syncthreads();
-                for (int idx = t; idx < H2 * H2; idx += NT) {
-                    const int r = idx % H2, c = idx / H2;
-                    if (r < nbr) {
-                        double acc = Xb[idx];
-                        for (int k = 0; k < H; ++k) acc -= Wr[r + k * H2] * Qb[c + k * H2];
-                        bput(band, ldb, o + H2 + r, o + c, acc);
-                    }
-                }
+                block_gemm<H2, H2, H, TL::MM_M, TL::MM_N, NT>(
+                    t, [&](int i, int k) -> double { return Wr[i + k * H2]; },
+                    [&](int k, int c) -> double { return Qb[c + k * H2]; },
+                    [&](int i, int c, double v) {
+                        if (i < nbr) bput(band, ldb, o + H2 + i, o + c, Xb[i + c * H2] - v);
+                    });
             }
             // ---- publish
             __threadfence();
@@ -482,6 +470,10 @@ int64_t chase_flag_ints(int64_t n, int b) {
 void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch, int* flags,
                        int* error, int max_grid, hipStream_t s) {
     (void)f32;
+    if (band_group_supported(b) && ldband == 2 * b + 1) {
+        launch_band_halve_group(n, band, ldband, b, flags, error, max_grid, s);
+        return;
+    }
     switch (b) {
         case 2: launch_chase<1>(n, band, ldband, scratch, flags, error, max_grid, s); break;
         case 4: launch_chase<2>(n, band, ldband, scratch, flags, error, max_grid, s); break;

@@ -105,3 +105,57 @@ __device__ __forceinline__ int sbr_load_acquire(const int* p) {
 __device__ __forceinline__ void sbr_store_release(int* p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// Move a double across lanes with a DPP control (two 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the TPC lanes of an aligned group (TPC in {2, 4, 8}):
+// quad_perm(1,0,3,2) = lane ^ 1, quad_perm(2,3,0,1) = lane ^ 2,
+// row_half_mirror = lane i <-> 7 - i inside each 8-lane half row.
+template <int TPC>
+__device__ __forceinline__ double group_sum(double v) {
+    static_assert(TPC == 2 || TPC == 4 || TPC == 8, "group size");
+    v += dpp_d<0xB1>(v);
+    if (TPC >= 4) v += dpp_d<0x4E>(v);
+    if (TPC >= 8) v += dpp_d<0x141>(v);
+    return v;
+}
+
+// Small dense product done cooperatively by NT threads: every output
+// (i, j) in [0, M) x [0, N) gets sum_{k < K} A(i, k) B(k, j), handed to
+// store(i, j, value).  Each thread computes RM x RN register blocks, so an
+// operand element read from memory feeds RN (or RM) fused multiply-adds.
+template <int M, int N, int K, int RM, int RN, int NT, class FA, class FB, class FS>
+__device__ __forceinline__ void block_gemm(int t, const FA& A, const FB& B, const FS& store) {
+    static_assert(M % RM == 0 && N % RN == 0, "register block must divide the product");
+    constexpr int BM = M / RM, NB = BM * (N / RN);
+    for (int blk = t; blk < NB; blk += NT) {
+        const int i0 = (blk % BM) * RM, j0 = (blk / BM) * RN;
+        double acc[RM][RN];
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+#pragma unroll
+            for (int c = 0; c < RN; ++c) acc[r][c] = 0.0;
+#pragma unroll 4
+        for (int k = 0; k < K; ++k) {
+            double av[RM], bv[RN];
+#pragma unroll
+            for (int r = 0; r < RM; ++r) av[r] = A(i0 + r, k);
+#pragma unroll
+            for (int c = 0; c < RN; ++c) bv[c] = B(k, j0 + c);
+#pragma unroll
+            for (int r = 0; r < RM; ++r)
+#pragma unroll
+                for (int c = 0; c < RN; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+        }
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+#pragma unroll
+            for (int c = 0; c < RN; ++c) store(i0 + r, j0 + c, acc[r][c]);
+    }
+}

@@ -73,6 +73,11 @@ int64_t chase_flag_ints(int64_t n, int b);
 void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch,
                        int* flags, int* error, int max_grid, hipStream_t s);
 void launch_fill_int(int* p, int64_t count, int v, hipStream_t s);
+// ---- sbr_band_group.hip: small bandwidths, sweep groups with LDS windows --
+bool band_group_supported(int b);
+void launch_band_halve_group(int64_t n, double* band, int64_t ldband, int b, int* flags, int* error, int max_grid,
+                             hipStream_t s);
+int init_band_group_attributes();
 void launch_band_to_tridiag(int64_t n, const double* band, int64_t ldband, double* d, double* e,
                             hipStream_t s);
 int init_band_attributes();

@@ -93,25 +93,6 @@ struct GroupQR {
     static constexpr int NACC = RPT >= 4 ? 4 : RPT;   // independent partial sums
 };
 
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-
-// Sum over the TPC lanes of a group (TPC in {2, 4, 8}, groups aligned):
-// quad_perm(1,0,3,2) = lane ^ 1, quad_perm(2,3,0,1) = lane ^ 2,
-// row_half_mirror = lane i <-> 7 - i inside each 8-lane half row.
-template <int TPC>
-__device__ __forceinline__ double group_sum(double v) {
-    static_assert(TPC == 2 || TPC == 4 || TPC == 8, "group size");
-    v += dpp_d<0xB1>(v);
-    if (TPC >= 4) v += dpp_d<0x4E>(v);
-    if (TPC >= 8) v += dpp_d<0x141>(v);
-    return v;
-}
-
 template <int RPT, int NACC>
 __device__ __forceinline__ double dot_rows(const double* x, const double* v, int s, int tpc) {
     double acc[NACC];
