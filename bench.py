@@ -173,9 +173,9 @@ def main():
     syr2k_ms = mean([t["ms_syr2k"] for t in tims])
     symm_ms = mean([t["ms_symm"] for t in tims])
     if syr2k_ms >= symm_ms:
-        kname, kflops, kms, klaunch = "syr2k_lower_kernel<double,64,2,2>", sum(syr2k_f), syr2k_ms, len(syr2k_f)
+        kname, kflops, kms, klaunch = "syr2k_lower_kernel<double,128,2,4>", sum(syr2k_f), syr2k_ms, len(syr2k_f)
     else:
-        kname, kflops, kms, klaunch = "symm_lower_kernel<double,64,128,2,2>", sum(symm_f), symm_ms, len(symm_f)
+        kname, kflops, kms, klaunch = "symm_lower_kernel<double,128,128,2,4>", sum(symm_f), symm_ms, len(symm_f)
     achieved = kflops / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
     stage_ms = [mean([t["ms_stage"][i] for t in tims]) for i in range(len(tims[0]["ms_stage"]))]
     stages = []
@@ -205,6 +205,10 @@ def main():
                    "n": n, "b0": b0},
         "s_per_solve": round(ms_per_step / 1e3, 4),
         "phases_ms": {"f2b": round(f2b_ms, 3), "band": round(band_ms, 3), "bisect": round(bis_ms, 3)},
+        "f2b_kernels_ms": {"symm": round(symm_ms, 3), "syr2k": round(syr2k_ms, 3),
+                           "symm_TFLOPs": round(sum(symm_f) / (symm_ms * 1e-3) / 1e12, 2) if symm_ms > 0 else None,
+                           "syr2k_TFLOPs": round(sum(syr2k_f) / (syr2k_ms * 1e-3) / 1e12, 2) if syr2k_ms > 0 else None,
+                           "panel_and_other": round(f2b_ms - symm_ms - syr2k_ms, 3)},
         "band_stages": stages,
         "band_GBps_alg": round(band_bytes / (band_ms * 1e-3) / 1e9, 1) if band_ms > 0 else None,
         "checks": {"trace_rel": tr_err, "frobenius_rel": fr_err},

@@ -52,6 +52,11 @@ struct sbr_plan_s {
     size_t ws_bytes = 0;
     // carved pointers
     double *Q = nullptr, *U = nullptr, *Y = nullptr, *W = nullptr, *V = nullptr;
+    double* Ub[2] = {nullptr, nullptr};   // U of the current and of the next panel
+    // panel lookahead: the next panel is factored on `side` while the bulk
+    // of the current trailing update runs on the caller's stream
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double *part = nullptr;
     int64_t part_doubles = 0;
     double *T = nullptr, *W1inv = nullptr, *Mm = nullptr, *Zm = nullptr, *S = nullptr;
@@ -122,7 +127,7 @@ Layout make_layout(int64_t n, int b) {
     L.part_doubles = part;
     size_t cur = 0;
     L.off_Q = take(cur, nb * D);
-    L.off_U = take(cur, nb * D);
+    L.off_U = take(cur, 2 * nb * D);
     L.off_Y = take(cur, nb * D);
     L.off_W = take(cur, nb * D);
     L.off_V = take(cur, nb * D);
@@ -171,6 +176,8 @@ int ensure_workspace(sbr_plan_t p, int64_t n, int b) {
     char* base = (char*)ws;
     p->Q = (double*)(base + L.off_Q);
     p->U = (double*)(base + L.off_U);
+    p->Ub[0] = p->U;
+    p->Ub[1] = p->U + nn * bb;
     p->Y = (double*)(base + L.off_Y);
     p->W = (double*)(base + L.off_W);
     p->V = (double*)(base + L.off_V);
@@ -219,15 +226,15 @@ void factor_block(sbr_plan_t p, int64_t m, int bw, double* P, int64_t ldp, doubl
     launch_panel_writeback(m, bw, P, ldp, tsqr_root_r(tr), S, s);
 }
 
-void factor_panel(sbr_plan_t p, int64_t m, int b, double* P, int64_t ldp, hipStream_t s) {
+void factor_panel(sbr_plan_t p, int64_t m, int b, double* P, int64_t ldp, double* U, hipStream_t s) {
     const int64_t ldq = p->n_cap;
     if (b <= TSQR_MAX_B) {
-        factor_block(p, m, b, P, ldp, p->U, p->T, b, p->S, s);
+        factor_block(p, m, b, P, ldp, U, p->T, b, p->S, s);
         return;
     }
     const int h = b / 2;
-    double* UL = p->U;
-    double* UR = p->U + (int64_t)h * ldq;
+    double* UL = U;
+    double* UR = U + (int64_t)h * ldq;
     double* C = P + (int64_t)h * ldp;                 // right half of the panel
     // left half
     factor_block(p, m, h, P, ldp, UL, p->T, b, p->S, s);
@@ -249,18 +256,36 @@ void factor_panel(sbr_plan_t p, int64_t m, int b, double* P, int64_t ldp, hipStr
     launch_zero_block(h, h, p->T + h, b, s);          // T21 = 0
 }
 
+int ensure_side_stream(sbr_plan_t p) {
+    if (p->side) return 0;
+    hipError_t e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+    return e == hipSuccess ? 0 : hip_fail(e);
+}
+
+// Panel k (columns c0 .. c0+b-1, rows below the band) and its trailing
+// update.  The update of panel k's trailing matrix is split: the columns of
+// panel k+1 first, then the rest.  Panel k+1 is factored on the side stream
+// as soon as its columns are final, concurrently with the rest of the update
+// (which touches neither those columns nor the buffers the factorization
+// writes); the caller's stream waits for it before the next W = A22 Y.
 int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, bool f32, hipStream_t s) {
     const int64_t ldq = p->n_cap;
     int64_t k = 0;
+    int cur = 0;
+    if (n - b >= b) {
+        const int rc = ensure_side_stream(p);
+        if (rc) return rc;
+        factor_panel(p, n - b, b, A + b, lda, p->Ub[0], s);
+        launch_gemm(false, false, false, n - b, b, b, 1.0, p->Ub[0], ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, s);
+    }
     for (;; ++k) {
         const int64_t c0 = k * b, r0 = c0 + b, m = n - r0;
         if (m < b) break;
-        double* P = A + r0 + c0 * lda;
+        double* U = p->Ub[cur];
         double* A22 = A + r0 + r0 * lda;
-        factor_panel(p, m, b, P, lda, s);
-        // Y = U T
-        launch_gemm(false, false, false, m, b, b, 1.0, p->U, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, s);
-        // W = A22 Y
+        // W = A22 Y  (Y = U T)
         EventPair ep;
         if (p->timing) { ep.a = p->ev(); p->mark(ep.a, s); }
         const int ss = symm_splits(m, b);
@@ -268,15 +293,33 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
         if (p->timing) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_symm.push_back(ep); }
         // Z = U^T W ; M = T^T Z ; V = 1/2 U M - W
         const int gs = gemm_splits(b, b, m);
-        launch_gemm_splitk(false, true, false, b, b, m, 1.0, p->U, ldq, p->W, ldq, 0.0, nullptr, 0, p->Zm, b,
+        launch_gemm_splitk(false, true, false, b, b, m, 1.0, U, ldq, p->W, ldq, 0.0, nullptr, 0, p->Zm, b,
                            p->part, gs, s);
         launch_gemm(false, true, false, b, b, b, 1.0, p->T, b, p->Zm, b, 0.0, nullptr, 0, p->Mm, b, s);
-        launch_gemm(false, false, false, m, b, b, 0.5, p->U, ldq, p->Mm, b, -1.0, p->W, ldq, p->V, ldq, s);
+        launch_gemm(false, false, false, m, b, b, 0.5, U, ldq, p->Mm, b, -1.0, p->W, ldq, p->V, ldq, s);
         // A22 += U V^T + V U^T
         EventPair eq;
         if (p->timing) { eq.a = p->ev(); p->mark(eq.a, s); }
-        launch_syr2k_lower(f32, m, b, p->U, ldq, p->V, ldq, A22, lda, s);
-        if (p->timing) { eq.b = p->ev(); p->mark(eq.b, s); p->ev_syr2k.push_back(eq); }
+        const int64_t mn = m - b;          // rows of the next panel
+        if (mn >= b) {
+            launch_syr2k_lower_cols(f32, m, b, b, U, ldq, p->V, ldq, A22, lda, s);
+            hipError_t e = hipEventRecord(p->ev_fork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+            if (e != hipSuccess) return hip_fail(e);
+            double* Un = p->Ub[cur ^ 1];
+            factor_panel(p, mn, b, A22 + b, lda, Un, p->side);
+            launch_gemm(false, false, false, mn, b, b, 1.0, Un, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, p->side);
+            e = hipEventRecord(p->ev_join, p->side);
+            if (e != hipSuccess) return hip_fail(e);
+            launch_syr2k_lower(f32, mn, b, U + b, ldq, p->V + b, ldq, A22 + b + b * lda, lda, s);
+            if (p->timing) { eq.b = p->ev(); p->mark(eq.b, s); p->ev_syr2k.push_back(eq); }
+            e = hipStreamWaitEvent(s, p->ev_join, 0);
+            if (e != hipSuccess) return hip_fail(e);
+            cur ^= 1;
+        } else {
+            launch_syr2k_lower(f32, m, b, U, ldq, p->V, ldq, A22, lda, s);
+            if (p->timing) { eq.b = p->ev(); p->mark(eq.b, s); p->ev_syr2k.push_back(eq); }
+        }
         SBR_CHECK_LAUNCH();
     }
     const int64_t c0 = k * b, r0 = c0 + b, m = n - r0;
@@ -368,6 +411,9 @@ int sbr_plan_create(sbr_plan_t* plan, int64_t n_max, int32_t batch_max, sbr_prec
 int sbr_plan_destroy(sbr_plan_t plan) {
     if (!plan) return -1;
     for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
+    if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+    if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
+    if (plan->side) (void)hipStreamDestroy(plan->side);
     if (plan->ws) (void)hipFree(plan->ws);
     delete plan;
     return 0;

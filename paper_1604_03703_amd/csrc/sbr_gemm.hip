@@ -112,23 +112,41 @@ __global__ void reduce_slices_kernel(int64_t M, int64_t N, int splits, const dou
     Cout[i + j * ldco] = v;
 }
 
-// Lower triangle of C (m x m) += U V^T + V U^T; one block per lower tile pair
-// (I >= J).  The two products are one GEMM with K' = 2K:
-// [U_I, V_I] * [V_J, U_J]^T.
+// Blocks are dealt round-robin to the 8 XCDs (block x runs on XCD x mod 8).
+// Renumber them so that each XCD works on a contiguous range of logical
+// tiles: neighbouring tiles share operand rows, which then stay in that
+// XCD's L2.
+__device__ __forceinline__ int64_t xcd_logical_tile(int64_t x, int64_t ntiles) {
+    const int64_t q = ntiles / 8, r = ntiles % 8, k = x % 8;
+    return k * q + (k < r ? k : r) + x / 8;
+}
+
+// Lower triangle of C (m x m) += U V^T + V U^T, restricted to the columns
+// j < nc; one block per lower tile pair (I >= J).  The two products are one
+// GEMM with K' = 2K: [U_I, V_I] * [V_J, U_J]^T.  jt = 0: all lower tiles,
+// enumerated triangularly (nc = m); jt > 0: the first jt tile columns,
+// enumerated row by row.  Double-buffered LDS, one barrier per K chunk.
 template <typename CT, int BM, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
-    int64_t m, int64_t K, const double* __restrict__ U, int64_t ldu,
-    const double* __restrict__ V, int64_t ldv, double* C, int64_t ldc) {
+    int64_t m, int64_t nc, int64_t jt, int64_t K, const double* __restrict__ U, int64_t ldu,
+    const double* __restrict__ V, int64_t ldv, double* C, int64_t ldc, int64_t ntiles) {
     typedef TileEngine<CT, BM, BM, WM, WN> E;
     typedef TileMap<BM, E::NT, false> MA;   // row fastest (column-major U, V)
     typedef TileMap<BM, E::NT, false> MB;
-    __shared__ CT As[SBR_BK * E::LDA];
-    __shared__ CT Bs[SBR_BK * E::LDB];
-    const int64_t x = blockIdx.x;
-    int64_t I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-    while (I * (I + 1) / 2 > x) --I;
-    while ((I + 1) * (I + 2) / 2 <= x) ++I;
-    const int64_t J = x - I * (I + 1) / 2;
+    __shared__ CT As[2][SBR_BK * E::LDA];
+    __shared__ CT Bs[2][SBR_BK * E::LDB];
+    const int64_t x = xcd_logical_tile(blockIdx.x, ntiles);
+    int64_t I, J;
+    if (jt == 0) {
+        I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+        while (I * (I + 1) / 2 > x) --I;
+        while ((I + 1) * (I + 2) / 2 <= x) ++I;
+        J = x - I * (I + 1) / 2;
+    } else {
+        I = x / jt;
+        J = x % jt;
+        if (J > I) return;   // whole block: above the diagonal
+    }
     const int64_t i0 = I * BM, j0 = J * BM;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave % WM, wn = wave / WM;
@@ -156,32 +174,31 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
             rb[e] = (CT)v;
         }
     };
-    auto store = [&]() {
+    auto store = [&](int buf) {
 #pragma unroll
         for (int e = 0; e < MA::E; ++e) {
             int i, k;
             MA::coords(t, e, i, k);
-            As[k * E::LDA + i] = ra[e];
+            As[buf][k * E::LDA + i] = ra[e];
         }
 #pragma unroll
         for (int e = 0; e < MB::E; ++e) {
             int j, k;
             MB::coords(t, e, j, k);
-            Bs[k * E::LDB + j] = rb[e];
+            Bs[buf][k * E::LDB + j] = rb[e];
         }
     };
+    const int64_t nch = (K2 + SBR_BK - 1) / SBR_BK;
     load(0);
-    store();
+    store(0);
     __syncthreads();
-    for (int64_t k0 = 0; k0 < K2; k0 += SBR_BK) {
-        const bool more = k0 + SBR_BK < K2;
-        if (more) load(k0 + SBR_BK);
-        eng.chunk(As, Bs, wm, wn, lane);
+    for (int64_t c = 0; c < nch; ++c) {
+        const int cur = (int)(c & 1);
+        const bool more = c + 1 < nch;
+        if (more) load((c + 1) * SBR_BK);
+        eng.chunk(As[cur], Bs[cur], wm, wn, lane);
+        if (more) store(cur ^ 1);     // that buffer was last read before the previous barrier
         __syncthreads();
-        if (more) {
-            store();
-            __syncthreads();
-        }
     }
 #pragma unroll
     for (int tn = 0; tn < E::TN; ++tn)
@@ -191,14 +208,14 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = i0 + E::row_of(wm, tm, lane);
                 const int64_t j = j0 + E::col_of(wn, tn, lane, r);
-                if (i < m && j <= i) C[i + j * ldc] += (double)eng.acc[tn][tm][r];
+                if (i < m && j <= i && j < nc) C[i + j * ldc] += (double)eng.acc[tn][tm][r];
             }
 }
 
 // W (m x nb) = A Y with A symmetric, lower triangle stored.  A K-chunk of
 // the A tile lies entirely below the diagonal (read A[i + k lda], rows
 // contiguous), entirely above it (read the mirror A[k + i lda], k
-// contiguous) or straddles it (element-wise choice).
+// contiguous) or straddles it (element-wise choice).  Double-buffered LDS.
 template <typename CT, int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void symm_lower_kernel(
     int64_t m, int64_t nb, int64_t kchunk, const double* __restrict__ A, int64_t lda,
@@ -208,8 +225,8 @@ __global__ __launch_bounds__(64 * WM * WN) void symm_lower_kernel(
     typedef TileMap<BM, E::NT, true> MAk;    // k fastest
     typedef TileMap<BN, E::NT, true> MB;     // Y[k + j ldy]: k contiguous
     static_assert(MAi::E == MAk::E, "maps");
-    __shared__ CT As[SBR_BK * E::LDA];
-    __shared__ CT Bs[SBR_BK * E::LDB];
+    __shared__ CT As[2][SBR_BK * E::LDA];
+    __shared__ CT Bs[2][SBR_BK * E::LDB];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave % WM, wn = wave / WM;
     const int64_t i0 = (int64_t)blockIdx.x * BM, j0 = (int64_t)blockIdx.y * BN;
@@ -240,33 +257,32 @@ __global__ __launch_bounds__(64 * WM * WN) void symm_lower_kernel(
             rb[e] = (CT)v;
         }
     };
-    auto store = [&]() {
+    auto store = [&](int buf) {
 #pragma unroll
         for (int e = 0; e < MAi::E; ++e) {
             int i, k;
             if (kfast) MAk::coords(t, e, i, k); else MAi::coords(t, e, i, k);
-            As[k * E::LDA + i] = ra[e];
+            As[buf][k * E::LDA + i] = ra[e];
         }
 #pragma unroll
         for (int e = 0; e < MB::E; ++e) {
             int j, k;
             MB::coords(t, e, j, k);
-            Bs[k * E::LDB + j] = rb[e];
+            Bs[buf][k * E::LDB + j] = rb[e];
         }
     };
     if (kbeg < kend) {
+        const int64_t nch = (kend - kbeg + SBR_BK - 1) / SBR_BK;
         load(kbeg);
-        store();
+        store(0);
         __syncthreads();
-        for (int64_t k0 = kbeg; k0 < kend; k0 += SBR_BK) {
-            const bool more = k0 + SBR_BK < kend;
-            if (more) load(k0 + SBR_BK);     // sets the map the registers are stored with
-            eng.chunk(As, Bs, wm, wn, lane);
+        for (int64_t c = 0; c < nch; ++c) {
+            const int cur = (int)(c & 1);
+            const bool more = c + 1 < nch;
+            if (more) load(kbeg + (c + 1) * SBR_BK);   // sets the map the registers are stored with
+            eng.chunk(As[cur], Bs[cur], wm, wn, lane);
+            if (more) store(cur ^ 1);
             __syncthreads();
-            if (more) {
-                store();
-                __syncthreads();
-            }
         }
     }
     double* Wo = W + (int64_t)blockIdx.z * slice_stride;
@@ -319,8 +335,13 @@ template <typename CT>
 void symm_dispatch(int64_t m, int64_t nb, int64_t kchunk, int splits, const double* A, int64_t lda,
                    const double* Y, int64_t ldy, double* W, int64_t ldw, int64_t slice_stride, hipStream_t s) {
     if (nb > 64) {
-        dim3 g(cdiv(m, 64), cdiv(nb, 128), splits);
-        symm_lower_kernel<CT, 64, 128, 2, 2><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+        if (m >= 2048) {
+            dim3 g(cdiv(m, 128), cdiv(nb, 128), splits);
+            symm_lower_kernel<CT, 128, 128, 2, 4><<<g, 512, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+        } else {
+            dim3 g(cdiv(m, 64), cdiv(nb, 128), splits);
+            symm_lower_kernel<CT, 64, 128, 2, 2><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+        }
     } else if (nb > 32) {
         dim3 g(cdiv(m, 64), cdiv(nb, 64), splits);
         symm_lower_kernel<CT, 64, 64, 2, 2><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
@@ -378,16 +399,39 @@ void launch_gemm_splitk(bool f32, bool ta, bool tb, int64_t M, int64_t N, int64_
 void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t ldu, const double* V,
                         int64_t ldv, double* C, int64_t ldc, hipStream_t s) {
     if (m <= 0 || K <= 0) return;
+    // 128 x 128 tiles on 8 waves (each wave 64 x 32) once there are enough
+    // of them to fill the chip; 64 x 64 tiles on 4 waves below that
+    const int64_t T128 = (m + 127) / 128;
+    if (T128 * (T128 + 1) / 2 >= 512) {
+        const int64_t nt = T128 * (T128 + 1) / 2;
+        if (f32) syr2k_lower_kernel<float, 128, 2, 4><<<(unsigned)nt, 512, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
+        else syr2k_lower_kernel<double, 128, 2, 4><<<(unsigned)nt, 512, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
+        return;
+    }
     const int64_t T = (m + 63) / 64;
-    const int64_t blocks = T * (T + 1) / 2;
-    if (f32) syr2k_lower_kernel<float, 64, 2, 2><<<(unsigned)blocks, 256, 0, s>>>(m, K, U, ldu, V, ldv, C, ldc);
-    else syr2k_lower_kernel<double, 64, 2, 2><<<(unsigned)blocks, 256, 0, s>>>(m, K, U, ldu, V, ldv, C, ldc);
+    const int64_t nt = T * (T + 1) / 2;
+    if (f32) syr2k_lower_kernel<float, 64, 2, 2><<<(unsigned)nt, 256, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
+    else syr2k_lower_kernel<double, 64, 2, 2><<<(unsigned)nt, 256, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
+}
+
+void launch_syr2k_lower_cols(bool f32, int64_t m, int64_t nc, int64_t K, const double* U, int64_t ldu,
+                             const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s) {
+    if (m <= 0 || K <= 0 || nc <= 0) return;
+    if (nc > m) nc = m;
+    // a tall column block: 64 x 64 tiles for more blocks in flight
+    const int64_t T = (m + 63) / 64, jt = (nc + 63) / 64;
+    const int64_t nt = T * jt;
+    if (f32) syr2k_lower_kernel<float, 64, 2, 2><<<(unsigned)nt, 256, 0, s>>>(m, nc, jt, K, U, ldu, V, ldv, C, ldc, nt);
+    else syr2k_lower_kernel<double, 64, 2, 2><<<(unsigned)nt, 256, 0, s>>>(m, nc, jt, K, U, ldu, V, ldv, C, ldc, nt);
 }
 
 int symm_splits(int64_t m, int64_t nb) {
-    const int64_t tiles = ((m + 63) / 64) * ((nb + 127) / 128);
+    // split the reduction over A22's columns until about 1024 blocks are in
+    // flight, keeping at least 1024 columns per slice
+    const int64_t bm = (nb > 64 && m >= 2048) ? 128 : 64;
+    const int64_t tiles = ((m + bm - 1) / bm) * ((nb + 127) / 128);
     int64_t splits = 1;
-    while (tiles * splits < 1024 && m / (splits * 2) >= 1024) splits *= 2;
+    while (tiles * splits < 1024 && m / (splits * 2) >= 1024 && splits < 16) splits *= 2;
     return (int)splits;
 }
 

@@ -17,6 +17,9 @@ void launch_gemm_splitk(bool f32, bool ta, bool tb, int64_t M, int64_t N, int64_
                         int splits, hipStream_t s);
 void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t ldu, const double* V,
                         int64_t ldv, double* C, int64_t ldc, hipStream_t s);
+// The columns j < nc of the same update (all rows, lower triangle only).
+void launch_syr2k_lower_cols(bool f32, int64_t m, int64_t nc, int64_t K, const double* U, int64_t ldu,
+                             const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s);
 int symm_splits(int64_t m, int64_t nb);
 void launch_symm_lower(bool f32, int64_t m, int64_t nb, const double* A, int64_t lda, const double* Y,
                        int64_t ldy, double* W, int64_t ldw, double* part, int splits, hipStream_t s);
