@@ -362,6 +362,7 @@ int init_attributes() {
     int rc = init_tsqr_attributes();
     rc |= init_band_attributes();
     rc |= init_band_group_attributes();
+    rc |= init_band_mfma_attributes();
     return rc;
 }
 

@@ -246,8 +246,7 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
                         const int row = qs + TPCQ * r;
                         const double vv = (row < k) ? 0.0 : ((row == k) ? 1.0 : x[r] * scal);
                         v[row] = vv;
-                        if (row == k) x[r] = beta;
-                        else if (row > k) x[r] = vv;
+                        x[r] = (row == k) ? beta : ((row > k) ? vv : x[r]);   // selects, no branches
                     }
                     if (qs == 0) tau[k] = tk;
                 }
@@ -453,12 +452,9 @@ void launch_band_copy(int64_t n, const double* src, int64_t ldsrc, int keep, dou
 int64_t chase_workspace_doubles(int64_t n, int b, int* grid_out) {
     int64_t per = 0;
     int grid = 1;
-    switch (b) {
-        case 128: per = ChaseLayout<64>::TOTAL; grid = chase_grid<64>(n); break;
-        default: per = 0; break;
-    }
+    (void)per;
     if (grid_out) *grid_out = grid;
-    return per * grid;
+    return band_mfma_workspace_doubles(n, b);
 }
 
 int64_t chase_flag_ints(int64_t n, int b) {
@@ -472,6 +468,10 @@ void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32,
     (void)f32;
     if (band_group_supported(b) && ldband == 2 * b + 1) {
         launch_band_halve_group(n, band, ldband, b, flags, error, max_grid, s);
+        return;
+    }
+    if (band_mfma_supported(b)) {
+        launch_band_halve_mfma(n, band, ldband, b, scratch, flags, error, max_grid, s);
         return;
     }
     switch (b) {

@@ -1,0 +1,504 @@
+// sbr_chase_mfma.hip -- one halving b -> h = b/2 of the band (Algorithm 4.2
+// with k = 2) for b in {32, 64, 128}, every product of a chase on FP64 MFMA.
+//
+// A chase (i, j) works on the rows [o, o + n_r) of the band, o = ih + (j-1)b
+// (the same offsets, extents and pipelined schedule as the small-b kernels:
+// chase (i, j) starts after chase (i, j-1) of the same block and after sweep
+// i-1 has finished chase j + 2).  With [U, T, R] = QR(QR block) and
+// Q = I - U T U^T:
+//   left block  X_L  (rows [o, o+n_r), cols [o-h, o), j > 1):  X_L <- Q^T X_L
+//   below block X_B  (rows [o+b, o+2b), cols [o, o+n_r)):      X_B <- X_B Q
+//   diagonal    D    (rows and cols [o, o+n_r), symmetric):    D   <- Q^T D Q
+// computed as
+//   X_L -= (U T^T)(U^T X_L)
+//   X_B -= ((X_B U) T) U^T
+//   W = (D U) T,  G = U^T W,  V = 1/2 (U T^T) G - W,  D += U V^T + V U^T.
+// T comes from the identity T^{-1} = diag(1/tau) + strict upper part of U^T U
+// (the compact WY form of a product of reflectors), inverted column by column.
+//
+// Wave w of the block owns the rows [16w, 16w + 16) of every b x h quantity.
+// MFMA 16x16x4 lane layout: with a = R(k0 + l/16, c0 + l%16) and
+// b = L(r0 + l%16, k0 + l/16), accumulator element r of lane l is
+// (L R)(r0 + l%16, c0 + 4r + l/16).  A row tile held this way ("row-in-lane"
+// layout) is, element for element, the b operand of a following product
+// L' R' with L' = that tile; so the chains X_B U -> (.) T -> (.) U^T and
+// D U -> (.) T stay in registers.  Cross-wave quantities (U, T, U^T X_L,
+// U^T W) go through LDS; W goes through LDS (b <= 64) or a per-block global
+// scratch slice (b = 128).
+//
+// The update of D is split in two wave-local phases separated by a barrier:
+// wave w adds V_w U_X^T to its own tiles (w, X <= w), then U_X V_w^T to the
+// tiles (X >= w, w) of its column; every tile is read-modified-written by at
+// most one wave per phase.
+#include "sbr_device.h"
+#include "sbr_internal.h"
+
+namespace {
+
+struct MChaseArgs {
+    int64_t n;
+    double* band;
+    int64_t ldb;
+    int nsweeps;
+    int* ticket;       // one int
+    int* progress;     // nsweeps + 1 ints; progress[i] = chases of sweep i done
+    double* gscratch;  // per-block W slices (b = 128)
+    int64_t scratch_stride;
+    int* error;
+};
+
+// 10 s of the 100 MHz wall clock; only bounds the kernel's lifetime should
+// the schedule's progress guarantee ever be broken.
+constexpr uint64_t MWAIT_LIMIT_TICKS = 1000000000ull;
+constexpr int MSWEEP_DONE = 1 << 30;
+
+template <int H>
+struct MChase {
+    static constexpr int B = 2 * H;
+    static constexpr int NW = B / 16;          // one wave per 16-row tile
+    static constexpr int NT = 64 * NW;
+    static constexpr int RT = B / 16, CT = H / 16;
+    static constexpr int LDU = B + 1, LDH = H + 1;
+    static constexpr bool WR_LDS = H <= 32;
+    // LDS (doubles): U (b x h), T (h x h; QR staging before T exists), one
+    // h x h exchange buffer (L = T^{-1}, then U^T X_L, then U^T W), W (b x h)
+    static constexpr int US = 0;
+    static constexpr int TS = US + LDU * H;
+    static constexpr int RS = TS + LDH * H;
+    static constexpr int WS = RS + LDH * H;
+    static constexpr int TOTAL = WS + (WR_LDS ? B * H : 0);
+    static constexpr int TPCQ = 8, RPT = B / TPCQ;   // QR: 8 lanes per column
+    static_assert(H * TPCQ == NT, "QR layout");
+    static_assert(2 * B + H <= LDH * H, "QR staging fits in the T region");
+};
+
+__device__ __forceinline__ sbr_d4 mma(double a, double b, sbr_d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ sbr_d4 zero4() { return sbr_d4{0.0, 0.0, 0.0, 0.0}; }
+
+template <int H>
+__global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a) {
+    typedef MChase<H> C;
+    constexpr int B = C::B, NW = C::NW, RT = C::RT, CT = C::CT, LDU = C::LDU, LDH = C::LDH;
+    constexpr int TPCQ = C::TPCQ, RPT = C::RPT;
+    extern __shared__ double sm[];
+    double* Us = sm + C::US;
+    double* Ts = sm + C::TS;
+    double* Rs = sm + C::RS;
+    double* vbuf = Ts;            // two reflectors in flight during the QR ...
+    double* tau = Ts + 2 * B;     // ... and the tau, until T is formed
+    double* Wsc = C::WR_LDS ? sm + C::WS : a.gscratch + (int64_t)blockIdx.x * a.scratch_stride;
+    __shared__ int sweep_sh;
+    __shared__ int abort_sh;
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int qc = t / TPCQ, qs = t % TPCQ;
+    const int64_t n = a.n, ldb = a.ldb;
+    double* band = a.band;
+    // band element (r, c), r >= c, of the chase-local rows/cols
+    auto B_at = [&](int64_t r, int64_t c) -> double& { return band[(r - c) + c * ldb]; };
+
+    while (true) {
+        if (t == 0) {
+            const bool failed = __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            sweep_sh = failed ? a.nsweeps + 1 : atomicAdd(a.ticket, 1) + 1;
+            abort_sh = 0;
+        }
+        __syncthreads();
+        const int i = sweep_sh;
+        __syncthreads();
+        if (i > a.nsweeps) break;
+        const int64_t nchase = (n - 2 - (int64_t)i * H) / B + 1;
+        for (int64_t j = 1; j <= nchase; ++j) {
+            if (i > 1) {
+                if (t == 0) {
+                    const int need = (int)(j + 2);
+                    const uint64_t t0 = wall_clock64();
+                    while (__hip_atomic_load(&a.progress[i - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                           need) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            abort_sh = 1;
+                            break;
+                        }
+                        if (wall_clock64() - t0 > MWAIT_LIMIT_TICKS) {
+                            atomicExch(a.error, B);   // the stage (its bandwidth b) that stalled
+                            abort_sh = 1;
+                            break;
+                        }
+                    }
+                }
+                __syncthreads();
+                if (abort_sh) return;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            const int64_t o = (int64_t)i * H + (j - 1) * B;
+            const int nr = (int)((n - o < B) ? (n - o) : B);
+            const int64_t cq = (j == 1) ? o - H : o - B;
+            int64_t nb64 = n - (o + B);
+            if (nb64 > B) nb64 = B;
+            const int nbr = nb64 > 0 ? (int)nb64 : 0;
+
+            // ---- 1. Householder QR of the QR block (rows [o, o+nr), cols
+            // [cq, cq+h)): 8 lanes per column, one barrier per reflector
+            {
+                double x[RPT];
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const int row = qs + TPCQ * r;
+                    x[r] = (row < nr) ? B_at(o + row, cq + qc) : 0.0;
+                }
+                for (int k = 0; k < H; ++k) {
+                    double* v = vbuf + (k & 1) * B;
+                    if (qc == k) {
+                        double ss = 0.0, xk = 0.0;
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) {
+                            const int row = qs + TPCQ * r;
+                            if (row > k) ss += x[r] * x[r];
+                            else if (row == k) xk = x[r];
+                        }
+                        ss = group_sum<TPCQ>(ss);
+                        xk = group_sum<TPCQ>(xk);
+                        double beta, tk, scal;
+                        if (ss == 0.0) {
+                            beta = xk; tk = 0.0; scal = 0.0;
+                        } else {
+                            const double nrm = sqrt(xk * xk + ss);
+                            beta = (xk >= 0.0) ? -nrm : nrm;
+                            tk = (beta - xk) / beta;
+                            scal = 1.0 / (xk - beta);
+                        }
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) {
+                            const int row = qs + TPCQ * r;
+                            const double vv = (row < k) ? 0.0 : ((row == k) ? 1.0 : x[r] * scal);
+                            v[row] = vv;
+                            x[r] = (row == k) ? beta : ((row > k) ? vv : x[r]);   // selects, no branches
+                        }
+                        if (qs == 0) tau[k] = tk;
+                    }
+                    __syncthreads();
+                    if (qc > k) {
+                        const double tk = tau[k];
+                        if (tk != 0.0) {
+                            double d = 0.0;
+#pragma unroll
+                            for (int r = 0; r < RPT; ++r) d += v[qs + TPCQ * r] * x[r];
+                            d = group_sum<TPCQ>(d);
+                            const double f = tk * d;
+#pragma unroll
+                            for (int r = 0; r < RPT; ++r) x[r] -= f * v[qs + TPCQ * r];
+                        }
+                    }
+                }
+                // U (unit lower; a zero column where no reflector was applied)
+                // into LDS, [R; 0] into the band
+                const double tq = tau[qc];
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const int row = qs + TPCQ * r;
+                    double u = 0.0;
+                    if (tq != 0.0) u = (row == qc) ? 1.0 : ((row > qc) ? x[r] : 0.0);
+                    Us[row + qc * LDU] = u;
+                    if (row < nr) B_at(o + row, cq + qc) = (row <= qc) ? x[r] : 0.0;
+                }
+            }
+            __syncthreads();
+
+            // ---- 2. L = T^{-1}: strict upper part of U^T U, tau on the diagonal
+            // (the multiplier that replaces 1/tau below; a zero tau gives a zero
+            // row and column of T)
+            {
+                constexpr int NTL = CT * (CT + 1) / 2;
+                for (int idx = w; idx < NTL; idx += NW) {
+                    int I = 0, rem = idx;
+                    while (rem >= CT - I) { rem -= CT - I; ++I; }
+                    const int J = I + rem;
+                    sbr_d4 acc = zero4();
+#pragma unroll 8
+                    for (int k0 = 0; k0 < B; k0 += 4)
+                        acc = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int gi = I * 16 + li, gj = J * 16 + 4 * r + lk;
+                        Rs[gi + gj * LDH] = (gi < gj) ? acc[r] : ((gi == gj) ? tau[gi] : 0.0);
+                    }
+                }
+            }
+            __syncthreads();
+
+            // ---- 3. T by columns: T[j][j] = tau_j, T[i][j] = -tau_i sum_{i<k<=j}
+            // L[i][k] T[k][j] for i = j-1 .. 0; 8 lanes per column
+            {
+                const int jc = t >> 3, s = t & 7;
+                const int jmax = ((t >> 6) << 3) + 7;    // last column of this wave
+                if (s == 0) Ts[jc + jc * LDH] = Rs[jc + jc * LDH];
+                for (int r = jc + 1 + s; r < H; r += 8) Ts[r + jc * LDH] = 0.0;
+                for (int r = jmax - 1; r >= 0; --r) {
+                    double p = 0.0;
+                    if (r < jc)
+                        for (int k = r + 1 + s; k <= jc; k += 8) p += Rs[r + k * LDH] * Ts[k + jc * LDH];
+                    p = group_sum<8>(p);
+                    if (r < jc && s == 0) Ts[r + jc * LDH] = -Rs[r + r * LDH] * p;
+                }
+            }
+            __syncthreads();
+
+            // ---- 4. Z_w = U_w T^T (row-in-lane, rows of this wave)
+            sbr_d4 Z[CT];
+#pragma unroll
+            for (int J = 0; J < CT; ++J) {
+                Z[J] = zero4();
+#pragma unroll
+                for (int k0 = J * 16; k0 < H; k0 += 4)      // T^T(k, c) = 0 for k < c
+                    Z[J] = mma(Ts[(J * 16 + li) + (k0 + lk) * LDH], Us[(w * 16 + li) + (k0 + lk) * LDU], Z[J]);
+            }
+
+            // ---- 5. left block (j > 1): M_L = U^T X_L into LDS, then X_L -= Z M_L
+            if (j > 1) {
+                for (int idx = w; idx < CT * CT; idx += NW) {
+                    const int I = idx % CT, J = idx / CT;
+                    const int64_t gc = o - H + J * 16 + li;
+                    sbr_d4 acc = zero4();
+#pragma unroll 4
+                    for (int k0 = 0; k0 < B; k0 += 4) {
+                        const int row = k0 + lk;
+                        const double av = (row < nr) ? B_at(o + row, gc) : 0.0;
+                        acc = mma(av, Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Rs[(I * 16 + li) + (J * 16 + 4 * r + lk) * LDH] = acc[r];
+                }
+                __syncthreads();
+                if (w * 16 < nr) {
+#pragma unroll
+                    for (int J = 0; J < CT; ++J) {
+                        sbr_d4 acc = zero4();
+#pragma unroll
+                        for (int K = 0; K < CT; ++K)
+#pragma unroll
+                            for (int r4 = 0; r4 < 4; ++r4)
+                                acc = mma(Rs[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], Z[K][r4], acc);
+                        const int row = w * 16 + li;
+                        if (row < nr) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) B_at(o + row, o - H + J * 16 + 4 * r + lk) -= acc[r];
+                        }
+                    }
+                }
+            }
+
+            // ---- 6. below block: P = X_B U, W_B = P T, X_B -= W_B U^T
+            if (w * 16 < nbr) {
+                const int row = w * 16 + li;
+                sbr_d4 P[CT];
+#pragma unroll
+                for (int J = 0; J < CT; ++J) P[J] = zero4();
+#pragma unroll 4
+                for (int k0 = 0; k0 < B; k0 += 4) {
+                    const int col = k0 + lk;
+                    const double bv = (row < nbr && col < nr) ? B_at(o + B + row, o + col) : 0.0;
+#pragma unroll
+                    for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
+                }
+                sbr_d4 WB[CT];
+#pragma unroll
+                for (int J = 0; J < CT; ++J) {
+                    WB[J] = zero4();
+#pragma unroll
+                    for (int K = 0; K <= J; ++K)                // T(k, c) = 0 for k > c
+#pragma unroll
+                        for (int r4 = 0; r4 < 4; ++r4)
+                            WB[J] = mma(Ts[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], P[K][r4], WB[J]);
+                }
+                for (int X = 0; X < RT; ++X) {
+                    if (X * 16 >= nr) break;
+                    sbr_d4 acc = zero4();
+#pragma unroll
+                    for (int K = 0; K < CT; ++K)
+#pragma unroll
+                        for (int r4 = 0; r4 < 4; ++r4)
+                            acc = mma(Us[(X * 16 + li) + (K * 16 + 4 * r4 + lk) * LDU], WB[K][r4], acc);
+                    if (row < nbr) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int col = X * 16 + 4 * r + lk;
+                            if (col < nr) B_at(o + B + row, o + col) -= acc[r];
+                        }
+                    }
+                }
+            }
+
+            // ---- 7. diagonal block: W_w = (D_w U) T, to the exchange buffer
+            sbr_d4 WR[CT];
+            {
+                const int row = w * 16 + li;
+                sbr_d4 P[CT];
+#pragma unroll
+                for (int J = 0; J < CT; ++J) P[J] = zero4();
+#pragma unroll 4
+                for (int k0 = 0; k0 < B; k0 += 4) {
+                    const int col = k0 + lk;
+                    double bv = 0.0;
+                    if (row < nr && col < nr) bv = (row >= col) ? B_at(o + row, o + col) : B_at(o + col, o + row);
+#pragma unroll
+                    for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
+                }
+#pragma unroll
+                for (int J = 0; J < CT; ++J) {
+                    WR[J] = zero4();
+#pragma unroll
+                    for (int K = 0; K <= J; ++K)
+#pragma unroll
+                        for (int r4 = 0; r4 < 4; ++r4)
+                            WR[J] = mma(Ts[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], P[K][r4], WR[J]);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Wsc[row + (J * 16 + 4 * r + lk) * B] = WR[J][r];
+                }
+            }
+            __syncthreads();
+
+            // ---- 8. G = U^T W into LDS (the left block is done with it)
+            for (int idx = w; idx < CT * CT; idx += NW) {
+                const int I = idx % CT, J = idx / CT;
+                sbr_d4 acc = zero4();
+#pragma unroll 8
+                for (int k0 = 0; k0 < B; k0 += 4)
+                    acc = mma(Wsc[(k0 + lk) + (J * 16 + li) * B], Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Rs[(I * 16 + li) + (J * 16 + 4 * r + lk) * LDH] = acc[r];
+            }
+            __syncthreads();
+
+            // ---- 9. V_w = 1/2 Z_w G - W_w
+            sbr_d4 V[CT];
+#pragma unroll
+            for (int J = 0; J < CT; ++J) {
+                sbr_d4 acc = zero4();
+#pragma unroll
+                for (int K = 0; K < CT; ++K)
+#pragma unroll
+                    for (int r4 = 0; r4 < 4; ++r4)
+                        acc = mma(Rs[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], Z[K][r4], acc);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) V[J][r] = 0.5 * acc[r] - WR[J][r];
+            }
+
+            // ---- 10. D += V U^T + U V^T, lower triangle: tiles (w, X <= w)
+            // with V_w U_X^T, then tiles (X >= w, w) with U_X V_w^T
+            if (w * 16 < nr) {
+                const int row = w * 16 + li;
+                for (int X = 0; X <= w; ++X) {
+                    sbr_d4 acc = zero4();
+#pragma unroll
+                    for (int K = 0; K < CT; ++K)
+#pragma unroll
+                        for (int r4 = 0; r4 < 4; ++r4)
+                            acc = mma(Us[(X * 16 + li) + (K * 16 + 4 * r4 + lk) * LDU], V[K][r4], acc);
+                    if (row < nr) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int col = X * 16 + 4 * r + lk;
+                            if (col <= row) B_at(o + row, o + col) += acc[r];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            for (int X = w; X < RT; ++X) {
+                if (X * 16 >= nr) break;
+                sbr_d4 acc = zero4();
+#pragma unroll
+                for (int K = 0; K < CT; ++K)
+#pragma unroll
+                    for (int r4 = 0; r4 < 4; ++r4)
+                        acc = mma(V[K][r4], Us[(X * 16 + li) + (K * 16 + 4 * r4 + lk) * LDU], acc);
+                const int row = X * 16 + li;
+                if (row < nr) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int col = w * 16 + 4 * r + lk;
+                        if (col <= row) B_at(o + row, o + col) += acc[r];
+                    }
+                }
+            }
+
+            // ---- publish
+            __threadfence();
+            __syncthreads();
+            if (t == 0) sbr_store_release(&a.progress[i], (j == nchase) ? MSWEEP_DONE : (int)j);
+        }
+    }
+}
+
+template <int H>
+int mchase_grid(int64_t n) {
+    const int64_t nsweeps = (n - 2) / H;
+    const int64_t cap = (H == 64) ? 256 : (H == 32 ? 768 : 1024);
+    int64_t g = nsweeps < cap ? nsweeps : cap;
+    return (int)(g < 1 ? 1 : g);
+}
+
+template <int H>
+void launch_mchase(int64_t n, double* band, int64_t ldb, double* scratch, int* flags, int* error, int max_grid,
+                   hipStream_t s) {
+    const int64_t nsweeps = (n - 2) / H;
+    if (nsweeps < 1) return;
+    typedef MChase<H> C;
+    MChaseArgs a;
+    a.n = n;
+    a.band = band;
+    a.ldb = ldb;
+    a.nsweeps = (int)nsweeps;
+    a.ticket = flags;
+    a.progress = flags + 1;
+    a.gscratch = scratch;
+    a.scratch_stride = (int64_t)C::B * H;
+    a.error = error;
+    sbr::launch_fill_int(flags, nsweeps + 2, 0, s);
+    int grid = mchase_grid<H>(n);
+    if (max_grid > 0 && grid > max_grid) grid = max_grid;
+    chase_mfma_kernel<H><<<grid, C::NT, (size_t)C::TOTAL * sizeof(double), s>>>(a);
+}
+
+template <int H>
+int set_mchase_attr() {
+    const int bytes = MChase<H>::TOTAL * (int)sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void*)chase_mfma_kernel<H>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+}  // namespace
+
+namespace sbr {
+
+bool band_mfma_supported(int b) { return b == 32 || b == 64 || b == 128; }
+
+int64_t band_mfma_workspace_doubles(int64_t n, int b) {
+    if (b != 128) return 0;
+    return (int64_t)mchase_grid<64>(n) * MChase<64>::B * 64;
+}
+
+void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, int* flags,
+                            int* error, int max_grid, hipStream_t s) {
+    switch (b) {
+        case 32: launch_mchase<16>(n, band, ldband, scratch, flags, error, max_grid, s); break;
+        case 64: launch_mchase<32>(n, band, ldband, scratch, flags, error, max_grid, s); break;
+        case 128: launch_mchase<64>(n, band, ldband, scratch, flags, error, max_grid, s); break;
+        default: break;
+    }
+}
+
+int init_band_mfma_attributes() {
+    int rc = 0;
+    rc |= set_mchase_attr<16>();
+    rc |= set_mchase_attr<32>();
+    rc |= set_mchase_attr<64>();
+    return rc;
+}
+
+}  // namespace sbr

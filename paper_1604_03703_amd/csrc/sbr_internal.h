@@ -76,6 +76,12 @@ int64_t chase_flag_ints(int64_t n, int b);
 void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch,
                        int* flags, int* error, int max_grid, hipStream_t s);
 void launch_fill_int(int* p, int64_t count, int v, hipStream_t s);
+// ---- sbr_chase_mfma.hip: b in {32, 64, 128}, chase products on FP64 MFMA --
+bool band_mfma_supported(int b);
+int64_t band_mfma_workspace_doubles(int64_t n, int b);
+void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, int* flags,
+                            int* error, int max_grid, hipStream_t s);
+int init_band_mfma_attributes();
 // ---- sbr_band_group.hip: small bandwidths, sweep groups with LDS windows --
 bool band_group_supported(int b);
 void launch_band_halve_group(int64_t n, double* band, int64_t ldband, int b, int* flags, int* error, int max_grid,

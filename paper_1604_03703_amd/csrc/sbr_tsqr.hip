@@ -157,8 +157,7 @@ __global__ __launch_bounds__(GroupQR<B>::NT) void tsqr_qr_kernel(TsqrLevelArgs a
                 const int row = s + TPC * r;
                 const double vv = (row < k) ? 0.0 : ((row == k) ? 1.0 : x[r] * scal);
                 v[row] = vv;
-                if (row == k) x[r] = beta;
-                else if (row > k) x[r] = vv;
+                x[r] = (row == k) ? beta : ((row > k) ? vv : x[r]);   // selects, no branches
             }
             if (s == 0) tsh[k] = tau;
         }
