@@ -27,25 +27,19 @@ namespace {
 
 template <int H>
 struct GroupCfg {
-    // sweeps per group and threads per chase, sized so the ring plus the
-    // per-team scratch stay near 110 KB of LDS
-    static constexpr int S = (H == 1) ? 384 : (H == 2) ? 96 : (H == 4) ? 24 : 6;
-    static constexpr int TEAM = (H == 1) ? 1 : (H == 2) ? 4 : (H == 4) ? 16 : 64;
-    static constexpr int NT = S * TEAM;
+    // one team of 2h lanes per chase (lane u holds band row u of the chase's
+    // 2h-row blocks); sweeps per group sized so the ring plus the per-team
+    // scratch stay under 150 KB of LDS
+    static constexpr int TEAM = 2 * H;
+    static constexpr int NT = (H <= 2) ? 512 : (H == 4 ? 256 : 128);
+    static constexpr int S = NT / TEAM;
     static constexpr int LDW = 4 * H + 1;        // stored diagonals per column
     static constexpr int BATCH = (H >= 8) ? 4 : 8;   // steps per load / write-back batch
     static constexpr int WC = 5 * H * S + 2 * H * (BATCH + 6);
     static constexpr int H2 = 2 * H;
-    // per-team scratch (doubles)
-    static constexpr int UB = 0;                 // 2H x H  QR block -> U
-    static constexpr int TT = UB + H2 * H;       // H x H
-    static constexpr int YY = TT + H * H;        // 2H x H  U T
-    static constexpr int WR = YY + H2 * H;       // 2H x H  W / V of the qr rows
-    static constexpr int GG = WR + H2 * H;       // H x H
-    static constexpr int MM = GG + H * H;        // H x H
-    static constexpr int WX = MM + H * H;        // 2H x H  W of the left / below block
-    static constexpr int TAU = WX + H2 * H;      // H
-    static constexpr int SCR = TAU + H;
+    // per-team scratch (doubles): U rows (2h x h), a second 2h x h block
+    // (the left block, then W, then V) and an h x h product
+    static constexpr int SCR = 2 * H2 * H + H * H;
     static constexpr int LDS_DOUBLES = WC * LDW + S * SCR;
 };
 
@@ -72,6 +66,18 @@ __device__ __forceinline__ void team_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// All-reduce sum over the TEAM lanes of an aligned team (TEAM in {2, 4, 8,
+// 16}); row_mirror (lane i <-> 15 - i) joins the two 8-lane halves.
+template <int TEAM>
+__device__ __forceinline__ double team_sum(double v) {
+    if constexpr (TEAM <= 8) {
+        return group_sum<TEAM>(v);
+    } else {
+        v = group_sum<8>(v);
+        return v + dpp_d<0x140>(v);
+    }
+}
+
 template <int H>
 __device__ __forceinline__ int64_t nchase_of(int64_t n, int64_t i) {
     return (n - 2 - i * H) / (2 * H) + 1;
@@ -88,14 +94,9 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
     const int t = threadIdx.x;
     const int tm = t / TEAM, u = t % TEAM;
     double* scr = smem + WC * LDW + tm * C::SCR;
-    double* Ub = scr + C::UB;
-    double* Tm = scr + C::TT;
-    double* Yb = scr + C::YY;
-    double* Wr = scr + C::WR;
-    double* Gm = scr + C::GG;
-    double* Mm = scr + C::MM;
-    double* Wx = scr + C::WX;
-    double* tau = scr + C::TAU;
+    double* Us = scr;                 // U, row u at Us[u * H]
+    double* Xs = scr + H2 * H;        // left block / W / V rows
+    double* Ms = scr + 2 * H2 * H;    // U^T X_L, then U^T W
     const int64_t n = a.n;
     double* gband = a.band;
 
@@ -212,175 +213,176 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
             cs = cq;
             sbase = act ? cs % WC : 0;
 
-            // QR block into Ub
-            if (act)
-                for (int idx = u; idx < H2 * H; idx += TEAM) {
-                    const int r = idx % H2, c = idx / H2;
-                    Ub[idx] = (r < nr) ? R(o + r, cq + c) : 0.0;
-                }
-            team_sync<TEAM>();
-            for (int k = 0; k < H; ++k) {
-                if (act && u == 0) {
-                    double ss = 0.0;
-                    for (int r = k + 1; r < H2; ++r) ss += Ub[r + k * H2] * Ub[r + k * H2];
-                    const double xk = Ub[k + k * H2];
-                    double beta, tk, scal;
-                    if (ss == 0.0) {
-                        beta = xk; tk = 0.0; scal = 0.0;
-                    } else {
-                        const double nrm = sqrt(xk * xk + ss);
-                        beta = (xk >= 0.0) ? -nrm : nrm;
-                        tk = (beta - xk) / beta;
-                        scal = 1.0 / (xk - beta);
+            // One band row per lane: u = row of the QR, left and diagonal blocks
+            // (rows o + u) and of the below block (row o + 2h + u).  Column sums
+            // are team all-reduces; products with T = (diag(1/tau) + strict
+            // upper part of U^T U)^{-1} are substitutions with G = U^T U, so T
+            // itself is never formed.
+            if (act) {
+                const bool rv = u < nr, bvr = u < nbr;
+                double q[H], d[H2], bl[H2], lf[H];
+#pragma unroll
+                for (int c = 0; c < H; ++c) q[c] = rv ? R(o + u, cq + c) : 0.0;
+#pragma unroll
+                for (int k = 0; k < H2; ++k)
+                    d[k] = (rv && k < nr) ? ((u >= k) ? R(o + u, o + k) : R(o + k, o + u)) : 0.0;
+#pragma unroll
+                for (int c = 0; c < H; ++c) lf[c] = (rv && j > 1) ? R(o + u, o - H + c) : 0.0;
+#pragma unroll
+                for (int k = 0; k < H2; ++k) bl[k] = (bvr && k < nr) ? R(o + H2 + u, o + k) : 0.0;
+
+                // ---- Householder QR of the 2h x h QR block
+                double tv[H];
+#pragma unroll
+                for (int k = 0; k < H; ++k) {
+                    const double xk = team_sum<TEAM>((u == k) ? q[k] : 0.0);
+                    const double ss = team_sum<TEAM>((u > k) ? q[k] * q[k] : 0.0);
+                    const bool none = (ss == 0.0);
+                    const double nrm = sqrt(xk * xk + ss);
+                    const double beta = none ? xk : ((xk >= 0.0) ? -nrm : nrm);
+                    const double tk = none ? 0.0 : (beta - xk) / beta;
+                    const double scal = none ? 0.0 : 1.0 / (xk - beta);
+                    const double v = (u == k) ? 1.0 : ((u > k) ? q[k] * scal : 0.0);
+#pragma unroll
+                    for (int c = k + 1; c < H; ++c) {
+                        const double dc = team_sum<TEAM>(v * q[c]);
+                        q[c] -= tk * dc * v;
                     }
-                    Ub[k + k * H2] = beta;
-                    for (int r = k + 1; r < H2; ++r) Ub[r + k * H2] *= scal;
-                    tau[k] = tk;
+                    q[k] = (u == k) ? beta : ((u > k) ? v : q[k]);
+                    tv[k] = tk;
+                }
+                double Uu[H];
+#pragma unroll
+                for (int c = 0; c < H; ++c)
+                    Uu[c] = (tv[c] != 0.0) ? ((u == c) ? 1.0 : ((u > c) ? q[c] : 0.0)) : 0.0;
+                if (rv) {
+#pragma unroll
+                    for (int c = 0; c < H; ++c) R(o + u, cq + c) = (u <= c) ? q[c] : 0.0;
+                }
+                double G[H][H];
+#pragma unroll
+                for (int p = 0; p < H; ++p)
+#pragma unroll
+                    for (int c = p + 1; c < H; ++c) G[p][c] = team_sum<TEAM>(Uu[p] * Uu[c]);
+#pragma unroll
+                for (int c = 0; c < H; ++c) Us[u * H + c] = Uu[c];
+                // Z = U T^T (back substitution): Z_c = tau_c (U_c - sum_{p>c} Z_p G[c][p])
+                double Z[H];
+#pragma unroll
+                for (int c = H - 1; c >= 0; --c) {
+                    double sacc = Uu[c];
+#pragma unroll
+                    for (int p = c + 1; p < H; ++p) sacc -= Z[p] * G[c][p];
+                    Z[c] = tv[c] * sacc;
                 }
                 team_sync<TEAM>();
-                if (act) {
-                    const double tk = tau[k];
-                    if (tk != 0.0)
-                        for (int c = k + 1 + u; c < H; c += TEAM) {
-                            double dot = Ub[k + c * H2];
-                            for (int r = k + 1; r < H2; ++r) dot += Ub[r + k * H2] * Ub[r + c * H2];
-                            const double f = tk * dot;
-                            Ub[k + c * H2] -= f;
-                            for (int r = k + 1; r < H2; ++r) Ub[r + c * H2] -= f * Ub[r + k * H2];
+
+                // ---- below block: X_B -= ((X_B U) T) U^T
+                if (nbr > 0) {
+                    double P[H];
+#pragma unroll
+                    for (int c = 0; c < H; ++c) P[c] = 0.0;
+#pragma unroll
+                    for (int k = 0; k < H2; ++k)
+#pragma unroll
+                        for (int c = 0; c < H; ++c) P[c] += bl[k] * Us[k * H + c];
+                    double Wb[H];
+#pragma unroll
+                    for (int c = 0; c < H; ++c) {
+                        double sacc = P[c];
+#pragma unroll
+                        for (int p = 0; p < c; ++p) sacc -= Wb[p] * G[p][c];
+                        Wb[c] = tv[c] * sacc;
+                    }
+                    if (bvr) {
+#pragma unroll
+                        for (int k = 0; k < H2; ++k) {
+                            double sacc = 0.0;
+#pragma unroll
+                            for (int c = 0; c < H; ++c) sacc += Wb[c] * Us[k * H + c];
+                            if (k < nr) R(o + H2 + u, o + k) = bl[k] - sacc;
                         }
+                    }
+                }
+
+                // ---- left block (j > 1): X_L -= Z (U^T X_L)
+                if (j > 1) {
+#pragma unroll
+                    for (int c = 0; c < H; ++c) Xs[u * H + c] = lf[c];
+                    team_sync<TEAM>();
+                    for (int e = u; e < H * H; e += H2) {
+                        const int p = e % H, c = e / H;
+                        double sacc = 0.0;
+#pragma unroll
+                        for (int r = 0; r < H2; ++r) sacc += Us[r * H + p] * Xs[r * H + c];
+                        Ms[p * H + c] = sacc;
+                    }
+                    team_sync<TEAM>();
+                    if (rv) {
+#pragma unroll
+                        for (int c = 0; c < H; ++c) {
+                            double sacc = 0.0;
+#pragma unroll
+                            for (int p = 0; p < H; ++p) sacc += Z[p] * Ms[p * H + c];
+                            R(o + u, o - H + c) = lf[c] - sacc;
+                        }
+                    }
+                    team_sync<TEAM>();
+                }
+
+                // ---- diagonal block: W = (D U) T, V = 1/2 Z (U^T W) - W,
+                // D += U V^T + V U^T (lower triangle)
+                double W[H];
+                {
+                    double P[H];
+#pragma unroll
+                    for (int c = 0; c < H; ++c) P[c] = 0.0;
+#pragma unroll
+                    for (int k = 0; k < H2; ++k)
+#pragma unroll
+                        for (int c = 0; c < H; ++c) P[c] += d[k] * Us[k * H + c];
+#pragma unroll
+                    for (int c = 0; c < H; ++c) {
+                        double sacc = P[c];
+#pragma unroll
+                        for (int p = 0; p < c; ++p) sacc -= W[p] * G[p][c];
+                        W[c] = tv[c] * sacc;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < H; ++c) Xs[u * H + c] = W[c];
+                team_sync<TEAM>();
+                for (int e = u; e < H * H; e += H2) {
+                    const int p = e % H, c = e / H;
+                    double sacc = 0.0;
+#pragma unroll
+                    for (int r = 0; r < H2; ++r) sacc += Us[r * H + p] * Xs[r * H + c];
+                    Ms[p * H + c] = sacc;
                 }
                 team_sync<TEAM>();
+                double V[H];
+#pragma unroll
+                for (int c = 0; c < H; ++c) {
+                    double sacc = 0.0;
+#pragma unroll
+                    for (int p = 0; p < H; ++p) sacc += Z[p] * Ms[p * H + c];
+                    V[c] = 0.5 * sacc - W[c];
+                }
+#pragma unroll
+                for (int c = 0; c < H; ++c) Xs[u * H + c] = V[c];
+                team_sync<TEAM>();
+                if (rv) {
+#pragma unroll
+                    for (int k = 0; k < H2; ++k) {
+                        if (k <= u && k < nr) {
+                            double sacc = 0.0;
+#pragma unroll
+                            for (int c = 0; c < H; ++c) sacc += Uu[c] * Xs[k * H + c] + V[c] * Us[k * H + c];
+                            R(o + u, o + k) = d[k] + sacc;
+                        }
+                    }
+                }
             }
-            // R into the ring ([R; 0]), Ub becomes the explicit unit lower U
-            if (act)
-                for (int idx = u; idx < H2 * H; idx += TEAM) {
-                    const int r = idx % H2, c = idx / H2;
-                    const double val = Ub[idx];
-                    const bool refl = tau[c] != 0.0;
-                    if (r < nr) R(o + r, cq + c) = (r <= c) ? val : 0.0;
-                    Ub[idx] = (r < c) ? 0.0 : ((r == c) ? (refl ? 1.0 : 0.0) : (refl ? val : 0.0));
-                }
-            team_sync<TEAM>();
-            // T: T[c][c] = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] (U^T U)[0:c, c]
-            if (act)
-                for (int idx = u; idx < H * H; idx += TEAM) {
-                    const int ra = idx % H, c = idx / H;
-                    double acc = 0.0;
-                    if (ra < c)
-                        for (int r = 0; r < H2; ++r) acc += Ub[r + ra * H2] * Ub[r + c * H2];
-                    Gm[idx] = acc;
-                    Tm[idx] = 0.0;
-                }
-            team_sync<TEAM>();
-            for (int c = 0; c < H; ++c) {
-                if (act)
-                    for (int ra = u; ra <= c; ra += TEAM) {
-                        if (ra == c) {
-                            Tm[c + c * H] = tau[c];
-                        } else {
-                            double acc = 0.0;
-                            for (int k = ra; k < c; ++k) acc += Tm[ra + k * H] * Gm[k + c * H];
-                            Tm[ra + c * H] = -tau[c] * acc;
-                        }
-                    }
-                team_sync<TEAM>();
-            }
-            // Y = U T ; W_R = D Y (D the symmetric diagonal block)
-            if (act)
-                for (int idx = u; idx < H2 * H; idx += TEAM) {
-                    const int r = idx % H2, c = idx / H2;
-                    double acc = 0.0;
-                    for (int k = 0; k <= c; ++k) acc += Ub[r + k * H2] * Tm[k + c * H];
-                    Yb[idx] = acc;
-                }
-            team_sync<TEAM>();
-            if (act)
-                for (int idx = u; idx < H2 * H; idx += TEAM) {
-                    const int r = idx % H2, c = idx / H2;
-                    double acc = 0.0;
-                    if (r < nr)
-                        for (int k = 0; k < nr; ++k) {
-                            const double dv = (r >= k) ? R(o + r, o + k) : R(o + k, o + r);
-                            acc += dv * Yb[k + c * H2];
-                        }
-                    Wr[idx] = acc;
-                }
-            team_sync<TEAM>();
-            // G = U^T W_R ; M = T^T G ; V_R = 1/2 U M - W_R
-            if (act)
-                for (int idx = u; idx < H * H; idx += TEAM) {
-                    const int ra = idx % H, c = idx / H;
-                    double acc = 0.0;
-                    for (int r = 0; r < H2; ++r) acc += Ub[r + ra * H2] * Wr[r + c * H2];
-                    Gm[idx] = acc;
-                }
-            team_sync<TEAM>();
-            if (act)
-                for (int idx = u; idx < H * H; idx += TEAM) {
-                    const int ra = idx % H, c = idx / H;
-                    double acc = 0.0;
-                    for (int k = 0; k <= ra; ++k) acc += Tm[k + ra * H] * Gm[k + c * H];
-                    Mm[idx] = acc;
-                }
-            team_sync<TEAM>();
-            if (act)
-                for (int idx = u; idx < H2 * H; idx += TEAM) {
-                    const int r = idx % H2, c = idx / H2;
-                    double acc = 0.0;
-                    for (int k = 0; k < H; ++k) acc += Ub[r + k * H2] * Mm[k + c * H];
-                    Wr[idx] = 0.5 * acc - Wr[idx];
-                }
-            team_sync<TEAM>();
-            // diagonal block += U V_R^T + V_R U^T (lower part)
-            if (act)
-                for (int idx = u; idx < H2 * H2; idx += TEAM) {
-                    const int r = idx % H2, c = idx / H2;
-                    if (r >= c && r < nr) {
-                        double acc = 0.0;
-                        for (int k = 0; k < H; ++k)
-                            acc += Ub[r + k * H2] * Wr[c + k * H2] + Wr[r + k * H2] * Ub[c + k * H2];
-                        R(o + r, o + c) += acc;
-                    }
-                }
-            // left block (j > 1): X -= U (X^T Y)^T
-            const bool left = act && (j > 1);
-            if (left)
-                for (int idx = u; idx < H * H; idx += TEAM) {
-                    const int c = idx % H, k = idx / H;
-                    double acc = 0.0;
-                    for (int r = 0; r < nr; ++r) acc += R(o + r, o - H + c) * Yb[r + k * H2];
-                    Wx[c + k * H] = acc;
-                }
-            team_sync<TEAM>();
-            if (left)
-                for (int idx = u; idx < H2 * H; idx += TEAM) {
-                    const int r = idx % H2, c = idx / H2;
-                    if (r < nr) {
-                        double acc = 0.0;
-                        for (int k = 0; k < H; ++k) acc += Ub[r + k * H2] * Wx[c + k * H];
-                        R(o + r, o - H + c) -= acc;
-                    }
-                }
-            team_sync<TEAM>();
-            // below block: X -= (X Y) U^T
-            if (act && nbr > 0)
-                for (int idx = u; idx < H2 * H; idx += TEAM) {
-                    const int r = idx % H2, k = idx / H2;
-                    double acc = 0.0;
-                    if (r < nbr)
-                        for (int c = 0; c < H2; ++c) acc += R(o + H2 + r, o + c) * Yb[c + k * H2];
-                    Wx[idx] = acc;
-                }
-            team_sync<TEAM>();
-            if (act && nbr > 0)
-                for (int idx = u; idx < H2 * H2; idx += TEAM) {
-                    const int r = idx % H2, c = idx / H2;
-                    if (r < nbr) {
-                        double acc = 0.0;
-                        for (int k = 0; k < H; ++k) acc += Wx[r + k * H2] * Ub[c + k * H2];
-                        R(o + H2 + r, o + c) -= acc;
-                    }
-                }
             team_sync<TEAM>();
             __syncthreads();   // next step reads columns the neighbouring sweeps wrote
 
