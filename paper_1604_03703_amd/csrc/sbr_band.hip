@@ -190,10 +190,12 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
                             break;
                         }
                     }
+                    // one acquire for the block: it invalidates this CU's L1 and
+                    // the XCD's L2, which every wave of the block reads through
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
                 __syncthreads();
                 if (abort_sh) return;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             const int64_t o = (int64_t)i * H + (j - 1) * H2;
             const int nr = (int)((n - o < H2) ? (n - o) : H2);
@@ -374,8 +376,9 @@ __global__ __launch_bounds__(NT) void chase_kernel(ChaseArgs a) {
                         if (i < nbr) bput(band, ldb, o + H2 + i, o + c, Xb[i + c * H2] - v);
                     });
             }
-            // ---- publish
-            __threadfence();
+            // ---- publish: every wave's stores complete to L2, then one
+            // agent-scope release (L2 write-back) by thread 0 covers the block
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (t == 0) sbr_store_release(&a.progress[i], (j == nchase) ? SWEEP_DONE : (int)j);
         }
@@ -466,12 +469,12 @@ int64_t chase_flag_ints(int64_t n, int b) {
 void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch, int* flags,
                        int* error, int max_grid, hipStream_t s) {
     (void)f32;
-    if (band_group_supported(b) && ldband == 2 * b + 1) {
-        launch_band_halve_group(n, band, ldband, b, flags, error, max_grid, s);
-        return;
-    }
     if (band_mfma_supported(b)) {
         launch_band_halve_mfma(n, band, ldband, b, scratch, flags, error, max_grid, s);
+        return;
+    }
+    if (band_group_supported(b) && ldband == 2 * b + 1) {
+        launch_band_halve_group(n, band, ldband, b, flags, error, max_grid, s);
         return;
     }
     switch (b) {

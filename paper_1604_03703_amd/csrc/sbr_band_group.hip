@@ -180,11 +180,12 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                                 }
                                 vis_sh = d;
                                 fresh_sh = 1;
+                                // one acquire for the block (CU L1 + XCD L2)
+                                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                             }
                         }
                         __syncthreads();
                         if (abort_sh) return;
-                        if (fresh_sh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     }
                     // load [loaded, need) into the ring
                     const int cnt = (int)(need - loaded) * LDW;
@@ -419,7 +420,8 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                     }
                     written = done;
                 }
-                if (moved || last) __threadfence();
+                // stores complete to L2; thread 0's release below writes the L2 back
+                if (moved || last) __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
                 if (t == 0 && (moved || last)) {
                     int pub = (int)written;

@@ -55,21 +55,23 @@ constexpr int MSWEEP_DONE = 1 << 30;
 template <int H>
 struct MChase {
     static constexpr int B = 2 * H;
+    static constexpr int HP = H < 16 ? 16 : H;   // h rounded up to whole 16-wide tiles
     static constexpr int NW = B / 16;          // one wave per 16-row tile
     static constexpr int NT = 64 * NW;
-    static constexpr int RT = B / 16, CT = H / 16;
-    static constexpr int LDU = B + 1, LDH = H + 1;
+    static constexpr int RT = B / 16, CT = HP / 16;
+    static constexpr int LDU = B + 1, LDH = HP + 1;
     static constexpr bool WR_LDS = H <= 32;
     // LDS (doubles): U (b x h), T (h x h; QR staging before T exists), one
-    // h x h exchange buffer (L = T^{-1}, then U^T X_L, then U^T W), W (b x h)
+    // h x h exchange buffer (L = T^{-1}, then U^T X_L, then U^T W), W (b x h);
+    // for h < 16 the columns h .. 15 are zero padding
     static constexpr int US = 0;
-    static constexpr int TS = US + LDU * H;
-    static constexpr int RS = TS + LDH * H;
-    static constexpr int WS = RS + LDH * H;
-    static constexpr int TOTAL = WS + (WR_LDS ? B * H : 0);
+    static constexpr int TS = US + LDU * HP;
+    static constexpr int RS = TS + LDH * HP;
+    static constexpr int WS = RS + LDH * HP;
+    static constexpr int TOTAL = WS + (WR_LDS ? B * HP : 0);
     static constexpr int TPCQ = 8, RPT = B / TPCQ;   // QR: 8 lanes per column
     static_assert(H * TPCQ == NT, "QR layout");
-    static_assert(2 * B + H <= LDH * H, "QR staging fits in the T region");
+    static_assert(2 * B + H <= LDH * HP, "QR staging fits in the T region");
 };
 
 __device__ __forceinline__ sbr_d4 mma(double a, double b, sbr_d4 c) {
@@ -80,7 +82,7 @@ __device__ __forceinline__ sbr_d4 zero4() { return sbr_d4{0.0, 0.0, 0.0, 0.0}; }
 template <int H>
 __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a) {
     typedef MChase<H> C;
-    constexpr int B = C::B, NW = C::NW, RT = C::RT, CT = C::CT, LDU = C::LDU, LDH = C::LDH;
+    constexpr int B = C::B, HP = C::HP, NW = C::NW, RT = C::RT, CT = C::CT, LDU = C::LDU, LDH = C::LDH;
     constexpr int TPCQ = C::TPCQ, RPT = C::RPT;
     extern __shared__ double sm[];
     double* Us = sm + C::US;
@@ -100,6 +102,12 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
     // band element (r, c), r >= c, of the chase-local rows/cols
     auto B_at = [&](int64_t r, int64_t c) -> double& { return band[(r - c) + c * ldb]; };
 
+    if (HP > H) {
+        // padding columns (h .. 15) of U, T and the exchange blocks are read by
+        // the 16-wide tiles and must be zero; nothing writes them later
+        for (int idx = t; idx < C::TOTAL; idx += C::NT) sm[idx] = 0.0;
+        __syncthreads();
+    }
     while (true) {
         if (t == 0) {
             const bool failed = __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
@@ -129,10 +137,12 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                             break;
                         }
                     }
+                    // one acquire for the block: it invalidates this CU's L1 and
+                    // the XCD's L2, which every wave of the block reads through
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
                 __syncthreads();
                 if (abort_sh) return;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             const int64_t o = (int64_t)i * H + (j - 1) * B;
             const int nr = (int)((n - o < B) ? (n - o) : B);
@@ -224,7 +234,7 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int gi = I * 16 + li, gj = J * 16 + 4 * r + lk;
-                        Rs[gi + gj * LDH] = (gi < gj) ? acc[r] : ((gi == gj) ? tau[gi] : 0.0);
+                        Rs[gi + gj * LDH] = (gi < gj) ? acc[r] : ((gi == gj && gi < H) ? tau[gi] : 0.0);
                     }
                 }
             }
@@ -236,7 +246,7 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 const int jc = t >> 3, s = t & 7;
                 const int jmax = ((t >> 6) << 3) + 7;    // last column of this wave
                 if (s == 0) Ts[jc + jc * LDH] = Rs[jc + jc * LDH];
-                for (int r = jc + 1 + s; r < H; r += 8) Ts[r + jc * LDH] = 0.0;
+                for (int r = jc + 1 + s; r < HP; r += 8) Ts[r + jc * LDH] = 0.0;
                 for (int r = jmax - 1; r >= 0; --r) {
                     double p = 0.0;
                     if (r < jc)
@@ -253,7 +263,7 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
             for (int J = 0; J < CT; ++J) {
                 Z[J] = zero4();
 #pragma unroll
-                for (int k0 = J * 16; k0 < H; k0 += 4)      // T^T(k, c) = 0 for k < c
+                for (int k0 = J * 16; k0 < HP; k0 += 4)     // T^T(k, c) = 0 for k < c
                     Z[J] = mma(Ts[(J * 16 + li) + (k0 + lk) * LDH], Us[(w * 16 + li) + (k0 + lk) * LDU], Z[J]);
             }
 
@@ -262,11 +272,12 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 for (int idx = w; idx < CT * CT; idx += NW) {
                     const int I = idx % CT, J = idx / CT;
                     const int64_t gc = o - H + J * 16 + li;
+                    const bool colv = J * 16 + li < H;
                     sbr_d4 acc = zero4();
 #pragma unroll 4
                     for (int k0 = 0; k0 < B; k0 += 4) {
                         const int row = k0 + lk;
-                        const double av = (row < nr) ? B_at(o + row, gc) : 0.0;
+                        const double av = (row < nr && colv) ? B_at(o + row, gc) : 0.0;
                         acc = mma(av, Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
                     }
 #pragma unroll
@@ -285,7 +296,8 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                         const int row = w * 16 + li;
                         if (row < nr) {
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) B_at(o + row, o - H + J * 16 + 4 * r + lk) -= acc[r];
+                            for (int r = 0; r < 4; ++r)
+                                if (J * 16 + 4 * r + lk < H) B_at(o + row, o - H + J * 16 + 4 * r + lk) -= acc[r];
                         }
                     }
                 }
@@ -426,8 +438,9 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 }
             }
 
-            // ---- publish
-            __threadfence();
+            // ---- publish: every wave's stores complete to L2, then one
+            // agent-scope release (L2 write-back) by thread 0 covers the block
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (t == 0) sbr_store_release(&a.progress[i], (j == nchase) ? MSWEEP_DONE : (int)j);
         }
@@ -476,7 +489,7 @@ int set_mchase_attr() {
 
 namespace sbr {
 
-bool band_mfma_supported(int b) { return b == 32 || b == 64 || b == 128; }
+bool band_mfma_supported(int b) { return b == 16 || b == 32 || b == 64 || b == 128; }
 
 int64_t band_mfma_workspace_doubles(int64_t n, int b) {
     if (b != 128) return 0;
@@ -486,6 +499,7 @@ int64_t band_mfma_workspace_doubles(int64_t n, int b) {
 void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, int* flags,
                             int* error, int max_grid, hipStream_t s) {
     switch (b) {
+        case 16: launch_mchase<8>(n, band, ldband, scratch, flags, error, max_grid, s); break;
         case 32: launch_mchase<16>(n, band, ldband, scratch, flags, error, max_grid, s); break;
         case 64: launch_mchase<32>(n, band, ldband, scratch, flags, error, max_grid, s); break;
         case 128: launch_mchase<64>(n, band, ldband, scratch, flags, error, max_grid, s); break;
@@ -495,6 +509,7 @@ void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, doub
 
 int init_band_mfma_attributes() {
     int rc = 0;
+    rc |= set_mchase_attr<8>();
     rc |= set_mchase_attr<16>();
     rc |= set_mchase_attr<32>();
     rc |= set_mchase_attr<64>();
