@@ -55,8 +55,11 @@ def band_stage_bytes(n: int, b: int) -> float:
 
 
 def f2b_update_flops(n: int, b: int):
-    """Per-panel algorithmic flops of the two dominant kernels:
-    SYMM W = A22 Y (2 m^2 b) and the lower-triangle SYR2K (2 b m (m+1))."""
+    """Per-panel algorithmic flops of the two dominant kernels: SYMM
+    W = A22 Y (2 m^2 b) and the bulk lower-triangle SYR2K launch.  The trailing
+    update of a panel with a next panel is split: the next panel's b columns
+    first (not counted here), then the remaining m' = m - b rows and columns,
+    2 b m' (m' + 1) flops; the last panel's update is one launch over m."""
     symm, syr2k = [], []
     k = 0
     while True:
@@ -64,9 +67,31 @@ def f2b_update_flops(n: int, b: int):
         if m < b:
             break
         symm.append(2.0 * m * m * b)
-        syr2k.append(2.0 * b * m * (m + 1))
+        mr = m - b if m - b >= b else m
+        syr2k.append(2.0 * b * mr * (mr + 1))
         k += 1
     return symm, syr2k
+
+
+def measured_traffic(kernel_src: str):
+    """HBM bytes per launch of the bulk SYR2K from the committed counter
+    profile, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "syr2k_lower_kernel_n32768_b128_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    rec = None
+    for line in text.splitlines():
+        if line.startswith("TRAFFIC "):
+            rec = json.loads(line[len("TRAFFIC "):])
+    if rec is None:
+        return None
+    src = open(os.path.join(ROOT, "paper_1604_03703_amd", "csrc", kernel_src), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec.get("src_sha256"):
+        return None
+    return rec["bytes_per_launch"]
 
 
 def run_form(sbr, torch, A0, n, b0, precision, steps, warmup, plan):
@@ -132,6 +157,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run three device-to-device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the eigensolver here runs on a single device "
@@ -140,6 +167,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe > 0:
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "copies": 3}), flush=True)
+        return
 
     import sbr_inputs as si
     import paper_1604_03703_amd as sbr
@@ -173,9 +211,11 @@ def main():
     syr2k_ms = mean([t["ms_syr2k"] for t in tims])
     symm_ms = mean([t["ms_symm"] for t in tims])
     if syr2k_ms >= symm_ms:
-        kname, kflops, kms, klaunch = "syr2k_lower_kernel<double,128,2,4>", sum(syr2k_f), syr2k_ms, len(syr2k_f)
+        kname, kflops, kms, klaunch = "syr2k_lower_kernel (bulk trailing update)", sum(syr2k_f), syr2k_ms, len(syr2k_f)
+        traffic = measured_traffic("sbr_gemm.hip")
     else:
-        kname, kflops, kms, klaunch = "symm_lower_kernel<double,128,128,2,4>", sum(symm_f), symm_ms, len(symm_f)
+        kname, kflops, kms, klaunch = "symm_lower_kernel", sum(symm_f), symm_ms, len(symm_f)
+        traffic = None
     achieved = kflops / (kms * 1e-3) / 1e12 if kms > 0 else 0.0
     stage_ms = [mean([t["ms_stage"][i] for t in tims]) for i in range(len(tims[0]["ms_stage"]))]
     stages = []
@@ -214,7 +254,7 @@ def main():
         "checks": {"trace_rel": tr_err, "frobenius_rel": fr_err},
         "roofline": {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA, 4),
-                     "traffic": None, "launches": klaunch, "avg_launch_ms": round(kms / max(1, klaunch), 4)},
+                     "traffic": traffic, "launches": klaunch, "avg_launch_ms": round(kms / max(1, klaunch), 4)},
     }
 
     if not args.no_fp32:

@@ -83,7 +83,8 @@ typedef struct {
     double ms_bisect;         /* tridiagonal extraction + bisection */
     double ms_update_kernels; /* sum over launches of the SYMM + SYR2K kernels */
     int64_t update_launches;  /* number of those launches */
-    double ms_syr2k;          /* SYR2K launches only */
+    double ms_syr2k;          /* bulk SYR2K launches only: the trailing update
+                                 minus the next panel's column block */
     int64_t syr2k_launches;
     double ms_symm;           /* SYMM launches only */
     int64_t symm_launches;

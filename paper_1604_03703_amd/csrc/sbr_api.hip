@@ -297,9 +297,8 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
                            p->part, gs, s);
         launch_gemm(false, true, false, b, b, b, 1.0, p->T, b, p->Zm, b, 0.0, nullptr, 0, p->Mm, b, s);
         launch_gemm(false, false, false, m, b, b, 0.5, U, ldq, p->Mm, b, -1.0, p->W, ldq, p->V, ldq, s);
-        // A22 += U V^T + V U^T
+        // A22 += U V^T + V U^T (the timed pair brackets the bulk launch only)
         EventPair eq;
-        if (p->timing) { eq.a = p->ev(); p->mark(eq.a, s); }
         const int64_t mn = m - b;          // rows of the next panel
         if (mn >= b) {
             launch_syr2k_lower_cols(f32, m, b, b, U, ldq, p->V, ldq, A22, lda, s);
@@ -311,12 +310,14 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
             launch_gemm(false, false, false, mn, b, b, 1.0, Un, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, p->side);
             e = hipEventRecord(p->ev_join, p->side);
             if (e != hipSuccess) return hip_fail(e);
+            if (p->timing) { eq.a = p->ev(); p->mark(eq.a, s); }
             launch_syr2k_lower(f32, mn, b, U + b, ldq, p->V + b, ldq, A22 + b + b * lda, lda, s);
             if (p->timing) { eq.b = p->ev(); p->mark(eq.b, s); p->ev_syr2k.push_back(eq); }
             e = hipStreamWaitEvent(s, p->ev_join, 0);
             if (e != hipSuccess) return hip_fail(e);
             cur ^= 1;
         } else {
+            if (p->timing) { eq.a = p->ev(); p->mark(eq.a, s); }
             launch_syr2k_lower(f32, m, b, U, ldq, p->V, ldq, A22, lda, s);
             if (p->timing) { eq.b = p->ev(); p->mark(eq.b, s); p->ev_syr2k.push_back(eq); }
         }

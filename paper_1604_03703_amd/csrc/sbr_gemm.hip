@@ -121,10 +121,36 @@ __device__ __forceinline__ int64_t xcd_logical_tile(int64_t x, int64_t ntiles) {
     return k * q + (k < r ? k : r) + x / 8;
 }
 
+// Lower tile x (of T x T tiles, lower triangle) in an L2-friendly order: bands
+// of 8 tile rows, and inside a band the tiles column by column, so the 8 row
+// operands of a band stay in L2 and each column operand serves 8 tiles in a
+// row.  Bands before the last are full; the last may have fewer rows.
+__device__ __forceinline__ void lower_tile_banded(int64_t x, int64_t T, int64_t& I, int64_t& J) {
+    auto cum = [](int64_t P) -> int64_t { return 32 * P * P + 4 * P; };   // tiles in bands < P
+    int64_t P = (int64_t)((sqrt(16.0 + 128.0 * (double)x) - 4.0) / 64.0);
+    while (P > 0 && cum(P) > x) --P;
+    while (cum(P + 1) <= x && 8 * (P + 1) < T) ++P;
+    int64_t y = x - cum(P);
+    const int64_t r = (T - 8 * P < 8) ? T - 8 * P : 8;
+    if (y < r * 8 * P) {
+        I = 8 * P + y % r;
+        J = y / r;
+        return;
+    }
+    y -= r * 8 * P;
+    int64_t q = 0;
+    while (y >= r - q) {
+        y -= r - q;
+        ++q;
+    }
+    J = 8 * P + q;
+    I = J + y;
+}
+
 // Lower triangle of C (m x m) += U V^T + V U^T, restricted to the columns
 // j < nc; one block per lower tile pair (I >= J).  The two products are one
 // GEMM with K' = 2K: [U_I, V_I] * [V_J, U_J]^T.  jt = 0: all lower tiles,
-// enumerated triangularly (nc = m); jt > 0: the first jt tile columns,
+// in the banded order above (nc = m); jt > 0: the first jt tile columns,
 // enumerated row by row.  Double-buffered LDS, one barrier per K chunk.
 template <typename CT, int BM, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
@@ -138,10 +164,7 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     const int64_t x = xcd_logical_tile(blockIdx.x, ntiles);
     int64_t I, J;
     if (jt == 0) {
-        I = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-        while (I * (I + 1) / 2 > x) --I;
-        while ((I + 1) * (I + 2) / 2 <= x) ++I;
-        J = x - I * (I + 1) / 2;
+        lower_tile_banded(x, (m + BM - 1) / BM, I, J);
     } else {
         I = x / jt;
         J = x % jt;
