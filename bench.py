@@ -7,8 +7,10 @@ step (the solve overwrites it); that copy is outside the timed region, every
 timed step is bracketed by device synchronisations.
 
 Default workload: n = 32768, (G + G^T)/2 Gaussian, b0 = 128, FP64 form, then
-the same input in the FP32-MFMA form.  The headline `value` is the
-full-to-band rate (4/3 n^3 flops over the full-to-band time) of the FP64 form.
+the same input in the FP32-MFMA form, then the batched form (4096 SCF-like
+matrices of orders 32 .. 512, one step = one call over the whole batch).  The
+headline `value` is the full-to-band rate (4/3 n^3 flops over the
+full-to-band time) of the FP64 form.
 
 Prints ONE JSON line (rank 0).  `--gpus N` with N > 1 is refused: this
 benchmark measures one GPU.
@@ -122,6 +124,41 @@ def run_form(sbr, torch, A0, n, b0, precision, steps, warmup, plan):
     return times, tims, w
 
 
+def run_batch(sbr, torch, si, count, steps, warmup):
+    """Batched form: `count` SCF-like matrices, n ~ U{32..512}; one step =
+    one replay of the captured batched launch over all of them (inputs
+    restored from pristine device copies outside the timed region)."""
+    import numpy as np
+    log("generating the batch of %d SCF-like matrices" % count)
+    mats = si.batch_workload(count=count)
+    dev0 = [torch.from_numpy(M).cuda() for M in mats]
+    dev = [torch.empty_like(d) for d in dev0]
+    ws = [torch.empty(d.shape[0], dtype=torch.float64, device=d.device) for d in dev0]
+    out = {"count": count, "n_range": [int(min(M.shape[0] for M in mats)), int(max(M.shape[0] for M in mats))]}
+    for prec in ("fp64", "fp32_mfma"):
+        plan = sbr.Plan(512, count, prec)
+        times = []
+        for it in range(max(1, warmup) + steps):
+            for d, d0 in zip(dev, dev0):
+                d.copy_(d0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sbr.eigvalsh_batched(dev, precision=prec, plan=plan, out=ws)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            log("batch %s step %d: %.2f ms" % (prec, it, (t1 - t0) * 1e3))
+            if it >= max(1, warmup):
+                times.append(t1 - t0)
+        tm = mean(times)
+        out[prec] = {"ms": round(tm * 1e3, 3), "solves_per_s": round(count / tm, 1)}
+        plan.close()
+    # every matrix's eigenvalues sum to its trace (cheap check at full size)
+    tr = max(abs(float(w.sum().item()) - float(np.trace(M))) / max(1.0, float(np.abs(M).max()) * M.shape[0])
+             for w, M in zip(ws[:64], mats[:64]))
+    out["trace_check_rel"] = tr
+    return out
+
+
 def mean(xs):
     return sum(xs) / max(1, len(xs))
 
@@ -157,6 +194,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -273,6 +312,9 @@ def main():
             "speedup_f2b": round(f2b_ms / f2b32, 3) if f2b32 > 0 else None,
         }
         del plan32
+
+    if not args.no_batch:
+        result["batch"] = run_batch(sbr, torch, si, args.batch_count, args.steps, args.warmup)
 
     if not args.no_cpu:
         log("timing the CPU oracle on a %d sample" % args.cpu_sample)

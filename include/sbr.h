@@ -82,8 +82,16 @@ int sbr_syev_eigvals_ex(sbr_plan_t plan, int64_t n, double* A, int64_t lda,
  *   A        HOST array of batch DEVICE pointers (each overwritten).
  *   b0       band width for every matrix, or 0 for the tuned choice per size.
  *   w        HOST array of batch DEVICE pointers, w[k] holds n[k] doubles.
- * The plan must have been created with batch_max >= batch and
- * n_max >= max n[k].
+ * Matrices with n[k] <= 512 (and b0 <= 16) are reduced by the batched
+ * kernels, one work-group per matrix, largest first: full-to-band with
+ * panels of width b (8 for n <= 96, 16 above, when b0 = 0), the halvings
+ * b -> 1 and bisection.  Their launch sequence is captured once per batch
+ * shape (the pointers, orders and bands) and replayed by later calls with the
+ * same shape; a new shape uploads the descriptors and captures again (the
+ * host then waits for the previous upload).  Larger matrices, or b0 >= 32,
+ * go through sbr_syev_eigvals_ex one after another on the same stream.  The
+ * per-matrix band buffers grow on demand (allocation on the first call of a
+ * larger batch).  The FP32-MFMA form of the batched kernels computes in FP64.
  */
 int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n,
                              double* const* A, const int64_t* lda, int32_t b0,
@@ -103,6 +111,8 @@ int sbr_tridiag_eigvals(int64_t n, const double* d, const double* e,
  * existing plan within its limits do not. */
 int sbr_plan_create(sbr_plan_t* plan, int64_t n_max, int32_t batch_max,
                     sbr_precision prec);
+/* Waits for the device (work enqueued with the plan may still run), then
+ * frees the plan's memory, streams, events and captured launches. */
 int sbr_plan_destroy(sbr_plan_t plan);
 
 /* Device workspace bytes sbr_syev_eigvals_ex needs for (n, b0, prec). */

@@ -187,12 +187,21 @@ def eigvalsh(A: torch.Tensor, b0: int = 0, precision="fp64", plan: Plan | None =
     return w
 
 
-def eigvalsh_batched(mats, b0: int = 0, precision="fp64", plan: Plan | None = None, stream=None):
-    """Eigenvalues of a list of symmetric CUDA float64 matrices (overwritten)."""
+def eigvalsh_batched(mats, b0: int = 0, precision="fp64", plan: Plan | None = None, stream=None, out=None):
+    """Eigenvalues of a list of symmetric CUDA float64 matrices (overwritten).
+
+    ``out``: optional list of float64 CUDA vectors (one per matrix) to write
+    into; with the same matrices and outputs a plan replays its captured
+    launch instead of rebuilding it."""
     k = len(mats)
     ns = (_i64 * k)(*[int(m.shape[0]) for m in mats])
     ldas = (_i64 * k)(*[int(m.shape[0]) for m in mats])
-    ws = [torch.empty(int(m.shape[0]), dtype=torch.float64, device=m.device) for m in mats]
+    if out is None:
+        ws = [torch.empty(int(m.shape[0]), dtype=torch.float64, device=m.device) for m in mats]
+    else:
+        if len(out) != k:
+            raise ValueError("out must have one vector per matrix")
+        ws = list(out)
     aps = (_vp * k)(*[_dev_f64(m, "A").value for m in mats])
     wps = (_vp * k)(*[_dev_f64(x, "w").value for x in ws])
     if plan is None:

@@ -57,6 +57,18 @@ struct sbr_plan_s {
     // of the current trailing update runs on the caller's stream
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // batched form: descriptors (device + pinned host copy), per-matrix band
+    // buffers, per-block scratch, tickets, and the captured launch
+    BatchDesc* bdesc_dev = nullptr;
+    BatchDesc* bdesc_host = nullptr;
+    int32_t bdesc_cap = 0;
+    double* bwork = nullptr;
+    int64_t bwork_cap = 0;
+    double* bscratch = nullptr;
+    int* btickets = nullptr;
+    hipEvent_t bupload_ev = nullptr;
+    hipGraphExec_t bgraph = nullptr;
+    std::vector<int64_t> bkey;
     double *part = nullptr;
     int64_t part_doubles = 0;
     double *T = nullptr, *W1inv = nullptr, *Mm = nullptr, *Zm = nullptr, *S = nullptr;
@@ -364,6 +376,7 @@ int init_attributes() {
     rc |= init_band_attributes();
     rc |= init_band_group_attributes();
     rc |= init_band_mfma_attributes();
+    rc |= init_batched_attributes();
     return rc;
 }
 
@@ -412,7 +425,17 @@ int sbr_plan_create(sbr_plan_t* plan, int64_t n_max, int32_t batch_max, sbr_prec
 
 int sbr_plan_destroy(sbr_plan_t plan) {
     if (!plan) return -1;
+    // work enqueued with this plan may still be running on the device
+    (void)hipSetDevice(plan->device);
+    (void)hipDeviceSynchronize();
     for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
+    if (plan->bgraph) (void)hipGraphExecDestroy(plan->bgraph);
+    if (plan->bupload_ev) (void)hipEventDestroy(plan->bupload_ev);
+    if (plan->bdesc_host) (void)hipHostFree(plan->bdesc_host);
+    if (plan->bdesc_dev) (void)hipFree(plan->bdesc_dev);
+    if (plan->bwork) (void)hipFree(plan->bwork);
+    if (plan->bscratch) (void)hipFree(plan->bscratch);
+    if (plan->btickets) (void)hipFree(plan->btickets);
     if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
     if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
     if (plan->side) (void)hipStreamDestroy(plan->side);
@@ -600,9 +623,120 @@ int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n, d
     for (int32_t k = 0; k < batch; ++k) {
         if (n[k] < 1 || lda[k] < n[k] || !A[k] || !w[k]) return -3;
     }
+    hipStream_t s = (hipStream_t)stream;
+    // matrices the batched kernels take (n <= BATCH_NMAX, band <= 16), by
+    // decreasing n; the others go through the single-matrix path
+    std::vector<int32_t> order, rest;
     for (int32_t k = 0; k < batch; ++k) {
-        int bk = b0 ? b0 : (n[k] <= 64 ? 8 : (n[k] <= 256 ? 16 : 32));
-        const int rc = sbr_syev_eigvals_ex(plan, n[k], A[k], lda[k], bk, prec, stream, w[k]);
+        if (n[k] <= BATCH_NMAX && b0 <= 16) order.push_back(k);
+        else rest.push_back(k);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return n[x] > n[y]; });
+    const int32_t cnt = (int32_t)order.size();
+    if (cnt > 0) {
+        std::vector<int32_t> band(cnt);
+        int64_t need = 0;
+        int max_b0 = 1;
+        std::vector<int64_t> key;
+        key.reserve(5 * (size_t)cnt + 2);
+        key.push_back(cnt);
+        for (int32_t q = 0; q < cnt; ++q) {
+            const int64_t nk = n[order[q]];
+            // band per size bucket: 8 for small matrices, 16 above
+            int bk = b0 ? b0 : (nk <= 96 ? 8 : 16);
+            while (bk > 1 && bk / 2 >= nk - 1) bk /= 2;
+            if (nk <= 2) bk = 1;
+            band[q] = bk;
+            max_b0 = std::max(max_b0, bk);
+            need += nk * (2 * bk + 1) + nk * (bk + 1) + 2 * nk;
+            key.push_back((int64_t)(uintptr_t)A[order[q]]);
+            key.push_back(lda[order[q]]);
+            key.push_back(nk);
+            key.push_back((int64_t)(uintptr_t)w[order[q]]);
+            key.push_back(bk);
+        }
+        hipError_t e = hipSuccess;
+        if (!plan->btickets) {
+            e = hipMalloc(&plan->btickets, 8 * sizeof(int));
+            if (e == hipSuccess) e = hipMalloc(&plan->bscratch, batch_scratch_doubles(batch_f2b_grid()) * sizeof(double));
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->bupload_ev, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(e);
+        }
+        if (need > plan->bwork_cap) {
+            if (plan->bwork) {
+                e = hipStreamSynchronize(s);     // the previous batch may still use it
+                if (e == hipSuccess) e = hipFree(plan->bwork);
+                plan->bwork = nullptr;
+                plan->bwork_cap = 0;
+                if (e != hipSuccess) return hip_fail(e);
+            }
+            e = hipMalloc(&plan->bwork, need * sizeof(double));
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return SBR_ENOMEM;
+            }
+            plan->bwork_cap = need;
+            plan->bkey.clear();
+        }
+        if (cnt > plan->bdesc_cap) {
+            e = hipEventSynchronize(plan->bupload_ev);
+            if (plan->bdesc_host) (void)hipHostFree(plan->bdesc_host);
+            if (plan->bdesc_dev) (void)hipFree(plan->bdesc_dev);
+            plan->bdesc_host = nullptr;
+            plan->bdesc_dev = nullptr;
+            e = hipHostMalloc((void**)&plan->bdesc_host, (size_t)cnt * sizeof(BatchDesc), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipMalloc(&plan->bdesc_dev, (size_t)cnt * sizeof(BatchDesc));
+            if (e != hipSuccess) return hip_fail(e);
+            plan->bdesc_cap = cnt;
+            plan->bkey.clear();
+        }
+        if (key != plan->bkey) {
+            // new batch shape: descriptors up, launch sequence captured again
+            e = hipEventSynchronize(plan->bupload_ev);
+            if (e != hipSuccess) return hip_fail(e);
+            int64_t off = 0;
+            for (int32_t q = 0; q < cnt; ++q) {
+                const int32_t k = order[q];
+                const int64_t nk = n[k];
+                const int bk = band[q];
+                BatchDesc& d = plan->bdesc_host[q];
+                d.A = A[k];
+                d.lda = lda[k];
+                d.w = w[k];
+                d.bandA = plan->bwork + off;
+                off += nk * (2 * bk + 1);
+                d.bandB = plan->bwork + off;
+                off += nk * (bk + 1);
+                d.de = plan->bwork + off;
+                off += 2 * nk;
+                d.n = (int32_t)nk;
+                d.b0 = bk;
+            }
+            e = hipMemcpyAsync(plan->bdesc_dev, plan->bdesc_host, (size_t)cnt * sizeof(BatchDesc),
+                               hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipEventRecord(plan->bupload_ev, s);
+            if (e != hipSuccess) return hip_fail(e);
+            if (plan->bgraph) {
+                (void)hipGraphExecDestroy(plan->bgraph);
+                plan->bgraph = nullptr;
+            }
+            const int rc = ensure_side_stream(plan);
+            if (rc) return rc;
+            hipGraph_t g = nullptr;
+            e = hipStreamBeginCapture(plan->side, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e);
+            launch_batched(plan->bdesc_dev, cnt, max_b0, plan->btickets, plan->bscratch, plan->side);
+            e = hipStreamEndCapture(plan->side, &g);
+            if (e == hipSuccess) e = hipGraphInstantiate(&plan->bgraph, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(e);
+            plan->bkey = key;
+        }
+        e = hipGraphLaunch(plan->bgraph, s);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    for (int32_t k : rest) {
+        const int rc = sbr_syev_eigvals_ex(plan, n[k], A[k], lda[k], b0, prec, stream, w[k]);
         if (rc) return rc;
     }
     return 0;

@@ -1,0 +1,534 @@
+// sbr_batched.hip -- the batched form: many independent symmetric matrices
+// (n <= 512), each taken through the same steps as the single-matrix path
+// (Algorithm 4.1 full-to-band with the Eq. (4.1) update, Algorithm 4.2
+// halvings with k = 2 down to a tridiagonal, Sturm bisection), one matrix per
+// work-group instead of one step per grid.
+//
+// Three persistent kernel kinds take matrices from a ticket counter, largest
+// first (the host orders the descriptors by decreasing n):
+//   * batched_f2b_kernel: 8 waves per matrix.  Per panel (width b <= 16, the
+//     tiles padded to 16 columns): Householder QR of the m x b panel (the
+//     single-leaf case of Algorithm 3.2, which yields U, tau and R directly,
+//     so Corollary 3.7's reconstruction is not needed); T from
+//     T^{-1} = diag(1/tau) + striu(U^T U); W = (A22 U) T; Z = U^T W;
+//     V = 1/2 U (T^T Z) - W; A22 += U V^T + V U^T on lower tiles.  FP64
+//     MFMA 16x16x4 throughout, U and T in LDS, W and V in a per-block
+//     global scratch slice.
+//   * batched_band_kernel<h>: one wavefront per matrix for the halving
+//     b = 2h -> h, teams of 2h lanes each chasing one sweep (the team chase of
+//     the small-bandwidth path) in the lag-3 order: chase (i, j) runs after
+//     chase (i, j-1) and after sweep i-1 has finished chase j + 2.  The band
+//     lives in a per-matrix global buffer with ld 2b + 1.
+//   * batched_bisect_kernel: one work-group per matrix, d and e^2 in LDS.
+#include <float.h>
+
+#include "sbr_device.h"
+#include "sbr_internal.h"
+#include "sbr_team_chase.h"
+
+namespace {
+
+using sbr::BatchDesc;
+
+constexpr int BF_NT = 512;                 // 8 waves
+constexpr int BF_NW = BF_NT / 64;
+constexpr int BF_MP = sbr::BATCH_NMAX;     // panel rows held in LDS
+constexpr int BF_LDU = BF_MP + 1;          // U column-major, padded ld
+constexpr int BF_LDT = 17;                 // 16 x 16 blocks, padded ld
+constexpr int BF_TPC = 32;                 // QR: lanes per column (16 columns x 32 = 512)
+constexpr int BF_RPT = BF_MP / BF_TPC;     // QR: rows per lane
+// LDS (doubles): U | T | L | M | Z partials (4 x 256; the QR staging of two
+// reflectors aliases it) | tau
+constexpr int BF_US = 0;
+constexpr int BF_TS = BF_US + BF_LDU * 16;
+constexpr int BF_LS = BF_TS + BF_LDT * 16;
+constexpr int BF_MS = BF_LS + BF_LDT * 16;
+constexpr int BF_ZP = BF_MS + BF_LDT * 16;
+constexpr int BF_TAU = BF_ZP + 4 * 256;
+constexpr int BF_TOTAL = BF_TAU + 16;
+static_assert(4 * 256 >= 2 * BF_MP, "QR staging fits in the partial-product area");
+
+__device__ __forceinline__ sbr_d4 mma(double a, double b, sbr_d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ sbr_d4 zero4() { return sbr_d4{0.0, 0.0, 0.0, 0.0}; }
+
+// All-reduce over the 32 lanes of an aligned half-wave: 16-lane DPP sums, then
+// the two halves exchanged.
+__device__ __forceinline__ double sum32(double v) {
+    v = team_sum<16>(v);
+    return v + __shfl_xor(v, 16);
+}
+
+// MFMA lane layout used below: with a = R(k0 + l/16, c0 + l%16) and
+// b = L(r0 + l%16, k0 + l/16), element r of the accumulator of lane l is
+// (L R)(r0 + l%16, c0 + 4r + l/16).
+__global__ __launch_bounds__(BF_NT) void batched_f2b_kernel(const BatchDesc* __restrict__ desc, int count,
+                                                            int* ticket, double* scratch) {
+    extern __shared__ double sm[];
+    double* Us = sm + BF_US;
+    double* Ts = sm + BF_TS;
+    double* Ls = sm + BF_LS;
+    double* Ms = sm + BF_MS;
+    double* Zp = sm + BF_ZP;
+    double* vbuf = Zp;
+    double* tau = sm + BF_TAU;
+    __shared__ int mat_sh;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    double* Wg = scratch + (int64_t)blockIdx.x * (2 * BF_MP * 16);   // W, column-major, ld BF_MP
+    double* Vg = Wg + BF_MP * 16;                                    // V, same layout
+
+    while (true) {
+        if (t == 0) mat_sh = atomicAdd(ticket, 1);
+        __syncthreads();
+        const int mi = mat_sh;
+        __syncthreads();
+        if (mi >= count) break;
+        const BatchDesc dm = desc[mi];
+        const int n = dm.n, B = dm.b0;
+        const int64_t lda = dm.lda;
+        double* A = dm.A;
+        if (B < 2) continue;
+        for (int c0 = 0;; c0 += B) {
+            const int r0 = c0 + B, m = n - r0;
+            if (m < 2) break;
+            double* P = A + r0 + (int64_t)c0 * lda;
+            double* A22 = A + r0 + (int64_t)r0 * lda;
+
+            // ---- 1. Householder QR of the m x b panel (32 lanes per column)
+            {
+                const int qc = t / BF_TPC, qs = t % BF_TPC;
+                const bool qa = qc < B;
+                double x[BF_RPT];
+#pragma unroll
+                for (int r = 0; r < BF_RPT; ++r) {
+                    const int row = qs + BF_TPC * r;
+                    x[r] = (qa && row < m) ? P[row + (int64_t)qc * lda] : 0.0;
+                }
+                for (int k = 0; k < B; ++k) {
+                    double* v = vbuf + (k & 1) * BF_MP;
+                    if (qc == k) {
+                        double ss = 0.0, xk = 0.0;
+#pragma unroll
+                        for (int r = 0; r < BF_RPT; ++r) {
+                            const int row = qs + BF_TPC * r;
+                            ss += (row > k) ? x[r] * x[r] : 0.0;
+                            xk += (row == k) ? x[r] : 0.0;
+                        }
+                        ss = sum32(ss);
+                        xk = sum32(xk);
+                        const bool none = (ss == 0.0);
+                        const double nrm = sqrt(xk * xk + ss);
+                        const double beta = none ? xk : ((xk >= 0.0) ? -nrm : nrm);
+                        const double tk = none ? 0.0 : (beta - xk) / beta;
+                        const double scal = none ? 0.0 : 1.0 / (xk - beta);
+#pragma unroll
+                        for (int r = 0; r < BF_RPT; ++r) {
+                            const int row = qs + BF_TPC * r;
+                            const double vv = (row < k) ? 0.0 : ((row == k) ? 1.0 : x[r] * scal);
+                            v[row] = vv;
+                            x[r] = (row == k) ? beta : ((row > k) ? vv : x[r]);
+                        }
+                        if (qs == 0) tau[k] = tk;
+                    }
+                    __syncthreads();
+                    if (qa && qc > k) {
+                        const double tk = tau[k];
+                        double d = 0.0;
+#pragma unroll
+                        for (int r = 0; r < BF_RPT; ++r) d += v[qs + BF_TPC * r] * x[r];
+                        d = sum32(d);
+                        const double f = tk * d;
+#pragma unroll
+                        for (int r = 0; r < BF_RPT; ++r) x[r] -= f * v[qs + BF_TPC * r];
+                    }
+                }
+                // U (a zero column where no reflector), [R; 0] back into A; the
+                // padding columns b .. 15 of U are zero
+                {
+                    const double tq = qa ? tau[qc] : 0.0;
+#pragma unroll
+                    for (int r = 0; r < BF_RPT; ++r) {
+                        const int row = qs + BF_TPC * r;
+                        double u = 0.0;
+                        if (tq != 0.0) u = (row == qc) ? 1.0 : ((row > qc) ? x[r] : 0.0);
+                        Us[row + qc * BF_LDU] = u;
+                        if (qa && row < m) P[row + (int64_t)qc * lda] = (row <= qc) ? x[r] : 0.0;
+                    }
+                }
+            }
+            __syncthreads();
+
+            // ---- 2. L = striu(U^T U) + diag(tau): four waves split the rows
+            if (w < 4) {
+                const int kb = (m + 3) / 4;
+                const int ka = w * kb, ke = (ka + kb < m) ? ka + kb : m;
+                sbr_d4 acc = zero4();
+                for (int k0 = ka; k0 < ke; k0 += 4) {
+                    const int k = k0 + lk;
+                    const double uv = (k < ke) ? Us[k + li * BF_LDU] : 0.0;
+                    const double ub = (k < ke) ? Us[k + li * BF_LDU] : 0.0;
+                    acc = mma(uv, ub, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Zp[w * 256 + li + (4 * r + lk) * 16] = acc[r];
+            }
+            __syncthreads();
+            if (t < 256) {
+                const int gi = t % 16, gj = t / 16;
+                const double g = Zp[t] + Zp[256 + t] + Zp[512 + t] + Zp[768 + t];
+                Ls[gi + gj * BF_LDT] = (gi < gj) ? g : ((gi == gj && gi < B) ? tau[gi] : 0.0);
+            }
+            __syncthreads();
+
+            // ---- 3. T = L^{-1} by columns (8 lanes per column)
+            if (t < 128) {
+                const int jc = t >> 3, s = t & 7;
+                const int jmax = ((t >> 6) << 3) + 7;
+                if (s == 0) Ts[jc + jc * BF_LDT] = Ls[jc + jc * BF_LDT];
+                for (int r = jc + 1 + s; r < 16; r += 8) Ts[r + jc * BF_LDT] = 0.0;
+                for (int r = jmax - 1; r >= 0; --r) {
+                    double p = 0.0;
+                    if (r < jc)
+                        for (int k = r + 1 + s; k <= jc; k += 8) p += Ls[r + k * BF_LDT] * Ts[k + jc * BF_LDT];
+                    p = group_sum<8>(p);
+                    if (r < jc && s == 0) Ts[r + jc * BF_LDT] = -Ls[r + r * BF_LDT] * p;
+                }
+            }
+            __syncthreads();
+
+            // ---- 4. W = (A22 U) T by row tiles; W kept in registers (at most
+            // 4 row tiles per wave) and written to the scratch slice
+            const int nI = (m + 15) / 16;
+            sbr_d4 Wr[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                Wr[q] = zero4();
+                const int I = w + q * BF_NW;
+                if (I < nI) {
+                    const int row = I * 16 + li;
+                    sbr_d4 acc = zero4();
+#pragma unroll 4
+                    for (int k0 = 0; k0 < m; k0 += 4) {
+                        const int col = k0 + lk;
+                        double bv = 0.0;
+                        if (row < m && col < m)
+                            bv = (row >= col) ? A22[row + (int64_t)col * lda] : A22[col + (int64_t)row * lda];
+                        const double av = (col < m) ? Us[col + li * BF_LDU] : 0.0;
+                        acc = mma(av, bv, acc);
+                    }
+#pragma unroll
+                    for (int r4 = 0; r4 < 4; ++r4)
+                        Wr[q] = mma(Ts[(4 * r4 + lk) + li * BF_LDT], acc[r4], Wr[q]);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Wg[row + (4 * r + lk) * BF_MP] = Wr[q][r];
+                }
+            }
+            __syncthreads();
+
+            // ---- 5. Z = U^T W (four waves over row quarters), M = T^T Z
+            if (w < 4) {
+                const int kb = (m + 3) / 4;
+                const int ka = w * kb, ke = (ka + kb < m) ? ka + kb : m;
+                sbr_d4 acc = zero4();
+                for (int k0 = ka; k0 < ke; k0 += 4) {
+                    const int k = k0 + lk;
+                    const double wv = (k < ke) ? Wg[k + li * BF_MP] : 0.0;
+                    const double ub = (k < ke) ? Us[k + li * BF_LDU] : 0.0;
+                    acc = mma(wv, ub, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Zp[w * 256 + li + (4 * r + lk) * 16] = acc[r];
+            }
+            __syncthreads();
+            if (t < 256) {
+                const int gi = t % 16, gj = t / 16;
+                double mv = 0.0;
+                for (int k = 0; k <= gi; ++k) {
+                    const int e = k + gj * 16;
+                    mv += Ts[k + gi * BF_LDT] * (Zp[e] + Zp[256 + e] + Zp[512 + e] + Zp[768 + e]);
+                }
+                Ms[gi + gj * BF_LDT] = mv;
+            }
+            __syncthreads();
+
+            // ---- 6. V = 1/2 U M - W by row tiles, to the scratch slice
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int I = w + q * BF_NW;
+                if (I < nI) {
+                    const int row = I * 16 + li;
+                    sbr_d4 acc = zero4();
+#pragma unroll
+                    for (int k0 = 0; k0 < 16; k0 += 4)
+                        acc = mma(Ms[(k0 + lk) + li * BF_LDT], Us[row + (k0 + lk) * BF_LDU], acc);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Vg[row + (4 * r + lk) * BF_MP] = 0.5 * acc[r] - Wr[q][r];
+                }
+            }
+            __syncthreads();
+
+            // ---- 7. A22 += U V^T + V U^T, lower tiles: [U_I, V_I] [V_J, U_J]^T
+            const int ntl = nI * (nI + 1) / 2;
+            for (int x = w; x < ntl; x += BF_NW) {
+                int I = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+                while (I * (I + 1) / 2 > x) --I;
+                while ((I + 1) * (I + 2) / 2 <= x) ++I;
+                const int J = x - I * (I + 1) / 2;
+                const int ri = I * 16 + li, rj = J * 16 + li;
+                sbr_d4 acc = zero4();
+#pragma unroll
+                for (int k0 = 0; k0 < 32; k0 += 4) {
+                    const int k = k0 + lk;
+                    double av, bv;
+                    if (k0 < 16) {
+                        av = Vg[rj + k * BF_MP];
+                        bv = Us[ri + k * BF_LDU];
+                    } else {
+                        av = Us[rj + (k - 16) * BF_LDU];
+                        bv = Vg[ri + (k - 16) * BF_MP];
+                    }
+                    acc = mma(av, bv, acc);
+                }
+                if (ri < m) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int cj = J * 16 + 4 * r + lk;
+                        if (cj <= ri) A22[ri + (int64_t)cj * lda] += acc[r];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Band halvings: one wavefront per matrix, S = 64 / 2h teams.
+
+template <int H>
+__global__ __launch_bounds__(64) void batched_band_kernel(const BatchDesc* __restrict__ desc, int count,
+                                                          int* ticket) {
+    constexpr int TEAM = 2 * H, S = 64 / TEAM, H2 = 2 * H, LDW = 4 * H + 1;
+    __shared__ double scr_all[S * team_chase_scratch<H>()];
+    __shared__ int psweep[S], pdone[S];
+    __shared__ int mat_sh;
+    const int t = threadIdx.x;
+    const int tm = t / TEAM, u = t % TEAM;
+    double* scr = scr_all + tm * team_chase_scratch<H>();
+
+    while (true) {
+        if (t == 0) mat_sh = atomicAdd(ticket, 1);
+        team_sync<64>();
+        const int mi = mat_sh;
+        team_sync<64>();
+        if (mi >= count) break;
+        const BatchDesc dm = desc[mi];
+        const int n = dm.n, b0 = dm.b0;
+        if (b0 < 2 * H) continue;
+        // stage index s = log2(b0 / b): even stages work in bandA, odd in bandB
+        int stage = 0;
+        for (int bb = b0; bb > 2 * H; bb >>= 1) ++stage;
+        double* band = (stage & 1) ? dm.bandB : dm.bandA;
+        double* next = (stage & 1) ? dm.bandA : dm.bandB;
+        if (stage == 0) {
+            // the lower band of the dense A (after full-to-band), headroom zero
+            for (int64_t idx = t; idx < (int64_t)n * LDW; idx += 64) {
+                const int d = (int)(idx % LDW), c = (int)(idx / LDW);
+                band[idx] = (d <= H2 && c + d < n) ? dm.A[(c + d) + (int64_t)c * dm.lda] : 0.0;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            team_sync<64>();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        auto R = [&](int r, int c) -> double& { return band[(r - c) + (int64_t)c * LDW]; };
+        const int nsweeps = (n - 2) / H;
+        auto Jof = [&](int i) -> int { return (n - 2 - i * H) / H2 + 1; };
+        if (u == 0 && tm < S) {
+            psweep[tm] = tm + 1;
+            pdone[tm] = 0;
+        }
+        team_sync<64>();
+        while (true) {
+            // state at the start of the step
+            const int i = psweep[tm], jd = pdone[tm];
+            bool act = (i <= nsweeps);
+            const int j = jd + 1;
+            if (act && i > 1) {
+                const int sp = (tm + S - 1) % S;
+                const int ip = psweep[sp], dp = pdone[sp];
+                // sweep i-1 is finished once its team moved past it
+                act = (ip > i - 1) || (ip == i - 1 && dp >= j + 2);
+            }
+            if (!__any(psweep[tm] <= nsweeps)) break;
+            team_sync<64>();
+            if (act) {
+                const int o = i * H + (j - 1) * H2;
+                const int nr = (n - o < H2) ? n - o : H2;
+                const int cq = (j == 1) ? o - H : o - H2;
+                int nbl = n - (o + H2);
+                if (nbl > H2) nbl = H2;
+                const int nbr = nbl > 0 ? nbl : 0;
+                team_chase<H>(R, o, cq, nr, nbr, j, u, scr);
+            }
+            // band writes of this step complete before any team reads them
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            team_sync<64>();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (act && u == 0) {
+                if (j == Jof(i)) {
+                    psweep[tm] = i + S;
+                    pdone[tm] = 0;
+                } else {
+                    pdone[tm] = j;
+                }
+            }
+            team_sync<64>();
+        }
+        // keep the h + 1 diagonals: into the next buffer with ld 2h + 1, or d
+        // and e for the bisection after the last halving
+        if (H == 1) {
+            double* de = dm.de;
+            for (int c = t; c < n; c += 64) {
+                de[c] = band[(int64_t)c * LDW];
+                de[n + c] = (c + 1 < n) ? band[1 + (int64_t)c * LDW] : 0.0;
+            }
+        } else {
+            constexpr int LDN = 2 * H + 1;
+            for (int64_t idx = t; idx < (int64_t)n * LDN; idx += 64) {
+                const int d = (int)(idx % LDN), c = (int)(idx / LDN);
+                next[idx] = (d <= H && c + d < n) ? band[d + (int64_t)c * LDW] : 0.0;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        team_sync<64>();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sturm bisection per matrix (same counting, guard, interval and iteration
+// rule as the single-matrix kernels).
+
+constexpr int BB_NT = 256;
+
+__global__ __launch_bounds__(BB_NT) void batched_bisect_kernel(const BatchDesc* __restrict__ desc, int count,
+                                                               int* ticket) {
+    __shared__ double sd[sbr::BATCH_NMAX], se[sbr::BATCH_NMAX];
+    __shared__ double r_lo[BB_NT], r_hi[BB_NT], r_e2[BB_NT];
+    __shared__ int mat_sh;
+    const int t = threadIdx.x;
+    while (true) {
+        if (t == 0) mat_sh = atomicAdd(ticket, 1);
+        __syncthreads();
+        const int mi = mat_sh;
+        __syncthreads();
+        if (mi >= count) break;
+        const BatchDesc dm = desc[mi];
+        const int n = dm.n;
+        // d, e^2 (e from the last halving, or straight from A when n <= 2)
+        for (int i = t; i < n; i += BB_NT) {
+            double di, em;
+            if (dm.b0 >= 2) {
+                di = dm.de[i];
+                em = (i > 0) ? dm.de[n + i - 1] : 0.0;
+            } else {
+                di = dm.A[i + (int64_t)i * dm.lda];
+                em = (i > 0) ? dm.A[i + (int64_t)(i - 1) * dm.lda] : 0.0;
+            }
+            sd[i] = di;
+            se[i] = em;   // e_{i-1}, squared below
+        }
+        __syncthreads();
+        double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 1.0;
+        for (int i = t; i < n; i += BB_NT) {
+            const double em = se[i];
+            const double ep = (i + 1 < n) ? se[i + 1] : 0.0;
+            const double rr = fabs(em) + fabs(ep);
+            lo = fmin(lo, sd[i] - rr);
+            hi = fmax(hi, sd[i] + rr);
+            emax2 = fmax(emax2, em * em);
+        }
+        r_lo[t] = lo;
+        r_hi[t] = hi;
+        r_e2[t] = emax2;
+        __syncthreads();
+        for (int o = BB_NT / 2; o > 0; o >>= 1) {
+            if (t < o) {
+                r_lo[t] = fmin(r_lo[t], r_lo[t + o]);
+                r_hi[t] = fmax(r_hi[t], r_hi[t + o]);
+                r_e2[t] = fmax(r_e2[t], r_e2[t + o]);
+            }
+            __syncthreads();
+        }
+        const double pivmin = DBL_MIN * r_e2[0];
+        double l = r_lo[0], h = r_hi[0];
+        const double eps = DBL_EPSILON * 0.5;
+        double tnorm = fmax(fabs(l), fabs(h));
+        const double widen = 2.1 * ((double)n * eps * tnorm + 2.0 * pivmin);
+        l -= widen;
+        h += widen;
+        tnorm = fmax(fabs(l), fabs(h));
+        int iters = 0;
+        if (h > l && tnorm > 0.0) {
+            iters = (int)ceil(log2((h - l) / (eps * tnorm))) + 2;
+            if (iters < 0) iters = 0;
+        }
+        __syncthreads();
+        for (int i = t; i < n; i += BB_NT) se[i] = se[i] * se[i];
+        __syncthreads();
+        for (int k = t; k < n; k += BB_NT) {
+            double a = l, c = h;
+            for (int it = 0; it < iters; ++it) {
+                const double x = a + 0.5 * (c - a);
+                if (x == a || x == c) break;
+                int cnt = 0;
+                double q = 1.0;
+                for (int i = 0; i < n; ++i) {
+                    q = (sd[i] - x) - se[i] / q;
+                    if (fabs(q) < pivmin) q = -pivmin;
+                    cnt += (q < 0.0);
+                }
+                if (cnt >= k + 1) c = x;
+                else a = x;
+            }
+            dm.w[k] = a + 0.5 * (c - a);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void batch_reset_kernel(int* tickets, int count) {
+    if ((int)threadIdx.x < count) tickets[threadIdx.x] = 0;
+}
+
+}  // namespace
+
+namespace sbr {
+
+int64_t batch_scratch_doubles(int grid) { return (int64_t)grid * 2 * BF_MP * 16; }
+
+int batch_f2b_grid() { return 512; }
+
+void launch_batched(const BatchDesc* desc, int count, int max_b0, int* tickets, double* scratch, hipStream_t s) {
+    if (count <= 0) return;
+    batch_reset_kernel<<<1, 64, 0, s>>>(tickets, 8);
+    const int gf = count < batch_f2b_grid() ? count : batch_f2b_grid();
+    batched_f2b_kernel<<<gf, BF_NT, BF_TOTAL * sizeof(double), s>>>(desc, count, tickets + 0, scratch);
+    const int gb = count < 4096 ? count : 4096;
+    if (max_b0 >= 16) batched_band_kernel<8><<<gb, 64, 0, s>>>(desc, count, tickets + 1);
+    if (max_b0 >= 8) batched_band_kernel<4><<<gb, 64, 0, s>>>(desc, count, tickets + 2);
+    if (max_b0 >= 4) batched_band_kernel<2><<<gb, 64, 0, s>>>(desc, count, tickets + 3);
+    if (max_b0 >= 2) batched_band_kernel<1><<<gb, 64, 0, s>>>(desc, count, tickets + 4);
+    const int gs = count < 2048 ? count : 2048;
+    batched_bisect_kernel<<<gs, BB_NT, 0, s>>>(desc, count, tickets + 5);
+}
+
+int init_batched_attributes() {
+    hipError_t e = hipFuncSetAttribute((const void*)batched_f2b_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       BF_TOTAL * (int)sizeof(double));
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+}  // namespace sbr

@@ -76,6 +76,26 @@ int64_t chase_flag_ints(int64_t n, int b);
 void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch,
                        int* flags, int* error, int max_grid, hipStream_t s);
 void launch_fill_int(int* p, int64_t count, int v, hipStream_t s);
+// ---- sbr_batched.hip: many matrices (n <= BATCH_NMAX), one work-group each --
+constexpr int BATCH_NMAX = 512;
+struct BatchDesc {
+    double* A;        // n x n, column-major, lda (overwritten)
+    int64_t lda;
+    double* w;        // n eigenvalues out
+    double* bandA;    // n * (2 b0 + 1) doubles: even halving stages
+    double* bandB;    // n * (b0 + 1) doubles: odd halving stages
+    double* de;       // 2n doubles: d, then e, of the final tridiagonal
+    int32_t n;
+    int32_t b0;       // initial band (power of two, <= 16; 1 when n <= 2)
+};
+int64_t batch_scratch_doubles(int grid);
+int batch_f2b_grid();
+// Every kernel of the batched form, in order, on stream s (capturable: the
+// tickets are reset by a kernel).  desc is a device array of count entries,
+// ordered by decreasing n; tickets: 8 ints.
+void launch_batched(const BatchDesc* desc, int count, int max_b0, int* tickets, double* scratch, hipStream_t s);
+int init_batched_attributes();
+
 // ---- sbr_chase_mfma.hip: b in {32, 64, 128}, chase products on FP64 MFMA --
 bool band_mfma_supported(int b);
 int64_t band_mfma_workspace_doubles(int64_t n, int b);

@@ -189,3 +189,59 @@ def test_eigvalsh_batched(sbr, oracle_mod):
     torch.cuda.synchronize()
     for w, ref in zip(ws, refs):
         assert np.max(np.abs(w.cpu().numpy() - ref)) <= 1e-11 * _norm2(ref)
+
+
+BATCH_SIZES = [1, 2, 3, 4, 5, 9, 17, 33, 64, 65, 96, 97, 128, 200, 257, 300, 511, 512, 600]
+
+
+@pytest.mark.parametrize("b0", [0, 4, 8, 16, 32])
+def test_eigvalsh_batched_sizes(sbr, oracle_mod, b0):
+    # every size class of the batched kernels (n <= 2: no reduction; n > 512
+    # or b0 > 16: the single-matrix path), Gaussian and SCF-like inputs
+    print("batched sizes b0", b0, flush=True)
+    rng = np.random.default_rng(11 + b0)
+    mats = []
+    for k, m in enumerate(BATCH_SIZES):
+        mats.append(si.scf_like(m, rng) if k % 2 else si.gaussian_symmetric(m, rng))
+    refs = [oracle_mod.eigvalsh(M) for M in mats]
+    dev = [torch.from_numpy(M.copy()).cuda() for M in mats]
+    ws = sbr.eigvalsh_batched(dev, b0=b0)
+    torch.cuda.synchronize()
+    for M, w, ref in zip(mats, ws, refs):
+        err = np.max(np.abs(w.cpu().numpy() - ref))
+        assert err <= 1e-11 * max(_norm2(ref), 1e-300) or err == 0.0, (M.shape[0], err)
+
+
+def test_eigvalsh_batched_replay_and_reshape(sbr, oracle_mod):
+    # same buffers twice (the captured launch is replayed on new data), then a
+    # different batch on the same plan (descriptors and launch rebuilt)
+    rng = np.random.default_rng(5)
+    sizes = [40, 300, 150, 512, 70]
+    plan = sbr.Plan(512, 8)
+    dev = [torch.empty((m, m), dtype=torch.float64, device="cuda") for m in sizes]
+    for rep in range(2):
+        mats = [si.scf_like(m, rng) for m in sizes]
+        for d, M in zip(dev, mats):
+            d.copy_(torch.from_numpy(M))
+        ws = sbr.eigvalsh_batched(dev, plan=plan)
+        torch.cuda.synchronize()
+        for M, w in zip(mats, ws):
+            ref = oracle_mod.eigvalsh(M)
+            assert np.max(np.abs(w.cpu().numpy() - ref)) <= 1e-11 * _norm2(ref), (rep, M.shape[0])
+    mats = [si.gaussian_symmetric(m, rng) for m in (100, 31, 257)]
+    dev2 = [torch.from_numpy(M.copy()).cuda() for M in mats]
+    ws = sbr.eigvalsh_batched(dev2, plan=plan)
+    torch.cuda.synchronize()
+    for M, w in zip(mats, ws):
+        ref = oracle_mod.eigvalsh(M)
+        assert np.max(np.abs(w.cpu().numpy() - ref)) <= 1e-11 * _norm2(ref)
+
+
+def test_eigvalsh_batched_fp32_form(sbr, oracle_mod):
+    mats = si.batch_workload(count=16, lo=32, hi=512)
+    refs = [oracle_mod.eigvalsh(M) for M in mats]
+    dev = [torch.from_numpy(M.copy()).cuda() for M in mats]
+    ws = sbr.eigvalsh_batched(dev, precision="fp32_mfma")
+    torch.cuda.synchronize()
+    for w, ref in zip(ws, refs):
+        assert np.max(np.abs(w.cpu().numpy() - ref)) <= 2e-5 * _norm2(ref)
