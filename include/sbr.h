@@ -39,9 +39,14 @@ typedef struct sbr_plan_s* sbr_plan_t;         /* opaque: workspace + tuning */
 
 typedef enum {
     SBR_FP64 = 0,        /* every step in FP64 */
-    SBR_FP32_MFMA = 1    /* trailing updates and WY applications on FP32 MFMA
-                            with FP32 accumulation; storage, Householder norms,
-                            the TSQR R factor and the Sturm counts stay FP64 */
+    SBR_FP32_MFMA = 1    /* full-to-band trailing updates on FP32 MFMA with
+                            FP32 accumulation into an FP32 copy of the
+                            trailing matrix (n^2 floats of plan workspace;
+                            FP64 storage with FP32 products if it cannot be
+                            allocated); each panel's column block returns to
+                            FP64 before its QR, so the panel QR, Householder
+                            norms, R factor, band stages and Sturm counts
+                            stay FP64 */
 } sbr_precision;
 
 enum {

@@ -69,6 +69,9 @@ struct sbr_plan_s {
     hipEvent_t bupload_ev = nullptr;
     hipGraphExec_t bgraph = nullptr;
     std::vector<int64_t> bkey;
+    // FP32-storage copy of the trailing matrix for the FP32-MFMA form
+    float* as_buf = nullptr;
+    int64_t as_cap = 0;
     double *part = nullptr;
     int64_t part_doubles = 0;
     double *T = nullptr, *W1inv = nullptr, *Mm = nullptr, *Zm = nullptr, *S = nullptr;
@@ -276,19 +279,47 @@ int ensure_side_stream(sbr_plan_t p) {
     return e == hipSuccess ? 0 : hip_fail(e);
 }
 
+// FP32 copy of the trailing matrix for the FP32-MFMA form; false when it
+// cannot be allocated (the form then keeps FP64 storage).
+bool ensure_f32_storage(sbr_plan_t p, int64_t n) {
+    if (p->as_cap >= n * n) return true;
+    if (p->as_buf) {
+        (void)hipFree(p->as_buf);
+        p->as_buf = nullptr;
+        p->as_cap = 0;
+    }
+    void* q = nullptr;
+    if (hipMalloc(&q, (size_t)n * n * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    p->as_buf = (float*)q;
+    p->as_cap = n * n;
+    return true;
+}
+
 // Panel k (columns c0 .. c0+b-1, rows below the band) and its trailing
 // update.  The update of panel k's trailing matrix is split: the columns of
 // panel k+1 first, then the rest.  Panel k+1 is factored on the side stream
 // as soon as its columns are final, concurrently with the rest of the update
 // (which touches neither those columns nor the buffers the factorization
 // writes); the caller's stream waits for it before the next W = A22 Y.
+//
+// FP32-MFMA form: the trailing matrix lives in an FP32 copy As (SYMM and SYR2K
+// read and update it with FP32 MFMA and FP32 accumulation); before a panel is
+// factored its column block (diagonal block and panel) is copied back into A,
+// so the panel QR, reconstruction and band stay FP64.
 int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, bool f32, hipStream_t s) {
     const int64_t ldq = p->n_cap;
     int64_t k = 0;
     int cur = 0;
+    const bool f32s = f32 && n - b >= b && ensure_f32_storage(p, n);
+    float* As = f32s ? p->as_buf : nullptr;
+    const int64_t lds = n;
     if (n - b >= b) {
         const int rc = ensure_side_stream(p);
         if (rc) return rc;
+        if (f32s) launch_lower_to_f32(n - b, A + b + b * lda, lda, As + b + b * lds, lds, s);
         factor_panel(p, n - b, b, A + b, lda, p->Ub[0], s);
         launch_gemm(false, false, false, n - b, b, b, 1.0, p->Ub[0], ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, s);
     }
@@ -297,11 +328,13 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
         if (m < b) break;
         double* U = p->Ub[cur];
         double* A22 = A + r0 + r0 * lda;
+        float* A22s = f32s ? As + r0 + r0 * lds : nullptr;
         // W = A22 Y  (Y = U T)
         EventPair ep;
         if (p->timing) { ep.a = p->ev(); p->mark(ep.a, s); }
         const int ss = symm_splits(m, b);
-        launch_symm_lower(f32, m, b, A22, lda, p->Y, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
+        if (f32s) launch_symm_lower_f32s(m, b, A22s, lds, p->Y, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
+        else launch_symm_lower(f32, m, b, A22, lda, p->Y, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
         if (p->timing) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_symm.push_back(ep); }
         // Z = U^T W ; M = T^T Z ; V = 1/2 U M - W
         const int gs = gemm_splits(b, b, m);
@@ -313,7 +346,12 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
         EventPair eq;
         const int64_t mn = m - b;          // rows of the next panel
         if (mn >= b) {
-            launch_syr2k_lower_cols(f32, m, b, b, U, ldq, p->V, ldq, A22, lda, s);
+            if (f32s) {
+                launch_syr2k_lower_cols_f32s(m, b, b, U, ldq, p->V, ldq, A22s, lds, s);
+                launch_cols_to_f64(m, b, A22s, lds, A22, lda, s);
+            } else {
+                launch_syr2k_lower_cols(f32, m, b, b, U, ldq, p->V, ldq, A22, lda, s);
+            }
             hipError_t e = hipEventRecord(p->ev_fork, s);
             if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
             if (e != hipSuccess) return hip_fail(e);
@@ -323,15 +361,19 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
             e = hipEventRecord(p->ev_join, p->side);
             if (e != hipSuccess) return hip_fail(e);
             if (p->timing) { eq.a = p->ev(); p->mark(eq.a, s); }
-            launch_syr2k_lower(f32, mn, b, U + b, ldq, p->V + b, ldq, A22 + b + b * lda, lda, s);
+            if (f32s) launch_syr2k_lower_f32s(mn, b, U + b, ldq, p->V + b, ldq, A22s + b + b * lds, lds, s);
+            else launch_syr2k_lower(f32, mn, b, U + b, ldq, p->V + b, ldq, A22 + b + b * lda, lda, s);
             if (p->timing) { eq.b = p->ev(); p->mark(eq.b, s); p->ev_syr2k.push_back(eq); }
             e = hipStreamWaitEvent(s, p->ev_join, 0);
             if (e != hipSuccess) return hip_fail(e);
             cur ^= 1;
         } else {
             if (p->timing) { eq.a = p->ev(); p->mark(eq.a, s); }
-            launch_syr2k_lower(f32, m, b, U, ldq, p->V, ldq, A22, lda, s);
+            if (f32s) launch_syr2k_lower_f32s(m, b, U, ldq, p->V, ldq, A22s, lds, s);
+            else launch_syr2k_lower(f32, m, b, U, ldq, p->V, ldq, A22, lda, s);
             if (p->timing) { eq.b = p->ev(); p->mark(eq.b, s); p->ev_syr2k.push_back(eq); }
+            // the rest of the trailing matrix back to FP64 for the ragged tail
+            if (f32s) launch_cols_to_f64(m, m, A22s, lds, A22, lda, s);
         }
         SBR_CHECK_LAUNCH();
     }
@@ -418,6 +460,7 @@ int sbr_plan_create(sbr_plan_t* plan, int64_t n_max, int32_t batch_max, sbr_prec
             delete p;
             return rc;
         }
+        if (prec == SBR_FP32_MFMA) (void)ensure_f32_storage(p, n_max);
     }
     *plan = p;
     return 0;
@@ -429,6 +472,7 @@ int sbr_plan_destroy(sbr_plan_t plan) {
     (void)hipSetDevice(plan->device);
     (void)hipDeviceSynchronize();
     for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
+    if (plan->as_buf) (void)hipFree(plan->as_buf);
     if (plan->bgraph) (void)hipGraphExecDestroy(plan->bgraph);
     if (plan->bupload_ev) (void)hipEventDestroy(plan->bupload_ev);
     if (plan->bdesc_host) (void)hipHostFree(plan->bdesc_host);
@@ -451,6 +495,7 @@ int sbr_workspace_size(int64_t n, int32_t b0, sbr_precision prec, size_t* bytes)
     if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -3;
     if (!bytes) return -4;
     *bytes = make_layout(std::max<int64_t>(n, 1), b0).bytes;
+    if (prec == SBR_FP32_MFMA) *bytes += (size_t)n * n * sizeof(float);   // FP32 copy of the trailing matrix
     return 0;
 }
 

@@ -19,7 +19,8 @@
 //     the small-bandwidth path) in the lag-3 order: chase (i, j) runs after
 //     chase (i, j-1) and after sweep i-1 has finished chase j + 2.  The band
 //     lives in a per-matrix global buffer with ld 2b + 1.
-//   * batched_bisect_kernel: one work-group per matrix, d and e^2 in LDS.
+//   * batched_bisect_kernel: one wavefront per matrix, d and e^2 in LDS, each
+//     lane bisecting up to 8 eigenvalue indices in lockstep.
 #include <float.h>
 
 #include "sbr_device.h"
@@ -411,91 +412,128 @@ __global__ __launch_bounds__(64) void batched_band_kernel(const BatchDesc* __res
 // Sturm bisection per matrix (same counting, guard, interval and iteration
 // rule as the single-matrix kernels).
 
-constexpr int BB_NT = 256;
+constexpr int BB_NT = 64;   // one wavefront per matrix
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// KQ eigenvalue indices per lane (k = lane + 64 q), bisected in lockstep: KQ
+// independent count recurrences per step hide the latency of each chain's
+// divisions.
+template <int KQ>
+__device__ __forceinline__ void bisect_lanes(int n, const double* sd, const double* se, double lo, double hi,
+                                             double piv, int iters, double* w, int lane) {
+    double a[KQ], c[KQ];
+    bool live[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+        a[q] = lo;
+        c[q] = hi;
+        live[q] = lane + 64 * q < n;
+    }
+    for (int it = 0; it < iters; ++it) {
+        double x[KQ], qv[KQ];
+        int cnt[KQ];
+        bool anyl = false;
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            x[q] = a[q] + 0.5 * (c[q] - a[q]);
+            if (live[q] && (x[q] == a[q] || x[q] == c[q])) live[q] = false;
+            anyl |= live[q];
+            qv[q] = 1.0;
+            cnt[q] = 0;
+        }
+        if (!__any(anyl)) break;
+        for (int i = 0; i < n; ++i) {
+            const double di = sd[i], ei = se[i];
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) {
+                double v = (di - x[q]) - ei / qv[q];
+                v = (fabs(v) < piv) ? -piv : v;
+                qv[q] = v;
+                cnt[q] += (v < 0.0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            if (live[q]) {
+                if (cnt[q] >= lane + 64 * q + 1) c[q] = x[q];
+                else a[q] = x[q];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < KQ; ++q)
+        if (lane + 64 * q < n) w[lane + 64 * q] = a[q] + 0.5 * (c[q] - a[q]);
+}
 
 __global__ __launch_bounds__(BB_NT) void batched_bisect_kernel(const BatchDesc* __restrict__ desc, int count,
                                                                int* ticket) {
     __shared__ double sd[sbr::BATCH_NMAX], se[sbr::BATCH_NMAX];
-    __shared__ double r_lo[BB_NT], r_hi[BB_NT], r_e2[BB_NT];
     __shared__ int mat_sh;
     const int t = threadIdx.x;
     while (true) {
         if (t == 0) mat_sh = atomicAdd(ticket, 1);
-        __syncthreads();
+        team_sync<64>();
         const int mi = mat_sh;
-        __syncthreads();
+        team_sync<64>();
         if (mi >= count) break;
         const BatchDesc dm = desc[mi];
         const int n = dm.n;
-        // d, e^2 (e from the last halving, or straight from A when n <= 2)
+        // d, e_{i-1} (from the last halving, or straight from A when n <= 2)
+        double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 1.0;
         for (int i = t; i < n; i += BB_NT) {
-            double di, em;
+            double di, em, ep;
             if (dm.b0 >= 2) {
                 di = dm.de[i];
                 em = (i > 0) ? dm.de[n + i - 1] : 0.0;
+                ep = (i + 1 < n) ? dm.de[n + i] : 0.0;
             } else {
                 di = dm.A[i + (int64_t)i * dm.lda];
                 em = (i > 0) ? dm.A[i + (int64_t)(i - 1) * dm.lda] : 0.0;
+                ep = (i + 1 < n) ? dm.A[(i + 1) + (int64_t)i * dm.lda] : 0.0;
             }
             sd[i] = di;
-            se[i] = em;   // e_{i-1}, squared below
-        }
-        __syncthreads();
-        double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 1.0;
-        for (int i = t; i < n; i += BB_NT) {
-            const double em = se[i];
-            const double ep = (i + 1 < n) ? se[i + 1] : 0.0;
+            se[i] = em * em;
             const double rr = fabs(em) + fabs(ep);
-            lo = fmin(lo, sd[i] - rr);
-            hi = fmax(hi, sd[i] + rr);
+            lo = fmin(lo, di - rr);
+            hi = fmax(hi, di + rr);
             emax2 = fmax(emax2, em * em);
         }
-        r_lo[t] = lo;
-        r_hi[t] = hi;
-        r_e2[t] = emax2;
-        __syncthreads();
-        for (int o = BB_NT / 2; o > 0; o >>= 1) {
-            if (t < o) {
-                r_lo[t] = fmin(r_lo[t], r_lo[t + o]);
-                r_hi[t] = fmax(r_hi[t], r_hi[t + o]);
-                r_e2[t] = fmax(r_e2[t], r_e2[t + o]);
-            }
-            __syncthreads();
-        }
-        const double pivmin = DBL_MIN * r_e2[0];
-        double l = r_lo[0], h = r_hi[0];
+        lo = wave_min(lo);
+        hi = wave_max(hi);
+        emax2 = wave_max(emax2);
+        team_sync<64>();
+        const double pivmin = DBL_MIN * emax2;
         const double eps = DBL_EPSILON * 0.5;
-        double tnorm = fmax(fabs(l), fabs(h));
+        double tnorm = fmax(fabs(lo), fabs(hi));
         const double widen = 2.1 * ((double)n * eps * tnorm + 2.0 * pivmin);
-        l -= widen;
-        h += widen;
+        const double l = lo - widen, h = hi + widen;
         tnorm = fmax(fabs(l), fabs(h));
         int iters = 0;
         if (h > l && tnorm > 0.0) {
             iters = (int)ceil(log2((h - l) / (eps * tnorm))) + 2;
             if (iters < 0) iters = 0;
         }
-        __syncthreads();
-        for (int i = t; i < n; i += BB_NT) se[i] = se[i] * se[i];
-        __syncthreads();
-        for (int k = t; k < n; k += BB_NT) {
-            double a = l, c = h;
-            for (int it = 0; it < iters; ++it) {
-                const double x = a + 0.5 * (c - a);
-                if (x == a || x == c) break;
-                int cnt = 0;
-                double q = 1.0;
-                for (int i = 0; i < n; ++i) {
-                    q = (sd[i] - x) - se[i] / q;
-                    if (fabs(q) < pivmin) q = -pivmin;
-                    cnt += (q < 0.0);
-                }
-                if (cnt >= k + 1) c = x;
-                else a = x;
-            }
-            dm.w[k] = a + 0.5 * (c - a);
+        switch ((n + 63) / 64) {
+            case 1: bisect_lanes<1>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
+            case 2: bisect_lanes<2>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
+            case 3: bisect_lanes<3>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
+            case 4: bisect_lanes<4>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
+            case 5: bisect_lanes<5>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
+            case 6: bisect_lanes<6>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
+            case 7: bisect_lanes<7>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
+            default: bisect_lanes<8>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
         }
-        __syncthreads();
+        team_sync<64>();
     }
 }
 
@@ -521,7 +559,7 @@ void launch_batched(const BatchDesc* desc, int count, int max_b0, int* tickets, 
     if (max_b0 >= 8) batched_band_kernel<4><<<gb, 64, 0, s>>>(desc, count, tickets + 2);
     if (max_b0 >= 4) batched_band_kernel<2><<<gb, 64, 0, s>>>(desc, count, tickets + 3);
     if (max_b0 >= 2) batched_band_kernel<1><<<gb, 64, 0, s>>>(desc, count, tickets + 4);
-    const int gs = count < 2048 ? count : 2048;
+    const int gs = count < 8192 ? count : 8192;
     batched_bisect_kernel<<<gs, BB_NT, 0, s>>>(desc, count, tickets + 5);
 }
 

@@ -70,21 +70,30 @@ __global__ __launch_bounds__(PREP_NT) void bisect_prep_kernel(int64_t n, const d
     }
 }
 
-template <int NT, int CH>
+// Multisection: G lanes per eigenvalue index, lane g evaluates the Sturm count
+// at x_g = a + (g + 1) (c - a) / (G + 1); the interval then shrinks to the
+// piece between the last point with count <= k and the next one, a factor
+// G + 1 per round.  More lanes per index keep every SIMD busy when there are
+// few indices per SIMD (the count recurrence is a serial chain of divisions).
+template <int NT, int CH, int G>
 __global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __restrict__ d,
                                                     const double* __restrict__ e2p,
                                                     const sbr::BisectSetup* __restrict__ setup,
                                                     double* __restrict__ w) {
+    static_assert(G == 4 || G == 8, "lanes per index");
     __shared__ double sd[CH], se[CH];
-    const int t = threadIdx.x;
-    const int64_t k = (int64_t)blockIdx.x * NT + t;   // 0-based index: the (k+1)-th smallest
+    const int t = threadIdx.x, g = t % G;
+    const int64_t k = (int64_t)blockIdx.x * (NT / G) + t / G;   // 0-based: the (k+1)-th smallest
     const double lo = setup->lo, hi = setup->hi, piv = setup->pivmin;
+    // rounds so that (hi - lo) / (G + 1)^rounds is below the bisection's
+    // final width (hi - lo) / 2^iters
     const int iters = setup->iters;
+    const int rounds = (int)ceil((double)iters / log2((double)(G + 1)));
     double a = lo, c = hi;
     bool live = (k < n);
-    for (int it = 0; it < iters; ++it) {
-        const double x = a + 0.5 * (c - a);
-        const bool act = live && (x != a) && (x != c);
+    for (int it = 0; it < rounds; ++it) {
+        const double x = a + (double)(g + 1) * ((c - a) / (double)(G + 1));
+        const bool act = live && (c - a) > 0.0 && (x > a) && (x < c);
         if (!__syncthreads_or(act)) break;
         int64_t cnt = 0;
         double q = 1.0;
@@ -102,14 +111,34 @@ __global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __r
                 cnt += (q < 0.0);
             }
         }
-        if (act) {
-            if (cnt >= k + 1) c = x;
-            else a = x;
-        } else {
-            live = false;
+        // p = number of points left of the eigenvalue (count <= k); the
+        // counts are monotone in x, so the eigenvalue lies in [x_{p-1}, x_p]
+        // (x_{-1} = a, x_G = c).  The lanes of a group hold the same a, c and
+        // evaluate the same formula for the points, so they agree on the ends.
+        double left = (cnt <= k) ? 1.0 : 0.0;
+        double any = act ? 1.0 : 0.0;
+        left += dpp_d<0xB1>(left);
+        any += dpp_d<0xB1>(any);
+        left += dpp_d<0x4E>(left);
+        any += dpp_d<0x4E>(any);
+        if (G == 8) {
+            left += dpp_d<0x141>(left);
+            any += dpp_d<0x141>(any);
+        }
+        if (live) {
+            if (any > 0.0) {
+                const int p = (int)left;
+                const double step = (c - a) / (double)(G + 1);
+                const double na = (p == 0) ? a : a + (double)p * step;
+                const double nc = (p == G) ? c : a + (double)(p + 1) * step;
+                a = na;
+                c = nc;
+            } else {
+                live = false;   // no point of the group strictly inside: converged
+            }
         }
     }
-    if (k < n) w[k] = a + 0.5 * (c - a);
+    if (k < n && g == 0) w[k] = a + 0.5 * (c - a);
 }
 
 }  // namespace
@@ -120,9 +149,9 @@ void launch_tridiag_eigvals(int64_t n, const double* d, const double* e, double*
                             double* w, hipStream_t s) {
     if (n <= 0) return;
     bisect_prep_kernel<<<1, PREP_NT, 0, s>>>(n, d, e, e2p, setup);
-    constexpr int NT = 128, CH = 2048;
-    const unsigned blocks = (unsigned)((n + NT - 1) / NT);
-    bisect_kernel<NT, CH><<<blocks, NT, 0, s>>>(n, d, e2p, setup, w);
+    constexpr int NT = 256, CH = 2048, G = 4;
+    const unsigned blocks = (unsigned)((n + NT / G - 1) / (NT / G));
+    bisect_kernel<NT, CH, G><<<blocks, NT, 0, s>>>(n, d, e2p, setup, w);
 }
 
 }  // namespace sbr

@@ -59,12 +59,12 @@ struct TileMap {
 // Waves are arranged WM x WN; wave (wm, wn) owns C rows [wm*WTM, +WTM) and
 // columns [wn*WTN, +WTN).  Accumulator acc[tn][tm][r] holds
 //   C(wm*WTM + tm*16 + (lane & 15), wn*WTN + tn*16 + Mfma<CT>::out_row(lane, r)).
-template <typename CT, int BM, int BN, int WM, int WN>
+template <typename CT, int BM, int BN, int WM, int WN, int PAD = 2>
 struct TileEngine {
     static constexpr int NT = 64 * WM * WN;
     static constexpr int WTM = BM / WM, WTN = BN / WN;
     static constexpr int TM = WTM / 16, TN = WTN / 16;
-    static constexpr int LDA = BM + 2, LDB = BN + 2;
+    static constexpr int LDA = BM + PAD, LDB = BN + PAD;   // LDS row strides (elements)
     static_assert(TM >= 1 && TN >= 1 && TM * 16 * WM == BM && TN * 16 * WN == BN, "bad tile shape");
     typedef typename Mfma<CT>::acc_t acc_t;
     acc_t acc[TN][TM];

@@ -152,11 +152,12 @@ __device__ __forceinline__ void lower_tile_banded(int64_t x, int64_t T, int64_t&
 // GEMM with K' = 2K: [U_I, V_I] * [V_J, U_J]^T.  jt = 0: all lower tiles,
 // in the banded order above (nc = m); jt > 0: the first jt tile columns,
 // enumerated row by row.  Double-buffered LDS, one barrier per K chunk.
-template <typename CT, int BM, int WM, int WN>
+// ST: storage type of C (double, or float for the FP32-storage form).
+template <typename CT, int BM, int WM, int WN, int PAD = 2, typename ST = double>
 __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     int64_t m, int64_t nc, int64_t jt, int64_t K, const double* __restrict__ U, int64_t ldu,
-    const double* __restrict__ V, int64_t ldv, double* C, int64_t ldc, int64_t ntiles) {
-    typedef TileEngine<CT, BM, BM, WM, WN> E;
+    const double* __restrict__ V, int64_t ldv, ST* C, int64_t ldc, int64_t ntiles) {
+    typedef TileEngine<CT, BM, BM, WM, WN, PAD> E;
     typedef TileMap<BM, E::NT, false> MA;   // row fastest (column-major U, V)
     typedef TileMap<BM, E::NT, false> MB;
     __shared__ CT As[2][SBR_BK * E::LDA];
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = i0 + E::row_of(wm, tm, lane);
                 const int64_t j = j0 + E::col_of(wn, tn, lane, r);
-                if (i < m && j <= i && j < nc) C[i + j * ldc] += (double)eng.acc[tn][tm][r];
+                if (i < m && j <= i && j < nc) C[i + j * ldc] += (ST)eng.acc[tn][tm][r];
             }
 }
 
@@ -239,11 +240,11 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
 // the A tile lies entirely below the diagonal (read A[i + k lda], rows
 // contiguous), entirely above it (read the mirror A[k + i lda], k
 // contiguous) or straddles it (element-wise choice).  Double-buffered LDS.
-template <typename CT, int BM, int BN, int WM, int WN>
+template <typename CT, int BM, int BN, int WM, int WN, int PAD = 2, typename ST = double>
 __global__ __launch_bounds__(64 * WM * WN) void symm_lower_kernel(
-    int64_t m, int64_t nb, int64_t kchunk, const double* __restrict__ A, int64_t lda,
+    int64_t m, int64_t nb, int64_t kchunk, const ST* __restrict__ A, int64_t lda,
     const double* __restrict__ Y, int64_t ldy, double* W, int64_t ldw, int64_t slice_stride) {
-    typedef TileEngine<CT, BM, BN, WM, WN> E;
+    typedef TileEngine<CT, BM, BN, WM, WN, PAD> E;
     typedef TileMap<BM, E::NT, false> MAi;   // row fastest
     typedef TileMap<BM, E::NT, true> MAk;    // k fastest
     typedef TileMap<BN, E::NT, true> MB;     // Y[k + j ldy]: k contiguous
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(64 * WM * WN) void symm_lower_kernel(
             if (kfast) MAk::coords(t, e, i, k); else MAi::coords(t, e, i, k);
             const int64_t gi = i0 + i, gk = k0 + k;
             double v = 0.0;
-            if (gi < m && gk < kend) v = (gi >= gk) ? A[gi + gk * lda] : A[gk + gi * lda];
+            if (gi < m && gk < kend) v = (gi >= gk) ? (double)A[gi + gk * lda] : (double)A[gk + gi * lda];
             ra[e] = (CT)v;
         }
 #pragma unroll
@@ -354,27 +355,41 @@ void gemm_dispatch_t(bool ta, bool tb, int64_t M, int64_t N, int64_t K, int64_t 
     else gemm_dispatch<CT, true, true>(M, N, K, kchunk, splits, alpha, A, lda, B, ldb, beta, Cin, ldci, Cout, ldco, slice_stride, s);
 }
 
-template <typename CT>
-void symm_dispatch(int64_t m, int64_t nb, int64_t kchunk, int splits, const double* A, int64_t lda,
+template <typename CT, typename ST>
+void symm_dispatch(int64_t m, int64_t nb, int64_t kchunk, int splits, const ST* A, int64_t lda,
                    const double* Y, int64_t ldy, double* W, int64_t ldw, int64_t slice_stride, hipStream_t s) {
     if (nb > 64) {
         if (m >= 2048) {
             dim3 g(cdiv(m, 128), cdiv(nb, 128), splits);
-            symm_lower_kernel<CT, 128, 128, 2, 4><<<g, 512, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+            symm_lower_kernel<CT, 128, 128, 2, 4, 2, ST><<<g, 512, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
         } else {
             dim3 g(cdiv(m, 64), cdiv(nb, 128), splits);
-            symm_lower_kernel<CT, 64, 128, 2, 2><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+            symm_lower_kernel<CT, 64, 128, 2, 2, 2, ST><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
         }
     } else if (nb > 32) {
         dim3 g(cdiv(m, 64), cdiv(nb, 64), splits);
-        symm_lower_kernel<CT, 64, 64, 2, 2><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+        symm_lower_kernel<CT, 64, 64, 2, 2, 2, ST><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
     } else if (nb > 16) {
         dim3 g(cdiv(m, 64), cdiv(nb, 32), splits);
-        symm_lower_kernel<CT, 64, 32, 4, 1><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+        symm_lower_kernel<CT, 64, 32, 4, 1, 2, ST><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
     } else {
         dim3 g(cdiv(m, 64), cdiv(nb, 16), splits);
-        symm_lower_kernel<CT, 64, 16, 4, 1><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+        symm_lower_kernel<CT, 64, 16, 4, 1, 2, ST><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
     }
+}
+
+// Lower triangle of the m x m block of A (ld lda) into the FP32 copy As
+// (ld lds), and a column block of As (rows [0, m), the first nc columns, lower
+// part) back into A.
+__global__ void lower_to_f32_kernel(int64_t m, const double* __restrict__ A, int64_t lda, float* As, int64_t lds) {
+    const int64_t j = blockIdx.y;
+    for (int64_t i = j + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        As[i + j * lds] = (float)A[i + j * lda];
+}
+__global__ void cols_to_f64_kernel(int64_t m, const float* __restrict__ As, int64_t lds, double* A, int64_t lda) {
+    const int64_t j = blockIdx.y;
+    for (int64_t i = j + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        A[i + j * lda] = (double)As[i + j * lds];
 }
 
 void reduce_slices(int64_t M, int64_t N, int splits, const double* part, double alpha, double beta,
@@ -462,15 +477,64 @@ void launch_symm_lower(bool f32, int64_t m, int64_t nb, const double* A, int64_t
                        int64_t ldy, double* W, int64_t ldw, double* part, int splits, hipStream_t s) {
     if (m <= 0 || nb <= 0) return;
     if (splits <= 1 || part == nullptr) {
-        if (f32) symm_dispatch<float>(m, nb, m, 1, A, lda, Y, ldy, W, ldw, 0, s);
-        else symm_dispatch<double>(m, nb, m, 1, A, lda, Y, ldy, W, ldw, 0, s);
+        if (f32) symm_dispatch<float, double>(m, nb, m, 1, A, lda, Y, ldy, W, ldw, 0, s);
+        else symm_dispatch<double, double>(m, nb, m, 1, A, lda, Y, ldy, W, ldw, 0, s);
         return;
     }
     int64_t kchunk = (m + splits - 1) / splits;
     kchunk = (kchunk + SBR_BK - 1) / SBR_BK * SBR_BK;
-    if (f32) symm_dispatch<float>(m, nb, kchunk, splits, A, lda, Y, ldy, part, m, m * nb, s);
-    else symm_dispatch<double>(m, nb, kchunk, splits, A, lda, Y, ldy, part, m, m * nb, s);
+    if (f32) symm_dispatch<float, double>(m, nb, kchunk, splits, A, lda, Y, ldy, part, m, m * nb, s);
+    else symm_dispatch<double, double>(m, nb, kchunk, splits, A, lda, Y, ldy, part, m, m * nb, s);
     reduce_slices(m, nb, splits, part, 1.0, 0.0, nullptr, 0, W, ldw, s);
+}
+
+// ---- FP32-storage form: the trailing matrix lives in an FP32 copy
+void launch_syr2k_lower_f32s(int64_t m, int64_t K, const double* U, int64_t ldu, const double* V, int64_t ldv,
+                             float* C, int64_t ldc, hipStream_t s) {
+    if (m <= 0 || K <= 0) return;
+    const int64_t T128 = (m + 127) / 128;
+    if (T128 * (T128 + 1) / 2 >= 512) {
+        const int64_t nt = T128 * (T128 + 1) / 2;
+        syr2k_lower_kernel<float, 128, 2, 4, 2, float><<<(unsigned)nt, 512, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
+        return;
+    }
+    const int64_t T = (m + 63) / 64;
+    const int64_t nt = T * (T + 1) / 2;
+    syr2k_lower_kernel<float, 64, 2, 2, 2, float><<<(unsigned)nt, 256, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
+}
+
+void launch_syr2k_lower_cols_f32s(int64_t m, int64_t nc, int64_t K, const double* U, int64_t ldu, const double* V,
+                                  int64_t ldv, float* C, int64_t ldc, hipStream_t s) {
+    if (m <= 0 || K <= 0 || nc <= 0) return;
+    if (nc > m) nc = m;
+    const int64_t T = (m + 63) / 64, jt = (nc + 63) / 64;
+    const int64_t nt = T * jt;
+    syr2k_lower_kernel<float, 64, 2, 2, 2, float><<<(unsigned)nt, 256, 0, s>>>(m, nc, jt, K, U, ldu, V, ldv, C, ldc, nt);
+}
+
+void launch_symm_lower_f32s(int64_t m, int64_t nb, const float* A, int64_t lda, const double* Y, int64_t ldy,
+                            double* W, int64_t ldw, double* part, int splits, hipStream_t s) {
+    if (m <= 0 || nb <= 0) return;
+    if (splits <= 1 || part == nullptr) {
+        symm_dispatch<float, float>(m, nb, m, 1, A, lda, Y, ldy, W, ldw, 0, s);
+        return;
+    }
+    int64_t kchunk = (m + splits - 1) / splits;
+    kchunk = (kchunk + SBR_BK - 1) / SBR_BK * SBR_BK;
+    symm_dispatch<float, float>(m, nb, kchunk, splits, A, lda, Y, ldy, part, m, m * nb, s);
+    reduce_slices(m, nb, splits, part, 1.0, 0.0, nullptr, 0, W, ldw, s);
+}
+
+void launch_lower_to_f32(int64_t m, const double* A, int64_t lda, float* As, int64_t lds, hipStream_t s) {
+    if (m <= 0) return;
+    dim3 g((unsigned)cdiv(m, 1024) < 64 ? (unsigned)cdiv(m, 1024) : 64, (unsigned)m);
+    lower_to_f32_kernel<<<g, 256, 0, s>>>(m, A, lda, As, lds);
+}
+
+void launch_cols_to_f64(int64_t m, int64_t nc, const float* As, int64_t lds, double* A, int64_t lda, hipStream_t s) {
+    if (m <= 0 || nc <= 0) return;
+    dim3 g((unsigned)cdiv(m, 1024) < 64 ? (unsigned)cdiv(m, 1024) : 64, (unsigned)nc);
+    cols_to_f64_kernel<<<g, 256, 0, s>>>(m, As, lds, A, lda);
 }
 
 }  // namespace sbr

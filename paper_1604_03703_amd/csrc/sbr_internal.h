@@ -21,6 +21,18 @@ void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t
 void launch_syr2k_lower_cols(bool f32, int64_t m, int64_t nc, int64_t K, const double* U, int64_t ldu,
                              const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s);
 int symm_splits(int64_t m, int64_t nb);
+// FP32-storage form: C / A are an FP32 copy of the trailing matrix (FP32
+// MFMA products, FP32 accumulation into FP32 storage).
+void launch_syr2k_lower_f32s(int64_t m, int64_t K, const double* U, int64_t ldu, const double* V, int64_t ldv,
+                             float* C, int64_t ldc, hipStream_t s);
+void launch_syr2k_lower_cols_f32s(int64_t m, int64_t nc, int64_t K, const double* U, int64_t ldu, const double* V,
+                                  int64_t ldv, float* C, int64_t ldc, hipStream_t s);
+void launch_symm_lower_f32s(int64_t m, int64_t nb, const float* A, int64_t lda, const double* Y, int64_t ldy,
+                            double* W, int64_t ldw, double* part, int splits, hipStream_t s);
+// Lower triangle of A's m x m block -> As (FP32); the first nc columns of As's
+// m x m block (lower part) -> A (FP64).
+void launch_lower_to_f32(int64_t m, const double* A, int64_t lda, float* As, int64_t lds, hipStream_t s);
+void launch_cols_to_f64(int64_t m, int64_t nc, const float* As, int64_t lds, double* A, int64_t lda, hipStream_t s);
 void launch_symm_lower(bool f32, int64_t m, int64_t nb, const double* A, int64_t lda, const double* Y,
                        int64_t ldy, double* W, int64_t ldw, double* part, int splits, hipStream_t s);
 
