@@ -178,7 +178,41 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     E eng;
     eng.zero();
     CT ra[MA::E], rb[MB::E];
+    // Fast path (U and V share the leading dimension and K is a multiple of
+    // the chunk depth, so a chunk lies wholly in the U or the V half of K'):
+    // per-thread element offsets are fixed, a chunk only moves the base.
+    // (FP32 compute only: in FP64 the offsets cost the registers of a second
+    // resident block, which hides more latency than they save)
+    constexpr bool kOffsets = sizeof(CT) == 4;
+    const bool fast = kOffsets && (ldu == ldv) && (K % SBR_BK == 0) && (m + BM) + (int64_t)SBR_BK * ldu < INT32_MAX;
+    int32_t offa[MA::E], offb[MB::E];
+    bool oka[MA::E], okb[MB::E];
+    if constexpr (kOffsets) {
+#pragma unroll
+        for (int e = 0; e < MA::E; ++e) {
+            int i, k;
+            MA::coords(t, e, i, k);
+            offa[e] = (int32_t)((i0 + i) + (int64_t)k * ldu);
+            oka[e] = i0 + i < m;
+        }
+#pragma unroll
+        for (int e = 0; e < MB::E; ++e) {
+            int j, k;
+            MB::coords(t, e, j, k);
+            offb[e] = (int32_t)((j0 + j) + (int64_t)k * ldu);
+            okb[e] = j0 + j < m;
+        }
+    }
     auto load = [&](int64_t k0) {
+        if (kOffsets && fast) {
+            const double* pa = (k0 < K) ? U + k0 * ldu : V + (k0 - K) * ldu;
+            const double* pb = (k0 < K) ? V + k0 * ldu : U + (k0 - K) * ldu;
+#pragma unroll
+            for (int e = 0; e < MA::E; ++e) ra[e] = oka[e] ? (CT)pa[offa[e]] : (CT)0;
+#pragma unroll
+            for (int e = 0; e < MB::E; ++e) rb[e] = okb[e] ? (CT)pb[offb[e]] : (CT)0;
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < MA::E; ++e) {
             int i, k;
@@ -260,8 +294,52 @@ __global__ __launch_bounds__(64 * WM * WN) void symm_lower_kernel(
     eng.zero();
     CT ra[MAi::E], rb[MB::E];
     bool kfast = false;
+    // per-thread element offsets of the three chunk kinds: below the diagonal
+    // (A read directly, rows contiguous), above it (the mirror, k contiguous),
+    // and Y; a chunk only moves the base pointer
+    // (32-bit offsets: the fast path is taken only when they fit; FP32
+    // compute only, as in syr2k_lower_kernel)
+    constexpr bool kOffsets = sizeof(CT) == 4;
+    const bool fit = kOffsets && (m + BM) * (lda > ldy ? lda : ldy) + SBR_BK * (lda > ldy ? lda : ldy) < INT32_MAX;
+    int32_t offd[MAi::E], offm[MAi::E], offy[MB::E];
+    bool okd[MAi::E], okm[MAi::E], oky[MB::E];
+    if constexpr (kOffsets) {
+#pragma unroll
+        for (int e = 0; e < MAi::E; ++e) {
+            int i, k;
+            MAi::coords(t, e, i, k);
+            offd[e] = (int32_t)((i0 + i) + (int64_t)k * lda);
+            okd[e] = i0 + i < m;
+            MAk::coords(t, e, i, k);
+            offm[e] = (int32_t)(k + (i0 + i) * lda);
+            okm[e] = i0 + i < m;
+        }
+#pragma unroll
+        for (int e = 0; e < MB::E; ++e) {
+            int j, k;
+            MB::coords(t, e, j, k);
+            offy[e] = (int32_t)(k + (j0 + j) * ldy);
+            oky[e] = j0 + j < nb;
+        }
+    }
     auto load = [&](int64_t k0) {
         kfast = (k0 >= i0 + BM - 1);           // whole chunk at or above the diagonal
+        const bool below = (k0 + SBR_BK - 1 <= i0);
+        if (kOffsets && fit && k0 + SBR_BK <= kend && (kfast || below)) {
+            if (kfast) {
+                const ST* pa = A + k0;
+#pragma unroll
+                for (int e = 0; e < MAi::E; ++e) ra[e] = okm[e] ? (CT)pa[offm[e]] : (CT)0;
+            } else {
+                const ST* pa = A + k0 * lda;
+#pragma unroll
+                for (int e = 0; e < MAi::E; ++e) ra[e] = okd[e] ? (CT)pa[offd[e]] : (CT)0;
+            }
+            const double* py = Y + k0;
+#pragma unroll
+            for (int e = 0; e < MB::E; ++e) rb[e] = oky[e] ? (CT)py[offy[e]] : (CT)0;
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < MAi::E; ++e) {
             int i, k;
