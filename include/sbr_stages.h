@@ -100,6 +100,17 @@ int sbr_plan_set_timing(sbr_plan_t plan, int enable);
  * same because every chase does the same arithmetic on the same data. */
 int sbr_plan_set_chase_blocks(sbr_plan_t plan, int32_t max_blocks);
 
+/* CUs kept free of the bulk trailing-update launches of the full-to-band
+ * stage (default 32; 0 = none).  The next panel is factored concurrently on
+ * another stream (Section 4 lookahead); a trailing-update grid that covers the
+ * whole chip would hold every CU until it drains, so the bulk launch goes to
+ * a stream restricted to the other CUs (CUs 0 .. cus-1 of the logical
+ * numbering, which interleaves the XCDs, are left out) and the panel kernels
+ * start at once.  Synchronises the device when the
+ * value changes.  Returns 0, -1 (null plan), -2 (cus < 0) or SBR_EHIP.  Where
+ * CU-masked streams are unavailable the setting has no effect. */
+int sbr_plan_set_panel_cus(sbr_plan_t plan, int32_t cus);
+
 /* Blocking: copies the plan's device status word.  Nonzero means a pipelined
  * band-to-band kernel stopped waiting for the previous sweep (after 10 s)
  * and abandoned the stage; results of that call are then invalid. */

@@ -70,6 +70,7 @@ def _load():
         "sbr_plan_set_timing": ([_vp, ctypes.c_int], ctypes.c_int),
         "sbr_plan_get_timing": ([_vp, ctypes.POINTER(_Timing)], ctypes.c_int),
         "sbr_plan_set_chase_blocks": ([_vp, _i32], ctypes.c_int),
+        "sbr_plan_set_panel_cus": ([_vp, _i32], ctypes.c_int),
         "sbr_plan_status": ([_vp, ctypes.POINTER(_i32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -85,7 +86,7 @@ EXPORTED = (
     "sbr_plan_create", "sbr_plan_destroy", "sbr_workspace_size", "sbr_default_band",
     "sbr_last_hip_error", "sbr_full_to_band", "sbr_dense_to_band", "sbr_band_halve", "sbr_panel_qr",
     "sbr_gemm", "sbr_syr2k_lower", "sbr_symm_lower", "sbr_plan_set_timing", "sbr_plan_get_timing",
-    "sbr_plan_set_chase_blocks", "sbr_plan_status",
+    "sbr_plan_set_chase_blocks", "sbr_plan_set_panel_cus", "sbr_plan_status",
 )
 
 
@@ -148,6 +149,9 @@ class Plan:
 
     def set_chase_blocks(self, max_blocks: int):
         _check(_lib.sbr_plan_set_chase_blocks(self._h, int(max_blocks)), "sbr_plan_set_chase_blocks")
+
+    def set_panel_cus(self, cus: int):
+        _check(_lib.sbr_plan_set_panel_cus(self._h, int(cus)), "sbr_plan_set_panel_cus")
 
     def status(self) -> int:
         v = _i32()

@@ -57,6 +57,13 @@ struct sbr_plan_s {
     // of the current trailing update runs on the caller's stream
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // the bulk update runs on `upd`, a stream barred from `panel_cus` CUs, so
+    // that the panel kernels always find free CUs instead of queueing behind
+    // a grid that fills the whole chip (upd = nullptr: caller's stream)
+    hipStream_t upd = nullptr;
+    hipEvent_t ev_ujoin = nullptr;
+    int32_t panel_cus = 32;
+    bool upd_ready = false;
     // batched form: descriptors (device + pinned host copy), per-matrix band
     // buffers, per-block scratch, tickets, and the captured launch
     BatchDesc* bdesc_dev = nullptr;
@@ -272,11 +279,43 @@ void factor_panel(sbr_plan_t p, int64_t m, int b, double* P, int64_t ldp, double
 }
 
 int ensure_side_stream(sbr_plan_t p) {
-    if (p->side) return 0;
-    hipError_t e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+    if (!p->side) {
+        hipError_t e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (p->upd_ready) return 0;
+    p->upd_ready = true;
+    if (p->panel_cus <= 0) return 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, p->device);
+    if (e != hipSuccess) return hip_fail(e);
+    const int ncu = prop.multiProcessorCount;
+    if (ncu <= 2 * p->panel_cus) return 0;
+    // CUs 0 .. panel_cus - 1 are left to the panel.  The logical CU numbering
+    // interleaves the XCDs, so every XCD gives up the same share; a mask that
+    // thinned one XCD only would make it the straggler of every launch, since
+    // work-groups are dealt to the XCDs round robin.
+    std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+    for (int cu = p->panel_cus; cu < ncu; ++cu) mask[cu / 32] |= 1u << (cu % 32);
+    e = hipExtStreamCreateWithCUMask(&p->upd, (uint32_t)mask.size(), mask.data());
+    if (e != hipSuccess) {
+        // no CU masking here: the bulk update stays on the caller's stream
+        (void)hipGetLastError();
+        p->upd = nullptr;
+        return 0;
+    }
+    e = hipEventCreateWithFlags(&p->ev_ujoin, hipEventDisableTiming);
     return e == hipSuccess ? 0 : hip_fail(e);
+}
+
+void release_upd_stream(sbr_plan_t p) {
+    if (p->ev_ujoin) (void)hipEventDestroy(p->ev_ujoin);
+    if (p->upd) (void)hipStreamDestroy(p->upd);
+    p->ev_ujoin = nullptr;
+    p->upd = nullptr;
+    p->upd_ready = false;
 }
 
 // FP32 copy of the trailing matrix for the FP32-MFMA form; false when it
@@ -352,19 +391,33 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
             } else {
                 launch_syr2k_lower_cols(f32, m, b, b, U, ldq, p->V, ldq, A22, lda, s);
             }
+            // the bulk update (on the CU-restricted stream when there is one)
+            // is enqueued before the panel kernels: the host needs longer to
+            // issue a panel than the GPU to run one, so the other order would
+            // start the bulk only after most of the panel
             hipError_t e = hipEventRecord(p->ev_fork, s);
             if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+            if (e == hipSuccess && p->upd) e = hipStreamWaitEvent(p->upd, p->ev_fork, 0);
             if (e != hipSuccess) return hip_fail(e);
+            auto bulk = [&](hipStream_t us) {
+                if (p->timing) { eq.a = p->ev(); p->mark(eq.a, us); }
+                if (f32s) launch_syr2k_lower_f32s(mn, b, U + b, ldq, p->V + b, ldq, A22s + b + b * lds, lds, us);
+                else launch_syr2k_lower(f32, mn, b, U + b, ldq, p->V + b, ldq, A22 + b + b * lda, lda, us);
+                if (p->timing) { eq.b = p->ev(); p->mark(eq.b, us); p->ev_syr2k.push_back(eq); }
+            };
+            if (p->upd) {
+                bulk(p->upd);
+                e = hipEventRecord(p->ev_ujoin, p->upd);
+                if (e != hipSuccess) return hip_fail(e);
+            }
             double* Un = p->Ub[cur ^ 1];
             factor_panel(p, mn, b, A22 + b, lda, Un, p->side);
             launch_gemm(false, false, false, mn, b, b, 1.0, Un, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, p->side);
             e = hipEventRecord(p->ev_join, p->side);
             if (e != hipSuccess) return hip_fail(e);
-            if (p->timing) { eq.a = p->ev(); p->mark(eq.a, s); }
-            if (f32s) launch_syr2k_lower_f32s(mn, b, U + b, ldq, p->V + b, ldq, A22s + b + b * lds, lds, s);
-            else launch_syr2k_lower(f32, mn, b, U + b, ldq, p->V + b, ldq, A22 + b + b * lda, lda, s);
-            if (p->timing) { eq.b = p->ev(); p->mark(eq.b, s); p->ev_syr2k.push_back(eq); }
-            e = hipStreamWaitEvent(s, p->ev_join, 0);
+            if (p->upd) e = hipStreamWaitEvent(s, p->ev_ujoin, 0);
+            else bulk(s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join, 0);
             if (e != hipSuccess) return hip_fail(e);
             cur ^= 1;
         } else {
@@ -483,6 +536,7 @@ int sbr_plan_destroy(sbr_plan_t plan) {
     if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
     if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
     if (plan->side) (void)hipStreamDestroy(plan->side);
+    release_upd_stream(plan);
     if (plan->ws) (void)hipFree(plan->ws);
     delete plan;
     return 0;
@@ -503,6 +557,18 @@ int sbr_plan_set_chase_blocks(sbr_plan_t plan, int32_t max_blocks) {
     if (!plan) return -1;
     if (max_blocks < 0) return -2;
     plan->chase_max_grid = max_blocks;
+    return 0;
+}
+
+int sbr_plan_set_panel_cus(sbr_plan_t plan, int32_t cus) {
+    if (!plan) return -1;
+    if (cus < 0) return -2;
+    if (cus == plan->panel_cus) return 0;
+    hipError_t e = hipSetDevice(plan->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e);
+    release_upd_stream(plan);
+    plan->panel_cus = cus;
     return 0;
 }
 

@@ -106,23 +106,27 @@ __device__ __forceinline__ void sbr_store_release(int* p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Move a double across lanes with a DPP control (two 32-bit halves).
+// Move a double across lanes with a DPP control (two 32-bit halves).  Only
+// full permutations are used (quad_perm, row_half_mirror, row_mirror), so no
+// lane reads an invalid source and no fallback value is needed.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the TPC lanes of an aligned group (TPC in {2, 4, 8}):
+// Sum over the TPC lanes of an aligned group (TPC in {2, 4, 8, 16}):
 // quad_perm(1,0,3,2) = lane ^ 1, quad_perm(2,3,0,1) = lane ^ 2,
-// row_half_mirror = lane i <-> 7 - i inside each 8-lane half row.
+// row_half_mirror = lane i <-> 7 - i inside each 8-lane half row,
+// row_mirror = lane i <-> 15 - i inside each 16-lane row.
 template <int TPC>
 __device__ __forceinline__ double group_sum(double v) {
-    static_assert(TPC == 2 || TPC == 4 || TPC == 8, "group size");
+    static_assert(TPC == 2 || TPC == 4 || TPC == 8 || TPC == 16, "group size");
     v += dpp_d<0xB1>(v);
-    if (TPC >= 4) v += dpp_d<0x4E>(v);
-    if (TPC >= 8) v += dpp_d<0x141>(v);
+    if constexpr (TPC >= 4) v += dpp_d<0x4E>(v);
+    if constexpr (TPC >= 8) v += dpp_d<0x141>(v);
+    if constexpr (TPC >= 16) v += dpp_d<0x140>(v);
     return v;
 }
 

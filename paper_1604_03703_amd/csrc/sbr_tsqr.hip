@@ -1,13 +1,15 @@
 // sbr_tsqr.hip -- panel QR of the full-to-band stage.
 //
 // * TSQR (Algorithm 3.2, rect-QR, on one GPU): the m x b panel is split into
-//   row blocks of b rows (the last block takes the remainder, < 2b rows); each
-//   block is factored by Householder QR (Lemma 3.4), then pairs of b x b R
-//   factors are stacked and factored level by level up a binary tree (after
-//   the first level every tree node is two stacked upper triangles).  The
-//   explicit thin Q is formed top-down: the root applies its reflectors to
-//   [I; 0], each node applies its reflectors to [Z; 0] with Z handed down by
-//   its parent, and the leaves write their rows of Q (Q_i = W_i Z_i).
+//   row blocks of 4b rows (the last block takes the remainder); each block is
+//   factored by Householder QR (Lemma 3.4), then groups of up to four b x b R
+//   factors are stacked and factored level by level up a 4-ary tree (a binary
+//   tree for b = 128).  A wider fan-in than the binary tree of the algorithm
+//   halves the number of levels, each of which is a chain of b dependent
+//   Householder steps.  The explicit thin Q is formed top-down: the root
+//   applies its reflectors to [I; 0], each node applies its reflectors to
+//   [Z; 0] with Z handed down by its parent, and the leaves write their rows
+//   of Q (Q_i = W_i Z_i).
 // * Householder reconstruction (Corollary 3.7): [U1, W1] = LU(Q1 - S) without
 //   pivoting, S_ii = -sgn of the current pivot so |pivot| >= 1; U2 = Q2 W1^{-1}
 //   (a GEMM with the explicit inverse); T = -W1 S U1^{-T}.  Then
@@ -18,20 +20,42 @@
 //
 #include <math.h>
 
+#include <utility>
+
 #include "sbr_device.h"
 #include "sbr_internal.h"
 
 namespace {
 
+// Shape of the TSQR tree for panel width B: every node stacks the R factors
+// of up to F children (F B rows), every leaf is a row block of F B rows of the
+// panel (the last leaf takes what is left, at least one row).  TPC consecutive
+// lanes own one column; lane s of the group holds the rows s + TPC r, r < RPT.
+template <int B>
+struct TreeShape {
+    static constexpr int F = (B >= 128) ? 2 : 4;
+    static constexpr int ROWS = F * B;
+    static constexpr int TPC = (ROWS < 16) ? ROWS : ((B >= 128) ? 8 : 16);
+    static constexpr int RPT = ROWS / TPC;
+    static constexpr int NT = B * TPC;
+    static constexpr int NACC = RPT >= 4 ? 4 : RPT;   // independent partial sums
+    // the apply pass keeps the node's reflectors in LDS when they fit
+    static constexpr bool STAGE = (size_t)ROWS * B * sizeof(double) <= 128 * 1024;
+    static constexpr bool CACHE = RPT <= 16;   // keep a reflector in registers
+    // compile-time row skipping needs whole register blocks per child and is
+    // kept to panels whose unrolled steps fit the register file
+    static constexpr bool GENERIC = (B % TPC != 0) || B >= 128;
+};
+
+constexpr int tree_fanin(int b) { return b >= 128 ? 2 : 4; }
+
 struct TsqrLevelArgs {
-    int b;
     int is_leaf;
     int is_root;
     // leaves
     double* P;
     int64_t ldp;
     int64_t m;
-    int nleaves;
     // nodes
     double* child_slots;   // level below (b x b slots, ld b)
     int nchild;
@@ -42,160 +66,298 @@ struct TsqrLevelArgs {
     int64_t ldq;
 };
 
-struct Seg {
-    double* p0;
-    int64_t ld0;
-    int rows0;
-    double* p1;
-    int64_t ld1;
-    int rows1;
-};
-
-__device__ __forceinline__ Seg node_segments(const TsqrLevelArgs& a, int q) {
-    Seg s;
-    const int b = a.b;
-    if (a.is_leaf) {
-        const int64_t r0 = (int64_t)q * b;
-        const int64_t rows = (q == a.nleaves - 1) ? (a.m - r0) : b;
-        s.p0 = a.P + r0;
-        s.ld0 = a.ldp;
-        s.rows0 = (int)rows;
-        s.p1 = nullptr;
-        s.ld1 = 0;
-        s.rows1 = 0;
-    } else {
-        s.p0 = a.child_slots + (int64_t)(2 * q) * b * b;
-        s.ld0 = b;
-        s.rows0 = b;
-        if (2 * q + 1 < a.nchild) {
-            s.p1 = a.child_slots + (int64_t)(2 * q + 1) * b * b;
-            s.ld1 = b;
-            s.rows1 = b;
+// The stacked input of tree node (or leaf) q: rows() rows, element (row, col).
+template <int B>
+struct NodeView {
+    double* base;
+    int64_t ld;
+    int rows;
+    bool leaf;
+    __device__ NodeView(const TsqrLevelArgs& a, int q) {
+        constexpr int F = TreeShape<B>::F, ROWS = TreeShape<B>::ROWS;
+        leaf = a.is_leaf != 0;
+        if (leaf) {
+            const int64_t r0 = (int64_t)q * ROWS;
+            const int64_t left = a.m - r0;
+            rows = (int)(left < ROWS ? left : ROWS);
+            base = a.P + r0;
+            ld = a.ldp;
         } else {
-            s.p1 = nullptr;
-            s.ld1 = 0;
-            s.rows1 = 0;
+            const int nch = a.nchild - F * q;
+            rows = B * (nch < F ? nch : F);
+            base = a.child_slots + (int64_t)F * q * B * B;
+            ld = B;
         }
     }
-    return s;
-}
-
-// Register layout of the QR / apply kernels: TPC consecutive lanes own one
-// column (TPC = 8, or 2b when b < 4), lane s of the group holds the rows
-// s + TPC r (r < RPT = 2b / TPC).  Column sums are DPP exchanges inside the
-// group (no LDS traffic); one barrier per Householder step hands the
-// reflector from its owner group to the others through LDS.
-template <int B>
-struct GroupQR {
-    static constexpr int TPC = (2 * B < 8) ? 2 * B : 8;
-    static constexpr int RPT = 2 * B / TPC;
-    static constexpr int NT = B * TPC;
-    static constexpr int NACC = RPT >= 4 ? 4 : RPT;   // independent partial sums
+    // child slots are consecutive B x B blocks (ld B): row = j B + i
+    __device__ __forceinline__ double* at(int row, int col) const {
+        if (leaf) return base + row + (int64_t)col * ld;
+        return base + (int64_t)(row / B) * B * B + (row % B) + col * B;
+    }
 };
 
-template <int RPT, int NACC>
-__device__ __forceinline__ double dot_rows(const double* x, const double* v, int s, int tpc) {
-    double acc[NACC];
-#pragma unroll
-    for (int a = 0; a < NACC; ++a) acc[a] = 0.0;
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) acc[r % NACC] += v[s + tpc * r] * x[r];
-    double d = acc[0];
-#pragma unroll
-    for (int a = 1; a < NACC; ++a) d += acc[a];
-    return d;
+// Which rows of register block r (rows s + TPC r) can be nonzero in the
+// reflector of column k, for k in [TPC KR, TPC KR + TPC):
+//   SKIP  none (a leaf's rows above k; in a stacked node, every row of the
+//         top triangle outside its diagonal block KR and the rows of a lower
+//         triangle below block KR: column k of an upper triangle is zero below
+//         row k and the earlier reflectors never fill those rows);
+//   MIXED some: the rows are compared with k lane by lane;
+//   PLAIN all may be nonzero and all lie below row k.
+// Known at compile time, so the skipped blocks cost nothing.  The generic
+// shapes (panels narrower than TPC, or b = 128) use MIXED everywhere and run
+// all b steps as one block.
+enum RowClass { RC_SKIP, RC_MIXED, RC_PLAIN };
+
+template <int B, bool LEAF, int KR, int R>
+constexpr RowClass row_class() {
+    typedef TreeShape<B> L;
+    if constexpr (L::GENERIC) {
+        return RC_MIXED;
+    } else {
+        constexpr int RB = B / L::TPC;                 // register blocks per child
+        constexpr int j = LEAF ? 0 : R / RB;
+        constexpr int rr = LEAF ? R : R % RB;
+        if constexpr (LEAF) return rr < KR ? RC_SKIP : (rr == KR ? RC_MIXED : RC_PLAIN);
+        else if constexpr (j == 0) return rr == KR ? RC_MIXED : RC_SKIP;
+        else return rr > KR ? RC_SKIP : RC_PLAIN;
+    }
 }
 
 template <int B>
-__global__ __launch_bounds__(GroupQR<B>::NT) void tsqr_qr_kernel(TsqrLevelArgs a) {
-    typedef GroupQR<B> L;
-    constexpr int TPC = L::TPC, RPT = L::RPT, NACC = L::NACC;
-    __shared__ double vsh[2][2 * B];
-    __shared__ double tsh[B];
+constexpr int kr_blocks() {
+    return TreeShape<B>::GENERIC ? 1 : B / TreeShape<B>::TPC;
+}
+
+template <int B>
+constexpr int kr_steps() {
+    return TreeShape<B>::GENERIC ? B : TreeShape<B>::TPC;
+}
+
+// Steps k = TPC KR .. of the node QR.  Step k: the group owning column k
+// sums the squares below row k and publishes the unnormalised reflector
+// u = x - beta e_k in LDS (its entries below k go out before the norm is
+// known; the lane holding row k adds u_k = x_k - beta and beta); every later
+// column applies H = I + u u^T / (beta u_k), dividing by beta u_k itself.
+template <int B, bool LEAF, int KR>
+__device__ __forceinline__ void qr_steps(double (&x)[TreeShape<B>::RPT], int c, int s, double* ush, double* psh,
+                                         double* colsc) {
+    typedef TreeShape<B> L;
+    constexpr int TPC = L::TPC, RPT = L::RPT, NACC = L::NACC, ROWS = L::ROWS;
+    constexpr int KN = kr_steps<B>(), K0 = KR * KN;
+    for (int kk = 0; kk < KN; ++kk) {
+        const int k = K0 + kk;
+        double* u = ush + (k & 1) * ROWS;
+        double* ps = psh + (k & 1) * 2;
+        if (c == k) {
+            double sacc[NACC];
+#pragma unroll
+            for (int w = 0; w < NACC; ++w) sacc[w] = 0.0;
+            [&]<int... R>(std::integer_sequence<int, R...>) {
+                ([&] {
+                    constexpr RowClass rc = row_class<B, LEAF, KR, R>();
+                    const int row = s + TPC * R;
+                    if constexpr (rc == RC_PLAIN) {
+                        sacc[R % NACC] += x[R] * x[R];
+                        u[row] = x[R];
+                    } else if constexpr (rc == RC_MIXED) {
+                        sacc[R % NACC] += (row > k) ? x[R] * x[R] : 0.0;
+                        if (row != k) u[row] = (row > k) ? x[R] : 0.0;
+                    }
+                }(), ...);
+            }(std::make_integer_sequence<int, RPT>{});
+            double ss = sacc[0];
+#pragma unroll
+            for (int w = 1; w < NACC; ++w) ss += sacc[w];
+            ss = group_sum<TPC>(ss);
+            if (s == k % TPC) {   // this lane holds row k
+                double xk;
+                if constexpr (L::GENERIC) {
+                    xk = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) xk = (TPC * r == k - s) ? x[r] : xk;
+                } else {
+                    xk = x[KR];   // register block KR
+                }
+                double beta = xk, uk = 0.0;
+                if (ss != 0.0) {
+                    const double nrm = sqrt(xk * xk + ss);
+                    beta = (xk >= 0.0) ? -nrm : nrm;
+                    uk = xk - beta;
+                }
+                u[k] = uk;
+                ps[0] = beta;
+                ps[1] = uk;
+                colsc[k] = uk;
+                colsc[B + k] = beta;
+                if constexpr (L::GENERIC) {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) x[r] = (TPC * r == k - s) ? beta : x[r];
+                } else {
+                    x[KR] = beta;
+                }
+            }
+        }
+        __syncthreads();
+        if (c > k) {
+            const double uk = ps[1];
+            if (uk != 0.0) {
+                const double gk = -1.0 / (ps[0] * uk);
+                double acc[NACC];
+#pragma unroll
+                for (int w = 0; w < NACC; ++w) acc[w] = 0.0;
+                // the reflector stays in registers between the two passes
+                // unless that would spill (RPT > 16: it is read twice)
+                double uv[L::CACHE ? RPT : 1];
+                [&]<int... R>(std::integer_sequence<int, R...>) {
+                    ([&] {
+                        if constexpr (row_class<B, LEAF, KR, R>() != RC_SKIP) {
+                            const double ur = u[s + TPC * R];
+                            if constexpr (L::CACHE) uv[R] = ur;
+                            acc[R % NACC] += ur * x[R];
+                        }
+                    }(), ...);
+                }(std::make_integer_sequence<int, RPT>{});
+                double d = acc[0];
+#pragma unroll
+                for (int w = 1; w < NACC; ++w) d += acc[w];
+                const double f = group_sum<TPC>(d) * gk;
+                [&]<int... R>(std::integer_sequence<int, R...>) {
+                    ([&] {
+                        if constexpr (row_class<B, LEAF, KR, R>() != RC_SKIP) {
+                            if constexpr (L::CACHE) x[R] -= f * uv[R];
+                            else x[R] -= f * u[s + TPC * R];
+                        }
+                    }(), ...);
+                }(std::make_integer_sequence<int, RPT>{});
+            }
+        }
+    }
+}
+
+template <int B, bool LEAF, int KR = 0>
+__device__ __forceinline__ void qr_all_steps(double (&x)[TreeShape<B>::RPT], int c, int s, double* ush, double* psh,
+                                             double* colsc) {
+    qr_steps<B, LEAF, KR>(x, c, s, ush, psh, colsc);
+    if constexpr (KR + 1 < kr_blocks<B>()) qr_all_steps<B, LEAF, KR + 1>(x, c, s, ush, psh, colsc);
+}
+
+// Householder QR of one node or leaf (Lemma 3.4), one work-group; the
+// reflectors are scaled to v = u / u_k (tau = -u_k / beta) at the end.
+template <int B, bool LEAF>
+__global__ __launch_bounds__(TreeShape<B>::NT) void tsqr_qr_kernel(TsqrLevelArgs a) {
+    typedef TreeShape<B> L;
+    constexpr int TPC = L::TPC, RPT = L::RPT, ROWS = L::ROWS;
+    __shared__ double ush[2 * ROWS];
+    __shared__ double psh[4];
+    __shared__ double colsc[2 * B];   // u_k and beta of every column
     const int t = threadIdx.x, c = t / TPC, s = t % TPC;
     const int q = blockIdx.x;
-    const Seg g = node_segments(a, q);
-    const int rows = g.rows0 + g.rows1;
+    const NodeView<B> g(a, q);
     double x[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int row = s + TPC * r;
-        double v = 0.0;
-        if (row < g.rows0) v = g.p0[row + (int64_t)c * g.ld0];
-        else if (row < rows) v = g.p1[(row - g.rows0) + (int64_t)c * g.ld1];
-        x[r] = v;
+        x[r] = (row < g.rows) ? *g.at(row, c) : 0.0;
     }
-    for (int k = 0; k < B; ++k) {
-        double* v = vsh[k & 1];
-        if (c == k) {
-            double sacc[NACC];
-#pragma unroll
-            for (int u = 0; u < NACC; ++u) sacc[u] = 0.0;
-            double xk = 0.0;
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                const int row = s + TPC * r;
-                if (row > k) sacc[r % NACC] += x[r] * x[r];
-                else if (row == k) xk = x[r];
-            }
-            double ss = sacc[0];
-#pragma unroll
-            for (int u = 1; u < NACC; ++u) ss += sacc[u];
-            ss = group_sum<TPC>(ss);
-            xk = group_sum<TPC>(xk);
-            double beta, tau, scal;
-            if (ss == 0.0) {
-                beta = xk; tau = 0.0; scal = 0.0;
-            } else {
-                const double nrm = sqrt(xk * xk + ss);
-                beta = (xk >= 0.0) ? -nrm : nrm;
-                tau = (beta - xk) / beta;
-                scal = 1.0 / (xk - beta);
-            }
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                const int row = s + TPC * r;
-                const double vv = (row < k) ? 0.0 : ((row == k) ? 1.0 : x[r] * scal);
-                v[row] = vv;
-                x[r] = (row == k) ? beta : ((row > k) ? vv : x[r]);   // selects, no branches
-            }
-            if (s == 0) tsh[k] = tau;
-        }
-        __syncthreads();
-        if (c > k) {
-            const double tau = tsh[k];
-            if (tau != 0.0) {
-                const double d = group_sum<TPC>(dot_rows<RPT, NACC>(x, v, s, TPC));
-                const double f = tau * d;
-#pragma unroll
-                for (int r = 0; r < RPT; ++r) x[r] -= f * v[s + TPC * r];
-            }
-        }
-    }
-    // reflectors (below the diagonal) and R (on and above it) back in place
+    qr_all_steps<B, LEAF>(x, c, s, ush, psh, colsc);
+    __syncthreads();
+    const double my_uk = colsc[c], my_beta = colsc[B + c];
+    // reflectors scaled to a unit diagonal (below it) and R (on and above it)
+    // back in place
+    const double rinv = (my_uk != 0.0) ? 1.0 / my_uk : 0.0;
     double* R = a.own_slots + (int64_t)q * B * B;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int row = s + TPC * r;
-        if (row < g.rows0) g.p0[row + (int64_t)c * g.ld0] = x[r];
-        else if (row < rows) g.p1[(row - g.rows0) + (int64_t)c * g.ld1] = x[r];
-        if (row < B) R[row + c * B] = (row <= c) ? x[r] : 0.0;
+        const double val = (row > c) ? x[r] * rinv : x[r];
+        if (row < g.rows) *g.at(row, c) = val;
+        if (row < B) R[row + c * B] = (row <= c) ? val : 0.0;
     }
-    __syncthreads();
-    if (t < B) a.tau[(int64_t)q * B + t] = tsh[t];
+    if (s == 0) a.tau[(int64_t)q * B + c] = (my_uk != 0.0) ? -my_uk / my_beta : 0.0;
 }
 
-// X = H_0 ... H_{B-1} [Z; 0]: the node's explicit Q block times Z.
-template <int B>
-__global__ __launch_bounds__(GroupQR<B>::NT) void tsqr_apply_kernel(TsqrLevelArgs a) {
-    typedef GroupQR<B> L;
+// One reflector of the apply pass: x <- (I - tau v v^T) x over the register
+// blocks where reflector k can be nonzero.
+template <int B, bool LEAF, int KR>
+__device__ __forceinline__ void apply_reflector(double (&x)[TreeShape<B>::RPT], const double* v, double tau, int s) {
+    typedef TreeShape<B> L;
     constexpr int TPC = L::TPC, RPT = L::RPT, NACC = L::NACC;
-    __shared__ double vsh[2][2 * B];
+    double acc[NACC];
+#pragma unroll
+    for (int w = 0; w < NACC; ++w) acc[w] = 0.0;
+    double vv[L::CACHE ? RPT : 1];
+    [&]<int... R>(std::integer_sequence<int, R...>) {
+        ([&] {
+            if constexpr (row_class<B, LEAF, KR, R>() != RC_SKIP) {
+                const double vr = v[s + TPC * R];
+                if constexpr (L::CACHE) vv[R] = vr;
+                acc[R % NACC] += vr * x[R];
+            }
+        }(), ...);
+    }(std::make_integer_sequence<int, RPT>{});
+    double d = acc[0];
+#pragma unroll
+    for (int w = 1; w < NACC; ++w) d += acc[w];
+    const double f = tau * group_sum<TPC>(d);
+    [&]<int... R>(std::integer_sequence<int, R...>) {
+        ([&] {
+            if constexpr (row_class<B, LEAF, KR, R>() != RC_SKIP) {
+                if constexpr (L::CACHE) x[R] -= f * vv[R];
+                else x[R] -= f * v[s + TPC * R];
+            }
+        }(), ...);
+    }(std::make_integer_sequence<int, RPT>{});
+}
+
+// Reflector k, element `row`: 0 above k, 1 at k, stored value below.
+template <int B>
+__device__ __forceinline__ double reflector_entry(const NodeView<B>& g, int row, int k) {
+    if (row > k && row < g.rows) return *g.at(row, k);
+    return (row == k) ? 1.0 : 0.0;
+}
+
+template <int B, bool LEAF, int KR>
+__device__ __forceinline__ void apply_steps(double (&x)[TreeShape<B>::RPT], const NodeView<B>& g, double* vst,
+                                            const double* tsh, int t, int s) {
+    typedef TreeShape<B> L;
+    constexpr int ROWS = L::ROWS;
+    constexpr int KN = kr_steps<B>(), K0 = KR * KN;
+    for (int kk = KN - 1; kk >= 0; --kk) {
+        const int k = K0 + kk;
+        if constexpr (L::STAGE) {
+            const double tau = tsh[k];
+            if (tau != 0.0) apply_reflector<B, LEAF, KR>(x, vst + k * ROWS, tau, s);
+        } else {
+            // one reflector at a time through a double buffer
+            double* v = vst + (k & 1) * ROWS;
+            if (t < ROWS) v[t] = reflector_entry<B>(g, t, k);
+            __syncthreads();
+            const double tau = tsh[k];
+            if (tau != 0.0) apply_reflector<B, LEAF, KR>(x, v, tau, s);
+        }
+    }
+}
+
+template <int B, bool LEAF, int KR = kr_blocks<B>() - 1>
+__device__ __forceinline__ void apply_all_steps(double (&x)[TreeShape<B>::RPT], const NodeView<B>& g, double* vst,
+                                                const double* tsh, int t, int s) {
+    apply_steps<B, LEAF, KR>(x, g, vst, tsh, t, s);
+    if constexpr (KR > 0) apply_all_steps<B, LEAF, KR - 1>(x, g, vst, tsh, t, s);
+}
+
+// X = H_0 ... H_{B-1} [Z; 0]: the node's explicit Q block times Z (the root
+// starts from Z = I).  The node's reflectors are staged in LDS first when
+// they fit; otherwise they pass through a two-slot LDS buffer one by one.
+template <int B, bool LEAF>
+__global__ __launch_bounds__(TreeShape<B>::NT) void tsqr_apply_kernel(TsqrLevelArgs a) {
+    typedef TreeShape<B> L;
+    constexpr int TPC = L::TPC, RPT = L::RPT, ROWS = L::ROWS, NT = L::NT;
+    extern __shared__ double vst[];   // STAGE: ROWS x B reflectors; else 2 x ROWS
     __shared__ double tsh[B];
     const int t = threadIdx.x, c = t / TPC, s = t % TPC;
     const int q = blockIdx.x;
-    const Seg g = node_segments(a, q);
-    const int rows = g.rows0 + g.rows1;
+    const NodeView<B> g(a, q);
     const double* Z = a.own_slots + (int64_t)q * B * B;
     double x[RPT];
 #pragma unroll
@@ -206,35 +368,18 @@ __global__ __launch_bounds__(GroupQR<B>::NT) void tsqr_apply_kernel(TsqrLevelArg
         x[r] = v;
     }
     if (t < B) tsh[t] = a.tau[(int64_t)q * B + t];
-    // reflector k, element `row`: 0 above k, 1 at k, stored value below
-    auto fetchv = [&](int row, int k) -> double {
-        if (row > k && row < rows)
-            return (row < g.rows0) ? g.p0[row + (int64_t)k * g.ld0] : g.p1[(row - g.rows0) + (int64_t)k * g.ld1];
-        return (row == k) ? 1.0 : 0.0;
-    };
-    double vnext = (t < 2 * B) ? fetchv(t, B - 1) : 0.0;
-    for (int k = B - 1; k >= 0; --k) {
-        double* v = vsh[k & 1];
-        if (t < 2 * B) v[t] = vnext;
-        __syncthreads();
-        if (k > 0 && t < 2 * B) vnext = fetchv(t, k - 1);
-        const double tau = tsh[k];
-        if (tau != 0.0) {
-            const double d = group_sum<TPC>(dot_rows<RPT, NACC>(x, v, s, TPC));
-            const double f = tau * d;
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) x[r] -= f * v[s + TPC * r];
-        }
+    if constexpr (L::STAGE) {
+        for (int idx = t; idx < ROWS * B; idx += NT) vst[idx] = reflector_entry<B>(g, idx % ROWS, idx / ROWS);
     }
+    __syncthreads();
+    apply_all_steps<B, LEAF>(x, g, vst, tsh, t, s);
     __syncthreads();   // every read of the reflectors is done before they are overwritten
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int row = s + TPC * r;
-        if (a.is_leaf) {
-            if (row < g.rows0) a.Q[(int64_t)q * B + row + (int64_t)c * a.ldq] = x[r];
-        } else {
-            if (row < g.rows0) g.p0[row + (int64_t)c * g.ld0] = x[r];
-            else if (row < rows) g.p1[(row - g.rows0) + (int64_t)c * g.ld1] = x[r];
+        if (row < g.rows) {
+            if (LEAF) a.Q[(int64_t)q * ROWS + row + (int64_t)c * a.ldq] = x[r];
+            else *g.at(row, c) = x[r];
         }
     }
 }
@@ -434,10 +579,21 @@ __global__ __launch_bounds__(TAIL_NT) void f2b_tail_kernel(int m, int b, double*
 }
 
 template <int B>
+size_t apply_lds_bytes() {
+    typedef TreeShape<B> L;
+    return (L::STAGE ? (size_t)L::ROWS * B : 2 * (size_t)L::ROWS) * sizeof(double);
+}
+
+template <int B>
 void launch_level(bool qr, const TsqrLevelArgs& a, int blocks, hipStream_t s) {
-    constexpr int NT = GroupQR<B>::NT;
-    if (qr) tsqr_qr_kernel<B><<<blocks, NT, 0, s>>>(a);
-    else tsqr_apply_kernel<B><<<blocks, NT, 0, s>>>(a);
+    constexpr int NT = TreeShape<B>::NT;
+    if (qr) {
+        if (a.is_leaf) tsqr_qr_kernel<B, true><<<blocks, NT, 0, s>>>(a);
+        else tsqr_qr_kernel<B, false><<<blocks, NT, 0, s>>>(a);
+    } else {
+        if (a.is_leaf) tsqr_apply_kernel<B, true><<<blocks, NT, apply_lds_bytes<B>(), s>>>(a);
+        else tsqr_apply_kernel<B, false><<<blocks, NT, apply_lds_bytes<B>(), s>>>(a);
+    }
 }
 
 void launch_level_b(int b, bool qr, const TsqrLevelArgs& a, int blocks, hipStream_t s) {
@@ -453,6 +609,16 @@ void launch_level_b(int b, bool qr, const TsqrLevelArgs& a, int blocks, hipStrea
     }
 }
 
+template <int B>
+hipError_t set_apply_lds() {
+    hipError_t e = hipFuncSetAttribute((const void*)tsqr_apply_kernel<B, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)apply_lds_bytes<B>());
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)tsqr_apply_kernel<B, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)apply_lds_bytes<B>());
+    return e;
+}
+
 }  // namespace
 
 namespace sbr {
@@ -462,21 +628,25 @@ bool tsqr_supported(int b) {
 }
 
 int64_t tsqr_workspace_doubles(int64_t m, int b) {
-    int64_t count = m / b;
+    const int F = tree_fanin(b);
+    const int64_t rows = (int64_t)F * b;
+    int64_t count = (m + rows - 1) / rows;
     if (count < 1) count = 1;
     int64_t tot = 0;
     while (true) {
         tot += count * ((int64_t)b * b + b);
         if (count == 1) break;
-        count = (count + 1) / 2;
+        count = (count + F - 1) / F;
     }
     return tot;
 }
 
 void tsqr_plan(TsqrTree& tr, int64_t m, int b, double* ws) {
+    const int F = tree_fanin(b);
+    const int64_t rows = (int64_t)F * b;
     tr.b = b;
     tr.m = m;
-    int64_t count = m / b;
+    int64_t count = (m + rows - 1) / rows;
     if (count < 1) count = 1;
     int lv = 0;
     double* p = ws;
@@ -488,7 +658,7 @@ void tsqr_plan(TsqrTree& tr, int64_t m, int b, double* ws) {
         p += count * (int64_t)b;
         ++lv;
         if (count == 1) break;
-        count = (count + 1) / 2;
+        count = (count + F - 1) / F;
     }
     tr.levels = lv;
 }
@@ -498,11 +668,9 @@ const double* tsqr_root_r(const TsqrTree& tr) { return tr.slots[tr.levels - 1]; 
 void launch_tsqr(const TsqrTree& tr, double* P, int64_t ldp, double* Q, int64_t ldq, hipStream_t s) {
     const int b = tr.b;
     TsqrLevelArgs a{};
-    a.b = b;
     a.P = P;
     a.ldp = ldp;
     a.m = tr.m;
-    a.nleaves = tr.count[0];
     a.Q = Q;
     a.ldq = ldq;
     // up-sweep
@@ -531,6 +699,13 @@ int init_tsqr_attributes() {
     const int bytes = 128 * 129 * (int)sizeof(double);
     hipError_t e = hipFuncSetAttribute((const void*)reconstruct_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        bytes);
+    if (e == hipSuccess) e = set_apply_lds<2>();
+    if (e == hipSuccess) e = set_apply_lds<4>();
+    if (e == hipSuccess) e = set_apply_lds<8>();
+    if (e == hipSuccess) e = set_apply_lds<16>();
+    if (e == hipSuccess) e = set_apply_lds<32>();
+    if (e == hipSuccess) e = set_apply_lds<64>();
+    if (e == hipSuccess) e = set_apply_lds<128>();
     return e == hipSuccess ? 0 : (int)e;
 }
 

@@ -110,6 +110,27 @@ def test_band_halve_pipelined_equals_sequential(sbr, oracle_mod, b):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mfma"])
+def test_panel_cus_setting_is_bitwise_neutral(sbr, oracle_mod, precision):
+    # the CUs kept free for the concurrent panel only change where the bulk
+    # trailing update runs, never its arithmetic
+    print("panel_cus", precision, flush=True)
+    n, b0 = 1536, 64
+    A = si.gaussian_symmetric(n, si.make_rng(si.CFG_SMALL, 3))
+    outs = []
+    for cus in (0, 16, 64):
+        p = sbr.Plan(n, 0, precision)
+        p.set_panel_cus(cus)
+        w = sbr.eigvalsh(torch.from_numpy(A).cuda(), b0=b0, precision=precision, plan=p)
+        torch.cuda.synchronize()
+        outs.append(w.cpu().numpy())
+        p.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    ref = oracle_mod.eigvalsh(A)
+    tol = 1e-11 if precision == "fp64" else 2e-5
+    assert np.max(np.abs(outs[0] - ref)) <= tol * _norm2(ref)
+
+
 SIZES = [(1, 0), (2, 0), (3, 0), (4, 2), (5, 0), (17, 4), (33, 8), (64, 16), (100, 16), (256, 16),
          (300, 32), (257, 2), (1000, 64), (777, 128)]
 
