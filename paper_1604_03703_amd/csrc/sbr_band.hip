@@ -473,7 +473,8 @@ void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32,
         launch_band_halve_mfma(n, band, ldband, b, scratch, flags, error, max_grid, s);
         return;
     }
-    if (band_group_supported(b) && ldband == 2 * b + 1) {
+    // the group kernel indexes the band with 32-bit integers
+    if (band_group_supported(b) && ldband == 2 * b + 1 && n * (int64_t)ldband < (int64_t)INT32_MAX) {
         launch_band_halve_group(n, band, ldband, b, flags, error, max_grid, s);
         return;
     }

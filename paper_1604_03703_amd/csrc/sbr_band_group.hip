@@ -24,6 +24,10 @@
 #include "sbr_internal.h"
 #include "sbr_team_chase.h"
 
+#ifndef SBR_LANE_BATCH
+#define SBR_LANE_BATCH 16
+#endif
+
 namespace {
 
 template <int H>
@@ -31,17 +35,23 @@ struct GroupCfg {
     // one team of 2h lanes per chase (lane u holds band row u of the chase's
     // 2h-row blocks); sweeps per group sized so the ring plus the per-team
     // scratch stay under 150 KB of LDS
-    static constexpr int TEAM = 2 * H;
-    static constexpr int NT = (H <= 2) ? 512 : (H == 4 ? 256 : 128);
+    static constexpr bool LANE = (H <= 2);          // one lane per sweep (lane_chase)
+    static constexpr int TEAM = LANE ? 1 : 2 * H;
+    // lanes: one wave per group, so a step needs no block barrier; teams:
+    // several waves per group
+    static constexpr int NT = LANE ? 64 : (H == 4 ? 256 : 128);
     static constexpr int S = NT / TEAM;
     static constexpr int LDW = 4 * H + 1;        // stored diagonals per column
-    static constexpr int BATCH = (H >= 8) ? 4 : 8;   // steps per load / write-back batch
+    static constexpr int BATCH = LANE ? SBR_LANE_BATCH : ((H >= 8) ? 4 : 8);   // steps per load / write-back batch
     static constexpr int WC = 5 * H * S + 2 * H * (BATCH + 6);
     static constexpr int H2 = 2 * H;
     // per-team scratch (doubles): U rows (2h x h), a second 2h x h block
     // (the left block, then W, then V) and an h x h product
-    static constexpr int SCR = team_chase_scratch<H>();
+    static constexpr int SCR = LANE ? 0 : team_chase_scratch<H>();
     static constexpr int LDS_DOUBLES = WC * LDW + S * SCR;
+    // prefetch registers: one batch of columns spread over the wave
+    static constexpr int PFC = LANE ? 2 * H * BATCH : 0;
+    static constexpr int PFN = LANE ? (PFC * LDW + NT - 1) / NT : 1;
 };
 
 struct GroupArgs {
@@ -57,7 +67,7 @@ struct GroupArgs {
 constexpr uint64_t GROUP_WAIT_LIMIT = 1000000000ull;   // 10 s of the 100 MHz clock
 
 template <int H>
-__device__ __forceinline__ int64_t nchase_of(int64_t n, int64_t i) {
+__device__ __forceinline__ int nchase_of(int n, int i) {
     return (n - 2 - i * H) / (2 * H) + 1;
 }
 
@@ -68,11 +78,12 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
     extern __shared__ double smem[];
     double* ring = smem;
     __shared__ int g_sh, abort_sh, fresh_sh;
-    __shared__ int64_t vis_sh;
+    __shared__ int vis_sh;
     const int t = threadIdx.x;
     const int tm = t / TEAM, u = t % TEAM;
     double* scr = smem + WC * LDW + tm * C::SCR;
-    const int64_t n = a.n;
+    // column and row indices fit in 32 bits (n * LDW < 2^31 is checked on the host)
+    const int n = (int)a.n;
     double* gband = a.band;
 
     // ring slot of column c for the current chase: window columns are
@@ -92,45 +103,80 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
             vis_sh = 0;
         }
         __syncthreads();
-        const int g = g_sh;
+        // uniform across the block: keep the schedule arithmetic scalar
+        const int g = __builtin_amdgcn_readfirstlane(g_sh);
         __syncthreads();
         if (g >= a.ngroups) break;
-        const int64_t i0 = 1 + (int64_t)g * S;
-        const int ns = (int)((a.nsweeps - i0 + 1 < S) ? (a.nsweeps - i0 + 1) : S);
+        const int i0 = 1 + g * S;
+        const int ns = (a.nsweeps - i0 + 1 < S) ? (a.nsweeps - i0 + 1) : S;
         // Sweeps finish in order: sweep s does its last chase at step
         // f(s) = J_s + 3s, which increases with s.  At step tau the active
         // sweeps are s_lo(tau) .. s_hi(tau) with s_lo the first s with
         // f(s) >= tau and s_hi = min(ns-1, (tau-1)/3); window ends decrease
         // and window starts decrease with s, so the extremes are at s_lo
         // (end) and s_hi (start).
-        auto Jof = [&](int s) -> int64_t { return nchase_of<H>(n, i0 + s); };
-        auto wstart = [&](int s, int64_t j) -> int64_t {
-            const int64_t o = (i0 + s) * H + (j - 1) * H2;
+        auto Jof = [&](int s) -> int { return nchase_of<H>(n, i0 + s); };
+        auto wstart = [&](int s, int j) -> int {
+            const int o = (i0 + s) * H + (j - 1) * H2;
             return (j == 1) ? o - H : o - H2;
         };
-        auto wend = [&](int s, int64_t j) -> int64_t {
-            const int64_t e = (i0 + s) * H + j * H2;
+        auto wend = [&](int s, int j) -> int {
+            const int e = (i0 + s) * H + j * H2;
             return e < n ? e : n;
         };
-        const int64_t tau_end = 3 * (ns - 1) + Jof(ns - 1) > Jof(0) ? 3 * (ns - 1) + Jof(ns - 1) : Jof(0);
+        const int tau_end = 3 * (ns - 1) + Jof(ns - 1) > Jof(0) ? 3 * (ns - 1) + Jof(ns - 1) : Jof(0);
         // my sweep
-        const int64_t my_i = i0 + tm;
-        const int64_t my_J = (tm < ns) ? Jof(tm) : 0;
-        int64_t loaded = wstart(0, 1);   // columns [written, loaded) are in the ring
-        int64_t written = loaded;
-        int s_lo = 0;
+        const int my_i = i0 + tm;
+        const int my_J = (tm < ns) ? Jof(tm) : 0;
+        LaneCarry<H> carry;              // lane mode: the last chase's below block
+        int loaded = wstart(0, 1);   // columns [written, loaded) are in the ring
+        int written = loaded;
+        int pub_pending = -1;        // watermark whose write-back is in flight
+        int pf_lo = 0, pf_hi = 0;    // columns [pf_lo, pf_hi) prefetched into pf
+        double pf[C::PFN];
+        // lowest active sweep and the step of its last chase
+        int s_lo = 0, f_lo = Jof(0);
 
-        for (int64_t tau_s = 1; tau_s <= tau_end; ++tau_s) {
-            while (s_lo < ns && Jof(s_lo) + 3 * s_lo < tau_s) ++s_lo;
+        auto lowest_active = [&](int s0, int tau) {
+            int sl = s0;
+            while (sl < ns && Jof(sl) + 3 * sl < tau) ++sl;
+            return sl;
+        };
+        // columns the group needs through step tb, given its lowest active sweep
+        auto need_through = [&](int sl, int tb) -> int {
+            if (sl >= ns) return loaded;
+            if (Jof(sl) + 3 * sl <= tb) return n;   // a sweep ends by then: its window reaches n
+            const int jj = tb - 3 * sl;
+            return (jj >= 1) ? wend(sl, jj) : wend(sl, 1);
+        };
+        // ring slot of column c (any c inside [written, written + WC))
+        auto slot = [&](int c) { return c % WC; };
+
+        for (int tau_s = 1; tau_s <= tau_end; ++tau_s) {
+            if (tau_s > f_lo && s_lo < ns) {
+                s_lo = lowest_active(s_lo, tau_s);
+                f_lo = (s_lo < ns) ? Jof(s_lo) + 3 * s_lo : tau_end;
+            }
             // ---- columns needed within the next BATCH steps
             if (((tau_s - 1) % C::BATCH) == 0 && s_lo < ns) {
-                const int64_t tb = tau_s + C::BATCH - 1;
-                int64_t need;
-                if (Jof(s_lo) + 3 * s_lo <= tb) {
-                    need = n;                                   // a sweep ends inside the batch
-                } else {
-                    int64_t jj = tb - 3 * s_lo;
-                    need = (jj >= 1) ? wend(s_lo, jj) : wend(s_lo, 1);
+                const int need = need_through(s_lo, tau_s + C::BATCH - 1);
+                // the columns prefetched a batch ago go to the ring (their loads
+                // were waited for at the last write-back)
+                if (pf_hi > pf_lo) {
+                    const int cnt = (int)(pf_hi - pf_lo) * LDW;
+                    const int sl0 = slot(pf_lo);
+#pragma unroll
+                    for (int p = 0; p < C::PFN; ++p) {
+                        const int idx = t + p * C::NT;
+                        if (idx < cnt) {
+                            const int k = idx / LDW, d = idx - k * LDW;
+                            int sl = sl0 + k;
+                            if (sl >= WC) sl -= WC;
+                            ring[sl * LDW + d] = pf[p];
+                        }
+                    }
+                    loaded = pf_hi;
+                    pf_lo = pf_hi = 0;
                 }
                 if (need > loaded) {
                     // wait until the previous group has released the columns
@@ -164,60 +210,110 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                     }
                     // load [loaded, need) into the ring
                     const int cnt = (int)(need - loaded) * LDW;
-                    const int sl0 = (int)(loaded % WC);
+                    const int sl0 = slot(loaded);
                     for (int idx = t; idx < cnt; idx += C::NT) {
                         const int k = idx / LDW, d = idx - k * LDW;
                         int sl = sl0 + k;
                         if (sl >= WC) sl -= WC;
-                        ring[sl * LDW + d] = gband[(loaded + k) * (int64_t)LDW + d];
+                        ring[sl * LDW + d] = (loaded + k + d < n) ? gband[(loaded + k) * (int64_t)LDW + d] : 0.0;
                     }
                     loaded = need;
-                    __syncthreads();
                 }
+                // prefetch what the next batch will need, as far as the previous
+                // group has already released it: the loads run during this batch
+                {
+                    const int sl2 = lowest_active(s_lo, tau_s + C::BATCH);
+                    int want = need_through(sl2, tau_s + 2 * C::BATCH - 1);
+                    if (want > loaded + C::PFC) want = loaded + C::PFC;
+                    if (want > loaded && g > 0) {
+                        if (t == 0 && vis_sh < want) {
+                            const int d = __hip_atomic_load(&a.done[g - 1], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                            if (d > vis_sh) {
+                                vis_sh = d;
+                                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                            }
+                        }
+                        __syncthreads();
+                        if (want > vis_sh) want = vis_sh;
+                    }
+                    if (want > loaded) {
+                        const int cnt = (int)(want - loaded) * LDW;
+#pragma unroll
+                        for (int p = 0; p < C::PFN; ++p) {
+                            const int idx = t + p * C::NT;
+                            if (idx < cnt) {
+                                const int k = idx / LDW, d = idx - k * LDW;
+                                // entries past the matrix end read as zero
+                                pf[p] = (loaded + k + d < n) ? gband[(loaded + k) * (int64_t)LDW + d] : 0.0;
+                            }
+                        }
+                        pf_lo = loaded;
+                        pf_hi = want;
+                    }
+                }
+                __syncthreads();
             }
 
-            // ---- the chases of this step, one per team
-            const int64_t jl = tau_s - 3 * tm;
+            // ---- the chases of this step, one per team (or lane)
+            const int jl = tau_s - 3 * tm;
             const bool act = (tm < ns) && (jl >= 1) && (jl <= my_J);
             const int j = act ? (int)jl : 0;
-            const int o = act ? (int)(my_i * H + (int64_t)(j - 1) * H2) : 0;
+            const int o = act ? my_i * H + (j - 1) * H2 : 0;
             const int nr = act ? ((n - o < H2) ? (int)(n - o) : H2) : 0;
             const int cq = (j == 1) ? o - H : o - H2;
             int nbl = (int)(n - (o + H2));
             if (nbl > H2) nbl = H2;
             const int nbr = (act && nbl > 0) ? nbl : 0;
-            cs = cq;
-            sbase = act ? cs % WC : 0;
+            if constexpr (!C::LANE) {
+                cs = cq;
+                sbase = act ? cs % WC : 0;
+            }
 
-            if (act) team_chase<H>(R, o, cq, nr, nbr, j, u, scr);
+            if constexpr (C::LANE) {
+                if (act) {
+                    // columns past the matrix end can only be touched once
+                    // o + 2h > n (never for h = 1: o <= n - 2)
+                    if (H == 1 || o + H2 <= n) lane_chase<H, WC, LDW, false>(ring, o, j == 1, nr, nbr, carry);
+                    else lane_chase<H, WC, LDW, true>(ring, o, j == 1, nr, nbr, carry);
+                }
+            } else {
+                if (act) team_chase<H>(R, o, cq, nr, nbr, j, u, scr);
+            }
             team_sync<TEAM>();
             __syncthreads();   // next step reads columns the neighbouring sweeps wrote
 
-            // ---- write back columns no sweep of the group will touch again
+            // ---- write back columns no sweep of the group will touch again.
+            // The stores of one batch are published at the next batch end (or
+            // at the group's end), by when they have long completed, so the
+            // wave never stalls on a store round trip.
             const bool last = (tau_s == tau_end);
             if (last || (tau_s % C::BATCH) == 0) {
-                int64_t done = last ? loaded : n;
+                int done = last ? loaded : n;
                 if (!last) {
                     // next step's active range: the smallest window start is at
                     // the highest started sweep; the next sweep to start (if
                     // any) begins at its first window
-                    const int64_t tn = tau_s + 1;
+                    const int tn = tau_s + 1;
                     int s_hi = (int)((tn - 1) / 3);
                     if (s_hi > ns - 1) s_hi = ns - 1;
                     if (s_hi >= 0 && Jof(s_hi) + 3 * s_hi >= tn) {
-                        const int64_t st = wstart(s_hi, tn - 3 * s_hi);
+                        const int st = wstart(s_hi, tn - 3 * s_hi);
                         done = st < done ? st : done;
                     }
                     if (s_hi + 1 < ns) {
-                        const int64_t st = wstart(s_hi + 1, 1);
+                        const int st = wstart(s_hi + 1, 1);
                         done = st < done ? st : done;
                     }
                 }
                 if (done > loaded) done = loaded;
-                const bool moved = done > written;
-                if (moved) {
+                // the previous batch's stores (and the prefetch loads) are done
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (t == 0 && pub_pending >= 0 && !last) sbr_store_release(&a.done[g], (int)pub_pending);
+                if (done > written) {
                     const int cnt = (int)(done - written) * LDW;
-                    const int sl0 = (int)(written % WC);
+                    const int sl0 = slot(written);
                     for (int idx = t; idx < cnt; idx += C::NT) {
                         const int k = idx / LDW, d = idx - k * LDW;
                         int sl = sl0 + k;
@@ -225,13 +321,13 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                         gband[(written + k) * (int64_t)LDW + d] = ring[sl * LDW + d];
                     }
                     written = done;
+                    pub_pending = written;
                 }
-                // stores complete to L2; thread 0's release below writes the L2 back
-                if (moved || last) __builtin_amdgcn_s_waitcnt(0);
-                __syncthreads();
-                if (t == 0 && (moved || last)) {
-                    int pub = (int)written;
-                    if (last) {
+                if (last) {
+                    // stores complete to L2; thread 0's release below writes the L2 back
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();
+                    if (t == 0) {
                         // everything this group loaded is back; columns it never
                         // loaded are final once the previous group is complete
                         if (g > 0) {
@@ -246,9 +342,8 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                                 }
                             }
                         }
-                        pub = (int)n;
+                        sbr_store_release(&a.done[g], (int)n);
                     }
-                    sbr_store_release(&a.done[g], pub);
                 }
             }
         }
@@ -271,7 +366,7 @@ void launch_group(int64_t n, double* band, int* flags, int* error, int max_grid,
     a.done = flags + 1;
     a.error = error;
     sbr::launch_fill_int(flags, ngroups + 1, 0, s);
-    int64_t grid = ngroups < 256 ? ngroups : 256;
+    int64_t grid = ngroups < (C::LANE ? 1024 : 256) ? ngroups : (C::LANE ? 1024 : 256);
     if (max_grid > 0 && grid > max_grid) grid = max_grid;
     const size_t shm = (size_t)C::LDS_DOUBLES * sizeof(double);
     band_group_kernel<H><<<(unsigned)grid, C::NT, shm, s>>>(a);

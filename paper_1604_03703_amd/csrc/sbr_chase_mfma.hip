@@ -450,7 +450,7 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 template <int H>
 int mchase_grid(int64_t n) {
     const int64_t nsweeps = (n - 2) / H;
-    const int64_t cap = (H == 64) ? 256 : (H == 32 ? 768 : 1024);
+    const int64_t cap = (H >= 16) ? 256 : 1024;
     int64_t g = nsweeps < cap ? nsweeps : cap;
     return (int)(g < 1 ? 1 : g);
 }

@@ -217,3 +217,199 @@ __device__ __forceinline__ void team_chase(const Band& R, int o, int cq, int nr,
         }
     }
 }
+
+// One chase done by a single lane, for the smallest h.  The lane owns a whole
+// sweep and keeps the chase's below block in registers: it is the next
+// chase's QR block (its first h columns) and left block (its last h
+// columns), and no other sweep reads it in between (sweep i+1 reaches those
+// rows only after chase (i, j+1), by the lag-3 order).  So a chase loads only
+// its diagonal and below blocks (and, for j = 1, its QR block).
+//
+// Reflector k is kept unnormalised, u = x - beta e_k, so that
+// H_k = I + g u u^T with g = 1 / (beta u_k): one division per reflector and
+// no scaling of the vector.  Q = H_0 ... H_{h-1} is applied one reflector at
+// a time: left X_L <- Q^T X_L, below X_B <- X_B Q, diagonal D <- Q^T D Q,
+// each two-sided step being D += u w^T + w u^T with p = g D u,
+// w = p + (g/2)(u^T p) u.
+//
+// The band window is addressed through one LDS pointer per column: the ring
+// holds column c at slot c mod WC (LDW doubles, diagonal offset r - c), and
+// every element offset inside a column is a compile-time constant.
+template <int H>
+struct LaneCarry {
+    double b[2 * H][2 * H];   // rows o + 2h + r, columns o + c of the last chase
+};
+
+// GUARD: columns past the matrix end may fall inside the chase (o + 2h > n);
+// otherwise every column is inside and rows past n read (and keep) zeros.
+template <int H, int WC, int LDW, bool GUARD>
+__device__ __forceinline__ void lane_chase(double* ring, int o, bool first, int nr, int nbr, LaneCarry<H>& cy) {
+    constexpr int H2 = 2 * H, NC = 4 * H;
+    // column o - 2h + x lives at ring + col[x] * LDW
+    double* col[NC];
+    {
+        int sl = (o + WC - H2) % WC;
+#pragma unroll
+        for (int x = 0; x < NC; ++x) {
+            col[x] = ring + sl * LDW;
+            sl = (sl + 1 == WC) ? 0 : sl + 1;
+        }
+    }
+    // element (o + r, o - 2h + x): diagonal offset 2h + r - x
+    auto at = [&](int r, int x) -> double& { return col[x][H2 + r - x]; };
+    double q[H2][H], lf[H2][H], d[H2][H2], bl[H2][H2];
+#pragma unroll
+    for (int r = 0; r < H2; ++r)
+#pragma unroll
+        for (int c = 0; c < H; ++c) {
+            double m = at(r, H + c);                       // j = 1: QR block at columns o - h ..
+            if (GUARD) m = (r < nr) ? m : 0.0;
+            q[r][c] = first ? m : cy.b[r][c];
+            lf[r][c] = first ? 0.0 : cy.b[r][H + c];
+        }
+#pragma unroll
+    for (int r = 0; r < H2; ++r)
+#pragma unroll
+        for (int k = 0; k <= r; ++k) {
+            double v = (!GUARD || r < nr) ? at(r, H2 + k) : 0.0;
+            d[r][k] = v;
+            d[k][r] = v;
+        }
+#pragma unroll
+    for (int r = 0; r < H2; ++r)
+#pragma unroll
+        for (int k = 0; k < H2; ++k)
+            bl[r][k] = (!GUARD || (r < nbr && k < nr)) ? at(H2 + r, H2 + k) : 0.0;
+
+    if constexpr (H == 1) {
+        // a 2 x 1 QR block: the reflector is the symmetric 2 x 2 matrix
+        // [[c, s], [s, -c]] with (c, s) = (x0, x1) / beta, beta = -sgn(x0) r,
+        // applied in closed form (identity when x1 = 0)
+        const double x0 = q[0][0], x1 = q[1][0];
+        const bool none = (x1 == 0.0);
+        const double rinv = rsqrt(x0 * x0 + x1 * x1);
+        const double sg = (x0 >= 0.0) ? -1.0 : 1.0;          // sign of beta
+        const double c = none ? 1.0 : -fabs(x0) * rinv;
+        const double s = none ? 0.0 : sg * x1 * rinv;
+        q[0][0] = none ? x0 : sg * (x0 * x0 + x1 * x1) * rinv;
+        q[1][0] = 0.0;
+        {
+            const double l0 = lf[0][0], l1 = lf[1][0];
+            lf[0][0] = c * l0 + s * l1;
+            lf[1][0] = s * l0 - c * l1;
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const double e0 = bl[r][0], e1 = bl[r][1];
+            bl[r][0] = c * e0 + s * e1;
+            bl[r][1] = s * e0 - c * e1;
+        }
+        {
+            const double da = d[0][0], db = d[1][0], dd = d[1][1];
+            const double cc = c * c, ss2 = s * s, cs = c * s;
+            const double t2 = 2.0 * cs * db;
+            d[0][0] = cc * da + t2 + ss2 * dd;
+            d[1][1] = ss2 * da - t2 + cc * dd;
+            const double off = cs * (da - dd) + (ss2 - cc) * db;
+            d[1][0] = off;
+            d[0][1] = off;
+        }
+    } else {
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const double xk = q[k][k];
+        double ss = 0.0;
+#pragma unroll
+        for (int r = k + 1; r < H2; ++r) ss += q[r][k] * q[r][k];
+        const bool none = (ss == 0.0);
+        const double nrm = sqrt(xk * xk + ss);
+        const double beta = none ? xk : ((xk >= 0.0) ? -nrm : nrm);
+        const double uk = xk - beta;
+        const double g = none ? 0.0 : 1.0 / (beta * uk);
+        double u[H2];
+#pragma unroll
+        for (int r = 0; r < H2; ++r) u[r] = (r < k) ? 0.0 : ((r == k) ? uk : q[r][k]);
+        q[k][k] = beta;
+#pragma unroll
+        for (int r = k + 1; r < H2; ++r) q[r][k] = 0.0;
+        // the rest of the QR block and the left block: X += g u (u^T X)
+#pragma unroll
+        for (int c = k + 1; c < H; ++c) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int r = k; r < H2; ++r) sacc += u[r] * q[r][c];
+            const double f = g * sacc;
+#pragma unroll
+            for (int r = k; r < H2; ++r) q[r][c] += f * u[r];
+        }
+#pragma unroll
+        for (int c = 0; c < H; ++c) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int r = k; r < H2; ++r) sacc += u[r] * lf[r][c];
+            const double f = g * sacc;
+#pragma unroll
+            for (int r = k; r < H2; ++r) lf[r][c] += f * u[r];
+        }
+        // below block: X_B += g (X_B u) u^T
+#pragma unroll
+        for (int r = 0; r < H2; ++r) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int c = k; c < H2; ++c) sacc += bl[r][c] * u[c];
+            const double f = g * sacc;
+#pragma unroll
+            for (int c = k; c < H2; ++c) bl[r][c] += f * u[c];
+        }
+        // diagonal block: D <- H_k D H_k
+        double p[H2];
+#pragma unroll
+        for (int r = 0; r < H2; ++r) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int c = k; c < H2; ++c) sacc += d[r][c] * u[c];
+            p[r] = g * sacc;
+        }
+        double up = 0.0;
+#pragma unroll
+        for (int r = k; r < H2; ++r) up += u[r] * p[r];
+        const double kk = 0.5 * g * up;
+#pragma unroll
+        for (int r = 0; r < H2; ++r) p[r] += kk * u[r];
+#pragma unroll
+        for (int r = 0; r < H2; ++r)
+#pragma unroll
+            for (int c = 0; c <= r; ++c) {
+                const double nv = d[r][c] + (u[r] * p[c] + p[r] * u[c]);
+                d[r][c] = nv;
+                d[c][r] = nv;
+            }
+    }
+    }
+
+    // ---- write back: R and the annihilated entries (QR block), the left
+    // block (for j = 1 the QR block sits there: the same values go to the
+    // same place twice), the diagonal block and the below block (the next
+    // chase's copy in registers supersedes it; the last chase's is final)
+#pragma unroll
+    for (int r = 0; r < H2; ++r) {
+        if (!GUARD || r < nr) {
+#pragma unroll
+            for (int c = 0; c < H; ++c) {
+                if (!first) at(r, c) = q[r][c];
+                at(r, H + c) = first ? q[r][c] : lf[r][c];
+            }
+#pragma unroll
+            for (int c = 0; c <= r; ++c) at(r, H2 + c) = d[r][c];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < H2; ++r)
+#pragma unroll
+        for (int k = 0; k < H2; ++k)
+            if (!GUARD || (r < nbr && k < nr)) at(H2 + r, H2 + k) = bl[r][k];
+#pragma unroll
+    for (int r = 0; r < H2; ++r)
+#pragma unroll
+        for (int k = 0; k < H2; ++k) cy.b[r][k] = bl[r][k];
+}
