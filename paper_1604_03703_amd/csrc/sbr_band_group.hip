@@ -24,30 +24,33 @@
 #include "sbr_internal.h"
 #include "sbr_team_chase.h"
 
-#ifndef SBR_LANE_BATCH
-#define SBR_LANE_BATCH 16
-#endif
+
 
 namespace {
 
 template <int H>
 struct GroupCfg {
-    // one team of 2h lanes per chase (lane u holds band row u of the chase's
-    // 2h-row blocks); sweeps per group sized so the ring plus the per-team
-    // scratch stay under 150 KB of LDS
-    static constexpr bool LANE = (H <= 2);          // one lane per sweep (lane_chase)
-    static constexpr int TEAM = LANE ? 1 : 2 * H;
-    // lanes: one wave per group, so a step needs no block barrier; teams:
-    // several waves per group
-    static constexpr int NT = LANE ? 64 : (H == 4 ? 256 : 128);
+    // h = 1: one lane per sweep (lane_chase), one wave per group, so a step
+    // needs no block barrier.  h = 2 and 4: two and four lanes per sweep
+    // (team_lane_chase), two waves per group.  All carry the bulge in
+    // registers.  h = 8 (used
+    // only where the MFMA chase is not): one team of 2h lanes per chase
+    // (team_chase, lane u holds band row u).  Sweeps per group are sized so
+    // the ring (plus team_chase's scratch) stays in LDS.
+    static constexpr bool LANE = (H <= 4);
+    static constexpr int TEAM = (H == 1) ? 1 : (H == 2 ? 2 : (H == 4 ? 4 : 2 * H));
+    static constexpr int NT = (H == 1) ? 64 : 128;
     static constexpr int S = NT / TEAM;
     static constexpr int LDW = 4 * H + 1;        // stored diagonals per column
-    static constexpr int BATCH = LANE ? SBR_LANE_BATCH : ((H >= 8) ? 4 : 8);   // steps per load / write-back batch
+    // steps per load / write-back batch
+    static constexpr int BATCH = (H <= 2) ? 16 : (H == 4 ? 8 : 4);
     static constexpr int WC = 5 * H * S + 2 * H * (BATCH + 6);
     static constexpr int H2 = 2 * H;
     // per-team scratch (doubles): U rows (2h x h), a second 2h x h block
     // (the left block, then W, then V) and an h x h product
-    static constexpr int SCR = LANE ? 0 : team_chase_scratch<H>();
+    // per-team scratch: the team_lane_chase gather buffers (16-lane teams),
+    // or team_chase's blocks
+    static constexpr int SCR = LANE ? (TEAM > 4 ? 4 * H : 0) : team_chase_scratch<H>();
     static constexpr int LDS_DOUBLES = WC * LDW + S * SCR;
     // prefetch registers: one batch of columns spread over the wave
     static constexpr int PFC = LANE ? 2 * H * BATCH : 0;
@@ -274,8 +277,15 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                 if (act) {
                     // columns past the matrix end can only be touched once
                     // o + 2h > n (never for h = 1: o <= n - 2)
-                    if (H == 1 || o + H2 <= n) lane_chase<H, WC, LDW, false>(ring, o, j == 1, nr, nbr, carry);
-                    else lane_chase<H, WC, LDW, true>(ring, o, j == 1, nr, nbr, carry);
+                    if constexpr (TEAM == 1) {
+                        if (H == 1 || o + H2 <= n) lane_chase<H, WC, LDW, false>(ring, o, j == 1, nr, nbr, carry);
+                        else lane_chase<H, WC, LDW, true>(ring, o, j == 1, nr, nbr, carry);
+                    } else {
+                        if (o + H2 <= n)
+                            team_lane_chase<H, TEAM, WC, LDW, false>(ring, o, j == 1, nr, nbr, u, carry, scr);
+                        else
+                            team_lane_chase<H, TEAM, WC, LDW, true>(ring, o, j == 1, nr, nbr, u, carry, scr);
+                    }
                 }
             } else {
                 if (act) team_chase<H>(R, o, cq, nr, nbr, j, u, scr);

@@ -12,6 +12,8 @@
 //   X_B -= ((X_B U) T) U^T
 //   W = (D U) T, V = 1/2 Z (U^T W) - W, D += U V^T + V U^T (lower part)
 #pragma once
+#include <utility>
+
 #include "sbr_device.h"
 
 // A chase's team lies inside one wavefront (TEAM divides 64), whose lanes run
@@ -412,4 +414,196 @@ __device__ __forceinline__ void lane_chase(double* ring, int o, bool first, int 
     for (int r = 0; r < H2; ++r)
 #pragma unroll
         for (int k = 0; k < H2; ++k) cy.b[r][k] = bl[r][k];
+}
+
+// Broadcast lane SRC of each aligned group of T lanes (T in {2, 4, 16}) to
+// the whole group: quad_perm (lane q of a quad reads lane sel[q]) inside a
+// quad, row_newbcast (every lane of a 16-lane row reads lane SRC) for a row.
+template <int T, int SRC>
+__device__ __forceinline__ double group_bcast(double v) {
+    static_assert(T == 2 || T == 4 || T == 16, "group size");
+    constexpr int CTRL = (T == 16) ? (0x150 + SRC)
+                       : (T == 4) ? (SRC | (SRC << 2) | (SRC << 4) | (SRC << 6))
+                                  : (SRC | (SRC << 2) | ((2 + SRC) << 4) | ((2 + SRC) << 6));
+    return dpp_d<CTRL>(v);
+}
+
+// out[s'] = v of lane s' of the group, for every s' < T
+template <int T>
+__device__ __forceinline__ void group_gather(double v, double* out) {
+    [&]<int... S>(std::integer_sequence<int, S...>) {
+        ((out[S] = group_bcast<T, S>(v)), ...);
+    }(std::make_integer_sequence<int, T>{});
+}
+
+// Every lane of a team of T gets the whole 2h-vector whose rows s + T i the
+// lanes hold: by DPP broadcasts inside a quad, through the team's LDS slice
+// (2h doubles, written then read back by the same wavefront) for T = 16,
+// where 16 broadcasts per vector would keep too many registers live.
+template <int H, int T>
+__device__ __forceinline__ void team_gather(const double (&loc)[2 * H / T], double (&full)[2 * H], double* buf,
+                                            int s) {
+    constexpr int RL = 2 * H / T;
+    if constexpr (T <= 4) {
+#pragma unroll
+        for (int i = 0; i < RL; ++i) group_gather<T>(loc[i], full + T * i);
+    } else {
+#pragma unroll
+        for (int i = 0; i < RL; ++i) buf[s + T * i] = loc[i];
+        team_sync<T>();
+#pragma unroll
+        for (int r = 0; r < 2 * H; ++r) full[r] = buf[r];
+        team_sync<T>();
+    }
+}
+
+// One chase done by a team of T lanes (T in {2, 4, 16}, T <= 2h): lane s holds
+// the rows s + T i (i < 2h / T) of every 2h-row block of the chase, and,
+// like lane_chase, carries its rows of the below block into the next chase.
+// Column sums are team all-reduces; the reflector and the vector w of the
+// two-sided step are gathered into every lane by DPP broadcasts.
+template <int H, int T, int WC, int LDW, bool GUARD>
+__device__ __forceinline__ void team_lane_chase(double* ring, int o, bool first, int nr, int nbr, int s,
+                                                LaneCarry<H>& cy, double* tbuf) {
+    constexpr int H2 = 2 * H, NC = 4 * H, RL = H2 / T;
+    static_assert(H2 % T == 0, "rows per lane");
+    double* col[NC];
+    {
+        int sl = (o + WC - H2) % WC;
+#pragma unroll
+        for (int x = 0; x < NC; ++x) {
+            col[x] = ring + sl * LDW;
+            sl = (sl + 1 == WC) ? 0 : sl + 1;
+        }
+    }
+    auto at = [&](int r, int x) -> double& { return col[x][H2 + r - x]; };
+    // rows of this lane: r = s + T i.  The carry holds them in cy.b[i][.].
+    double q[RL][H], lf[RL][H], d[RL][H2], bl[RL][H2];
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+        const int r = s + T * i;
+#pragma unroll
+        for (int c = 0; c < H; ++c) {
+            double m = at(r, H + c);
+            if (GUARD) m = (r < nr) ? m : 0.0;
+            q[i][c] = first ? m : cy.b[i][c];
+            lf[i][c] = first ? 0.0 : cy.b[i][H + c];
+        }
+        // full row r of the diagonal block: D[r][c] = band(o + max, o + min);
+        // column o + r (a lane-dependent column) through its own pointer
+        const double* colr = ring + ((o + r) % WC) * LDW;
+#pragma unroll
+        for (int c = 0; c < H2; ++c) {
+            const double* pa = (c <= r) ? col[H2 + c] + (r - c) : colr + (c - r);
+            double v = *pa;
+            if (GUARD) v = (r < nr && c < nr) ? v : 0.0;
+            d[i][c] = v;
+        }
+#pragma unroll
+        for (int c = 0; c < H2; ++c) {
+            double v = at(H2 + r, H2 + c);
+            if (GUARD) v = (r < nbr && c < nr) ? v : 0.0;
+            bl[i][c] = v;
+        }
+    }
+
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        // ---- reflector k (x_k sits in lane k % T, row slot k / T)
+        double ssp = 0.0, xkp = 0.0;
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            const int r = s + T * i;
+            ssp += (r > k) ? q[i][k] * q[i][k] : 0.0;
+            xkp = (r == k) ? q[i][k] : xkp;
+        }
+        const double ss = group_sum<T>(ssp);
+        const double xk = group_sum<T>(xkp);
+        const bool none = (ss == 0.0);
+        const double nrm = sqrt(xk * xk + ss);
+        const double beta = none ? xk : ((xk >= 0.0) ? -nrm : nrm);
+        const double uk = xk - beta;
+        const double g = none ? 0.0 : 1.0 / (beta * uk);
+        double ul[RL];
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            const int r = s + T * i;
+            ul[i] = (r < k) ? 0.0 : ((r == k) ? uk : q[i][k]);
+            q[i][k] = (r == k) ? beta : ((r > k) ? 0.0 : q[i][k]);
+        }
+        // the reflector in every lane: uf[s' + T i] from lane s'
+        double uf[H2];
+        team_gather<H, T>(ul, uf, tbuf, s);
+        // QR block columns c > k and the left block: X += g u (u^T X)
+#pragma unroll
+        for (int c = k + 1; c < H; ++c) {
+            double p = 0.0;
+#pragma unroll
+            for (int i = 0; i < RL; ++i) p += ul[i] * q[i][c];
+            const double f = g * group_sum<T>(p);
+#pragma unroll
+            for (int i = 0; i < RL; ++i) q[i][c] += f * ul[i];
+        }
+#pragma unroll
+        for (int c = 0; c < H; ++c) {
+            double p = 0.0;
+#pragma unroll
+            for (int i = 0; i < RL; ++i) p += ul[i] * lf[i][c];
+            const double f = g * group_sum<T>(p);
+#pragma unroll
+            for (int i = 0; i < RL; ++i) lf[i][c] += f * ul[i];
+        }
+        // below block rows: X_B += g (X_B u) u^T
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            double p = 0.0;
+#pragma unroll
+            for (int c = k; c < H2; ++c) p += bl[i][c] * uf[c];
+            const double f = g * p;
+#pragma unroll
+            for (int c = k; c < H2; ++c) bl[i][c] += f * uf[c];
+        }
+        // diagonal block: p = g D u, w = p + (g/2)(u^T p) u, D += u w^T + w u^T
+        double pl[RL];
+        double upp = 0.0;
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = k; c < H2; ++c) acc += d[i][c] * uf[c];
+            pl[i] = g * acc;
+            upp += ul[i] * pl[i];
+        }
+        const double kk = 0.5 * g * group_sum<T>(upp);
+        double wl[RL];
+#pragma unroll
+        for (int i = 0; i < RL; ++i) wl[i] = pl[i] + kk * ul[i];
+        double wf[H2];
+        team_gather<H, T>(wl, wf, tbuf + H2, s);
+#pragma unroll
+        for (int i = 0; i < RL; ++i)
+#pragma unroll
+            for (int c = 0; c < H2; ++c) d[i][c] += ul[i] * wf[c] + wl[i] * uf[c];
+    }
+
+    // ---- write back (see lane_chase)
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+        const int r = s + T * i;
+        if (!GUARD || r < nr) {
+#pragma unroll
+            for (int c = 0; c < H; ++c) {
+                if (!first) at(r, c) = q[i][c];
+                at(r, H + c) = first ? q[i][c] : lf[i][c];
+            }
+#pragma unroll
+            for (int c = 0; c < H2; ++c)
+                if (c <= r) col[H2 + c][r - c] = d[i][c];
+        }
+#pragma unroll
+        for (int c = 0; c < H2; ++c)
+            if (!GUARD || (r < nbr && c < nr)) at(H2 + r, H2 + c) = bl[i][c];
+#pragma unroll
+        for (int c = 0; c < H2; ++c) cy.b[i][c] = bl[i][c];
+    }
 }
