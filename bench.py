@@ -152,6 +152,21 @@ def run_batch(sbr, torch, si, count, steps, warmup):
         tm = mean(times)
         out[prec] = {"ms": round(tm * 1e3, 3), "solves_per_s": round(count / tm, 1)}
         plan.close()
+    # the plain FP64 solver called once per matrix (one plan, the same stream)
+    # on the first `plain` matrices: what the batched launch replaces
+    plain = min(count, 512)
+    plan = sbr.Plan(512, 0, "fp64")
+    for d, d0 in zip(dev[:plain], dev0[:plain]):
+        d.copy_(d0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d, w in zip(dev[:plain], ws[:plain]):
+        w.copy_(sbr.eigvalsh(d, precision="fp64", plan=plan, overwrite=True))
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    plan.close()
+    out["plain_fp64_loop"] = {"count": plain, "solves_per_s": round(plain / tp, 1)}
+    out["batched_speedup_vs_plain"] = round(out["fp64"]["solves_per_s"] / (plain / tp), 2)
     # every matrix's eigenvalues sum to its trace (cheap check at full size)
     tr = max(abs(float(w.sum().item()) - float(np.trace(M))) / max(1.0, float(np.abs(M).max()) * M.shape[0])
              for w, M in zip(ws[:64], mats[:64]))
@@ -196,6 +211,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only run the batched form and print its results (profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -220,6 +237,10 @@ def main():
 
     import sbr_inputs as si
     import paper_1604_03703_amd as sbr
+
+    if args.batch_only:
+        print(json.dumps({"batch": run_batch(sbr, torch, si, args.batch_count, args.steps, args.warmup)}), flush=True)
+        return
 
     n, b0 = args.n, args.b0
     cfg = si.CFG_LARGE if n == 32768 else si.CFG_MEDIUM
@@ -250,7 +271,12 @@ def main():
     syr2k_ms = mean([t["ms_syr2k"] for t in tims])
     symm_ms = mean([t["ms_symm"] for t in tims])
     if syr2k_ms >= symm_ms:
-        kname, kflops, kms, klaunch = "syr2k_lower_kernel (bulk trailing update)", sum(syr2k_f), syr2k_ms, len(syr2k_f)
+        # the bulk launches on 128 x 128 tiles (`syr2k_lower_kernel<double, 128, ...>`,
+        # the first ones: the last, small trailing matrices run on 64 x 64 tiles)
+        nbig = int(tims[-1]["syr2k_big_launches"])
+        kname = "syr2k_lower_kernel<double, 128, 2, 4> (bulk trailing update)"
+        kflops, klaunch = sum(syr2k_f[:nbig]), nbig
+        kms = mean([t["ms_syr2k_big"] for t in tims])
         traffic = measured_traffic("sbr_gemm.hip")
     else:
         kname, kflops, kms, klaunch = "symm_lower_kernel", sum(symm_f), symm_ms, len(symm_f)

@@ -90,6 +90,10 @@ typedef struct {
     int64_t symm_launches;
     double ms_stage[8];       /* per halving stage (b0, b0/2, ...) */
     int32_t n_stages;
+    double ms_syr2k_big;      /* the bulk SYR2K launches on 128 x 128 tiles
+                                 (the first ones; the last, small trailing
+                                 matrices use 64 x 64 tiles) */
+    int64_t syr2k_big_launches;
 } sbr_timing;
 
 int sbr_plan_set_timing(sbr_plan_t plan, int enable);

@@ -39,6 +39,7 @@ class _Timing(ctypes.Structure):
         ("ms_syr2k", _dbl), ("syr2k_launches", _i64),
         ("ms_symm", _dbl), ("symm_launches", _i64),
         ("ms_stage", _dbl * 8), ("n_stages", _i32),
+        ("ms_syr2k_big", _dbl), ("syr2k_big_launches", _i64),
     ]
 
 

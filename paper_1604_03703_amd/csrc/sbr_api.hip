@@ -97,6 +97,7 @@ struct sbr_plan_s {
     size_t pool_used = 0;
     EventPair ev_total, ev_f2b, ev_band, ev_bis;
     std::vector<EventPair> ev_syr2k, ev_symm, ev_stage;
+    std::vector<char> syr2k_big;      // per bulk SYR2K launch: 128 x 128 tiles
 
     hipEvent_t ev() {
         if (pool_used == pool.size()) {
@@ -110,6 +111,7 @@ struct sbr_plan_s {
         pool_used = 0;
         ev_total = ev_f2b = ev_band = ev_bis = EventPair{};
         ev_syr2k.clear();
+        syr2k_big.clear();
         ev_symm.clear();
         ev_stage.clear();
     }
@@ -403,7 +405,12 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
                 if (p->timing) { eq.a = p->ev(); p->mark(eq.a, us); }
                 if (f32s) launch_syr2k_lower_f32s(mn, b, U + b, ldq, p->V + b, ldq, A22s + b + b * lds, lds, us);
                 else launch_syr2k_lower(f32, mn, b, U + b, ldq, p->V + b, ldq, A22 + b + b * lda, lda, us);
-                if (p->timing) { eq.b = p->ev(); p->mark(eq.b, us); p->ev_syr2k.push_back(eq); }
+                if (p->timing) {
+                    eq.b = p->ev();
+                    p->mark(eq.b, us);
+                    p->ev_syr2k.push_back(eq);
+                    p->syr2k_big.push_back(syr2k_big_tiles(mn) ? 1 : 0);
+                }
             };
             if (p->upd) {
                 bulk(p->upd);
@@ -424,7 +431,12 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
             if (p->timing) { eq.a = p->ev(); p->mark(eq.a, s); }
             if (f32s) launch_syr2k_lower_f32s(m, b, U, ldq, p->V, ldq, A22s, lds, s);
             else launch_syr2k_lower(f32, m, b, U, ldq, p->V, ldq, A22, lda, s);
-            if (p->timing) { eq.b = p->ev(); p->mark(eq.b, s); p->ev_syr2k.push_back(eq); }
+            if (p->timing) {
+                eq.b = p->ev();
+                p->mark(eq.b, s);
+                p->ev_syr2k.push_back(eq);
+                p->syr2k_big.push_back(syr2k_big_tiles(m) ? 1 : 0);
+            }
             // the rest of the trailing matrix back to FP64 for the ragged tail
             if (f32s) launch_cols_to_f64(m, m, A22s, lds, A22, lda, s);
         }
@@ -606,7 +618,15 @@ int sbr_plan_get_timing(sbr_plan_t plan, sbr_timing* out) {
     out->ms_f2b = pair_ms(plan->ev_f2b);
     out->ms_band = pair_ms(plan->ev_band);
     out->ms_bisect = pair_ms(plan->ev_bis);
-    for (auto& e : plan->ev_syr2k) { out->ms_syr2k += pair_ms(e); out->syr2k_launches++; }
+    for (size_t i = 0; i < plan->ev_syr2k.size(); ++i) {
+        const double ms = pair_ms(plan->ev_syr2k[i]);
+        out->ms_syr2k += ms;
+        out->syr2k_launches++;
+        if (i < plan->syr2k_big.size() && plan->syr2k_big[i]) {
+            out->ms_syr2k_big += ms;
+            out->syr2k_big_launches++;
+        }
+    }
     for (auto& e : plan->ev_symm) { out->ms_symm += pair_ms(e); out->symm_launches++; }
     out->ms_update_kernels = out->ms_syr2k + out->ms_symm;
     out->update_launches = out->syr2k_launches + out->symm_launches;

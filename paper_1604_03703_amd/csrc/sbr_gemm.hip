@@ -512,13 +512,18 @@ void launch_gemm_splitk(bool f32, bool ta, bool tb, int64_t M, int64_t N, int64_
     reduce_slices(M, N, splits, part, alpha, beta, Cin, ldci, Cout, ldco, s);
 }
 
-void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t ldu, const double* V,
-                        int64_t ldv, double* C, int64_t ldc, hipStream_t s) {
-    if (m <= 0 || K <= 0) return;
+bool syr2k_big_tiles(int64_t m) {
     // 128 x 128 tiles on 8 waves (each wave 64 x 32) once there are enough
     // of them to fill the chip; 64 x 64 tiles on 4 waves below that
     const int64_t T128 = (m + 127) / 128;
-    if (T128 * (T128 + 1) / 2 >= 512) {
+    return T128 * (T128 + 1) / 2 >= 512;
+}
+
+void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t ldu, const double* V,
+                        int64_t ldv, double* C, int64_t ldc, hipStream_t s) {
+    if (m <= 0 || K <= 0) return;
+    const int64_t T128 = (m + 127) / 128;
+    if (syr2k_big_tiles(m)) {
         const int64_t nt = T128 * (T128 + 1) / 2;
         if (f32) syr2k_lower_kernel<float, 128, 2, 4><<<(unsigned)nt, 512, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
         else syr2k_lower_kernel<double, 128, 2, 4><<<(unsigned)nt, 512, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
@@ -571,7 +576,7 @@ void launch_syr2k_lower_f32s(int64_t m, int64_t K, const double* U, int64_t ldu,
                              float* C, int64_t ldc, hipStream_t s) {
     if (m <= 0 || K <= 0) return;
     const int64_t T128 = (m + 127) / 128;
-    if (T128 * (T128 + 1) / 2 >= 512) {
+    if (syr2k_big_tiles(m)) {
         const int64_t nt = T128 * (T128 + 1) / 2;
         syr2k_lower_kernel<float, 128, 2, 4, 2, float><<<(unsigned)nt, 512, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
         return;

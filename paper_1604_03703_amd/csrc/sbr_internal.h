@@ -15,6 +15,8 @@ void launch_gemm_splitk(bool f32, bool ta, bool tb, int64_t M, int64_t N, int64_
                         const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                         const double* Cin, int64_t ldci, double* Cout, int64_t ldco, double* part,
                         int splits, hipStream_t s);
+// Whether a bulk SYR2K launch over m rows uses 128 x 128 tiles (else 64 x 64).
+bool syr2k_big_tiles(int64_t m);
 void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t ldu, const double* V,
                         int64_t ldv, double* C, int64_t ldc, hipStream_t s);
 // The columns j < nc of the same update (all rows, lower triangle only).
