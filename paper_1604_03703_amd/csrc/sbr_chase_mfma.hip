@@ -2,9 +2,11 @@
 // with k = 2) for b in {32, 64, 128}, every product of a chase on FP64 MFMA.
 //
 // A chase (i, j) works on the rows [o, o + n_r) of the band, o = ih + (j-1)b
-// (the same offsets, extents and pipelined schedule as the small-b kernels:
-// chase (i, j) starts after chase (i, j-1) of the same block and after sweep
-// i-1 has finished chase j + 2).  With [U, T, R] = QR(QR block) and
+// (the same offsets and extents as the small-b kernels; chase (i, j) starts
+// after chase (i, j-1) of the same block and after chase (i-1, j+2) has
+// finished its QR block, the only entries the two chases share, so a sweep
+// overlaps the second half of the chase two ahead of it in the previous sweep).
+// With [U, T, R] = QR(QR block) and
 // Q = I - U T U^T:
 //   left block  X_L  (rows [o, o+n_r), cols [o-h, o), j > 1):  X_L <- Q^T X_L
 //   below block X_B  (rows [o+b, o+2b), cols [o, o+n_r)):      X_B <- X_B Q
@@ -216,7 +218,15 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                     if (row < nr) B_at(o + row, cq + qc) = (row <= qc) ? x[r] : 0.0;
                 }
             }
+            // ---- publish the QR block: it is the only part of this chase that
+            // chase (i+1, j-2) shares (its below block meets this QR block; the
+            // rest of this chase lies beyond its columns), so sweep i+1 may go
+            // on while this chase updates its left, diagonal and below blocks.
+            // Every wave's stores complete to L2, then one agent-scope release
+            // (L2 write-back) by thread 0 covers the block.
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
+            if (t == 0) sbr_store_release(&a.progress[i], (int)j);
 
             // ---- 2. L = T^{-1}: strict upper part of U^T U, tau on the diagonal
             // (the multiplier that replaces 1/tau below; a zero tau gives a zero
@@ -438,11 +448,13 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 }
             }
 
-            // ---- publish: every wave's stores complete to L2, then one
-            // agent-scope release (L2 write-back) by thread 0 covers the block
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            if (t == 0) sbr_store_release(&a.progress[i], (j == nchase) ? MSWEEP_DONE : (int)j);
+            // ---- the sweep's last chase: publish the whole sweep (a chase of
+            // sweep i+1 without a partner two chases ahead waits for it)
+            if (j == nchase) {
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (t == 0) sbr_store_release(&a.progress[i], MSWEEP_DONE);
+            }
         }
     }
 }
