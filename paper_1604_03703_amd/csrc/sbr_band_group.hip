@@ -4,11 +4,14 @@
 // The chase mathematics is the one of sbr_band.hip (same offsets, extents and
 // Eq. (4.1)-form update); what differs is the schedule.  A work-group owns a
 // group of S consecutive sweeps i0 .. i0+S-1 and runs them as a pipeline of
-// its own: at step tau sweep i0+s performs chase j = tau - 3s.  Chases that
-// run in the same step are three chases apart in consecutive sweeps, so they
-// write disjoint band columns (chase (i, j) writes columns [o-2h, o+2h),
-// o = ih + (j-1)b, or [o-h, o+2h) for j = 1) and steps need only a work-group
-// barrier.  One team of TEAM threads performs each chase.
+// its own: at step tau sweep i0+s performs chase j = tau - LAG s.  For h <= 4
+// a chase is split in a QR phase and an update phase with a barrier between
+// them, and LAG = 2: chases of one step are two chases apart in consecutive
+// sweeps; the only entries two of them share are in the QR block of the
+// upper sweep's chase, which its QR phase finishes before the lower sweep's
+// update phase reads them.  For h = 8 (team_chase, one phase) LAG = 3: chases
+// of one step write disjoint band columns (chase (i, j) writes columns
+// [o-2h, o+2h), o = ih + (j-1)b, or [o-h, o+2h) for j = 1).
 //
 // The group's live columns sit in an LDS ring buffer (column c at slot
 // c mod WC, the 4h+1 stored diagonals contiguous, the same layout as the
@@ -16,9 +19,9 @@
 // the leading sweep and written back once every sweep of the group is past
 // them; the group then publishes a watermark done[g]: every column below it is
 // final as far as sweeps <= i0+S-1 are concerned.  Group g+1 loads a column
-// only below done[g]; this is the lag-3 rule between the last sweep of one
-// group and the first sweep of the next, enforced at batch granularity (one
-// agent-scope acquire per batch, not per chase).  Groups are taken from a
+// only below done[g], which keeps the first sweep of one group behind the
+// last sweep of the previous one, at batch granularity (one agent-scope
+// acquire per batch, not per chase).  Groups are taken from a
 // ticket counter in order, so the group a block waits on is always running.
 #include "sbr_device.h"
 #include "sbr_internal.h"
@@ -30,13 +33,13 @@ namespace {
 
 template <int H>
 struct GroupCfg {
-    // h = 1: one lane per sweep (lane_chase), one wave per group, so a step
-    // needs no block barrier.  h = 2 and 4: two and four lanes per sweep
-    // (team_lane_chase), two waves per group.  All carry the bulge in
-    // registers.  h = 8 (used
-    // only where the MFMA chase is not): one team of 2h lanes per chase
-    // (team_chase, lane u holds band row u).  Sweeps per group are sized so
-    // the ring (plus team_chase's scratch) stays in LDS.
+    // h = 1: one lane per sweep (lane_chase_qr / _update), one wave per
+    // group, so a step's barriers are cheap.  h = 2 and 4: two and four
+    // lanes per sweep (team_lane_chase_qr / _update), two waves per group.
+    // All carry the bulge in registers.  h = 8 (used only where the MFMA
+    // chase is not): one team of 2h lanes per chase (team_chase, lane u holds
+    // band row u).  Sweeps per group are sized so the ring (plus
+    // team_chase's scratch) stays in LDS.
     static constexpr bool LANE = (H <= 4);
     static constexpr int TEAM = (H == 1) ? 1 : (H == 2 ? 2 : (H == 4 ? 4 : 2 * H));
     static constexpr int NT = (H == 1) ? 64 : 128;
@@ -44,7 +47,13 @@ struct GroupCfg {
     static constexpr int LDW = 4 * H + 1;        // stored diagonals per column
     // steps per load / write-back batch
     static constexpr int BATCH = (H <= 2) ? 16 : (H == 4 ? 8 : 4);
-    static constexpr int WC = 5 * H * S + 2 * H * (BATCH + 6);
+    // steps between consecutive sweeps of the group: two with the two-phase
+    // lane chases (a QR phase and an update phase per step), three with
+    // team_chase, which does a whole chase between two barriers
+    static constexpr int LAG = LANE ? 2 : 3;
+    // ring columns: the active windows span (2 LAG - 1) h per sweep, plus
+    // the columns loaded for one batch of steps ahead
+    static constexpr int WC = (2 * LAG - 1) * H * S + 2 * H * (BATCH + 6);
     static constexpr int H2 = 2 * H;
     // per-team scratch (doubles): U rows (2h x h), a second 2h x h block
     // (the left block, then W, then V) and an h x h product
@@ -77,7 +86,7 @@ __device__ __forceinline__ int nchase_of(int n, int i) {
 template <int H>
 __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a) {
     typedef GroupCfg<H> C;
-    constexpr int H2 = C::H2, TEAM = C::TEAM, S = C::S, WC = C::WC, LDW = C::LDW;
+    constexpr int H2 = C::H2, TEAM = C::TEAM, S = C::S, WC = C::WC, LDW = C::LDW, LAG = C::LAG;
     extern __shared__ double smem[];
     double* ring = smem;
     __shared__ int g_sh, abort_sh, fresh_sh;
@@ -113,9 +122,9 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
         const int i0 = 1 + g * S;
         const int ns = (a.nsweeps - i0 + 1 < S) ? (a.nsweeps - i0 + 1) : S;
         // Sweeps finish in order: sweep s does its last chase at step
-        // f(s) = J_s + 3s, which increases with s.  At step tau the active
+        // f(s) = J_s + LAG s, which increases with s.  At step tau the active
         // sweeps are s_lo(tau) .. s_hi(tau) with s_lo the first s with
-        // f(s) >= tau and s_hi = min(ns-1, (tau-1)/3); window ends decrease
+        // f(s) >= tau and s_hi = min(ns-1, (tau-1)/LAG); window ends decrease
         // and window starts decrease with s, so the extremes are at s_lo
         // (end) and s_hi (start).
         auto Jof = [&](int s) -> int { return nchase_of<H>(n, i0 + s); };
@@ -127,7 +136,7 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
             const int e = (i0 + s) * H + j * H2;
             return e < n ? e : n;
         };
-        const int tau_end = 3 * (ns - 1) + Jof(ns - 1) > Jof(0) ? 3 * (ns - 1) + Jof(ns - 1) : Jof(0);
+        const int tau_end = LAG * (ns - 1) + Jof(ns - 1) > Jof(0) ? LAG * (ns - 1) + Jof(ns - 1) : Jof(0);
         // my sweep
         const int my_i = i0 + tm;
         const int my_J = (tm < ns) ? Jof(tm) : 0;
@@ -142,14 +151,14 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
 
         auto lowest_active = [&](int s0, int tau) {
             int sl = s0;
-            while (sl < ns && Jof(sl) + 3 * sl < tau) ++sl;
+            while (sl < ns && Jof(sl) + LAG * sl < tau) ++sl;
             return sl;
         };
         // columns the group needs through step tb, given its lowest active sweep
         auto need_through = [&](int sl, int tb) -> int {
             if (sl >= ns) return loaded;
-            if (Jof(sl) + 3 * sl <= tb) return n;   // a sweep ends by then: its window reaches n
-            const int jj = tb - 3 * sl;
+            if (Jof(sl) + LAG * sl <= tb) return n;   // a sweep ends by then: its window reaches n
+            const int jj = tb - LAG * sl;
             return (jj >= 1) ? wend(sl, jj) : wend(sl, 1);
         };
         // ring slot of column c (any c inside [written, written + WC))
@@ -158,7 +167,7 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
         for (int tau_s = 1; tau_s <= tau_end; ++tau_s) {
             if (tau_s > f_lo && s_lo < ns) {
                 s_lo = lowest_active(s_lo, tau_s);
-                f_lo = (s_lo < ns) ? Jof(s_lo) + 3 * s_lo : tau_end;
+                f_lo = (s_lo < ns) ? Jof(s_lo) + LAG * s_lo : tau_end;
             }
             // ---- columns needed within the next BATCH steps
             if (((tau_s - 1) % C::BATCH) == 0 && s_lo < ns) {
@@ -259,7 +268,7 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
             }
 
             // ---- the chases of this step, one per team (or lane)
-            const int jl = tau_s - 3 * tm;
+            const int jl = tau_s - LAG * tm;
             const bool act = (tm < ns) && (jl >= 1) && (jl <= my_J);
             const int j = act ? (int)jl : 0;
             const int o = act ? my_i * H + (j - 1) * H2 : 0;
@@ -274,17 +283,28 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
             }
 
             if constexpr (C::LANE) {
-                if (act) {
-                    // columns past the matrix end can only be touched once
-                    // o + 2h > n (never for h = 1: o <= n - 2)
-                    if constexpr (TEAM == 1) {
-                        if (H == 1 || o + H2 <= n) lane_chase<H, WC, LDW, false>(ring, o, j == 1, nr, nbr, carry);
-                        else lane_chase<H, WC, LDW, true>(ring, o, j == 1, nr, nbr, carry);
-                    } else {
-                        if (o + H2 <= n)
-                            team_lane_chase<H, TEAM, WC, LDW, false>(ring, o, j == 1, nr, nbr, u, carry, scr);
+                // columns past the matrix end can only be touched once
+                // o + 2h > n (never for h = 1: o <= n - 2)
+                const bool guard = act && (o + H2 > n);
+                if constexpr (TEAM == 1) {
+                    LaneRot rot;
+                    if (act) lane_chase_qr<WC, LDW>(ring, o, j == 1, carry, rot);
+                    __syncthreads();   // the update phases read QR blocks of the neighbours
+                    if (act) lane_chase_update<WC, LDW>(ring, o, j == 1, carry, rot);
+                } else {
+                    TeamRefl<H, TEAM> rf;
+                    if (act) {
+                        if (!guard) team_lane_chase_qr<H, TEAM, WC, LDW, false>(ring, o, j == 1, nr, u, carry, rf);
+                        else team_lane_chase_qr<H, TEAM, WC, LDW, true>(ring, o, j == 1, nr, u, carry, rf);
+                    }
+                    __syncthreads();
+                    if (act) {
+                        if (!guard)
+                            team_lane_chase_update<H, TEAM, WC, LDW, false>(ring, o, j == 1, nr, nbr, u, carry, rf,
+                                                                            scr);
                         else
-                            team_lane_chase<H, TEAM, WC, LDW, true>(ring, o, j == 1, nr, nbr, u, carry, scr);
+                            team_lane_chase_update<H, TEAM, WC, LDW, true>(ring, o, j == 1, nr, nbr, u, carry, rf,
+                                                                           scr);
                     }
                 }
             } else {
@@ -305,10 +325,10 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                     // the highest started sweep; the next sweep to start (if
                     // any) begins at its first window
                     const int tn = tau_s + 1;
-                    int s_hi = (int)((tn - 1) / 3);
+                    int s_hi = (int)((tn - 1) / LAG);
                     if (s_hi > ns - 1) s_hi = ns - 1;
-                    if (s_hi >= 0 && Jof(s_hi) + 3 * s_hi >= tn) {
-                        const int st = wstart(s_hi, tn - 3 * s_hi);
+                    if (s_hi >= 0 && Jof(s_hi) + LAG * s_hi >= tn) {
+                        const int st = wstart(s_hi, tn - LAG * s_hi);
                         done = st < done ? st : done;
                     }
                     if (s_hi + 1 < ns) {

@@ -220,19 +220,22 @@ __device__ __forceinline__ void team_chase(const Band& R, int o, int cq, int nr,
     }
 }
 
-// One chase done by a single lane, for the smallest h.  The lane owns a whole
-// sweep and keeps the chase's below block in registers: it is the next
-// chase's QR block (its first h columns) and left block (its last h
-// columns), and no other sweep reads it in between (sweep i+1 reaches those
-// rows only after chase (i, j+1), by the lag-3 order).  So a chase loads only
-// its diagonal and below blocks (and, for j = 1, its QR block).
+// Chases done by one lane (h = 1) or by a small team of lanes (h = 2, 4)
+// that own a whole sweep, in two phases so that consecutive sweeps can run
+// two chases apart: the QR phase reads the chase's QR block, forms the
+// reflectors and writes [R; 0] back; the update phase applies them to the
+// left block (X_L <- Q^T X_L), the below block (X_B <- X_B Q) and the
+// diagonal block (D <- Q^T D Q).  The caller puts a work-group barrier
+// between the phases of one step: a neighbouring sweep's update phase reads
+// entries of this chase's QR block, and this chase's update phase reads
+// entries of the neighbour's.
 //
-// Reflector k is kept unnormalised, u = x - beta e_k, so that
-// H_k = I + g u u^T with g = 1 / (beta u_k): one division per reflector and
-// no scaling of the vector.  Q = H_0 ... H_{h-1} is applied one reflector at
-// a time: left X_L <- Q^T X_L, below X_B <- X_B Q, diagonal D <- Q^T D Q,
-// each two-sided step being D += u w^T + w u^T with p = g D u,
-// w = p + (g/2)(u^T p) u.
+// The sweep keeps the chase's below block in registers: it is the next
+// chase's QR block (its first h columns) and left block (its last h
+// columns).  No other sweep writes those entries in between (the neighbour
+// one step behind touches the QR part only after the QR phase has stored it,
+// and never the left part), so a chase loads only its diagonal and below
+// blocks (and, for j = 1, its QR block).
 //
 // The band window is addressed through one LDS pointer per column: the ring
 // holds column c at slot c mod WC (LDW doubles, diagonal offset r - c), and
@@ -242,178 +245,75 @@ struct LaneCarry {
     double b[2 * H][2 * H];   // rows o + 2h + r, columns o + c of the last chase
 };
 
-// GUARD: columns past the matrix end may fall inside the chase (o + 2h > n);
-// otherwise every column is inside and rows past n read (and keep) zeros.
-template <int H, int WC, int LDW, bool GUARD>
-__device__ __forceinline__ void lane_chase(double* ring, int o, bool first, int nr, int nbr, LaneCarry<H>& cy) {
-    constexpr int H2 = 2 * H, NC = 4 * H;
-    // column o - 2h + x lives at ring + col[x] * LDW
-    double* col[NC];
+// col[x] -> column o - 2h + x, x < 4h
+template <int H, int WC, int LDW>
+__device__ __forceinline__ void chase_columns(double* ring, int o, double* (&col)[4 * H]) {
+    int sl = (o + WC - 2 * H) % WC;
+#pragma unroll
+    for (int x = 0; x < 4 * H; ++x) {
+        col[x] = ring + sl * LDW;
+        sl = (sl + 1 == WC) ? 0 : sl + 1;
+    }
+}
+
+// h = 1: the reflection of the 2 x 1 QR block x is the symmetric 2 x 2 matrix
+// [[c, s], [s, -c]] with (c, s) = (x0, x1) / beta, beta = -sgn(x0) ||x||,
+// applied in closed form (the identity when x1 = 0).  Columns never reach
+// past the matrix end (o <= n - 2); rows past it read and keep zeros.
+struct LaneRot {
+    double c, s;
+};
+
+template <int WC, int LDW>
+__device__ __forceinline__ void lane_chase_qr(double* ring, int o, bool first, const LaneCarry<1>& cy,
+                                              LaneRot& rot) {
+    double* col[4];
+    chase_columns<1, WC, LDW>(ring, o, col);
+    // element (o + r, o - 2 + x) is col[x][2 + r - x]; the QR block is column
+    // o - 1 (x = 1) for j = 1, else column o - 2 (x = 0), in the carry
+    const double x0 = first ? col[1][1] : cy.b[0][0];
+    const double x1 = first ? col[1][2] : cy.b[1][0];
+    const bool none = (x1 == 0.0);
+    const double rinv = rsqrt(x0 * x0 + x1 * x1);
+    const double sg = (x0 >= 0.0) ? -1.0 : 1.0;          // sign of beta
+    rot.c = none ? 1.0 : -fabs(x0) * rinv;
+    rot.s = none ? 0.0 : sg * x1 * rinv;
+    const double r0 = none ? x0 : sg * (x0 * x0 + x1 * x1) * rinv;
+    double* qc = first ? col[1] + 1 : col[0] + 2;
+    qc[0] = r0;
+    qc[1] = 0.0;
+}
+
+template <int WC, int LDW>
+__device__ __forceinline__ void lane_chase_update(double* ring, int o, bool first, LaneCarry<1>& cy,
+                                                  const LaneRot& rot) {
+    double* col[4];
+    chase_columns<1, WC, LDW>(ring, o, col);
+    const double c = rot.c, s = rot.s;
+    if (!first) {
+        // left block: column o - 1, rows o and o + 1
+        const double l0 = cy.b[0][1], l1 = cy.b[1][1];
+        col[1][1] = c * l0 + s * l1;
+        col[1][2] = s * l0 - c * l1;
+    }
     {
-        int sl = (o + WC - H2) % WC;
-#pragma unroll
-        for (int x = 0; x < NC; ++x) {
-            col[x] = ring + sl * LDW;
-            sl = (sl + 1 == WC) ? 0 : sl + 1;
-        }
-    }
-    // element (o + r, o - 2h + x): diagonal offset 2h + r - x
-    auto at = [&](int r, int x) -> double& { return col[x][H2 + r - x]; };
-    double q[H2][H], lf[H2][H], d[H2][H2], bl[H2][H2];
-#pragma unroll
-    for (int r = 0; r < H2; ++r)
-#pragma unroll
-        for (int c = 0; c < H; ++c) {
-            double m = at(r, H + c);                       // j = 1: QR block at columns o - h ..
-            if (GUARD) m = (r < nr) ? m : 0.0;
-            q[r][c] = first ? m : cy.b[r][c];
-            lf[r][c] = first ? 0.0 : cy.b[r][H + c];
-        }
-#pragma unroll
-    for (int r = 0; r < H2; ++r)
-#pragma unroll
-        for (int k = 0; k <= r; ++k) {
-            double v = (!GUARD || r < nr) ? at(r, H2 + k) : 0.0;
-            d[r][k] = v;
-            d[k][r] = v;
-        }
-#pragma unroll
-    for (int r = 0; r < H2; ++r)
-#pragma unroll
-        for (int k = 0; k < H2; ++k)
-            bl[r][k] = (!GUARD || (r < nbr && k < nr)) ? at(H2 + r, H2 + k) : 0.0;
-
-    if constexpr (H == 1) {
-        // a 2 x 1 QR block: the reflector is the symmetric 2 x 2 matrix
-        // [[c, s], [s, -c]] with (c, s) = (x0, x1) / beta, beta = -sgn(x0) r,
-        // applied in closed form (identity when x1 = 0)
-        const double x0 = q[0][0], x1 = q[1][0];
-        const bool none = (x1 == 0.0);
-        const double rinv = rsqrt(x0 * x0 + x1 * x1);
-        const double sg = (x0 >= 0.0) ? -1.0 : 1.0;          // sign of beta
-        const double c = none ? 1.0 : -fabs(x0) * rinv;
-        const double s = none ? 0.0 : sg * x1 * rinv;
-        q[0][0] = none ? x0 : sg * (x0 * x0 + x1 * x1) * rinv;
-        q[1][0] = 0.0;
-        {
-            const double l0 = lf[0][0], l1 = lf[1][0];
-            lf[0][0] = c * l0 + s * l1;
-            lf[1][0] = s * l0 - c * l1;
-        }
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const double e0 = bl[r][0], e1 = bl[r][1];
-            bl[r][0] = c * e0 + s * e1;
-            bl[r][1] = s * e0 - c * e1;
-        }
-        {
-            const double da = d[0][0], db = d[1][0], dd = d[1][1];
-            const double cc = c * c, ss2 = s * s, cs = c * s;
-            const double t2 = 2.0 * cs * db;
-            d[0][0] = cc * da + t2 + ss2 * dd;
-            d[1][1] = ss2 * da - t2 + cc * dd;
-            const double off = cs * (da - dd) + (ss2 - cc) * db;
-            d[1][0] = off;
-            d[0][1] = off;
-        }
-    } else {
-#pragma unroll
-    for (int k = 0; k < H; ++k) {
-        const double xk = q[k][k];
-        double ss = 0.0;
-#pragma unroll
-        for (int r = k + 1; r < H2; ++r) ss += q[r][k] * q[r][k];
-        const bool none = (ss == 0.0);
-        const double nrm = sqrt(xk * xk + ss);
-        const double beta = none ? xk : ((xk >= 0.0) ? -nrm : nrm);
-        const double uk = xk - beta;
-        const double g = none ? 0.0 : 1.0 / (beta * uk);
-        double u[H2];
-#pragma unroll
-        for (int r = 0; r < H2; ++r) u[r] = (r < k) ? 0.0 : ((r == k) ? uk : q[r][k]);
-        q[k][k] = beta;
-#pragma unroll
-        for (int r = k + 1; r < H2; ++r) q[r][k] = 0.0;
-        // the rest of the QR block and the left block: X += g u (u^T X)
-#pragma unroll
-        for (int c = k + 1; c < H; ++c) {
-            double sacc = 0.0;
-#pragma unroll
-            for (int r = k; r < H2; ++r) sacc += u[r] * q[r][c];
-            const double f = g * sacc;
-#pragma unroll
-            for (int r = k; r < H2; ++r) q[r][c] += f * u[r];
-        }
-#pragma unroll
-        for (int c = 0; c < H; ++c) {
-            double sacc = 0.0;
-#pragma unroll
-            for (int r = k; r < H2; ++r) sacc += u[r] * lf[r][c];
-            const double f = g * sacc;
-#pragma unroll
-            for (int r = k; r < H2; ++r) lf[r][c] += f * u[r];
-        }
-        // below block: X_B += g (X_B u) u^T
-#pragma unroll
-        for (int r = 0; r < H2; ++r) {
-            double sacc = 0.0;
-#pragma unroll
-            for (int c = k; c < H2; ++c) sacc += bl[r][c] * u[c];
-            const double f = g * sacc;
-#pragma unroll
-            for (int c = k; c < H2; ++c) bl[r][c] += f * u[c];
-        }
-        // diagonal block: D <- H_k D H_k
-        double p[H2];
-#pragma unroll
-        for (int r = 0; r < H2; ++r) {
-            double sacc = 0.0;
-#pragma unroll
-            for (int c = k; c < H2; ++c) sacc += d[r][c] * u[c];
-            p[r] = g * sacc;
-        }
-        double up = 0.0;
-#pragma unroll
-        for (int r = k; r < H2; ++r) up += u[r] * p[r];
-        const double kk = 0.5 * g * up;
-#pragma unroll
-        for (int r = 0; r < H2; ++r) p[r] += kk * u[r];
-#pragma unroll
-        for (int r = 0; r < H2; ++r)
-#pragma unroll
-            for (int c = 0; c <= r; ++c) {
-                const double nv = d[r][c] + (u[r] * p[c] + p[r] * u[c]);
-                d[r][c] = nv;
-                d[c][r] = nv;
-            }
-    }
-    }
-
-    // ---- write back: R and the annihilated entries (QR block), the left
-    // block (for j = 1 the QR block sits there: the same values go to the
-    // same place twice), the diagonal block and the below block (the next
-    // chase's copy in registers supersedes it; the last chase's is final)
-#pragma unroll
-    for (int r = 0; r < H2; ++r) {
-        if (!GUARD || r < nr) {
-#pragma unroll
-            for (int c = 0; c < H; ++c) {
-                if (!first) at(r, c) = q[r][c];
-                at(r, H + c) = first ? q[r][c] : lf[r][c];
-            }
-#pragma unroll
-            for (int c = 0; c <= r; ++c) at(r, H2 + c) = d[r][c];
-        }
+        const double da = col[2][0], db = col[2][1], dd = col[3][0];
+        const double cc = c * c, ss2 = s * s, cs = c * s;
+        const double t2 = 2.0 * cs * db;
+        col[2][0] = cc * da + t2 + ss2 * dd;
+        col[3][0] = ss2 * da - t2 + cc * dd;
+        col[2][1] = cs * (da - dd) + (ss2 - cc) * db;
     }
 #pragma unroll
-    for (int r = 0; r < H2; ++r)
-#pragma unroll
-        for (int k = 0; k < H2; ++k)
-            if (!GUARD || (r < nbr && k < nr)) at(H2 + r, H2 + k) = bl[r][k];
-#pragma unroll
-    for (int r = 0; r < H2; ++r)
-#pragma unroll
-        for (int k = 0; k < H2; ++k) cy.b[r][k] = bl[r][k];
+    for (int r = 0; r < 2; ++r) {
+        // below block row o + 2 + r: columns o (x = 2) and o + 1 (x = 3)
+        const double e0 = col[2][2 + r], e1 = col[3][1 + r];
+        const double f0 = c * e0 + s * e1, f1 = s * e0 - c * e1;
+        col[2][2 + r] = f0;
+        col[3][1 + r] = f1;
+        cy.b[r][0] = f0;
+        cy.b[r][1] = f1;
+    }
 }
 
 // Broadcast lane SRC of each aligned group of T lanes (T in {2, 4, 16}) to
@@ -457,28 +357,35 @@ __device__ __forceinline__ void team_gather(const double (&loc)[2 * H / T], doub
     }
 }
 
-// One chase done by a team of T lanes (T in {2, 4, 16}, T <= 2h): lane s holds
-// the rows s + T i (i < 2h / T) of every 2h-row block of the chase, and,
-// like lane_chase, carries its rows of the below block into the next chase.
-// Column sums are team all-reduces; the reflector and the vector w of the
-// two-sided step are gathered into every lane by DPP broadcasts.
+// h = 2 and 4: a team of T lanes (T in {2, 4, 16}, T <= 2h) per sweep; lane s
+// holds the rows s + T i (i < 2h / T) of every 2h-row block of the chase, and
+// carries its rows of the below block into the next chase.  Reflector k is
+// kept unnormalised, u = x - beta e_k, so that H_k = I + g u u^T with
+// g = 1 / (beta u_k): one division per reflector and no scaling of the
+// vector.  Q = H_0 ... H_{h-1} is applied one reflector at a time, each
+// two-sided diagonal step being D += u w^T + w u^T with p = g D u,
+// w = p + (g/2)(u^T p) u.  Column sums are team all-reduces; the reflector
+// and w are gathered into every lane.
+//
+// GUARD: columns past the matrix end may fall inside the chase (o + 2h > n);
+// otherwise every column is inside and rows past n read (and keep) zeros.
+template <int H, int T>
+struct TeamRefl {
+    double u[H][2 * H / T];   // this lane's rows of reflector k
+    double g[H];
+};
+
 template <int H, int T, int WC, int LDW, bool GUARD>
-__device__ __forceinline__ void team_lane_chase(double* ring, int o, bool first, int nr, int nbr, int s,
-                                                LaneCarry<H>& cy, double* tbuf) {
-    constexpr int H2 = 2 * H, NC = 4 * H, RL = H2 / T;
+__device__ __forceinline__ void team_lane_chase_qr(double* ring, int o, bool first, int nr, int s,
+                                                   const LaneCarry<H>& cy, TeamRefl<H, T>& rf) {
+    constexpr int H2 = 2 * H, RL = H2 / T;
     static_assert(H2 % T == 0, "rows per lane");
-    double* col[NC];
-    {
-        int sl = (o + WC - H2) % WC;
-#pragma unroll
-        for (int x = 0; x < NC; ++x) {
-            col[x] = ring + sl * LDW;
-            sl = (sl + 1 == WC) ? 0 : sl + 1;
-        }
-    }
+    double* col[4 * H];
+    chase_columns<H, WC, LDW>(ring, o, col);
+    // element (o + r, o - 2h + x): diagonal offset 2h + r - x
     auto at = [&](int r, int x) -> double& { return col[x][H2 + r - x]; };
-    // rows of this lane: r = s + T i.  The carry holds them in cy.b[i][.].
-    double q[RL][H], lf[RL][H], d[RL][H2], bl[RL][H2];
+    // the QR block: columns o - h .. (x = h ..) for j = 1, else the carry
+    double q[RL][H];
 #pragma unroll
     for (int i = 0; i < RL; ++i) {
         const int r = s + T * i;
@@ -487,10 +394,71 @@ __device__ __forceinline__ void team_lane_chase(double* ring, int o, bool first,
             double m = at(r, H + c);
             if (GUARD) m = (r < nr) ? m : 0.0;
             q[i][c] = first ? m : cy.b[i][c];
-            lf[i][c] = first ? 0.0 : cy.b[i][H + c];
         }
-        // full row r of the diagonal block: D[r][c] = band(o + max, o + min);
-        // column o + r (a lane-dependent column) through its own pointer
+    }
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        // x_k sits in lane k % T, row slot k / T
+        double ssp = 0.0, xkp = 0.0;
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            const int r = s + T * i;
+            ssp += (r > k) ? q[i][k] * q[i][k] : 0.0;
+            xkp = (r == k) ? q[i][k] : xkp;
+        }
+        const double ss = group_sum<T>(ssp);
+        const double xk = group_sum<T>(xkp);
+        const bool none = (ss == 0.0);
+        const double nrm = sqrt(xk * xk + ss);
+        const double beta = none ? xk : ((xk >= 0.0) ? -nrm : nrm);
+        const double uk = xk - beta;
+        const double g = none ? 0.0 : 1.0 / (beta * uk);
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            const int r = s + T * i;
+            rf.u[k][i] = (r < k) ? 0.0 : ((r == k) ? uk : q[i][k]);
+            q[i][k] = (r == k) ? beta : ((r > k) ? 0.0 : q[i][k]);
+        }
+        rf.g[k] = g;
+        // the QR block's columns c > k: X += g u (u^T X)
+#pragma unroll
+        for (int c = k + 1; c < H; ++c) {
+            double p = 0.0;
+#pragma unroll
+            for (int i = 0; i < RL; ++i) p += rf.u[k][i] * q[i][c];
+            const double f = g * group_sum<T>(p);
+#pragma unroll
+            for (int i = 0; i < RL; ++i) q[i][c] += f * rf.u[k][i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+        const int r = s + T * i;
+        if (!GUARD || r < nr) {
+#pragma unroll
+            for (int c = 0; c < H; ++c) at(r, first ? H + c : c) = q[i][c];
+        }
+    }
+}
+
+template <int H, int T, int WC, int LDW, bool GUARD>
+__device__ __forceinline__ void team_lane_chase_update(double* ring, int o, bool first, int nr, int nbr, int s,
+                                                       LaneCarry<H>& cy, const TeamRefl<H, T>& rf,
+                                                       double* tbuf) {
+    constexpr int H2 = 2 * H, RL = H2 / T;
+    double* col[4 * H];
+    chase_columns<H, WC, LDW>(ring, o, col);
+    auto at = [&](int r, int x) -> double& { return col[x][H2 + r - x]; };
+    // the left block (columns o - h .., j > 1) from the carry, this lane's
+    // full rows of the diagonal block and its rows of the below block
+    double lf[RL][H], d[RL][H2], bl[RL][H2];
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+        const int r = s + T * i;
+#pragma unroll
+        for (int c = 0; c < H; ++c) lf[i][c] = cy.b[i][H + c];
+        // D[r][c] = band(o + max, o + min); column o + r (a lane-dependent
+        // column) through its own pointer
         const double* colr = ring + ((o + r) % WC) * LDW;
 #pragma unroll
         for (int c = 0; c < H2; ++c) {
@@ -506,52 +474,22 @@ __device__ __forceinline__ void team_lane_chase(double* ring, int o, bool first,
             bl[i][c] = v;
         }
     }
-
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-        // ---- reflector k (x_k sits in lane k % T, row slot k / T)
-        double ssp = 0.0, xkp = 0.0;
-#pragma unroll
-        for (int i = 0; i < RL; ++i) {
-            const int r = s + T * i;
-            ssp += (r > k) ? q[i][k] * q[i][k] : 0.0;
-            xkp = (r == k) ? q[i][k] : xkp;
-        }
-        const double ss = group_sum<T>(ssp);
-        const double xk = group_sum<T>(xkp);
-        const bool none = (ss == 0.0);
-        const double nrm = sqrt(xk * xk + ss);
-        const double beta = none ? xk : ((xk >= 0.0) ? -nrm : nrm);
-        const double uk = xk - beta;
-        const double g = none ? 0.0 : 1.0 / (beta * uk);
-        double ul[RL];
-#pragma unroll
-        for (int i = 0; i < RL; ++i) {
-            const int r = s + T * i;
-            ul[i] = (r < k) ? 0.0 : ((r == k) ? uk : q[i][k]);
-            q[i][k] = (r == k) ? beta : ((r > k) ? 0.0 : q[i][k]);
-        }
-        // the reflector in every lane: uf[s' + T i] from lane s'
+        const double g = rf.g[k];
         double uf[H2];
-        team_gather<H, T>(ul, uf, tbuf, s);
-        // QR block columns c > k and the left block: X += g u (u^T X)
+        team_gather<H, T>(rf.u[k], uf, tbuf, s);
+        if (!first) {
+            // left block: X += g u (u^T X)
 #pragma unroll
-        for (int c = k + 1; c < H; ++c) {
-            double p = 0.0;
+            for (int c = 0; c < H; ++c) {
+                double p = 0.0;
 #pragma unroll
-            for (int i = 0; i < RL; ++i) p += ul[i] * q[i][c];
-            const double f = g * group_sum<T>(p);
+                for (int i = 0; i < RL; ++i) p += rf.u[k][i] * lf[i][c];
+                const double f = g * group_sum<T>(p);
 #pragma unroll
-            for (int i = 0; i < RL; ++i) q[i][c] += f * ul[i];
-        }
-#pragma unroll
-        for (int c = 0; c < H; ++c) {
-            double p = 0.0;
-#pragma unroll
-            for (int i = 0; i < RL; ++i) p += ul[i] * lf[i][c];
-            const double f = g * group_sum<T>(p);
-#pragma unroll
-            for (int i = 0; i < RL; ++i) lf[i][c] += f * ul[i];
+                for (int i = 0; i < RL; ++i) lf[i][c] += f * rf.u[k][i];
+            }
         }
         // below block rows: X_B += g (X_B u) u^T
 #pragma unroll
@@ -572,29 +510,29 @@ __device__ __forceinline__ void team_lane_chase(double* ring, int o, bool first,
 #pragma unroll
             for (int c = k; c < H2; ++c) acc += d[i][c] * uf[c];
             pl[i] = g * acc;
-            upp += ul[i] * pl[i];
+            upp += rf.u[k][i] * pl[i];
         }
         const double kk = 0.5 * g * group_sum<T>(upp);
         double wl[RL];
 #pragma unroll
-        for (int i = 0; i < RL; ++i) wl[i] = pl[i] + kk * ul[i];
+        for (int i = 0; i < RL; ++i) wl[i] = pl[i] + kk * rf.u[k][i];
         double wf[H2];
         team_gather<H, T>(wl, wf, tbuf + H2, s);
 #pragma unroll
         for (int i = 0; i < RL; ++i)
 #pragma unroll
-            for (int c = 0; c < H2; ++c) d[i][c] += ul[i] * wf[c] + wl[i] * uf[c];
+            for (int c = 0; c < H2; ++c) d[i][c] += rf.u[k][i] * wf[c] + wl[i] * uf[c];
     }
-
-    // ---- write back (see lane_chase)
+    // write back the left block (j > 1), the lower part of the diagonal block
+    // and the below block (the next chase's copy in registers supersedes it;
+    // the last chase's is final)
 #pragma unroll
     for (int i = 0; i < RL; ++i) {
         const int r = s + T * i;
         if (!GUARD || r < nr) {
+            if (!first) {
 #pragma unroll
-            for (int c = 0; c < H; ++c) {
-                if (!first) at(r, c) = q[i][c];
-                at(r, H + c) = first ? q[i][c] : lf[i][c];
+                for (int c = 0; c < H; ++c) at(r, H + c) = lf[i][c];
             }
 #pragma unroll
             for (int c = 0; c < H2; ++c)

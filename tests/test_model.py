@@ -217,3 +217,36 @@ def test_chase_schedule_after_previous_qr_orders_every_conflict(n, b):
     # chase (i-1, j+2) has finished its QR block (the only entries the two
     # share); every pair of phases that touch a common entry stays ordered
     assert _phase_conflicts_not_ordered(n, b) == 0
+
+
+def _lockstep_phase_conflicts(n, b, lag):
+    # the small-band pipeline: at step tau every sweep s of a group does chase
+    # j = tau - lag*s, first all the QR blocks (phase 0), then the rest (phase 1);
+    # a conflicting pair of phases must run at different times, in the order of
+    # the sequential loop nest (sweep-major, QR phase first)
+    chases = M.chase_list(n, b)
+    first_i = min(c["i"] for c in chases)
+    nodes = []
+    for c in chases:
+        q, r = _phase_touched(c)
+        tau = c["j"] + lag * (c["i"] - first_i)
+        nodes.append(((tau, 0), (c["i"], c["j"], 0), q))
+        nodes.append(((tau, 1), (c["i"], c["j"], 1), r))
+    bad = 0
+    for a, c in itertools.combinations(nodes, 2):
+        if a[1][:2] == c[1][:2] or not (a[2] & c[2]):
+            continue
+        if a[0] == c[0] or (a[0] < c[0]) != (a[1] < c[1]):
+            bad += 1
+    return bad
+
+
+@pytest.mark.parametrize("n,b", [(64, 8), (67, 4), (60, 2), (45, 8), (100, 16)])
+def test_lockstep_two_phase_lag2_orders_every_conflict(n, b):
+    # two phases per step (QR blocks, then the rest) let consecutive sweeps run
+    # two chases apart instead of three
+    assert _lockstep_phase_conflicts(n, b, 2) == 0
+
+
+def test_lockstep_two_phase_lag1_is_not_enough():
+    assert _lockstep_phase_conflicts(64, 8, 1) > 0
