@@ -20,7 +20,8 @@ extern "C" {
  * A (n x n, lower triangle) is overwritten: on return A[i + j*lda] for
  * 0 <= i - j <= b holds the band matrix with the eigenvalues of the input,
  * and A[i + j*lda] = 0 for i - j > b.  The strict upper triangle is scratch.
- * b: power of two, 2 <= b <= 128.
+ * b: power of two, 2 <= b <= 128.  SBR_ENOTSUP when (n + 128 lda) * 8
+ * reaches 2^31 (the symmetric products' 32-bit offsets; lda beyond ~2^20).
  */
 int sbr_full_to_band(sbr_plan_t plan, int64_t n, double* A, int64_t lda,
                      int32_t b, sbr_precision prec, sbr_stream_t stream);
@@ -69,7 +70,10 @@ int sbr_syr2k_lower(int64_t m, int64_t k, const double* U, int64_t ldu,
                     const double* V, int64_t ldv, double* C, int64_t ldc,
                     sbr_precision prec, sbr_stream_t stream);
 
-/* W = A Y with A symmetric (m x m, lower triangle read), Y m x k. */
+/* W = A Y with A symmetric (m x m, lower triangle read), Y m x k.
+ * The kernel addresses A and Y with 32-bit byte offsets: returns
+ * SBR_ENOTSUP when (m + 128 lda) * 8 or (16 + 127 ldy) * 8 reaches 2^31
+ * (leading dimensions beyond about 2^20). */
 int sbr_symm_lower(int64_t m, int64_t k, const double* A, int64_t lda,
                    const double* Y, int64_t ldy, double* W, int64_t ldw,
                    sbr_precision prec, sbr_stream_t stream);

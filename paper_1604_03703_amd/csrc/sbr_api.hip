@@ -352,6 +352,7 @@ bool ensure_f32_storage(sbr_plan_t p, int64_t n) {
 // so the panel QR, reconstruction and band stay FP64.
 int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, bool f32, hipStream_t s) {
     const int64_t ldq = p->n_cap;
+    if (!symm_offsets_fit(n, lda, ldq, sizeof(double))) return SBR_ENOTSUP;
     int64_t k = 0;
     int cur = 0;
     const bool f32s = f32 && n - b >= b && ensure_f32_storage(p, n);
@@ -994,6 +995,7 @@ int sbr_symm_lower(int64_t m, int64_t k, const double* A, int64_t lda, const dou
     if (m > 0 && k > 0 && !W) return -7;
     if (ldw < std::max<int64_t>(1, m)) return -8;
     if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -9;
+    if (!symm_offsets_fit(m, lda, ldy, sizeof(double))) return SBR_ENOTSUP;
     launch_symm_lower(prec == SBR_FP32_MFMA, m, k, A, lda, Y, ldy, W, ldw, nullptr, 1, (hipStream_t)stream);
     SBR_CHECK_LAUNCH();
     return 0;

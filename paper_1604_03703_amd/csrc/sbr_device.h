@@ -59,7 +59,7 @@ struct TileMap {
 // Waves are arranged WM x WN; wave (wm, wn) owns C rows [wm*WTM, +WTM) and
 // columns [wn*WTN, +WTN).  Accumulator acc[tn][tm][r] holds
 //   C(wm*WTM + tm*16 + (lane & 15), wn*WTN + tn*16 + Mfma<CT>::out_row(lane, r)).
-template <typename CT, int BM, int BN, int WM, int WN, int PAD = 2>
+template <typename CT, int BM, int BN, int WM, int WN, int PAD = 2, bool PF = true>
 struct TileEngine {
     static constexpr int NT = 64 * WM * WN;
     static constexpr int WTM = BM / WM, WTN = BN / WN;
@@ -76,20 +76,43 @@ struct TileEngine {
             for (int b = 0; b < TM; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
     }
 
+    // One LDS chunk (SBR_BK deep, four k-steps).  PF: the operands of step
+    // s + 1 are read before the products of step s are issued (a scheduling
+    // barrier keeps the compiler from sinking the reads back below them), so
+    // the LDS latency of a step hides behind the matrix instructions of the
+    // previous one, for 2 (TM + TN) more registers.
     __device__ __forceinline__ void chunk(const CT* As, const CT* Bs, int wm, int wn, int lane) {
         const int kr = lane >> 4, c = lane & 15;
+        constexpr int KS = SBR_BK / 4;
+        CT p[2][TN], q[2][TM];
+        auto read = [&](int s, int slot) {
 #pragma unroll
-        for (int kk = 0; kk < SBR_BK; kk += 4) {
-            CT p[TN], q[TM];
+            for (int tn = 0; tn < TN; ++tn) p[slot][tn] = Bs[(4 * s + kr) * LDB + wn * WTN + tn * 16 + c];
 #pragma unroll
-            for (int tn = 0; tn < TN; ++tn) p[tn] = Bs[(kk + kr) * LDB + wn * WTN + tn * 16 + c];
+            for (int tm = 0; tm < TM; ++tm) q[slot][tm] = As[(4 * s + kr) * LDA + wm * WTM + tm * 16 + c];
+        };
+        if constexpr (PF) {
+            read(0, 0);
 #pragma unroll
-            for (int tm = 0; tm < TM; ++tm) q[tm] = As[(kk + kr) * LDA + wm * WTM + tm * 16 + c];
+            for (int s = 0; s < KS; ++s) {
+                if (s + 1 < KS) read(s + 1, (s + 1) & 1);
+                __builtin_amdgcn_sched_barrier(0);
+                products(p[s & 1], q[s & 1]);
+            }
+        } else {
 #pragma unroll
-            for (int tn = 0; tn < TN; ++tn)
-#pragma unroll
-                for (int tm = 0; tm < TM; ++tm) acc[tn][tm] = Mfma<CT>::mma(p[tn], q[tm], acc[tn][tm]);
+            for (int s = 0; s < KS; ++s) {
+                read(s, 0);
+                products(p[0], q[0]);
+            }
         }
+    }
+
+    __device__ __forceinline__ void products(const CT (&p)[TN], const CT (&q)[TM]) {
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn)
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) acc[tn][tm] = Mfma<CT>::mma(p[tn], q[tm], acc[tn][tm]);
     }
 
     static __device__ __forceinline__ int row_of(int wm, int tm, int lane) { return wm * WTM + tm * 16 + (lane & 15); }
@@ -97,6 +120,24 @@ struct TileEngine {
         return wn * WTN + tn * 16 + Mfma<CT>::out_row(lane, r);
     }
 };
+
+// Raw buffer loads for operand staging.  A buffer resource covers
+// num_records bytes from its base; a load whose (per-lane) offset is at or
+// beyond that range returns zero instead of touching memory, so a lane whose
+// element lies outside the matrix gets the offset SBR_BUF_OOB and needs no
+// branch.  Offsets are 32-bit byte offsets from a base that the caller moves
+// per chunk (uniform across the block).
+constexpr uint32_t SBR_BUF_OOB = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t sbr_buffer(const void* base, uint32_t bytes) {
+    // dword 3 of the descriptor: 32-bit data format, no swizzle (gfx9 family)
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double sbr_buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float sbr_buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
 
 // Agent-scope flag helpers for the pipelined chase schedule.
 __device__ __forceinline__ int sbr_load_acquire(const int* p) {

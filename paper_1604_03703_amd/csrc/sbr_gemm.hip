@@ -153,7 +153,7 @@ __device__ __forceinline__ void lower_tile_banded(int64_t x, int64_t T, int64_t&
 // in the banded order above (nc = m); jt > 0: the first jt tile columns,
 // enumerated row by row.  Double-buffered LDS, one barrier per K chunk.
 // ST: storage type of C (double, or float for the FP32-storage form).
-template <typename CT, int BM, int WM, int WN, int PAD = 2, typename ST = double>
+template <typename CT, int BM, int WM, int WN, int PAD = 2, typename ST = double, bool FAST = true>
 __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     int64_t m, int64_t nc, int64_t jt, int64_t K, const double* __restrict__ U, int64_t ldu,
     const double* __restrict__ V, int64_t ldv, ST* C, int64_t ldc, int64_t ntiles) {
@@ -178,39 +178,39 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     E eng;
     eng.zero();
     CT ra[MA::E], rb[MB::E];
-    // Fast path (U and V share the leading dimension and K is a multiple of
-    // the chunk depth, so a chunk lies wholly in the U or the V half of K'):
-    // per-thread element offsets are fixed, a chunk only moves the base.
-    // (FP32 compute only: in FP64 the offsets cost the registers of a second
-    // resident block, which hides more latency than they save)
-    constexpr bool kOffsets = sizeof(CT) == 4;
-    const bool fast = kOffsets && (ldu == ldv) && (K % SBR_BK == 0) && (m + BM) + (int64_t)SBR_BK * ldu < INT32_MAX;
-    int32_t offa[MA::E], offb[MB::E];
-    bool oka[MA::E], okb[MB::E];
-    if constexpr (kOffsets) {
+    // FAST (U and V share the leading dimension, K is a multiple of the chunk
+    // depth, so a chunk lies wholly in the U or the V half of K', and
+    // (m + (SBR_BK - 1) ldu) * 8 < 2^31; the launcher checks): raw buffer
+    // loads with fixed per-thread byte offsets; a chunk only moves the
+    // (block-uniform) buffer base, and rows past m read zero through an
+    // out-of-range offset.  No branches and no 64-bit address arithmetic per
+    // element.  Otherwise element-wise loads with bounds checks.
+    const uint32_t span = (uint32_t)((m + (int64_t)(SBR_BK - 1) * ldu) * (int64_t)sizeof(double));
+    uint32_t offa[MA::E], offb[MB::E];
+    if constexpr (FAST) {
 #pragma unroll
         for (int e = 0; e < MA::E; ++e) {
             int i, k;
             MA::coords(t, e, i, k);
-            offa[e] = (int32_t)((i0 + i) + (int64_t)k * ldu);
-            oka[e] = i0 + i < m;
+            offa[e] = (i0 + i < m) ? (uint32_t)(((i0 + i) + (int64_t)k * ldu) * 8) : SBR_BUF_OOB;
         }
 #pragma unroll
         for (int e = 0; e < MB::E; ++e) {
             int j, k;
             MB::coords(t, e, j, k);
-            offb[e] = (int32_t)((j0 + j) + (int64_t)k * ldu);
-            okb[e] = j0 + j < m;
+            offb[e] = (j0 + j < m) ? (uint32_t)(((j0 + j) + (int64_t)k * ldu) * 8) : SBR_BUF_OOB;
         }
     }
     auto load = [&](int64_t k0) {
-        if (kOffsets && fast) {
+        if constexpr (FAST) {
             const double* pa = (k0 < K) ? U + k0 * ldu : V + (k0 - K) * ldu;
             const double* pb = (k0 < K) ? V + k0 * ldu : U + (k0 - K) * ldu;
+            const __amdgpu_buffer_rsrc_t rsa = sbr_buffer(pa, span);
+            const __amdgpu_buffer_rsrc_t rsb = sbr_buffer(pb, span);
 #pragma unroll
-            for (int e = 0; e < MA::E; ++e) ra[e] = oka[e] ? (CT)pa[offa[e]] : (CT)0;
+            for (int e = 0; e < MA::E; ++e) ra[e] = (CT)sbr_buffer_load(rsa, offa[e], 0.0);
 #pragma unroll
-            for (int e = 0; e < MB::E; ++e) rb[e] = okb[e] ? (CT)pb[offb[e]] : (CT)0;
+            for (int e = 0; e < MB::E; ++e) rb[e] = (CT)sbr_buffer_load(rsb, offb[e], 0.0);
             return;
         }
 #pragma unroll
@@ -270,15 +270,23 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
             }
 }
 
-// W (m x nb) = A Y with A symmetric, lower triangle stored.  A K-chunk of
-// the A tile lies entirely below the diagonal (read A[i + k lda], rows
-// contiguous), entirely above it (read the mirror A[k + i lda], k
-// contiguous) or straddles it (element-wise choice).  Double-buffered LDS.
+// W (m x nb) = A Y with A symmetric, lower triangle stored.  The K range of
+// a tile row splits into chunks below the diagonal block (A read directly
+// from A[i0 + k0 lda], rows contiguous), the diagonal block itself
+// (element-wise choice between the lower part and its mirror) and chunks
+// above it (the mirror, read from A[k0 + i0 lda], k contiguous).  Each
+// segment runs its own double-buffered LDS pipeline, so the per-thread
+// offsets of one load form are live only during its segment.
+//
+// Operands come through raw buffer loads: 32-bit byte offsets from a
+// block-uniform base that a chunk moves, rows past m, columns past nb and k
+// past kend read zero through an out-of-range offset.  Every offset is below
+// 2^31 (the launcher checks (m + BM lda) sizeof(ST) and BN ldy 8 against it).
 template <typename CT, int BM, int BN, int WM, int WN, int PAD = 2, typename ST = double>
-__global__ __launch_bounds__(64 * WM * WN) void symm_lower_kernel(
+__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(BM == 128 ? 4 : 1))) void symm_lower_kernel(
     int64_t m, int64_t nb, int64_t kchunk, const ST* __restrict__ A, int64_t lda,
     const double* __restrict__ Y, int64_t ldy, double* W, int64_t ldw, int64_t slice_stride) {
-    typedef TileEngine<CT, BM, BN, WM, WN, PAD> E;
+    typedef TileEngine<CT, BM, BN, WM, WN, PAD, false> E;   // long K: no operand prefetch (registers)
     typedef TileMap<BM, E::NT, false> MAi;   // row fastest
     typedef TileMap<BM, E::NT, true> MAk;    // k fastest
     typedef TileMap<BN, E::NT, true> MB;     // Y[k + j ldy]: k contiguous
@@ -288,78 +296,74 @@ __global__ __launch_bounds__(64 * WM * WN) void symm_lower_kernel(
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave % WM, wn = wave / WM;
     const int64_t i0 = (int64_t)blockIdx.x * BM, j0 = (int64_t)blockIdx.y * BN;
-    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;   // kchunk is a multiple of SBR_BK
     const int64_t kend = (kbeg + kchunk < m) ? kbeg + kchunk : m;
     E eng;
     eng.zero();
     CT ra[MAi::E], rb[MB::E];
-    bool kfast = false;
-    // per-thread element offsets of the three chunk kinds: below the diagonal
-    // (A read directly, rows contiguous), above it (the mirror, k contiguous),
-    // and Y; a chunk only moves the base pointer
-    // (32-bit offsets: the fast path is taken only when they fit; FP32
-    // compute only, as in syr2k_lower_kernel)
-    constexpr bool kOffsets = sizeof(CT) == 4;
-    const bool fit = kOffsets && (m + BM) * (lda > ldy ? lda : ldy) + SBR_BK * (lda > ldy ? lda : ldy) < INT32_MAX;
-    int32_t offd[MAi::E], offm[MAi::E], offy[MB::E];
-    bool okd[MAi::E], okm[MAi::E], oky[MB::E];
-    if constexpr (kOffsets) {
+    constexpr uint32_t SA = sizeof(ST);
+    const uint32_t lda32 = (uint32_t)lda, ldy32 = (uint32_t)ldy;
+    const uint32_t spanD = (uint32_t)((BM + (int64_t)(SBR_BK - 1) * lda) * SA);
+    const uint32_t spanM = (uint32_t)((SBR_BK + (int64_t)(BM - 1) * lda) * SA);
+    const uint32_t spanS = (uint32_t)((m + (int64_t)BM * lda) * SA);
+    const uint32_t spanY = (uint32_t)((SBR_BK + (int64_t)(BN - 1) * ldy) * 8);
+    const uint32_t mrows = (uint32_t)(m - i0 < BM ? m - i0 : BM);      // valid rows of the tile
+    const uint32_t ncols = (uint32_t)(nb - j0 < BN ? nb - j0 : BN);    // valid columns of Y
+
+    auto load_y = [&](int64_t k0) {
+        const __amdgpu_buffer_rsrc_t ry = sbr_buffer(Y + k0 + j0 * ldy, spanY);
+        const int64_t kv = kend - k0;     // valid k of the chunk
+#pragma unroll
+        for (int e = 0; e < MB::E; ++e) {
+            int j, k;
+            MB::coords(t, e, j, k);
+            const bool ok = (uint32_t)j < ncols && k < kv;
+            rb[e] = (CT)sbr_buffer_load(ry, ok ? ((uint32_t)k + (uint32_t)j * ldy32) * 8u : SBR_BUF_OOB, 0.0);
+        }
+    };
+    // below the diagonal block: A[i0 + i + (k0 + k) lda]
+    auto load_below = [&](int64_t k0) {
+        const __amdgpu_buffer_rsrc_t rs = sbr_buffer(A + i0 + k0 * lda, spanD);
 #pragma unroll
         for (int e = 0; e < MAi::E; ++e) {
             int i, k;
             MAi::coords(t, e, i, k);
-            offd[e] = (int32_t)((i0 + i) + (int64_t)k * lda);
-            okd[e] = i0 + i < m;
+            ra[e] = (CT)sbr_buffer_load(rs, (uint32_t)i < mrows ? ((uint32_t)i + (uint32_t)k * lda32) * SA : SBR_BUF_OOB,
+                                        ST());
+        }
+        load_y(k0);
+    };
+    // above it: the mirror A[k0 + k + (i0 + i) lda]
+    auto load_above = [&](int64_t k0) {
+        const __amdgpu_buffer_rsrc_t rs = sbr_buffer(A + k0 + i0 * lda, spanM);
+#pragma unroll
+        for (int e = 0; e < MAk::E; ++e) {
+            int i, k;
             MAk::coords(t, e, i, k);
-            offm[e] = (int32_t)(k + (i0 + i) * lda);
-            okm[e] = i0 + i < m;
+            ra[e] = (CT)sbr_buffer_load(rs, (uint32_t)i < mrows ? ((uint32_t)k + (uint32_t)i * lda32) * SA : SBR_BUF_OOB,
+                                        ST());
         }
-#pragma unroll
-        for (int e = 0; e < MB::E; ++e) {
-            int j, k;
-            MB::coords(t, e, j, k);
-            offy[e] = (int32_t)(k + (j0 + j) * ldy);
-            oky[e] = j0 + j < nb;
-        }
-    }
-    auto load = [&](int64_t k0) {
-        kfast = (k0 >= i0 + BM - 1);           // whole chunk at or above the diagonal
-        const bool below = (k0 + SBR_BK - 1 <= i0);
-        if (kOffsets && fit && k0 + SBR_BK <= kend && (kfast || below)) {
-            if (kfast) {
-                const ST* pa = A + k0;
-#pragma unroll
-                for (int e = 0; e < MAi::E; ++e) ra[e] = okm[e] ? (CT)pa[offm[e]] : (CT)0;
-            } else {
-                const ST* pa = A + k0 * lda;
-#pragma unroll
-                for (int e = 0; e < MAi::E; ++e) ra[e] = okd[e] ? (CT)pa[offd[e]] : (CT)0;
-            }
-            const double* py = Y + k0;
-#pragma unroll
-            for (int e = 0; e < MB::E; ++e) rb[e] = oky[e] ? (CT)py[offy[e]] : (CT)0;
-            return;
-        }
+        load_y(k0);
+    };
+    // the diagonal block, or a chunk ending past kend: element-wise choice
+    // between the lower part and its mirror, offsets from the corner (d0, d0),
+    // d0 = min(i0, k0), where both choices are non-negative and the smaller
+    // index is below BM
+    auto load_mixed = [&](int64_t k0) {
+        const int64_t d0 = i0 < k0 ? i0 : k0;
+        const __amdgpu_buffer_rsrc_t rs = sbr_buffer(A + d0 + d0 * lda, spanS);
+        const int64_t kv = kend - k0;
 #pragma unroll
         for (int e = 0; e < MAi::E; ++e) {
             int i, k;
-            if (kfast) MAk::coords(t, e, i, k); else MAi::coords(t, e, i, k);
-            const int64_t gi = i0 + i, gk = k0 + k;
-            double v = 0.0;
-            if (gi < m && gk < kend) v = (gi >= gk) ? (double)A[gi + gk * lda] : (double)A[gk + gi * lda];
-            ra[e] = (CT)v;
+            MAi::coords(t, e, i, k);
+            const uint32_t r = (uint32_t)(i0 + i - d0), c = (uint32_t)(k0 + k - d0);
+            const uint32_t off = (r >= c) ? r + c * lda32 : c + r * lda32;
+            ra[e] = (CT)sbr_buffer_load(rs, ((uint32_t)i < mrows && k < kv) ? off * SA : SBR_BUF_OOB, ST());
         }
-#pragma unroll
-        for (int e = 0; e < MB::E; ++e) {
-            int j, k;
-            MB::coords(t, e, j, k);
-            const int64_t gj = j0 + j, gk = k0 + k;
-            double v = 0.0;
-            if (gj < nb && gk < kend) v = Y[gk + gj * ldy];
-            rb[e] = (CT)v;
-        }
+        load_y(k0);
     };
-    auto store = [&](int buf) {
+    auto store = [&](int buf, bool kfast) {
 #pragma unroll
         for (int e = 0; e < MAi::E; ++e) {
             int i, k;
@@ -373,19 +377,31 @@ __global__ __launch_bounds__(64 * WM * WN) void symm_lower_kernel(
             Bs[buf][k * E::LDB + j] = rb[e];
         }
     };
-    if (kbeg < kend) {
-        const int64_t nch = (kend - kbeg + SBR_BK - 1) / SBR_BK;
-        load(kbeg);
-        store(0);
+    // chunks [ka, kb) with one load form (kfast: the k-fastest map)
+    auto segment = [&](int64_t ka, int64_t kb, bool kfast, auto&& load) {
+        if (ka >= kb) return;
+        const int64_t nch = (kb - ka + SBR_BK - 1) / SBR_BK;
+        load(ka);
+        store(0, kfast);
         __syncthreads();
         for (int64_t c = 0; c < nch; ++c) {
             const int cur = (int)(c & 1);
             const bool more = c + 1 < nch;
-            if (more) load(kbeg + (c + 1) * SBR_BK);   // sets the map the registers are stored with
+            if (more) load(ka + (c + 1) * SBR_BK);
             eng.chunk(As[cur], Bs[cur], wm, wn, lane);
-            if (more) store(cur ^ 1);
+            if (more) store(cur ^ 1, kfast);     // that buffer was last read before the previous barrier
             __syncthreads();
         }
+    };
+    if (kbeg < kend) {
+        // whole chunks end at kfull; a last partial chunk takes the mixed form
+        const int64_t kfull = kbeg + (kend - kbeg) / SBR_BK * SBR_BK;
+        const int64_t dlo = i0, dhi = i0 + BM;             // the diagonal block's columns
+        segment(kbeg, kfull < dlo ? kfull : dlo, false, load_below);
+        segment(kbeg > dlo ? kbeg : dlo, kend < dhi ? kend : dhi, false, load_mixed);
+        segment(kbeg > dhi ? kbeg : dhi, kfull, true, load_above);
+        // the partial chunk, unless it lies in the diagonal block's segment
+        if (kfull < kend && (kfull < dlo || kfull >= dhi)) segment(kfull, kend, false, load_mixed);
     }
     double* Wo = W + (int64_t)blockIdx.z * slice_stride;
 #pragma unroll
@@ -519,20 +535,35 @@ bool syr2k_big_tiles(int64_t m) {
     return T128 * (T128 + 1) / 2 >= 512;
 }
 
+// One launch of syr2k_lower_kernel over nt tiles: the buffer-load form when
+// its conditions hold, the element-wise form otherwise.
+template <typename CT, int BM, int WM, int WN, typename ST>
+void syr2k_go(int64_t nt, int64_t m, int64_t nc, int64_t jt, int64_t K, const double* U, int64_t ldu,
+              const double* V, int64_t ldv, ST* C, int64_t ldc, hipStream_t s) {
+    const bool fast = (ldu == ldv) && (K % SBR_BK == 0) &&
+                      (m + (int64_t)(SBR_BK - 1) * ldu) * (int64_t)sizeof(double) < (int64_t)SBR_BUF_OOB;
+    if (fast)
+        syr2k_lower_kernel<CT, BM, WM, WN, 2, ST, true><<<(unsigned)nt, 64 * WM * WN, 0, s>>>(m, nc, jt, K, U, ldu, V,
+                                                                                          ldv, C, ldc, nt);
+    else
+        syr2k_lower_kernel<CT, BM, WM, WN, 2, ST, false><<<(unsigned)nt, 64 * WM * WN, 0, s>>>(m, nc, jt, K, U, ldu, V,
+                                                                                           ldv, C, ldc, nt);
+}
+
 void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t ldu, const double* V,
                         int64_t ldv, double* C, int64_t ldc, hipStream_t s) {
     if (m <= 0 || K <= 0) return;
     const int64_t T128 = (m + 127) / 128;
     if (syr2k_big_tiles(m)) {
         const int64_t nt = T128 * (T128 + 1) / 2;
-        if (f32) syr2k_lower_kernel<float, 128, 2, 4><<<(unsigned)nt, 512, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
-        else syr2k_lower_kernel<double, 128, 2, 4><<<(unsigned)nt, 512, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
+        if (f32) syr2k_go<float, 128, 2, 4, double>(nt, m, m, 0, K, U, ldu, V, ldv, C, ldc, s);
+        else syr2k_go<double, 128, 2, 4, double>(nt, m, m, 0, K, U, ldu, V, ldv, C, ldc, s);
         return;
     }
     const int64_t T = (m + 63) / 64;
     const int64_t nt = T * (T + 1) / 2;
-    if (f32) syr2k_lower_kernel<float, 64, 2, 2><<<(unsigned)nt, 256, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
-    else syr2k_lower_kernel<double, 64, 2, 2><<<(unsigned)nt, 256, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
+    if (f32) syr2k_go<float, 64, 2, 2, double>(nt, m, m, 0, K, U, ldu, V, ldv, C, ldc, s);
+    else syr2k_go<double, 64, 2, 2, double>(nt, m, m, 0, K, U, ldu, V, ldv, C, ldc, s);
 }
 
 void launch_syr2k_lower_cols(bool f32, int64_t m, int64_t nc, int64_t K, const double* U, int64_t ldu,
@@ -542,8 +573,13 @@ void launch_syr2k_lower_cols(bool f32, int64_t m, int64_t nc, int64_t K, const d
     // a tall column block: 64 x 64 tiles for more blocks in flight
     const int64_t T = (m + 63) / 64, jt = (nc + 63) / 64;
     const int64_t nt = T * jt;
-    if (f32) syr2k_lower_kernel<float, 64, 2, 2><<<(unsigned)nt, 256, 0, s>>>(m, nc, jt, K, U, ldu, V, ldv, C, ldc, nt);
-    else syr2k_lower_kernel<double, 64, 2, 2><<<(unsigned)nt, 256, 0, s>>>(m, nc, jt, K, U, ldu, V, ldv, C, ldc, nt);
+    if (f32) syr2k_go<float, 64, 2, 2, double>(nt, m, nc, jt, K, U, ldu, V, ldv, C, ldc, s);
+    else syr2k_go<double, 64, 2, 2, double>(nt, m, nc, jt, K, U, ldu, V, ldv, C, ldc, s);
+}
+
+bool symm_offsets_fit(int64_t m, int64_t lda, int64_t ldy, int64_t elem) {
+    // the largest tile (BM = BN = 128) bounds every buffer offset of the kernel
+    return (m + 128 * lda) * elem < (int64_t)SBR_BUF_OOB && (SBR_BK + 127 * ldy) * 8 < (int64_t)SBR_BUF_OOB;
 }
 
 int symm_splits(int64_t m, int64_t nb) {
@@ -578,12 +614,12 @@ void launch_syr2k_lower_f32s(int64_t m, int64_t K, const double* U, int64_t ldu,
     const int64_t T128 = (m + 127) / 128;
     if (syr2k_big_tiles(m)) {
         const int64_t nt = T128 * (T128 + 1) / 2;
-        syr2k_lower_kernel<float, 128, 2, 4, 2, float><<<(unsigned)nt, 512, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
+        syr2k_go<float, 128, 2, 4, float>(nt, m, m, 0, K, U, ldu, V, ldv, C, ldc, s);
         return;
     }
     const int64_t T = (m + 63) / 64;
     const int64_t nt = T * (T + 1) / 2;
-    syr2k_lower_kernel<float, 64, 2, 2, 2, float><<<(unsigned)nt, 256, 0, s>>>(m, m, 0, K, U, ldu, V, ldv, C, ldc, nt);
+    syr2k_go<float, 64, 2, 2, float>(nt, m, m, 0, K, U, ldu, V, ldv, C, ldc, s);
 }
 
 void launch_syr2k_lower_cols_f32s(int64_t m, int64_t nc, int64_t K, const double* U, int64_t ldu, const double* V,
@@ -592,7 +628,7 @@ void launch_syr2k_lower_cols_f32s(int64_t m, int64_t nc, int64_t K, const double
     if (nc > m) nc = m;
     const int64_t T = (m + 63) / 64, jt = (nc + 63) / 64;
     const int64_t nt = T * jt;
-    syr2k_lower_kernel<float, 64, 2, 2, 2, float><<<(unsigned)nt, 256, 0, s>>>(m, nc, jt, K, U, ldu, V, ldv, C, ldc, nt);
+    syr2k_go<float, 64, 2, 2, float>(nt, m, nc, jt, K, U, ldu, V, ldv, C, ldc, s);
 }
 
 void launch_symm_lower_f32s(int64_t m, int64_t nb, const float* A, int64_t lda, const double* Y, int64_t ldy,

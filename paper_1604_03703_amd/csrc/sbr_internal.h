@@ -23,6 +23,9 @@ void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t
 void launch_syr2k_lower_cols(bool f32, int64_t m, int64_t nc, int64_t K, const double* U, int64_t ldu,
                              const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s);
 int symm_splits(int64_t m, int64_t nb);
+// The symmetric product's 32-bit buffer offsets cover the operands
+// (lda, ldy up to about 2^20 doubles).
+bool symm_offsets_fit(int64_t m, int64_t lda, int64_t ldy, int64_t elem);
 // FP32-storage form: C / A are an FP32 copy of the trailing matrix (FP32
 // MFMA products, FP32 accumulation into FP32 storage).
 void launch_syr2k_lower_f32s(int64_t m, int64_t K, const double* U, int64_t ldu, const double* V, int64_t ldv,
