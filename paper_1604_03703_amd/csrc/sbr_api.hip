@@ -341,10 +341,11 @@ bool ensure_f32_storage(sbr_plan_t p, int64_t n) {
 
 // Panel k (columns c0 .. c0+b-1, rows below the band) and its trailing
 // update.  The update of panel k's trailing matrix is split: the columns of
-// panel k+1 first, then the rest.  Panel k+1 is factored on the side stream
-// as soon as its columns are final, concurrently with the rest of the update
-// (which touches neither those columns nor the buffers the factorization
-// writes); the caller's stream waits for it before the next W = A22 Y.
+// panel k+1, then the rest.  Once V is known the work forks: the rest of the
+// update (the bulk) on one stream, and on the side stream the update of
+// panel k+1's columns followed by its factorization (the bulk touches
+// neither those columns nor the buffers the factorization writes); the
+// caller's stream waits for both before the next W = A22 Y.
 //
 // FP32-MFMA form: the trailing matrix lives in an FP32 copy As (SYMM and SYR2K
 // read and update it with FP32 MFMA and FP32 accumulation); before a panel is
@@ -388,16 +389,12 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
         EventPair eq;
         const int64_t mn = m - b;          // rows of the next panel
         if (mn >= b) {
-            if (f32s) {
-                launch_syr2k_lower_cols_f32s(m, b, b, U, ldq, p->V, ldq, A22s, lds, s);
-                launch_cols_to_f64(m, b, A22s, lds, A22, lda, s);
-            } else {
-                launch_syr2k_lower_cols(f32, m, b, b, U, ldq, p->V, ldq, A22, lda, s);
-            }
-            // the bulk update (on the CU-restricted stream when there is one)
-            // is enqueued before the panel kernels: the host needs longer to
-            // issue a panel than the GPU to run one, so the other order would
-            // start the bulk only after most of the panel
+            // fork as soon as V is known: the bulk update (on the CU-restricted
+            // stream when there is one) is enqueued before the panel work (the
+            // host needs longer to issue a panel than the GPU to run one, so
+            // the other order would start the bulk only after most of the
+            // panel); the side stream updates panel k+1's columns (disjoint
+            // from the bulk region) and factors them
             hipError_t e = hipEventRecord(p->ev_fork, s);
             if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
             if (e == hipSuccess && p->upd) e = hipStreamWaitEvent(p->upd, p->ev_fork, 0);
@@ -417,6 +414,12 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
                 bulk(p->upd);
                 e = hipEventRecord(p->ev_ujoin, p->upd);
                 if (e != hipSuccess) return hip_fail(e);
+            }
+            if (f32s) {
+                launch_syr2k_lower_cols_f32s(m, b, b, U, ldq, p->V, ldq, A22s, lds, p->side);
+                launch_cols_to_f64(m, b, A22s, lds, A22, lda, p->side);
+            } else {
+                launch_syr2k_lower_cols(f32, m, b, b, U, ldq, p->V, ldq, A22, lda, p->side);
             }
             double* Un = p->Ub[cur ^ 1];
             factor_panel(p, mn, b, A22 + b, lda, Un, p->side);

@@ -584,11 +584,12 @@ bool symm_offsets_fit(int64_t m, int64_t lda, int64_t ldy, int64_t elem) {
 
 int symm_splits(int64_t m, int64_t nb) {
     // split the reduction over A22's columns until about 1024 blocks are in
-    // flight, keeping at least 1024 columns per slice
+    // flight, keeping at least 256 columns per slice (a small trailing
+    // matrix has few row tiles: without splits most CUs would idle)
     const int64_t bm = (nb > 64 && m >= 2048) ? 128 : 64;
     const int64_t tiles = ((m + bm - 1) / bm) * ((nb + 127) / 128);
     int64_t splits = 1;
-    while (tiles * splits < 1024 && m / (splits * 2) >= 1024 && splits < 16) splits *= 2;
+    while (tiles * splits < 1024 && m / (splits * 2) >= 256 && splits < 16) splits *= 2;
     return (int)splits;
 }
 

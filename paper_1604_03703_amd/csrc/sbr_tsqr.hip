@@ -483,6 +483,83 @@ __global__ __launch_bounds__(REC_NT) void reconstruct_kernel(int b, const double
     }
 }
 
+// The same reconstruction for b = 64 by one wavefront with the block in
+// registers: lane r holds row r (LU and T phases) or column r (the inverse
+// of W1).  Every cross-lane operand is a readlane with a compile-time lane
+// index (the loops are fully unrolled), so no step waits on a barrier or an
+// LDS round trip; the arithmetic and its order are those of
+// reconstruct_kernel.
+__device__ __forceinline__ double lane_value(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__global__ __launch_bounds__(64) void reconstruct64_kernel(const double* __restrict__ Q, int64_t ldq, double* U,
+                                                           int64_t ldu, double* T, int64_t ldt, double* W1inv,
+                                                           double* S) {
+    constexpr int B = 64;
+    const int r = threadIdx.x;
+    double a[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) a[c] = Q[r + (int64_t)c * ldq];
+    // ---- LU of Q1 - S without pivoting: the pivot of step i is the current
+    // diagonal entry less s_i = -sgn; rows below take the multiplier
+    double sr = 0.0, pr = 0.0;             // this row's sign and pivot
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        const double aii = lane_value(a[i], i);
+        const double si = (aii >= 0.0) ? -1.0 : 1.0;
+        const double piv = aii - si;
+        if (r == i) {
+            sr = si;
+            pr = piv;
+        }
+        const bool below = r > i;
+        const double l = a[i] / piv;
+        const double lm = below ? l : 0.0;
+#pragma unroll
+        for (int c = i + 1; c < B; ++c) a[c] -= lm * lane_value(a[c], i);
+        a[i] = below ? l : a[i];
+    }
+    // ---- U1 (unit lower) out, S out
+#pragma unroll
+    for (int c = 0; c < B; ++c) U[r + (int64_t)c * ldu] = (r > c) ? a[c] : (r == c ? 1.0 : 0.0);
+    S[r] = sr;
+    // ---- T from T U1^T = M, M = -W1 S (upper), row r: right-looking over
+    // the columns j, t[j'] -= t[j] U1[j'][j] for j' > j
+    {
+        double t[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            const double sj = lane_value(sr, j);
+            t[j] = (j > r) ? -a[j] * sj : (j == r ? -pr * sj : 0.0);
+        }
+#pragma unroll
+        for (int j = 0; j + 1 < B; ++j)
+#pragma unroll
+            for (int jp = j + 1; jp < B; ++jp) t[jp] -= t[j] * lane_value(a[j], jp);
+#pragma unroll
+        for (int j = 0; j < B; ++j) T[r + (int64_t)j * ldt] = (r <= j) ? t[j] : 0.0;
+    }
+    // ---- W1^{-1} (upper), column r: bottom-up x[i] = rhs[i] / W1[i][i],
+    // rhs[q] -= W1[q][i] x[i] for q < i, rhs = e_r
+    {
+        const double inv_r = 1.0 / pr;
+        double x[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) x[i] = (i == r) ? 1.0 : 0.0;
+#pragma unroll
+        for (int i = B - 1; i >= 0; --i) {
+            x[i] *= lane_value(inv_r, i);
+#pragma unroll
+            for (int q = 0; q < i; ++q) x[q] -= lane_value(a[i], q) * x[i];
+        }
+#pragma unroll
+        for (int i = 0; i < B; ++i) W1inv[i + (int64_t)r * B] = (i <= r) ? x[i] : 0.0;
+    }
+}
+
 __global__ void zero_block_kernel(int64_t m, int64_t nc, double* X, int64_t ldx) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= m * nc) return;
@@ -712,6 +789,10 @@ int init_tsqr_attributes() {
 void launch_reconstruct(int b, const double* Q, int64_t ldq, double* U, int64_t ldu, double* T, int64_t ldt,
                         double* W1inv, double* S, hipStream_t s) {
     const size_t shm = (size_t)b * (b + 1) * sizeof(double);
+    if (b == 64) {
+        reconstruct64_kernel<<<1, 64, 0, s>>>(Q, ldq, U, ldu, T, ldt, W1inv, S);
+        return;
+    }
     reconstruct_kernel<<<1, REC_NT, shm, s>>>(b, Q, ldq, U, ldu, T, ldt, W1inv, S);
 }
 
