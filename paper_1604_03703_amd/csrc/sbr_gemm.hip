@@ -152,12 +152,15 @@ __device__ __forceinline__ void lower_tile_banded(int64_t x, int64_t T, int64_t&
 // GEMM with K' = 2K: [U_I, V_I] * [V_J, U_J]^T.  jt = 0: all lower tiles,
 // in the banded order above (nc = m); jt > 0: the first jt tile columns,
 // enumerated row by row.  Double-buffered LDS, one barrier per K chunk.
+// The result is added into C with atomic adds that return nothing: with
+// K' = 256 a tile is only 16 chunks long, and a read-modify-write epilogue
+// would hold the block for a full C read latency.
 // ST: storage type of C (double, or float for the FP32-storage form).
 template <typename CT, int BM, int WM, int WN, int PAD = 2, typename ST = double, bool FAST = true>
 __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     int64_t m, int64_t nc, int64_t jt, int64_t K, const double* __restrict__ U, int64_t ldu,
     const double* __restrict__ V, int64_t ldv, ST* C, int64_t ldc, int64_t ntiles) {
-    typedef TileEngine<CT, BM, BM, WM, WN, PAD> E;
+    typedef TileEngine<CT, BM, BM, WM, WN, PAD, false> E;
     typedef TileMap<BM, E::NT, false> MA;   // row fastest (column-major U, V)
     typedef TileMap<BM, E::NT, false> MB;
     __shared__ CT As[2][SBR_BK * E::LDA];
@@ -266,7 +269,12 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = i0 + E::row_of(wm, tm, lane);
                 const int64_t j = j0 + E::col_of(wn, tn, lane, r);
-                if (i < m && j <= i && j < nc) C[i + j * ldc] += (ST)eng.acc[tn][tm][r];
+                // fire-and-forget atomic add: each element gets exactly one
+                // add per launch (deterministic), and the block does not wait
+                // for a read of C before it retires
+                if (i < m && j <= i && j < nc)
+                    __hip_atomic_fetch_add(&C[i + j * ldc], (ST)eng.acc[tn][tm][r], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
             }
 }
 
