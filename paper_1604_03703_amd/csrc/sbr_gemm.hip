@@ -14,7 +14,7 @@
 
 namespace {
 
-template <typename CT, bool TA, bool TB, int BM, int BN, int WM, int WN>
+template <typename CT, bool TA, bool TB, int BM, int BN, int WM, int WN, bool FAST = true>
 __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(
     int64_t M, int64_t N, int64_t K, int64_t kchunk, double alpha,
     const double* __restrict__ A, int64_t lda, const double* __restrict__ B, int64_t ldb,
@@ -32,7 +32,33 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(
     E eng;
     eng.zero();
     CT ra[MA::E], rb[MB::E];
+    // FAST (every offset below fits 31 bits; the launcher checks): raw buffer
+    // loads, 32-bit offsets from the chunk's corner, elements past M, N or
+    // kend read zero through an out-of-range offset.  Otherwise element-wise
+    // loads with bounds checks.
+    const uint32_t lda32 = (uint32_t)lda, ldb32 = (uint32_t)ldb;
+    const int mi = (int)(M - i0 < BM ? M - i0 : BM), nj = (int)(N - j0 < BN ? N - j0 : BN);
     auto load = [&](int64_t k0) {
+        if constexpr (FAST) {
+            const int kv = (int)(kend - k0 < SBR_BK ? kend - k0 : SBR_BK);
+            const __amdgpu_buffer_rsrc_t rsa = sbr_buffer(TA ? A + k0 + i0 * lda : A + i0 + k0 * lda, SBR_BUF_OOB - 1);
+            const __amdgpu_buffer_rsrc_t rsb = sbr_buffer(TB ? B + j0 + k0 * ldb : B + k0 + j0 * ldb, SBR_BUF_OOB - 1);
+#pragma unroll
+            for (int e = 0; e < MA::E; ++e) {
+                int i, k;
+                MA::coords(t, e, i, k);
+                const uint32_t off = TA ? (uint32_t)k + (uint32_t)i * lda32 : (uint32_t)i + (uint32_t)k * lda32;
+                ra[e] = (CT)sbr_buffer_load(rsa, (i < mi && k < kv) ? off * 8u : SBR_BUF_OOB, 0.0);
+            }
+#pragma unroll
+            for (int e = 0; e < MB::E; ++e) {
+                int j, k;
+                MB::coords(t, e, j, k);
+                const uint32_t off = TB ? (uint32_t)j + (uint32_t)k * ldb32 : (uint32_t)k + (uint32_t)j * ldb32;
+                rb[e] = (CT)sbr_buffer_load(rsb, (j < nj && k < kv) ? off * 8u : SBR_BUF_OOB, 0.0);
+            }
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < MA::E; ++e) {
             int i, k;
@@ -426,24 +452,39 @@ __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(BM
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+template <typename CT, bool TA, bool TB, bool FAST>
+void gemm_dispatch_f(int64_t M, int64_t N, int64_t K, int64_t kchunk, int splits, double alpha,
+                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                     const double* Cin, int64_t ldci, double* Cout, int64_t ldco, int64_t slice_stride,
+                     hipStream_t s) {
+    if (N > 32) {
+        dim3 g(cdiv(M, 64), cdiv(N, 64), splits);
+        gemm_kernel<CT, TA, TB, 64, 64, 2, 2, FAST><<<g, 256, 0, s>>>(M, N, K, kchunk, alpha, A, lda, B, ldb, beta,
+                                                                       Cin, ldci, Cout, ldco, slice_stride);
+    } else if (N > 16) {
+        dim3 g(cdiv(M, 64), cdiv(N, 32), splits);
+        gemm_kernel<CT, TA, TB, 64, 32, 4, 1, FAST><<<g, 256, 0, s>>>(M, N, K, kchunk, alpha, A, lda, B, ldb, beta,
+                                                                       Cin, ldci, Cout, ldco, slice_stride);
+    } else {
+        dim3 g(cdiv(M, 64), cdiv(N, 16), splits);
+        gemm_kernel<CT, TA, TB, 64, 16, 4, 1, FAST><<<g, 256, 0, s>>>(M, N, K, kchunk, alpha, A, lda, B, ldb, beta,
+                                                                       Cin, ldci, Cout, ldco, slice_stride);
+    }
+}
+
 template <typename CT, bool TA, bool TB>
 void gemm_dispatch(int64_t M, int64_t N, int64_t K, int64_t kchunk, int splits, double alpha,
                    const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                    const double* Cin, int64_t ldci, double* Cout, int64_t ldco, int64_t slice_stride,
                    hipStream_t s) {
-    if (N > 32) {
-        dim3 g(cdiv(M, 64), cdiv(N, 64), splits);
-        gemm_kernel<CT, TA, TB, 64, 64, 2, 2><<<g, 256, 0, s>>>(M, N, K, kchunk, alpha, A, lda, B, ldb, beta,
-                                                                 Cin, ldci, Cout, ldco, slice_stride);
-    } else if (N > 16) {
-        dim3 g(cdiv(M, 64), cdiv(N, 32), splits);
-        gemm_kernel<CT, TA, TB, 64, 32, 4, 1><<<g, 256, 0, s>>>(M, N, K, kchunk, alpha, A, lda, B, ldb, beta,
-                                                                 Cin, ldci, Cout, ldco, slice_stride);
-    } else {
-        dim3 g(cdiv(M, 64), cdiv(N, 16), splits);
-        gemm_kernel<CT, TA, TB, 64, 16, 4, 1><<<g, 256, 0, s>>>(M, N, K, kchunk, alpha, A, lda, B, ldb, beta,
-                                                                 Cin, ldci, Cout, ldco, slice_stride);
-    }
+    // the largest offset of a 64-row tile chunk: (64 + 16) (ld + 1) elements
+    const int64_t ld = lda > ldb ? lda : ldb;
+    if ((int64_t)(64 + SBR_BK) * (ld + 1) * 8 < (int64_t)SBR_BUF_OOB - 8)
+        gemm_dispatch_f<CT, TA, TB, true>(M, N, K, kchunk, splits, alpha, A, lda, B, ldb, beta, Cin, ldci, Cout,
+                                          ldco, slice_stride, s);
+    else
+        gemm_dispatch_f<CT, TA, TB, false>(M, N, K, kchunk, splits, alpha, A, lda, B, ldb, beta, Cin, ldci, Cout,
+                                           ldco, slice_stride, s);
 }
 
 template <typename CT>
