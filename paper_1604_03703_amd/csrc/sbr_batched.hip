@@ -456,7 +456,7 @@ __device__ __forceinline__ void bisect_lanes(int n, const double* sd, const doub
             const double di = sd[i], ei = se[i];
 #pragma unroll
             for (int q = 0; q < KQ; ++q) {
-                double v = (di - x[q]) - ei / qv[q];
+                double v = (di - x[q]) - ei * sbr_recip(qv[q]);   // pivmin >= DBL_MIN: finite
                 v = (fabs(v) < piv) ? -piv : v;
                 qv[q] = v;
                 cnt[q] += (v < 0.0);

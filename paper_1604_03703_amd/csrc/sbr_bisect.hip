@@ -3,8 +3,11 @@
 // thin band", done here on the tridiagonal reached by the halvings).
 //
 // Sturm count of T - x I: q_0 = d_0 - x, q_i = (d_i - x) - e_{i-1}^2 / q_{i-1};
-// a pivot with |q| < pivmin is replaced by -pivmin (Kahan's guard, keeps the
-// count monotone); the count is the number of negative pivots.  The interval
+// a pivot with |q| < pivmin is replaced by -pivmin (Kahan's guard); the count
+// is the number of negative pivots.  pivmin >= DBL_MIN, so 1/q is finite and
+// is taken as a Newton-refined reciprocal (about one ulp, like the division
+// it replaces: the count is exact for T with each e^2 perturbed by a few ulps,
+// the backward error the eigenvalue tolerance allows for).  The interval
 // is the Gershgorin interval widened by 2.1 (n eps |T| + 2 pivmin), and every
 // index runs the same fixed number of halvings
 // I = ceil(log2((hi - lo) / (eps max(|lo|, |hi|)))) + 2, stopping early when
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __r
             }
             __syncthreads();
             for (int i = 0; i < len; ++i) {
-                q = (sd[i] - x) - se[i] / q;
+                q = (sd[i] - x) - se[i] * sbr_recip(q);
                 if (fabs(q) < piv) q = -piv;
                 cnt += (q < 0.0);
             }

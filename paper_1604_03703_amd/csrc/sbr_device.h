@@ -139,6 +139,17 @@ __device__ __forceinline__ float sbr_buffer_load(__amdgpu_buffer_rsrc_t r, uint3
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
+// 1 / q for a normal q: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - q r) (each roughly squares the
+// relative error), which leaves an error of about one ulp at a third of the
+// cost of a correctly rounded division.
+__device__ __forceinline__ double sbr_recip(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(fma(-q, r, 1.0), r, r);
+    r = fma(fma(-q, r, 1.0), r, r);
+    return r;
+}
+
 // Agent-scope flag helpers for the pipelined chase schedule.
 __device__ __forceinline__ int sbr_load_acquire(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);

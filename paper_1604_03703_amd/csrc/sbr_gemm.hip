@@ -557,7 +557,7 @@ void launch_gemm(bool f32, bool ta, bool tb, int64_t M, int64_t N, int64_t K, do
 int gemm_splits(int64_t M, int64_t N, int64_t K) {
     const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
     int64_t splits = 1;
-    while (tiles * splits < 512 && K / (splits * 2) >= 256) splits *= 2;
+    while (tiles * splits < 512 && K / (splits * 2) >= 128) splits *= 2;
     return (int)splits;
 }
 
