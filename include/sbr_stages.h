@@ -100,6 +100,10 @@ typedef struct {
     int64_t syr2k_big_launches;
 } sbr_timing;
 
+/* enable: 0 off; 1 every pair above; 2 the phase totals and the bulk SYR2K
+ * launches only (no events around the SYMM launches, which sit on the
+ * full-to-band critical path: each recorded event costs the stream a few
+ * microseconds); ms_symm and symm_launches are then 0. */
 int sbr_plan_set_timing(sbr_plan_t plan, int enable);
 
 /* Cap on the number of work-groups of the pipelined band-to-band kernel

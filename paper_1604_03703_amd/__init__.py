@@ -138,8 +138,10 @@ class Plan:
     def handle(self):
         return self._h
 
-    def set_timing(self, on: bool = True):
-        _check(_lib.sbr_plan_set_timing(self._h, 1 if on else 0), "sbr_plan_set_timing")
+    def set_timing(self, on=True):
+        """True / 1: every event pair; 2: phase totals and bulk SYR2K pairs only; False / 0: off."""
+        level = 2 if on == 2 else (1 if on else 0)
+        _check(_lib.sbr_plan_set_timing(self._h, level), "sbr_plan_set_timing")
 
     def timing(self) -> dict:
         t = _Timing()

@@ -92,7 +92,7 @@ struct sbr_plan_s {
     BisectSetup* setup = nullptr;
     double* pcopy = nullptr;   // panel copy for sbr_panel_qr
     // timing
-    bool timing = false;
+    int timing = 0;   // 0 off, 1 all pairs, 2 no SYMM pairs
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     EventPair ev_total, ev_f2b, ev_band, ev_bis;
@@ -146,7 +146,7 @@ Layout make_layout(int64_t n, int b) {
             const int ss = symm_splits(m, bb);
             if (ss > 1) part = std::max(part, (int64_t)ss * m * bb);
             const int gs = gemm_splits(bb, bb, m);
-            if (gs > 1) part = std::max(part, (int64_t)gs * bb * bb);
+            part = std::max(part, (int64_t)std::max(gs, 1) * bb * bb);   // U^T W partials, also unsplit
         }
     L.part_doubles = part;
     size_t cur = 0;
@@ -374,16 +374,14 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
         float* A22s = f32s ? As + r0 + r0 * lds : nullptr;
         // W = A22 Y  (Y = U T)
         EventPair ep;
-        if (p->timing) { ep.a = p->ev(); p->mark(ep.a, s); }
+        if (p->timing == 1) { ep.a = p->ev(); p->mark(ep.a, s); }
         const int ss = symm_splits(m, b);
         if (f32s) launch_symm_lower_f32s(m, b, A22s, lds, p->Y, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
         else launch_symm_lower(f32, m, b, A22, lda, p->Y, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
-        if (p->timing) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_symm.push_back(ep); }
+        if (p->timing == 1) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_symm.push_back(ep); }
         // Z = U^T W ; M = T^T Z ; V = 1/2 U M - W
         const int gs = gemm_splits(b, b, m);
-        launch_gemm_splitk(false, true, false, b, b, m, 1.0, U, ldq, p->W, ldq, 0.0, nullptr, 0, p->Zm, b,
-                           p->part, gs, s);
-        launch_gemm(false, true, false, b, b, b, 1.0, p->T, b, p->Zm, b, 0.0, nullptr, 0, p->Mm, b, s);
+        launch_ttuw(b, m, U, ldq, p->W, ldq, p->T, b, p->Mm, p->part, gs, s);
         launch_gemm(false, false, false, m, b, b, 0.5, U, ldq, p->Mm, b, -1.0, p->W, ldq, p->V, ldq, s);
         // A22 += U V^T + V U^T (the timed pair brackets the bulk launch only)
         EventPair eq;
@@ -602,7 +600,7 @@ int sbr_plan_status(sbr_plan_t plan, int32_t* status) {
 
 int sbr_plan_set_timing(sbr_plan_t plan, int enable) {
     if (!plan) return -1;
-    plan->timing = enable != 0;
+    plan->timing = (enable == 2) ? 2 : (enable != 0 ? 1 : 0);
     return 0;
 }
 

@@ -138,6 +138,30 @@ __global__ void reduce_slices_kernel(int64_t M, int64_t N, int splits, const dou
     Cout[i + j * ldco] = v;
 }
 
+// M = T^T Z with Z the sum of `splits` split-K partial slices (b x b each,
+// ld b): one block per column j of M, thread k first sums row k of the
+// slices (slice order, as reduce_slices), then thread i forms
+// M[i][j] = sum_k T[k][i] Z[k][j], walking its own column of T.
+__global__ __launch_bounds__(128) void tt_reduce_kernel(int b, int splits, const double* __restrict__ part,
+                                                        const double* __restrict__ T, int64_t ldt,
+                                                        double* __restrict__ M) {
+    __shared__ double z[128];
+    const int j = blockIdx.x, t = threadIdx.x;
+    const int64_t bb = (int64_t)b * b;
+    if (t < b) {
+        double s = 0.0;
+        for (int q = 0; q < splits; ++q) s += part[q * bb + t + (int64_t)j * b];
+        z[t] = s;
+    }
+    __syncthreads();
+    if (t < b) {
+        const double* Tc = T + (int64_t)t * ldt;
+        double acc = 0.0;
+        for (int k = 0; k < b; ++k) acc += Tc[k] * z[k];
+        M[t + (int64_t)j * b] = acc;
+    }
+}
+
 // Blocks are dealt round-robin to the 8 XCDs (block x runs on XCD x mod 8).
 // Renumber them so that each XCD works on a contiguous range of logical
 // tiles: neighbouring tiles share operand rows, which then stay in that
@@ -575,6 +599,19 @@ void launch_gemm_splitk(bool f32, bool ta, bool tb, int64_t M, int64_t N, int64_
     if (f32) gemm_dispatch_t<float>(ta, tb, M, N, K, kchunk, splits, 1.0, A, lda, B, ldb, 0.0, nullptr, 0, part, M, M * N, s);
     else gemm_dispatch_t<double>(ta, tb, M, N, K, kchunk, splits, 1.0, A, lda, B, ldb, 0.0, nullptr, 0, part, M, M * N, s);
     reduce_slices(M, N, splits, part, alpha, beta, Cin, ldci, Cout, ldco, s);
+}
+
+void launch_ttuw(int b, int64_t m, const double* U, int64_t ldu, const double* W, int64_t ldw, const double* T,
+                 int64_t ldt, double* M, double* part, int splits, hipStream_t s) {
+    if (b <= 0 || b > 128) return;
+    if (splits < 1) splits = 1;
+    // partials of Z = U^T W (b x b slices in part), then M = T^T Z
+    int64_t kchunk = (m + splits - 1) / splits;
+    kchunk = (kchunk + SBR_BK - 1) / SBR_BK * SBR_BK;
+    if (kchunk < 1) kchunk = SBR_BK;
+    gemm_dispatch_t<double>(true, false, b, b, m, kchunk, splits, 1.0, U, ldu, W, ldw, 0.0, nullptr, 0, part, b,
+                            (int64_t)b * b, s);
+    tt_reduce_kernel<<<(unsigned)b, 128, 0, s>>>(b, splits, part, T, ldt, M);
 }
 
 bool syr2k_big_tiles(int64_t m) {

@@ -23,6 +23,11 @@ void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t
 void launch_syr2k_lower_cols(bool f32, int64_t m, int64_t nc, int64_t K, const double* U, int64_t ldu,
                              const double* V, int64_t ldv, double* C, int64_t ldc, hipStream_t s);
 int symm_splits(int64_t m, int64_t nb);
+// M = T^T (U^T W) for b x b T (b <= 128), U and W m x b: split-K partials of
+// U^T W in part (splits slices of b x b), then one kernel sums them and
+// multiplies by T^T.
+void launch_ttuw(int b, int64_t m, const double* U, int64_t ldu, const double* W, int64_t ldw, const double* T,
+                 int64_t ldt, double* M, double* part, int splits, hipStream_t s);
 // The symmetric product's 32-bit buffer offsets cover the operands
 // (lda, ldy up to about 2^20 doubles).
 bool symm_offsets_fit(int64_t m, int64_t lda, int64_t ldy, int64_t elem);
