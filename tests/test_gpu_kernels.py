@@ -75,6 +75,38 @@ def test_syr2k_lower(sbr, prec, m, k):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_mfma"])
+@pytest.mark.parametrize("m,k", [(17, 16), (1000, 64), (4100, 128)])
+def test_syr2k_lower_buffer_path(sbr, prec, m, k):
+    # U and V with one leading dimension and k a multiple of 16: the
+    # buffer-load form the full-to-band uses (64 x 64 tiles below 512 lower
+    # tiles, 128 x 128 tiles above: m = 4100 has 33 tile rows, the last
+    # ragged); the result goes in by atomic adds, exactly one per element
+    print("syr2k buffer", prec, m, k, flush=True)
+    rng = np.random.default_rng(m * 11 + k)
+    U = rng.standard_normal((m, k))
+    V = rng.standard_normal((m, k))
+    C = rng.standard_normal((m, m))
+    ld = m + 3
+    Ud, Vd, Cd = to_col(U, ld), to_col(V, ld), to_col(C, m + 1)
+    sbr.syr2k_lower(m, k, Ud, ld, Vd, ld, Cd, m + 1, precision=prec)
+    torch.cuda.synchronize()
+    out = from_col(Cd, m)
+    ref = C + U @ V.T + V @ U.T
+    low = np.tril_indices(m)
+    up = np.triu_indices(m, 1)
+    scale = 2 * k * np.abs(U).max() * np.abs(V).max() + np.abs(C).max()
+    tol = (8 * k * EPS64 if prec == "fp64" else 8 * math.sqrt(k) * EPS32) * scale
+    assert np.max(np.abs(out[low] - ref[low])) <= tol
+    assert np.all(out[up] == C[up])
+    # a second call adds the same update again (the epilogue adds, never stores)
+    sbr.syr2k_lower(m, k, Ud, ld, Vd, ld, Cd, m + 1, precision=prec)
+    torch.cuda.synchronize()
+    out2 = from_col(Cd, m)
+    ref2 = ref + U @ V.T + V @ U.T
+    assert np.max(np.abs(out2[low] - ref2[low])) <= 2 * tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_mfma"])
 @pytest.mark.parametrize("m,k", [(1, 1), (50, 16), (64, 64), (130, 128), (257, 32), (1000, 64)])
 def test_symm_lower(sbr, prec, m, k):
     print("symm", prec, m, k, flush=True)
