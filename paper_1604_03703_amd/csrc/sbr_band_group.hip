@@ -34,15 +34,17 @@ namespace {
 template <int H>
 struct GroupCfg {
     // h = 1: one lane per sweep (lane_chase_qr / _update), one wave per
-    // group, so a step's barriers are cheap.  h = 2 and 4: two and four
-    // lanes per sweep (team_lane_chase_qr / _update), two waves per group.
-    // All carry the bulge in registers.  h = 8 (used only where the MFMA
-    // chase is not): one team of 2h lanes per chase (team_chase, lane u holds
-    // band row u).  Sweeps per group are sized so the ring (plus
-    // team_chase's scratch) stays in LDS.
+    // group, so a step's barriers are cheap.  h = 2: four lanes per sweep,
+    // one band row each (team_lane_chase_qr / _update), 64 sweeps on four
+    // waves; h = 4: four lanes per sweep, two rows each, 32 sweeps on two
+    // waves (a row per lane there, eight lanes with ds_bpermute gathers,
+    // measured 10 % slower).  All carry the bulge in registers.  h = 8 (used
+    // only where the MFMA chase is not): one team of 2h lanes per chase
+    // (team_chase, lane u holds band row u).  Sweeps per group are sized so
+    // the ring (plus team_chase's scratch) stays in LDS.
     static constexpr bool LANE = (H <= 4);
-    static constexpr int TEAM = (H == 1) ? 1 : (H == 2 ? 2 : (H == 4 ? 4 : 2 * H));
-    static constexpr int NT = (H == 1) ? 64 : 128;
+    static constexpr int TEAM = (H == 1) ? 1 : (H == 2 ? 4 : (H == 4 ? 4 : 2 * H));
+    static constexpr int NT = (H == 1) ? 64 : (H == 2 ? 256 : 128);
     static constexpr int S = NT / TEAM;
     static constexpr int LDW = 4 * H + 1;        // stored diagonals per column
     // steps per load / write-back batch
