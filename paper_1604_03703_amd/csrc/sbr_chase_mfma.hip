@@ -63,14 +63,23 @@ struct MChase {
     static constexpr int RT = B / 16, CT = HP / 16;
     static constexpr int LDU = B + 1, LDH = HP + 1;
     static constexpr bool WR_LDS = H <= 32;
+    // CARRY: the updated below block stays in LDS for the next chase of the
+    // sweep (its QR and left blocks), the diagonal and below blocks are loaded
+    // into registers right after the wait, and the diagonal update is applied
+    // to those registers (V goes through LDS).  One round trip to memory per
+    // chase instead of one per block.
+    static constexpr bool CARRY = H <= 32;
+    static constexpr int LDX = B + 1;
     // LDS (doubles): U (b x h), T (h x h; QR staging before T exists), one
-    // h x h exchange buffer (L = T^{-1}, then U^T X_L, then U^T W), W (b x h);
+    // h x h exchange buffer (L = T^{-1}, then U^T X_L, then U^T W), W (b x h;
+    // V after G is formed), the carried below block (b x b);
     // for h < 16 the columns h .. 15 are zero padding
     static constexpr int US = 0;
     static constexpr int TS = US + LDU * HP;
     static constexpr int RS = TS + LDH * HP;
     static constexpr int WS = RS + LDH * HP;
-    static constexpr int TOTAL = WS + (WR_LDS ? B * HP : 0);
+    static constexpr int XS = WS + (WR_LDS ? B * HP : 0);
+    static constexpr int TOTAL = XS + (CARRY ? B * LDX : 0);
     static constexpr int TPCQ = 8, RPT = B / TPCQ;   // QR: 8 lanes per column
     static_assert(H * TPCQ == NT, "QR layout");
     static_assert(2 * B + H <= LDH * HP, "QR staging fits in the T region");
@@ -85,7 +94,8 @@ template <int H>
 __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a) {
     typedef MChase<H> C;
     constexpr int B = C::B, HP = C::HP, NW = C::NW, RT = C::RT, CT = C::CT, LDU = C::LDU, LDH = C::LDH;
-    constexpr int TPCQ = C::TPCQ, RPT = C::RPT;
+    constexpr int TPCQ = C::TPCQ, RPT = C::RPT, LDX = C::LDX;
+    constexpr bool CARRY = C::CARRY;
     extern __shared__ double sm[];
     double* Us = sm + C::US;
     double* Ts = sm + C::TS;
@@ -93,6 +103,7 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
     double* vbuf = Ts;            // two reflectors in flight during the QR ...
     double* tau = Ts + 2 * B;     // ... and the tau, until T is formed
     double* Wsc = C::WR_LDS ? sm + C::WS : a.gscratch + (int64_t)blockIdx.x * a.scratch_stride;
+    double* Xs = sm + C::XS;      // carried below block (CARRY only)
     __shared__ int sweep_sh;
     __shared__ int abort_sh;
 
@@ -153,14 +164,37 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
             if (nb64 > B) nb64 = B;
             const int nbr = nb64 > 0 ? (int)nb64 : 0;
 
+            // ---- 0. (CARRY) the chase's diagonal block (full, from the lower
+            // triangle) and below block, row-in-lane: element q of lane l is
+            // (16 w + l%16, 4 q + l/16); every load of the chase is issued here
+            constexpr int NQ = CARRY ? B / 4 : 1;
+            double dr[NQ], xb[NQ];
+            if (CARRY) {
+                const int row = w * 16 + li;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int col = 4 * q + lk;
+                    double dv = 0.0, bv = 0.0;
+                    if (row < nr && col < nr) dv = (row >= col) ? B_at(o + row, o + col) : B_at(o + col, o + row);
+                    if (row < nbr && col < nr) bv = B_at(o + B + row, o + col);
+                    dr[q] = dv;
+                    xb[q] = bv;
+                }
+            }
+
             // ---- 1. Householder QR of the QR block (rows [o, o+nr), cols
-            // [cq, cq+h)): 8 lanes per column, one barrier per reflector
+            // [cq, cq+h)): 8 lanes per column, one barrier per reflector.
+            // With CARRY, chase j > 1 finds the block in LDS: it is the first
+            // h columns of the previous chase's below block.
             {
                 double x[RPT];
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
                     const int row = qs + TPCQ * r;
-                    x[r] = (row < nr) ? B_at(o + row, cq + qc) : 0.0;
+                    if (CARRY && j > 1)
+                        x[r] = (row < nr) ? Xs[row + qc * LDX] : 0.0;
+                    else
+                        x[r] = (row < nr) ? B_at(o + row, cq + qc) : 0.0;
                 }
                 for (int k = 0; k < H; ++k) {
                     double* v = vbuf + (k & 1) * B;
@@ -287,7 +321,8 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 #pragma unroll 4
                     for (int k0 = 0; k0 < B; k0 += 4) {
                         const int row = k0 + lk;
-                        const double av = (row < nr && colv) ? B_at(o + row, gc) : 0.0;
+                        double av = 0.0;
+                        if (row < nr && colv) av = CARRY ? Xs[row + (H + J * 16 + li) * LDX] : B_at(o + row, gc);
                         acc = mma(av, Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
                     }
 #pragma unroll
@@ -306,8 +341,15 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                         const int row = w * 16 + li;
                         if (row < nr) {
 #pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                if (J * 16 + 4 * r + lk < H) B_at(o + row, o - H + J * 16 + 4 * r + lk) -= acc[r];
+                            for (int r = 0; r < 4; ++r) {
+                                const int col = J * 16 + 4 * r + lk;
+                                if (col < H) {
+                                    if (CARRY)
+                                        B_at(o + row, o - H + col) = Xs[row + (H + col) * LDX] - acc[r];
+                                    else
+                                        B_at(o + row, o - H + col) -= acc[r];
+                                }
+                            }
                         }
                     }
                 }
@@ -322,7 +364,11 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 #pragma unroll 4
                 for (int k0 = 0; k0 < B; k0 += 4) {
                     const int col = k0 + lk;
-                    const double bv = (row < nbr && col < nr) ? B_at(o + B + row, o + col) : 0.0;
+                    double bv;
+                    if (CARRY)
+                        bv = xb[k0 / 4];
+                    else
+                        bv = (row < nbr && col < nr) ? B_at(o + B + row, o + col) : 0.0;
 #pragma unroll
                     for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
                 }
@@ -344,7 +390,10 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 #pragma unroll
                         for (int r4 = 0; r4 < 4; ++r4)
                             acc = mma(Us[(X * 16 + li) + (K * 16 + 4 * r4 + lk) * LDU], WB[K][r4], acc);
-                    if (row < nbr) {
+                    if (CARRY) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) xb[4 * X + r] -= acc[r];
+                    } else if (row < nbr) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int col = X * 16 + 4 * r + lk;
@@ -365,7 +414,10 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 for (int k0 = 0; k0 < B; k0 += 4) {
                     const int col = k0 + lk;
                     double bv = 0.0;
-                    if (row < nr && col < nr) bv = (row >= col) ? B_at(o + row, o + col) : B_at(o + col, o + row);
+                    if (CARRY)
+                        bv = dr[k0 / 4];
+                    else if (row < nr && col < nr)
+                        bv = (row >= col) ? B_at(o + row, o + col) : B_at(o + col, o + row);
 #pragma unroll
                     for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
                 }
@@ -382,6 +434,19 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 }
             }
             __syncthreads();
+            // ---- (CARRY) the updated below block to LDS for the next chase,
+            // whose QR and left blocks write every entry of it back; the
+            // sweep's last chase stores it (every wave is past the left
+            // block's reads of the previous contents)
+            if (CARRY) {
+                const int row = w * 16 + li;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int col = 4 * q + lk;
+                    Xs[row + col * LDX] = xb[q];
+                    if (j == nchase && row < nbr && col < nr) B_at(o + B + row, o + col) = xb[q];
+                }
+            }
 
             // ---- 8. G = U^T W into LDS (the left block is done with it)
             for (int idx = w; idx < CT * CT; idx += NW) {
@@ -409,6 +474,36 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 for (int r = 0; r < 4; ++r) V[J][r] = 0.5 * acc[r] - WR[J][r];
             }
 
+            if (CARRY) {
+                // ---- 10. D += V U^T + U V^T on the registers of the diagonal
+                // block: wave w forms its tiles (w, X <= w) from V_w U_X^T and
+                // U_w V_X^T, V through LDS (in place of W, which G has consumed)
+                double* Vs = Wsc;
+                const int row = w * 16 + li;
+#pragma unroll
+                for (int J = 0; J < CT; ++J)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Vs[row + (J * 16 + 4 * r + lk) * B] = V[J][r];
+                __syncthreads();
+#pragma unroll
+                for (int X = 0; X < RT; ++X) {
+                    if (X > w || X * 16 >= nr) break;
+                    sbr_d4 acc = zero4();
+#pragma unroll
+                    for (int K = 0; K < CT; ++K)
+#pragma unroll
+                        for (int r4 = 0; r4 < 4; ++r4)
+                            acc = mma(Us[(X * 16 + li) + (K * 16 + 4 * r4 + lk) * LDU], V[K][r4], acc);
+#pragma unroll
+                    for (int k0 = 0; k0 < HP; k0 += 4)
+                        acc = mma(Vs[(X * 16 + li) + (k0 + lk) * B], Us[row + (k0 + lk) * LDU], acc);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int col = X * 16 + 4 * r + lk;
+                        if (row < nr && col <= row) B_at(o + row, o + col) = dr[4 * X + r] + acc[r];
+                    }
+                }
+            } else {
             // ---- 10. D += V U^T + U V^T, lower triangle: tiles (w, X <= w)
             // with V_w U_X^T, then tiles (X >= w, w) with U_X V_w^T
             if (w * 16 < nr) {
@@ -446,6 +541,7 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                         if (col <= row) B_at(o + row, o + col) += acc[r];
                     }
                 }
+            }
             }
 
             // ---- the sweep's last chase: publish the whole sweep (a chase of
