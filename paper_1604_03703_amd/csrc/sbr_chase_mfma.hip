@@ -90,6 +90,21 @@ __device__ __forceinline__ sbr_d4 mma(double a, double b, sbr_d4 c) {
 }
 __device__ __forceinline__ sbr_d4 zero4() { return sbr_d4{0.0, 0.0, 0.0, 0.0}; }
 
+// The value of lane q of each aligned group of 8 lanes, in all 8: quad_perm
+// (q%4 x4) fills the quads, row_half_mirror (lane i <-> 7 - i) brings the
+// source quad's value to the other quad.  q must fold to a constant.
+__device__ __forceinline__ double bcast8(double v, int q) {
+    double a;
+    switch (q & 3) {
+        case 0: a = dpp_d<0x00>(v); break;
+        case 1: a = dpp_d<0x55>(v); break;
+        case 2: a = dpp_d<0xAA>(v); break;
+        default: a = dpp_d<0xFF>(v); break;
+    }
+    const double b = dpp_d<0x141>(a);
+    return (((threadIdx.x >> 2) & 1) == (q >> 2)) ? a : b;
+}
+
 template <int H>
 __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a) {
     typedef MChase<H> C;
@@ -199,23 +214,37 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 for (int k = 0; k < H; ++k) {
                     double* v = vbuf + (k & 1) * B;
                     if (qc == k) {
-                        double ss = 0.0, xk = 0.0;
+                        double sq[RPT], xk = 0.0;
 #pragma unroll
                         for (int r = 0; r < RPT; ++r) {
                             const int row = qs + TPCQ * r;
-                            if (row > k) ss += x[r] * x[r];
-                            else if (row == k) xk = x[r];
+                            sq[r] = (row > k) ? x[r] * x[r] : 0.0;
+                            if (row == k) xk = x[r];
                         }
-                        ss = group_sum<TPCQ>(ss);
+                        const double ss = group_sum<TPCQ>(tree_sum<RPT>(sq));
                         xk = group_sum<TPCQ>(xk);
+                        // beta = -sign(xk) ||x||, tau = (beta - xk) / beta =
+                        // 1 + |xk| / ||x||, v below the diagonal = x / (xk - beta)
+                        // = sign(xk) x / (|xk| + ||x||): one reciprocal square
+                        // root and one reciprocal, Newton-refined
                         double beta, tk, scal;
                         if (ss == 0.0) {
                             beta = xk; tk = 0.0; scal = 0.0;
                         } else {
-                            const double nrm = sqrt(xk * xk + ss);
-                            beta = (xk >= 0.0) ? -nrm : nrm;
-                            tk = (beta - xk) / beta;
-                            scal = 1.0 / (xk - beta);
+                            const double s2 = fma(xk, xk, ss);
+                            const double sg = (xk >= 0.0) ? 1.0 : -1.0, ax = fabs(xk);
+                            if (s2 > 1e-290 && s2 < 1e290) {
+                                const double rs = sbr_rsqrt(s2);
+                                const double nrm = s2 * rs;
+                                beta = -sg * nrm;
+                                tk = fma(ax, rs, 1.0);
+                                scal = sg * sbr_recip(ax + nrm);
+                            } else {
+                                const double nrm = sqrt(s2);
+                                beta = -sg * nrm;
+                                tk = (beta - xk) / beta;
+                                scal = 1.0 / (xk - beta);
+                            }
                         }
 #pragma unroll
                         for (int r = 0; r < RPT; ++r) {
@@ -230,10 +259,10 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                     if (qc > k) {
                         const double tk = tau[k];
                         if (tk != 0.0) {
-                            double d = 0.0;
+                            double dp[RPT];
 #pragma unroll
-                            for (int r = 0; r < RPT; ++r) d += v[qs + TPCQ * r] * x[r];
-                            d = group_sum<TPCQ>(d);
+                            for (int r = 0; r < RPT; ++r) dp[r] = v[qs + TPCQ * r] * x[r];
+                            const double d = group_sum<TPCQ>(tree_sum<RPT>(dp));
                             const double f = tk * d;
 #pragma unroll
                             for (int r = 0; r < RPT; ++r) x[r] -= f * v[qs + TPCQ * r];
@@ -285,18 +314,37 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
             __syncthreads();
 
             // ---- 3. T by columns: T[j][j] = tau_j, T[i][j] = -tau_i sum_{i<k<=j}
-            // L[i][k] T[k][j] for i = j-1 .. 0; 8 lanes per column
+            // L[i][k] T[k][j] for i = j-1 .. 0; 8 lanes per column.  Lane s
+            // keeps the partial sums of the rows i = s (mod 8) in registers and
+            // adds L[i][k] T[k][j] once T[k][j] is known; the owner of row k-1
+            // then finishes T[k-1][j] and hands it to the other seven lanes
+            // (two DPP moves), so each new entry costs one FMA, one product and
+            // the hand-over.  Adding L[i][k] T[k][j] for i >= k is harmless:
+            // L is zero below its diagonal and a row's sum is no longer read
+            // once its entry is formed.
             {
+                constexpr int M = H / 8;
                 const int jc = t >> 3, s = t & 7;
-                const int jmax = ((t >> 6) << 3) + 7;    // last column of this wave
-                if (s == 0) Ts[jc + jc * LDH] = Rs[jc + jc * LDH];
+                double p[M], tr[M];
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    p[m] = 0.0;
+                    tr[m] = Rs[(s + 8 * m) + (s + 8 * m) * LDH];
+                }
+                double tk = Rs[jc + jc * LDH];
+                if (s == 0) Ts[jc + jc * LDH] = tk;
                 for (int r = jc + 1 + s; r < HP; r += 8) Ts[r + jc * LDH] = 0.0;
-                for (int r = jmax - 1; r >= 0; --r) {
-                    double p = 0.0;
-                    if (r < jc)
-                        for (int k = r + 1 + s; k <= jc; k += 8) p += Rs[r + k * LDH] * Ts[k + jc * LDH];
-                    p = group_sum<8>(p);
-                    if (r < jc && s == 0) Ts[r + jc * LDH] = -Rs[r + r * LDH] * p;
+#pragma unroll
+                for (int k = H - 1; k >= 1; --k) {
+                    if (k <= jc) {
+#pragma unroll
+                        for (int m = 0; m < M; ++m)
+                            if (8 * m < k) p[m] += Rs[(s + 8 * m) + k * LDH] * tk;
+                        const int q = (k - 1) & 7, mq = (k - 1) >> 3;
+                        const double tn = -tr[mq] * p[mq];
+                        if (s == q) Ts[(k - 1) + jc * LDH] = tn;
+                        tk = bcast8(tn, q);
+                    }
                 }
             }
             __syncthreads();
@@ -558,7 +606,7 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 template <int H>
 int mchase_grid(int64_t n) {
     const int64_t nsweeps = (n - 2) / H;
-    const int64_t cap = (H >= 16) ? 256 : 1024;
+    const int64_t cap = 256;
     int64_t g = nsweeps < cap ? nsweeps : cap;
     return (int)(g < 1 ? 1 : g);
 }

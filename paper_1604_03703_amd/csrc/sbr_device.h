@@ -150,6 +150,26 @@ __device__ __forceinline__ double sbr_recip(double q) {
     return r;
 }
 
+// 1/sqrt(a) for a normal a > 0: the hardware estimate refined by two Newton
+// steps y <- y + y (1 - a y^2) / 2 (each roughly doubles the correct bits),
+// about one ulp like sbr_recip.
+__device__ __forceinline__ double sbr_rsqrt(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+    y = fma(0.5 * y, fma(-a, y * y, 1.0), y);
+    y = fma(0.5 * y, fma(-a, y * y, 1.0), y);
+    return y;
+}
+
+// Sum of N values by pairs (a tree of depth log2 N instead of a chain of N).
+template <int N>
+__device__ __forceinline__ double tree_sum(const double* v) {
+    if constexpr (N == 1) {
+        return v[0];
+    } else {
+        return tree_sum<N / 2>(v) + tree_sum<N - N / 2>(v + N / 2);
+    }
+}
+
 // Agent-scope flag helpers for the pipelined chase schedule.
 __device__ __forceinline__ int sbr_load_acquire(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
