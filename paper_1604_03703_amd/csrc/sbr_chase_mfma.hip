@@ -179,34 +179,28 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
             if (nb64 > B) nb64 = B;
             const int nbr = nb64 > 0 ? (int)nb64 : 0;
 
-            // ---- 0. (CARRY) the chase's diagonal block (full, from the lower
-            // triangle) and below block, row-in-lane: element q of lane l is
-            // (16 w + l%16, 4 q + l/16); every load of the chase is issued here
-            constexpr int NQ = CARRY ? B / 4 : 1;
-            double dr[NQ], xb[NQ];
-            if (CARRY) {
-                const int row = w * 16 + li;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    const int col = 4 * q + lk;
-                    double dv = 0.0, bv = 0.0;
-                    if (row < nr && col < nr) dv = (row >= col) ? B_at(o + row, o + col) : B_at(o + col, o + row);
-                    if (row < nbr && col < nr) bv = B_at(o + B + row, o + col);
-                    dr[q] = dv;
-                    xb[q] = bv;
-                }
-            }
-
             // ---- 1. Householder QR of the QR block (rows [o, o+nr), cols
             // [cq, cq+h)): 8 lanes per column, one barrier per reflector.
             // With CARRY, chase j > 1 finds the block in LDS: it is the first
             // h columns of the previous chase's below block.
+            // The first chase of a sweep stages its QR block through the same
+            // LDS slots (each thread writes the entries it reads back), so the
+            // registers of the reflector loop are only ever filled from LDS and
+            // the loop never waits on the memory counter, which would also wait
+            // for the previous chase's stores.
             {
                 double x[RPT];
+                if (CARRY && j == 1) {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        const int row = qs + TPCQ * r;
+                        Xs[row + qc * LDX] = (row < nr) ? B_at(o + row, cq + qc) : 0.0;
+                    }
+                }
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
                     const int row = qs + TPCQ * r;
-                    if (CARRY && j > 1)
+                    if (CARRY)
                         x[r] = (row < nr) ? Xs[row + qc * LDX] : 0.0;
                     else
                         x[r] = (row < nr) ? B_at(o + row, cq + qc) : 0.0;
@@ -257,16 +251,18 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                     }
                     __syncthreads();
                     if (qc > k) {
+                        // tau and v in one round trip to LDS: a zero tau (v is
+                        // then finite, its tail zero) leaves x as it is
                         const double tk = tau[k];
-                        if (tk != 0.0) {
-                            double dp[RPT];
+                        double vr[RPT], dp[RPT];
 #pragma unroll
-                            for (int r = 0; r < RPT; ++r) dp[r] = v[qs + TPCQ * r] * x[r];
-                            const double d = group_sum<TPCQ>(tree_sum<RPT>(dp));
-                            const double f = tk * d;
-#pragma unroll
-                            for (int r = 0; r < RPT; ++r) x[r] -= f * v[qs + TPCQ * r];
+                        for (int r = 0; r < RPT; ++r) {
+                            vr[r] = v[qs + TPCQ * r];
+                            dp[r] = vr[r] * x[r];
                         }
+                        const double f = tk * group_sum<TPCQ>(tree_sum<RPT>(dp));
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) x[r] -= f * vr[r];
                     }
                 }
                 // U (unit lower; a zero column where no reflector was applied)
@@ -290,6 +286,27 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (t == 0) sbr_store_release(&a.progress[i], (int)j);
+
+            // ---- (CARRY) the chase's diagonal block (full, from the lower
+            // triangle) and below block, row-in-lane: element q of lane l is
+            // (16 w + l%16, 4 q + l/16), loaded together behind the QR block's
+            // publication (loads issued before the QR would make its first
+            // wait on the memory counter wait for them, and for the previous
+            // chase's stores)
+            constexpr int NQ = CARRY ? B / 4 : 1;
+            double dr[NQ], xb[NQ];
+            if (CARRY) {
+                const int row = w * 16 + li;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int col = 4 * q + lk;
+                    double dv = 0.0, bv = 0.0;
+                    if (row < nr && col < nr) dv = (row >= col) ? B_at(o + row, o + col) : B_at(o + col, o + row);
+                    if (row < nbr && col < nr) bv = B_at(o + B + row, o + col);
+                    dr[q] = dv;
+                    xb[q] = bv;
+                }
+            }
 
             // ---- 2. L = T^{-1}: strict upper part of U^T U, tau on the diagonal
             // (the multiplier that replaces 1/tau below; a zero tau gives a zero
