@@ -105,6 +105,39 @@ __device__ __forceinline__ double bcast8(double v, int q) {
     return (((threadIdx.x >> 2) & 1) == (q >> 2)) ? a : b;
 }
 
+// A product over k = 0 .. B-1 in steps of 4 whose operand for step k0 comes
+// from global memory: the operands of KB steps are loaded as a batch while
+// the previous batch's products run (two batches in registers).  use(k0, v)
+// issues the products of step k0.
+template <int B, int KB, class LoadF, class UseF>
+__device__ __forceinline__ void kloop_pipelined(const LoadF& load, const UseF& use) {
+    constexpr int NS = B / 4;
+    static_assert(NS % KB == 0, "batch size");
+    double cur[KB], nxt[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) cur[u] = load(4 * u);
+#pragma unroll 1
+    for (int kb = 0; kb < NS; kb += KB) {
+        if (kb + KB < NS) {
+#pragma unroll
+            for (int u = 0; u < KB; ++u) nxt[u] = load(4 * (kb + KB + u));
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u) use(4 * (kb + u), cur[u]);
+#pragma unroll
+        for (int u = 0; u < KB; ++u) cur[u] = nxt[u];
+    }
+}
+
+// The same product with the loads issued step by step (a partial unroll
+// keeps a few in flight); used where the two batches of the pipelined form
+// do not fit in the registers.
+template <int B, class LoadF, class UseF>
+__device__ __forceinline__ void kloop_plain(const LoadF& load, const UseF& use) {
+#pragma unroll 4
+    for (int k0 = 0; k0 < B; k0 += 4) use(k0, load(k0));
+}
+
 template <int H>
 __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a) {
     typedef MChase<H> C;
@@ -383,12 +416,21 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                     const int64_t gc = o - H + J * 16 + li;
                     const bool colv = J * 16 + li < H;
                     sbr_d4 acc = zero4();
+                    if constexpr (CARRY) {
 #pragma unroll 4
-                    for (int k0 = 0; k0 < B; k0 += 4) {
-                        const int row = k0 + lk;
-                        double av = 0.0;
-                        if (row < nr && colv) av = CARRY ? Xs[row + (H + J * 16 + li) * LDX] : B_at(o + row, gc);
-                        acc = mma(av, Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
+                        for (int k0 = 0; k0 < B; k0 += 4) {
+                            const int row = k0 + lk;
+                            double av = 0.0;
+                            if (row < nr && colv) av = Xs[row + (H + J * 16 + li) * LDX];
+                            acc = mma(av, Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
+                        }
+                    } else {
+                        kloop_pipelined<B, 4>(
+                            [&](int k0) {
+                                const int row = k0 + lk;
+                                return (row < nr && colv) ? B_at(o + row, gc) : 0.0;
+                            },
+                            [&](int k0, double av) { acc = mma(av, Us[(k0 + lk) + (I * 16 + li) * LDU], acc); });
                     }
 #pragma unroll
                     for (int r = 0; r < 4; ++r) Rs[(I * 16 + li) + (J * 16 + 4 * r + lk) * LDH] = acc[r];
@@ -426,16 +468,23 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 sbr_d4 P[CT];
 #pragma unroll
                 for (int J = 0; J < CT; ++J) P[J] = zero4();
+                if constexpr (CARRY) {
 #pragma unroll 4
-                for (int k0 = 0; k0 < B; k0 += 4) {
-                    const int col = k0 + lk;
-                    double bv;
-                    if (CARRY)
-                        bv = xb[k0 / 4];
-                    else
-                        bv = (row < nbr && col < nr) ? B_at(o + B + row, o + col) : 0.0;
+                    for (int k0 = 0; k0 < B; k0 += 4) {
+                        const double bv = xb[k0 / 4];
 #pragma unroll
-                    for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
+                        for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
+                    }
+                } else {
+                    kloop_plain<B>(
+                        [&](int k0) {
+                            const int col = k0 + lk;
+                            return (row < nbr && col < nr) ? B_at(o + B + row, o + col) : 0.0;
+                        },
+                        [&](int k0, double bv) {
+#pragma unroll
+                            for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
+                        });
                 }
                 sbr_d4 WB[CT];
 #pragma unroll
@@ -475,16 +524,25 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 sbr_d4 P[CT];
 #pragma unroll
                 for (int J = 0; J < CT; ++J) P[J] = zero4();
+                if constexpr (CARRY) {
 #pragma unroll 4
-                for (int k0 = 0; k0 < B; k0 += 4) {
-                    const int col = k0 + lk;
-                    double bv = 0.0;
-                    if (CARRY)
-                        bv = dr[k0 / 4];
-                    else if (row < nr && col < nr)
-                        bv = (row >= col) ? B_at(o + row, o + col) : B_at(o + col, o + row);
+                    for (int k0 = 0; k0 < B; k0 += 4) {
+                        const double bv = dr[k0 / 4];
 #pragma unroll
-                    for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
+                        for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
+                    }
+                } else {
+                    kloop_plain<B>(
+                        [&](int k0) {
+                            const int col = k0 + lk;
+                            double dv = 0.0;
+                            if (row < nr && col < nr) dv = (row >= col) ? B_at(o + row, o + col) : B_at(o + col, o + row);
+                            return dv;
+                        },
+                        [&](int k0, double bv) {
+#pragma unroll
+                            for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
+                        });
                 }
 #pragma unroll
                 for (int J = 0; J < CT; ++J) {
