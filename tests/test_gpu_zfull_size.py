@@ -1,0 +1,127 @@
+"""GPU parity at the full sizes of the named workloads (n = 8192, 16384 and
+32768), through one plan per solve and the band widths the benchmark uses.
+
+At n = 8192 the CPU oracle finishes in about half a minute and is compared
+element by element.  At n = 16384 and 32768 every case is checked against what
+holds without it:
+
+* prescribed spectra, A = Q diag(lam) Q^T with Q a product of 64 Gaussian
+  reflectors: every computed eigenvalue against the sorted lam, the FP64 path
+  within 1e-11 ||A||_2 and the FP32-MFMA form within 2e-5 ||A||_2, where
+  ||A||_2 = max |lam| (forming A in floating point moves its eigenvalues by
+  about 64 sqrt(n) eps ||A||_2, far inside the FP64 bound);
+* the Gaussian inputs: the sum of the eigenvalues against trace(A) and the sum
+  of their squares against ||A||_F^2 (both are invariant under orthogonal
+  similarity), within n 1e-11 ||A||_2 and 2 n 1e-11 ||A||_2^2, the most that
+  eigenvalues each within the FP64 tolerance can move them; the FP32-MFMA form
+  of the Gaussian n = 16384 input against the FP64 path, within 2e-5 ||A||_2.
+
+The file name sorts after the other GPU tests so that these slower cases run
+last.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import sbr_inputs as si
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def sbr():
+    import paper_1604_03703_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def _solve(sbr, A, b0, precision="fp64"):
+    n = A.shape[0]
+    print("solve n=%d b0=%d %s" % (n, b0, precision), flush=True)
+    plan = sbr.Plan(n, 0, precision)
+    Ad = torch.from_numpy(A).cuda()          # symmetric: row- and column-major agree
+    w = sbr.eigvalsh(Ad, b0=b0, precision=precision, plan=plan, overwrite=True)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    del Ad
+    out = w.cpu().numpy()
+    assert np.all(np.diff(out) >= 0.0), "eigenvalues must come out in ascending order"
+    return out
+
+
+def _report(tag, err, nrm):
+    print("%s: max %.3e rms %.3e (x ||A||_2 = %.4g)" % (tag, err.max() / nrm,
+                                                        math.sqrt(np.mean(err ** 2)) / nrm, nrm), flush=True)
+
+
+@pytest.fixture(scope="module")
+def large_clustered():
+    # n = 32768, 64 clusters of 512 eigenvalues, spread 1e-10
+    return si.workload(si.CFG_LARGE, 1)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32_mfma", 2e-5)])
+def test_n32768_clustered_spectrum(sbr, large_clustered, precision, tol):
+    A, lam = large_clustered
+    w = _solve(sbr, A, 128, precision)
+    nrm = float(np.max(np.abs(lam)))
+    err = np.abs(w - lam)
+    _report("n=32768 clustered %s" % precision, err, nrm)
+    assert err.max() <= tol * nrm
+
+
+def test_n32768_gaussian_invariants(sbr):
+    A, _ = si.workload(si.CFG_LARGE, 0)
+    n = A.shape[0]
+    tr = float(np.trace(A))
+    flat = A.reshape(-1)
+    fro2 = float(np.dot(flat, flat))
+    w = _solve(sbr, A, 128)
+    nrm = float(np.max(np.abs(w)))
+    d_tr = abs(float(w.sum()) - tr)
+    d_fr = abs(float(np.dot(w, w)) - fro2)
+    print("n=32768 gaussian: |sum w - tr A| = %.3e (bound %.3e), |sum w^2 - ||A||_F^2| = %.3e (bound %.3e)"
+          % (d_tr, n * 1e-11 * nrm, d_fr, 2 * n * 1e-11 * nrm * nrm), flush=True)
+    assert d_tr <= n * 1e-11 * nrm
+    assert d_fr <= 2 * n * 1e-11 * nrm * nrm
+
+
+def test_n8192_gaussian_vs_oracle(sbr, oracle_mod):
+    A, _ = si.workload(si.CFG_MEDIUM, 0)
+    ref = oracle_mod.eigvalsh(A)
+    w = _solve(sbr, A, 64)
+    nrm = float(np.max(np.abs(ref)))
+    err = np.abs(w - ref)
+    _report("n=8192 gaussian vs oracle", err, nrm)
+    assert err.max() <= 1e-11 * nrm
+
+
+def test_n8192_geometric_spectrum(sbr):
+    # |lam| from 1 down to 1e-8 with random signs
+    A, lam = si.workload(si.CFG_MEDIUM, 1)
+    w = _solve(sbr, A, 64)
+    nrm = float(np.max(np.abs(lam)))
+    err = np.abs(w - lam)
+    _report("n=8192 geometric", err, nrm)
+    assert err.max() <= 1e-11 * nrm
+
+
+def test_n16384_fp32_form_uniform_spectrum(sbr):
+    A, lam = si.workload(si.CFG_FP32, 1)
+    w = _solve(sbr, A, 0, "fp32_mfma")
+    nrm = float(np.max(np.abs(lam)))
+    err = np.abs(w - lam)
+    _report("n=16384 uniform fp32_mfma", err, nrm)
+    assert err.max() <= 2e-5 * nrm
+
+
+def test_n16384_fp32_form_gaussian_vs_fp64(sbr):
+    A, _ = si.workload(si.CFG_FP32, 0)
+    w64 = _solve(sbr, A, 0, "fp64")
+    w32 = _solve(sbr, A, 0, "fp32_mfma")
+    nrm = float(np.max(np.abs(w64)))
+    err = np.abs(w32 - w64)
+    _report("n=16384 gaussian fp32_mfma vs fp64", err, nrm)
+    assert err.max() <= 2e-5 * nrm
