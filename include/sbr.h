@@ -107,6 +107,7 @@ int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n,
  * Eigenvalues of the symmetric tridiagonal matrix with diagonal d[0..n-1]
  * and off-diagonal e[0..n-2] (device pointers; e may be NULL when n == 1),
  * by Sturm-sequence bisection; w (device, n doubles) ascending.
+ * SBR_ENOTSUP for n >= 2^31 (the Sturm counts are 32-bit).
  */
 int sbr_tridiag_eigvals(int64_t n, const double* d, const double* e,
                         sbr_stream_t stream, double* w);

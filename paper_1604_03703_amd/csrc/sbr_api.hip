@@ -722,6 +722,7 @@ int sbr_tridiag_eigvals(int64_t n, const double* d, const double* e, sbr_stream_
     if (n > 1 && !e) return -3;
     if (n > 0 && !w) return -5;
     if (n == 0) return 0;
+    if (n > INT32_MAX) return SBR_ENOTSUP;   // eigenvalue counts are 32-bit
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he != hipSuccess) return hip_fail(he);

@@ -452,6 +452,7 @@ __device__ __forceinline__ void bisect_lanes(int n, const double* sd, const doub
             cnt[q] = 0;
         }
         if (!__any(anyl)) break;
+#pragma unroll 4
         for (int i = 0; i < n; ++i) {
             const double di = sd[i], ei = se[i];
 #pragma unroll

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __r
                                                     const double* __restrict__ e2p,
                                                     const sbr::BisectSetup* __restrict__ setup,
                                                     double* __restrict__ w) {
-    static_assert(G == 4 || G == 8, "lanes per index");
+    static_assert(G == 4 || G == 8 || G == 16, "lanes per index");
     __shared__ double sd[CH], se[CH];
     const int t = threadIdx.x, g = t % G;
     const int64_t k = (int64_t)blockIdx.x * (NT / G) + t / G;   // 0-based: the (k+1)-th smallest
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __r
         const double x = a + (double)(g + 1) * ((c - a) / (double)(G + 1));
         const bool act = live && (c - a) > 0.0 && (x > a) && (x < c);
         if (!__syncthreads_or(act)) break;
-        int64_t cnt = 0;
+        int cnt = 0;   // n < 2^31 (checked at the entry points)
         double q = 1.0;
         for (int64_t s0 = 0; s0 < n; s0 += CH) {
             const int len = (int)((n - s0 < CH) ? (n - s0) : CH);
@@ -108,6 +108,7 @@ __global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __r
                 se[i] = e2p[s0 + i];
             }
             __syncthreads();
+#pragma unroll 8
             for (int i = 0; i < len; ++i) {
                 q = (sd[i] - x) - se[i] * sbr_recip(q);
                 if (fabs(q) < piv) q = -piv;
@@ -124,9 +125,13 @@ __global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __r
         any += dpp_d<0xB1>(any);
         left += dpp_d<0x4E>(left);
         any += dpp_d<0x4E>(any);
-        if (G == 8) {
+        if (G >= 8) {
             left += dpp_d<0x141>(left);
             any += dpp_d<0x141>(any);
+        }
+        if (G >= 16) {
+            left += dpp_d<0x140>(left);
+            any += dpp_d<0x140>(any);
         }
         if (live) {
             if (any > 0.0) {
