@@ -124,6 +124,26 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(
             }
 }
 
+// sum_{z < splits} p[z * stride], added in slice order (so the result does not
+// depend on how the loads are grouped), the loads eight at a time: a loop that
+// loads one slice and adds it before the next load makes every thread wait for
+// `splits` round trips to memory one after another (up to 128 slices for the
+// b x b products over the whole trailing matrix).
+__device__ __forceinline__ double sum_slices(const double* __restrict__ p, int64_t stride, int splits) {
+    constexpr int G = 8;
+    double s = 0.0;
+    int z = 0;
+    for (; z + G <= splits; z += G) {
+        double v[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) v[u] = p[(int64_t)(z + u) * stride];
+#pragma unroll
+        for (int u = 0; u < G; ++u) s += v[u];
+    }
+    for (; z < splits; ++z) s += p[(int64_t)z * stride];
+    return s;
+}
+
 // out = alpha * sum_s part[s] + beta * Cin (part[s] is M x N with ld M).
 __global__ void reduce_slices_kernel(int64_t M, int64_t N, int splits, const double* __restrict__ part,
                                      double alpha, double beta, const double* Cin, int64_t ldci,
@@ -131,8 +151,7 @@ __global__ void reduce_slices_kernel(int64_t M, int64_t N, int splits, const dou
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= M * N) return;
     const int64_t i = idx % M, j = idx / M;
-    double s = 0.0;
-    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + idx];
+    const double s = sum_slices(part + idx, M * N, splits);
     double v = alpha * s;
     if (beta != 0.0) v += beta * Cin[i + j * ldci];
     Cout[i + j * ldco] = v;
@@ -149,9 +168,7 @@ __global__ __launch_bounds__(128) void tt_reduce_kernel(int b, int splits, const
     const int j = blockIdx.x, t = threadIdx.x;
     const int64_t bb = (int64_t)b * b;
     if (t < b) {
-        double s = 0.0;
-        for (int q = 0; q < splits; ++q) s += part[q * bb + t + (int64_t)j * b];
-        z[t] = s;
+        z[t] = sum_slices(part + t + (int64_t)j * b, bb, splits);
     }
     __syncthreads();
     if (t < b) {
