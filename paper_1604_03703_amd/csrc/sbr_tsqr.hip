@@ -369,7 +369,18 @@ __global__ __launch_bounds__(TreeShape<B>::NT) void tsqr_apply_kernel(TsqrLevelA
     }
     if (t < B) tsh[t] = a.tau[(int64_t)q * B + t];
     if constexpr (L::STAGE) {
-        for (int idx = t; idx < ROWS * B; idx += NT) vst[idx] = reflector_entry<B>(g, idx % ROWS, idx / ROWS);
+        // (ROWS B / NT entries a thread, the loads issued together: a loop
+        // that waits for each load before the next costs that many round trips)
+        static_assert((ROWS * B) % NT == 0, "staging loop");
+        constexpr int PER = ROWS * B / NT;
+        double ent[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = t + u * NT;
+            ent[u] = reflector_entry<B>(g, idx % ROWS, idx / ROWS);
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) vst[t + u * NT] = ent[u];
     }
     __syncthreads();
     apply_all_steps<B, LEAF>(x, g, vst, tsh, t, s);
