@@ -108,21 +108,6 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(
         }
     }
     double* Co = Cout + (int64_t)blockIdx.z * slice_stride;
-    // beta C: all of the thread's elements are loaded before the first store
-    // (one round trip instead of one per element; C may be updated in place,
-    // and each element is still read before it is written)
-    constexpr int NE = E::TN * E::TM * 4;
-    double cv[NE];
-#pragma unroll
-    for (int tn = 0; tn < E::TN; ++tn)
-#pragma unroll
-        for (int tm = 0; tm < E::TM; ++tm)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t i = i0 + E::row_of(wm, tm, lane);
-                const int64_t j = j0 + E::col_of(wn, tn, lane, r);
-                cv[(tn * E::TM + tm) * 4 + r] = (beta != 0.0 && i < M && j < N) ? Cin[i + j * ldci] : 0.0;
-            }
 #pragma unroll
     for (int tn = 0; tn < E::TN; ++tn)
 #pragma unroll
@@ -133,7 +118,7 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_kernel(
                 const int64_t j = j0 + E::col_of(wn, tn, lane, r);
                 if (i < M && j < N) {
                     double v = alpha * (double)eng.acc[tn][tm][r];
-                    if (beta != 0.0) v += beta * cv[(tn * E::TM + tm) * 4 + r];
+                    if (beta != 0.0) v += beta * Cin[i + j * ldci];
                     Co[i + j * ldco] = v;
                 }
             }
