@@ -85,7 +85,8 @@ def test_band_halve(sbr, plan, oracle_mod, b, n_rel):
     assert np.max(np.abs(w - ref)) <= 1e-11 * _norm2(ref)
 
 
-@pytest.mark.parametrize("n,b", [(600, 4), (600, 16), (600, 32), (600, 64), (3000, 16), (3000, 32)])
+@pytest.mark.parametrize("n,b", [(600, 4), (600, 16), (600, 32), (600, 64), (700, 128), (3000, 16), (3000, 32),
+                                 (3000, 64)])
 def test_band_halve_pipelined_equals_sequential(sbr, oracle_mod, n, b):
     # every chase does the same arithmetic on the same data in any schedule
     # that respects the dependencies, so the pipelined grid and a single
