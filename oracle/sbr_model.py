@@ -7,16 +7,24 @@ algorithm for the symmetric eigenvalue problem":
 * ``rect_qr``               -- Algorithm 3.2 (rect-QR): row blocks, QR of each,
                                QR of the stacked R factors, Q_i = W_i Z_i.
 * ``householder_reconstruct`` -- Corollary 3.7: [U1, W1] = LU(Q1 - S),
-                               U = Q W1^{-1}, T from W1 and U1 (signs worked out
-                               in the design doc, reading G3).
+                               U = Q W1^{-1}, T from W1 and U1, with the sign
+                               matrix the corollary leaves out kept explicit:
+                               S_ii = -sign of the current pivot (so no pivot is
+                               below 1 in magnitude), (I - U T U^T)[:, :b] = Q S,
+                               T = -W1 S U1^{-T}, and the band receives S R.
 * ``two_sided_update``       -- Eq. (4.1): Q^T X Q = X + U V^T + V U^T with
                                V = 1/2 U T^T U^T X U T - X U T.
 * ``full_to_band``           -- Algorithm 4.1, right-looking (complete trailing
                                update after every panel, allowed by the
                                implementation notes of Section 5).
 * ``band_to_band``           -- Algorithm 4.2 with k = 2 and the offsets,
-                               loop bounds and exact window extents of the
-                               readings G4-G6 in the design doc.
+                               loop bounds read as follows: chase (i, j) exists
+                               while its QR block's first row is <= n - 2 and
+                               sweep i while i h <= n - 2 (the printed floor
+                               leaves tail sweeps without chases); the update's
+                               column offset for j = 1 is the QR block's first
+                               row; the update spans exactly 2b columns for
+                               j = 1 and 3b - h for j > 1.
 
 It exists to settle those readings on the CPU (exact zeros outside the band,
 eigenvalues preserved) and to describe each chase's touched entries for the

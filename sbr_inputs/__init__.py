@@ -6,11 +6,11 @@ them; it contains none of the eigensolver's own arithmetic (no band
 reduction, no bulge chasing, no Sturm counts).
 
 Every generator takes a ``numpy.random.Generator``; ``make_rng(cfg, inp)``
-returns the canonical one for workload ``cfg`` (0..4, in the order the
-workloads are listed in the design doc) and input variant ``inp`` (0 = first
+returns the canonical one for workload ``cfg`` (0..4: CFG_SMALL, CFG_MEDIUM,
+CFG_LARGE, CFG_FP32, CFG_BATCH below) and input variant ``inp`` (0 = first
 input of that workload, 1 = second).
 
-Recipes ("Input recipe"):
+Recipes:
 
 * ``gaussian_symmetric``  A = (G + G^T)/2, G_ij ~ N(0, 1).
 * ``spectrum_matrix``     A = Q diag(lam) Q^T, Q = H_1 ... H_64 with
@@ -29,7 +29,7 @@ import numpy as np
 
 SEED_PREFIX = (1604, 3703)
 
-# Workload indices (the order the workloads are listed in the design doc).
+# Workload indices.
 CFG_SMALL = 0        # n = 256, b0 = 16
 CFG_MEDIUM = 1       # n = 8192, b0 = 64
 CFG_LARGE = 2        # n = 32768, b0 = 128

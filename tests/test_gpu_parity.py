@@ -1,7 +1,7 @@
 """GPU parity of the stages and of the whole eigensolver against the CPU
 oracle on seeded inputs.
 
-Tolerances (from the accuracy targets of the method):
+Tolerances (the accuracy targets of the method):
 FP64 path  max |lam - lam_oracle| <= 1e-11 ||A||_2,
 FP32-MFMA  max |lam - lam_oracle| <= 2e-5  ||A||_2,
 with ||A||_2 = max |lam_oracle|.  Band structure is checked exactly (entries
