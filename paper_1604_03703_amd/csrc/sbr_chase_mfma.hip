@@ -90,6 +90,23 @@ __device__ __forceinline__ sbr_d4 mma(double a, double b, sbr_d4 c) {
 }
 __device__ __forceinline__ sbr_d4 zero4() { return sbr_d4{0.0, 0.0, 0.0, 0.0}; }
 
+// acc + the chain of N products mma(fa(i), fb(i)), i = 0 .. N-1, in that order,
+// with every operand read before the first product: left to itself the
+// compiler issues each product right after its operand's LDS read and a wait
+// for it.  Only where the registers allow it (two operands per step).
+template <int N, class FA, class FB>
+__device__ __forceinline__ sbr_d4 mma_chain(sbr_d4 acc, const FA& fa, const FB& fb) {
+    double a[N], b[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        a[i] = fa(i);
+        b[i] = fb(i);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc = mma(a[i], b[i], acc);
+    return acc;
+}
+
 // The value of lane q of each aligned group of 8 lanes, in all 8: quad_perm
 // (q%4 x4) fills the quads, row_half_mirror (lane i <-> 7 - i) brings the
 // source quad's value to the other quad.  q must fold to a constant.
@@ -469,12 +486,16 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 #pragma unroll
                 for (int J = 0; J < CT; ++J) P[J] = zero4();
                 if constexpr (CARRY) {
-#pragma unroll 4
-                    for (int k0 = 0; k0 < B; k0 += 4) {
-                        const double bv = xb[k0 / 4];
+                    // every U operand read from LDS before the first product
+                    double ua[B / 4][CT];
 #pragma unroll
-                        for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
-                    }
+                    for (int q = 0; q < B / 4; ++q)
+#pragma unroll
+                        for (int J = 0; J < CT; ++J) ua[q][J] = Us[(4 * q + lk) + (J * 16 + li) * LDU];
+#pragma unroll
+                    for (int q = 0; q < B / 4; ++q)
+#pragma unroll
+                        for (int J = 0; J < CT; ++J) P[J] = mma(ua[q][J], xb[q], P[J]);
                 } else {
                     kloop_plain<B>(
                         [&](int k0) {
@@ -499,11 +520,17 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 for (int X = 0; X < RT; ++X) {
                     if (X * 16 >= nr) break;
                     sbr_d4 acc = zero4();
+                    if constexpr (CARRY) {
+                        acc = mma_chain<CT * 4>(
+                            acc, [&](int i) { return Us[(X * 16 + li) + (4 * i + lk) * LDU]; },
+                            [&](int i) { return WB[i / 4][i % 4]; });
+                    } else {
 #pragma unroll
-                    for (int K = 0; K < CT; ++K)
+                        for (int K = 0; K < CT; ++K)
 #pragma unroll
-                        for (int r4 = 0; r4 < 4; ++r4)
-                            acc = mma(Us[(X * 16 + li) + (K * 16 + 4 * r4 + lk) * LDU], WB[K][r4], acc);
+                            for (int r4 = 0; r4 < 4; ++r4)
+                                acc = mma(Us[(X * 16 + li) + (K * 16 + 4 * r4 + lk) * LDU], WB[K][r4], acc);
+                    }
                     if (CARRY) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) xb[4 * X + r] -= acc[r];
@@ -525,12 +552,16 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 #pragma unroll
                 for (int J = 0; J < CT; ++J) P[J] = zero4();
                 if constexpr (CARRY) {
-#pragma unroll 4
-                    for (int k0 = 0; k0 < B; k0 += 4) {
-                        const double bv = dr[k0 / 4];
+                    // every U operand read from LDS before the first product
+                    double ua[B / 4][CT];
 #pragma unroll
-                        for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
-                    }
+                    for (int q = 0; q < B / 4; ++q)
+#pragma unroll
+                        for (int J = 0; J < CT; ++J) ua[q][J] = Us[(4 * q + lk) + (J * 16 + li) * LDU];
+#pragma unroll
+                    for (int q = 0; q < B / 4; ++q)
+#pragma unroll
+                        for (int J = 0; J < CT; ++J) P[J] = mma(ua[q][J], dr[q], P[J]);
                 } else {
                     kloop_plain<B>(
                         [&](int k0) {
@@ -575,9 +606,15 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
             for (int idx = w; idx < CT * CT; idx += NW) {
                 const int I = idx % CT, J = idx / CT;
                 sbr_d4 acc = zero4();
+                if constexpr (CARRY) {
+                    acc = mma_chain<B / 4>(
+                        acc, [&](int i) { return Wsc[(4 * i + lk) + (J * 16 + li) * B]; },
+                        [&](int i) { return Us[(4 * i + lk) + (I * 16 + li) * LDU]; });
+                } else {
 #pragma unroll 8
-                for (int k0 = 0; k0 < B; k0 += 4)
-                    acc = mma(Wsc[(k0 + lk) + (J * 16 + li) * B], Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
+                    for (int k0 = 0; k0 < B; k0 += 4)
+                        acc = mma(Wsc[(k0 + lk) + (J * 16 + li) * B], Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
+                }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) Rs[(I * 16 + li) + (J * 16 + 4 * r + lk) * LDH] = acc[r];
             }
@@ -611,15 +648,12 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 #pragma unroll
                 for (int X = 0; X < RT; ++X) {
                     if (X > w || X * 16 >= nr) break;
-                    sbr_d4 acc = zero4();
-#pragma unroll
-                    for (int K = 0; K < CT; ++K)
-#pragma unroll
-                        for (int r4 = 0; r4 < 4; ++r4)
-                            acc = mma(Us[(X * 16 + li) + (K * 16 + 4 * r4 + lk) * LDU], V[K][r4], acc);
-#pragma unroll
-                    for (int k0 = 0; k0 < HP; k0 += 4)
-                        acc = mma(Vs[(X * 16 + li) + (k0 + lk) * B], Us[row + (k0 + lk) * LDU], acc);
+                    sbr_d4 acc = mma_chain<CT * 4>(
+                        zero4(), [&](int i) { return Us[(X * 16 + li) + (4 * i + lk) * LDU]; },
+                        [&](int i) { return V[i / 4][i % 4]; });
+                    acc = mma_chain<HP / 4>(
+                        acc, [&](int i) { return Vs[(X * 16 + li) + (4 * i + lk) * B]; },
+                        [&](int i) { return Us[row + (4 * i + lk) * LDU]; });
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int col = X * 16 + 4 * r + lk;
