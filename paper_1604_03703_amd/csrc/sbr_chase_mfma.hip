@@ -368,9 +368,15 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                     while (rem >= CT - I) { rem -= CT - I; ++I; }
                     const int J = I + rem;
                     sbr_d4 acc = zero4();
+                    if constexpr (CARRY) {
+                        acc = mma_chain<B / 4>(
+                            acc, [&](int i) { return Us[(4 * i + lk) + (J * 16 + li) * LDU]; },
+                            [&](int i) { return Us[(4 * i + lk) + (I * 16 + li) * LDU]; });
+                    } else {
 #pragma unroll 8
-                    for (int k0 = 0; k0 < B; k0 += 4)
-                        acc = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
+                        for (int k0 = 0; k0 < B; k0 += 4)
+                            acc = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
+                    }
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int gi = I * 16 + li, gj = J * 16 + 4 * r + lk;
@@ -434,13 +440,13 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                     const bool colv = J * 16 + li < H;
                     sbr_d4 acc = zero4();
                     if constexpr (CARRY) {
-#pragma unroll 4
-                        for (int k0 = 0; k0 < B; k0 += 4) {
-                            const int row = k0 + lk;
-                            double av = 0.0;
-                            if (row < nr && colv) av = Xs[row + (H + J * 16 + li) * LDX];
-                            acc = mma(av, Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
-                        }
+                        acc = mma_chain<B / 4>(
+                            acc,
+                            [&](int i) {
+                                const int row = 4 * i + lk;
+                                return (row < nr && colv) ? Xs[row + (H + J * 16 + li) * LDX] : 0.0;
+                            },
+                            [&](int i) { return Us[(4 * i + lk) + (I * 16 + li) * LDU]; });
                     } else {
                         kloop_pipelined<B, 4>(
                             [&](int k0) {
@@ -457,11 +463,17 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 #pragma unroll
                     for (int J = 0; J < CT; ++J) {
                         sbr_d4 acc = zero4();
+                        if constexpr (CARRY) {
+                            acc = mma_chain<CT * 4>(
+                                acc, [&](int i) { return Rs[(4 * i + lk) + (J * 16 + li) * LDH]; },
+                                [&](int i) { return Z[i / 4][i % 4]; });
+                        } else {
 #pragma unroll
-                        for (int K = 0; K < CT; ++K)
+                            for (int K = 0; K < CT; ++K)
 #pragma unroll
-                            for (int r4 = 0; r4 < 4; ++r4)
-                                acc = mma(Rs[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], Z[K][r4], acc);
+                                for (int r4 = 0; r4 < 4; ++r4)
+                                    acc = mma(Rs[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], Z[K][r4], acc);
+                        }
                         const int row = w * 16 + li;
                         if (row < nr) {
 #pragma unroll
@@ -625,11 +637,17 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 #pragma unroll
             for (int J = 0; J < CT; ++J) {
                 sbr_d4 acc = zero4();
+                if constexpr (CARRY) {
+                    acc = mma_chain<CT * 4>(
+                        acc, [&](int i) { return Rs[(4 * i + lk) + (J * 16 + li) * LDH]; },
+                        [&](int i) { return Z[i / 4][i % 4]; });
+                } else {
 #pragma unroll
-                for (int K = 0; K < CT; ++K)
+                    for (int K = 0; K < CT; ++K)
 #pragma unroll
-                    for (int r4 = 0; r4 < 4; ++r4)
-                        acc = mma(Rs[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], Z[K][r4], acc);
+                        for (int r4 = 0; r4 < 4; ++r4)
+                            acc = mma(Rs[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], Z[K][r4], acc);
+                }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) V[J][r] = 0.5 * acc[r] - WR[J][r];
             }
