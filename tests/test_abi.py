@@ -54,6 +54,18 @@ def test_invalid_arguments_rejected_on_host(sbr):
     assert lib.sbr_band_halve(null, 10, dummy, 3, 2, 0, null) == -1
 
 
+def test_unsupported_sizes_rejected_on_host(sbr):
+    # SBR_ENOTSUP (3), returned before any device call
+    lib = sbr.lib()
+    null = ctypes.c_void_p(0)
+    dummy = ctypes.c_void_p(16)
+    # the Sturm counts of the bisection are 32-bit
+    assert lib.sbr_tridiag_eigvals(2 ** 31, dummy, dummy, null, dummy) == 3
+    assert lib.sbr_tridiag_eigvals(0, null, null, null, null) == 0
+    # the symmetric product addresses 128 columns of A with 32-bit byte offsets
+    assert lib.sbr_symm_lower(10, 4, dummy, 1 << 21, dummy, 10, dummy, 10, 0, null) == 3
+
+
 def test_workspace_size_and_default_band(sbr):
     lib = sbr.lib()
     sz = ctypes.c_size_t()
