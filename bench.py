@@ -120,7 +120,7 @@ def run_form(sbr, torch, A0, n, b0, precision, steps, warmup, plan):
             ["%.1f" % x for x in tm["ms_stage"]]))
         st = plan.status()
         if st != 0:
-            raise RuntimeError("band-to-band pipeline reported a stalled wait (stage b=%d)" % st)
+            raise RuntimeError("the plan reported status bits %d (1: a band stage stalled, 2: non-finite)" % st)
         if it >= warmup:
             times.append(t1 - t0)
             tims.append(tm)
@@ -140,7 +140,10 @@ def run_batch(sbr, torch, si, count, steps, warmup):
     dev = [torch.empty_like(d) for d in dev0]
     ws = [torch.empty(d.shape[0], dtype=torch.float64, device=d.device) for d in dev0]
     out = {"count": count, "n_range": [int(min(M.shape[0] for M in mats)), int(max(M.shape[0] for M in mats))]}
-    for prec in ("fp64", "fp32_mfma"):
+    # the batched kernels compute in FP64 whatever the precision argument says,
+    # so there is one batched form to time
+    out["fp32_mfma"] = "not measured: the batched kernels compute in FP64"
+    for prec in ("fp64",):
         plan = sbr.Plan(512, count, prec)
         times = []
         for it in range(max(1, warmup) + steps):
@@ -181,6 +184,37 @@ def run_batch(sbr, torch, si, count, steps, warmup):
 
 def mean(xs):
     return sum(xs) / max(1, len(xs))
+
+
+def golden_eigenvalues(A_host, n):
+    """The oracle's eigenvalues of this exact input, stored by
+    tests/golden/make_oracle_golden.py (None when there is no file for n or
+    the matrix bytes differ from the ones the values were computed on)."""
+    import hashlib
+    import numpy as np
+    gdir = os.path.join(ROOT, "tests", "golden")
+    try:
+        meta = json.load(open(os.path.join(gdir, "oracle_golden.json")))
+    except OSError:
+        return None
+    rec = meta.get("n%d" % n)
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    rows = max(1, (1 << 24) // n)
+    for r0 in range(0, n, rows):
+        h.update(np.ascontiguousarray(A_host[r0:r0 + rows]).tobytes())
+    if h.hexdigest() != rec["matrix_sha256"]:
+        log("golden eigenvalues are for another matrix (hash differs): not used")
+        return None
+    return np.load(os.path.join(gdir, rec["file"]))
+
+
+def err_vs(w, ref):
+    import numpy as np
+    d = np.abs(w - ref)
+    nrm = float(np.max(np.abs(ref)))
+    return {"max_rel": float(d.max() / nrm), "rms_rel": float(math.sqrt(float(np.mean(d * d))) / nrm)}
 
 
 def cpu_baseline(A_host, n_sample: int):
@@ -294,8 +328,10 @@ def main():
     b = b0
     for sms in stage_ms:
         by = band_stage_bytes(n, b)
+        gbps = by / (sms * 1e-3) / 1e9 if sms > 0 else None
         stages.append({"b": b, "ms": round(sms, 3), "alg_GB": round(by / 1e9, 3),
-                       "GBps": round(by / (sms * 1e-3) / 1e9, 1) if sms > 0 else None})
+                       "GBps": round(gbps, 1) if gbps else None,
+                       "frac_hbm": round(gbps / PEAK_HBM, 4) if gbps else None})
         b //= 2
     band_bytes = sum(band_stage_bytes(n, 2 ** k) for k in range(1, int(math.log2(b0)) + 1))
 
@@ -325,10 +361,19 @@ def main():
         "band_stages": stages,
         "band_GBps_alg": round(band_bytes / (band_ms * 1e-3) / 1e9, 1) if band_ms > 0 else None,
         "checks": {"trace_rel": tr_err, "frobenius_rel": fr_err},
+        "band_frac_hbm": round(band_bytes / (band_ms * 1e-3) / 1e9 / PEAK_HBM, 4) if band_ms > 0 else None,
         "roofline": {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA, 4),
                      "traffic": traffic, "launches": klaunch, "avg_launch_ms": round(kms / max(1, klaunch), 4)},
     }
+
+    golden = golden_eigenvalues(A_host, n)
+    if golden is not None:
+        result["checks"]["fp64_vs_oracle"] = err_vs(wh, golden)
+    # the FP64 plan's streams (side + CU-masked) go before the FP32 plan
+    # creates its own: the process has four hardware queues
+    plan.close()
+    del plan
 
     if not args.no_fp32:
         plan32 = sbr.Plan(n, 0, "fp32_mfma")
@@ -344,7 +389,12 @@ def main():
             "err_vs_fp64_max_rel": float(d.max() / norm2),
             "err_vs_fp64_rms_rel": float(math.sqrt(float(np.mean(d * d))) / norm2),
             "speedup_f2b": round(f2b_ms / f2b32, 3) if f2b32 > 0 else None,
+            "speedup_solve": round(mean(times) / mean(t32), 3),
+            "speedup_band": round(band_ms / mean([t["ms_band"] for t in tim32]), 3),
         }
+        if golden is not None:
+            result["fp32_mfma"]["err_vs_oracle"] = err_vs(w32.cpu().numpy(), golden)
+        plan32.close()
         del plan32
 
     if not args.no_batch:

@@ -45,16 +45,30 @@ typedef enum {
                             FP64 storage with FP32 products if it cannot be
                             allocated); each panel's column block returns to
                             FP64 before its QR, so the panel QR, Householder
-                            norms, R factor, band stages and Sturm counts
-                            stay FP64 */
+                            norms, R factor and Sturm counts stay FP64.  The
+                            band stages and the batched kernels compute in
+                            FP64 in both forms. */
 } sbr_precision;
 
 enum {
     SBR_OK = 0,
     SBR_ENOMEM = 1,      /* device workspace could not be allocated */
     SBR_EHIP = 2,        /* a HIP runtime call failed */
-    SBR_ENOTSUP = 3,     /* valid but unsupported parameter combination */
-    SBR_ENONFINITE = 4   /* reserved: non-finite input detected */
+    SBR_ENOTSUP = 3      /* valid but unsupported parameter combination */
+};
+
+/*
+ * Conditions found on the device while a call runs.  Calls return before the
+ * device has done the work, so these are not return codes: they are bits of
+ * the plan's status word, read (and cleared) by sbr_plan_status in
+ * sbr_stages.h, and every eigenvalue of the affected call is NaN.
+ */
+enum {
+    SBR_STATUS_STALLED = 1,    /* a pipelined band stage stopped waiting for
+                                  the previous sweep and was abandoned */
+    SBR_STATUS_NONFINITE = 2   /* the tridiagonal reached by the reductions
+                                  holds a NaN or an infinity (non-finite
+                                  input) */
 };
 
 /*
@@ -75,7 +89,10 @@ enum {
 int sbr_syev_eigvals(int64_t n, double* A, int64_t lda, int32_t b0,
                      sbr_stream_t stream, double* w);
 
-/* As sbr_syev_eigvals, with an explicit plan and precision form. */
+/* As sbr_syev_eigvals, with an explicit plan and precision form.  Once the
+ * plan holds workspace for (n, b0, prec) the call allocates nothing and does
+ * not wait for the device, so it can be captured in a HIP graph; a plan is
+ * not safe for calls that overlap (on two streams or two threads). */
 int sbr_syev_eigvals_ex(sbr_plan_t plan, int64_t n, double* A, int64_t lda,
                         int32_t b0, sbr_precision prec, sbr_stream_t stream,
                         double* w);
@@ -96,7 +113,8 @@ int sbr_syev_eigvals_ex(sbr_plan_t plan, int64_t n, double* A, int64_t lda,
  * host then waits for the previous upload).  Larger matrices, or b0 >= 32,
  * go through sbr_syev_eigvals_ex one after another on the same stream.  The
  * per-matrix band buffers grow on demand (allocation on the first call of a
- * larger batch).  The FP32-MFMA form of the batched kernels computes in FP64.
+ * larger batch).  The batched kernels compute in FP64 whatever prec says;
+ * prec applies to the matrices that go through sbr_syev_eigvals_ex.
  */
 int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n,
                              double* const* A, const int64_t* lda, int32_t b0,
@@ -106,8 +124,9 @@ int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n,
 /*
  * Eigenvalues of the symmetric tridiagonal matrix with diagonal d[0..n-1]
  * and off-diagonal e[0..n-2] (device pointers; e may be NULL when n == 1),
- * by Sturm-sequence bisection; w (device, n doubles) ascending.
- * SBR_ENOTSUP for n >= 2^31 (the Sturm counts are 32-bit).
+ * by Sturm-sequence bisection; w (device, n doubles) ascending, every entry
+ * NaN if d or e holds a NaN or an infinity.  SBR_ENOTSUP for n >= 2^31 (the
+ * Sturm counts are 32-bit).
  */
 int sbr_tridiag_eigvals(int64_t n, const double* d, const double* e,
                         sbr_stream_t stream, double* w);

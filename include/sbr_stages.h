@@ -37,10 +37,13 @@ int sbr_dense_to_band(int64_t n, const double* A, int64_t lda, int32_t b,
 /*
  * One band-to-band halving (Algorithm 4.2 with k = 2): the symmetric band
  * matrix of bandwidth b held in `band` (lower band storage as above, with
- * ldband >= 2b + 1 because the chase fills up to distance 2b - 1) is reduced
- * in place to bandwidth b/2.  On return the entries at distance > b/2 are
- * exactly zero.  b: power of two, 2 <= b <= 128.  `prec` selects FP64 or the
- * FP32 WY form for b >= 16.
+ * ldband >= 2b + 1 because the chase fills up to distance 2b - 1; the rows
+ * at distances b+1 .. 2b must hold zeros on entry, as sbr_dense_to_band
+ * leaves them) is reduced in place to bandwidth b/2.  On return the entries
+ * at distance > b/2 are exactly zero.  b: power of two, 2 <= b <= 128.
+ * The chases run in FP64 in both precision forms.  For b <= 8 with
+ * ldband != 2b + 1 the band goes through the plan's band buffer (two
+ * copies).  SBR_ENOTSUP for n >= 2^31.
  */
 int sbr_band_halve(sbr_plan_t plan, int64_t n, double* band, int64_t ldband,
                    int32_t b, sbr_precision prec, sbr_stream_t stream);
@@ -106,11 +109,26 @@ typedef struct {
  * microseconds); ms_symm and symm_launches are then 0. */
 int sbr_plan_set_timing(sbr_plan_t plan, int enable);
 
-/* Cap on the number of work-groups of the pipelined band-to-band kernel
- * (0 = automatic).  With 1 the chases run one at a time in the sequential
- * (sweep-major) order of Algorithm 4.2; the pipelined result is bitwise the
- * same because every chase does the same arithmetic on the same data. */
+/* Cap on the number of work-groups of the pipelined band-to-band kernels
+ * (0 = automatic).  With 1, a halving b >= 16 runs its chases one at a time
+ * in the sequential (sweep-major) order of Algorithm 4.2, and a halving
+ * b <= 8 runs its groups of consecutive sweeps one after another (inside a
+ * group the sweeps still advance in lock step, a fixed lag apart).  The
+ * result is bitwise the same at any cap: every chase does the same
+ * arithmetic on the same data. */
 int sbr_plan_set_chase_blocks(sbr_plan_t plan, int32_t max_blocks);
+
+/* Bandwidths b <= this value (at most 16) are halved by the sweep-group
+ * kernel (bulges in registers, live band in LDS), wider ones by the MFMA
+ * chase kernel (default 8). */
+int sbr_plan_set_group_max_band(sbr_plan_t plan, int32_t b);
+
+/* How long (ticks of the 100 MHz device clock) a pipelined band kernel waits
+ * for the previous sweep before it abandons the stage and raises
+ * SBR_STATUS_STALLED (0 = the default, 10^9 ticks = 10 s).  The schedule
+ * always makes progress, so the limit only bounds a kernel's lifetime; a
+ * tiny limit forces the abandon path from the host (for tests). */
+int sbr_plan_set_wait_limit(sbr_plan_t plan, int64_t ticks);
 
 /* CUs kept free of the bulk trailing-update launches of the full-to-band
  * stage (default 32; 0 = none).  The next panel is factored concurrently on
@@ -123,9 +141,11 @@ int sbr_plan_set_chase_blocks(sbr_plan_t plan, int32_t max_blocks);
  * CU-masked streams are unavailable the setting has no effect. */
 int sbr_plan_set_panel_cus(sbr_plan_t plan, int32_t cus);
 
-/* Blocking: copies the plan's device status word.  Nonzero means a pipelined
- * band-to-band kernel stopped waiting for the previous sweep (after 10 s)
- * and abandoned the stage; results of that call are then invalid. */
+/* Blocking (waits for the device): the SBR_STATUS_* bits raised by the calls
+ * made through the plan since the previous sbr_plan_status, then clears
+ * them.  Every call starts with a clear live word, so a stage abandoned by
+ * one call does not affect the next; the eigenvalues of a call that raised
+ * a bit are NaN. */
 int sbr_plan_status(sbr_plan_t plan, int32_t* status);
 int sbr_plan_get_timing(sbr_plan_t plan, sbr_timing* out);
 

@@ -73,6 +73,8 @@ def _load():
         "sbr_plan_set_chase_blocks": ([_vp, _i32], ctypes.c_int),
         "sbr_plan_set_panel_cus": ([_vp, _i32], ctypes.c_int),
         "sbr_plan_status": ([_vp, ctypes.POINTER(_i32)], ctypes.c_int),
+        "sbr_plan_set_wait_limit": ([_vp, _i64], ctypes.c_int),
+        "sbr_plan_set_group_max_band": ([_vp, _i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -88,7 +90,11 @@ EXPORTED = (
     "sbr_last_hip_error", "sbr_full_to_band", "sbr_dense_to_band", "sbr_band_halve", "sbr_panel_qr",
     "sbr_gemm", "sbr_syr2k_lower", "sbr_symm_lower", "sbr_plan_set_timing", "sbr_plan_get_timing",
     "sbr_plan_set_chase_blocks", "sbr_plan_set_panel_cus", "sbr_plan_status",
+    "sbr_plan_set_wait_limit", "sbr_plan_set_group_max_band",
 )
+
+STATUS_STALLED = 1      # SBR_STATUS_STALLED
+STATUS_NONFINITE = 2    # SBR_STATUS_NONFINITE
 
 
 def lib():
@@ -156,7 +162,14 @@ class Plan:
     def set_panel_cus(self, cus: int):
         _check(_lib.sbr_plan_set_panel_cus(self._h, int(cus)), "sbr_plan_set_panel_cus")
 
+    def set_group_max_band(self, b: int):
+        _check(_lib.sbr_plan_set_group_max_band(self._h, int(b)), "sbr_plan_set_group_max_band")
+
+    def set_wait_limit(self, ticks: int):
+        _check(_lib.sbr_plan_set_wait_limit(self._h, int(ticks)), "sbr_plan_set_wait_limit")
+
     def status(self) -> int:
+        """SBR_STATUS_* bits raised since the previous query (waits for the device, then clears)."""
         v = _i32()
         _check(_lib.sbr_plan_status(self._h, ctypes.byref(v)), "sbr_plan_status")
         return int(v.value)
@@ -173,22 +186,40 @@ class Plan:
             pass
 
 
+def _leading_dim(A: torch.Tensor) -> int:
+    """Leading dimension of the column-major matrix behind A, or 0 when A's
+    layout is not one: rows of A (= columns of the column-major matrix, A
+    being symmetric) must be contiguous and at least n apart."""
+    n = A.shape[0]
+    if n <= 1:
+        return max(n, 1)
+    if A.stride(1) == 1 and A.stride(0) >= n:
+        return int(A.stride(0))
+    return 0
+
+
 def eigvalsh(A: torch.Tensor, b0: int = 0, precision="fp64", plan: Plan | None = None,
-             overwrite: bool = False, stream=None) -> torch.Tensor:
-    """Ascending eigenvalues of the symmetric CUDA float64 matrix ``A``."""
+             overwrite: bool = False, stream=None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Ascending eigenvalues of the symmetric CUDA float64 matrix ``A``.
+
+    With ``overwrite`` the solver works in A's own storage when its rows are
+    contiguous (a view of a wider buffer passes that buffer's row stride as the
+    leading dimension); otherwise on a contiguous copy."""
     n = A.shape[0]
     if A.dim() != 2 or A.shape[1] != n:
         raise ValueError("A must be square")
-    work = A if (overwrite and A.is_contiguous()) else A.contiguous().clone()
-    w = torch.empty(n, dtype=torch.float64, device=A.device)
+    lda = _leading_dim(A) if overwrite else 0
+    work = A if lda else A.contiguous().clone()
+    lda = lda or max(n, 1)
+    w = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
     if plan is None and _prec(precision) == FP64:
-        rc = _lib.sbr_syev_eigvals(n, _dev_f64(work, "A"), max(n, 1), int(b0), _stream(stream),
+        rc = _lib.sbr_syev_eigvals(n, _dev_f64(work, "A"), lda, int(b0), _stream(stream),
                                    _dev_f64(w, "w"))
         _check(rc, "sbr_syev_eigvals")
     else:
         if plan is None:
             plan = Plan(n, 0, precision)
-        rc = _lib.sbr_syev_eigvals_ex(plan.handle, n, _dev_f64(work, "A"), max(n, 1), int(b0),
+        rc = _lib.sbr_syev_eigvals_ex(plan.handle, n, _dev_f64(work, "A"), lda, int(b0),
                                       _prec(precision), _stream(stream), _dev_f64(w, "w"))
         _check(rc, "sbr_syev_eigvals_ex")
     return w
@@ -201,8 +232,13 @@ def eigvalsh_batched(mats, b0: int = 0, precision="fp64", plan: Plan | None = No
     into; with the same matrices and outputs a plan replays its captured
     launch instead of rebuilding it."""
     k = len(mats)
+    for m in mats:
+        if m.dim() != 2 or m.shape[0] != m.shape[1]:
+            raise ValueError("every matrix must be square")
+        if not _leading_dim(m):
+            raise ValueError("every matrix needs contiguous rows at least n apart (it is solved in place)")
     ns = (_i64 * k)(*[int(m.shape[0]) for m in mats])
-    ldas = (_i64 * k)(*[int(m.shape[0]) for m in mats])
+    ldas = (_i64 * k)(*[_leading_dim(m) for m in mats])
     if out is None:
         ws = [torch.empty(int(m.shape[0]), dtype=torch.float64, device=m.device) for m in mats]
     else:

@@ -86,8 +86,12 @@ struct sbr_plan_s {
     double *bandA = nullptr, *bandB = nullptr;
     double* chase_scratch = nullptr;
     int* flags = nullptr;
-    int* status = nullptr;     // device word: nonzero if a pipelined kernel gave up waiting
+    // device words: status[0] the flags (SBR_STATUS_*) raised by the call in
+    // flight, status[1] those of earlier calls not yet read by sbr_plan_status
+    int* status = nullptr;
     int chase_max_grid = 0;
+    uint64_t wait_ticks = DEFAULT_WAIT_TICKS;
+    int group_max_b = DEFAULT_GROUP_MAX_B;
     double *d = nullptr, *e = nullptr, *e2p = nullptr;
     BisectSetup* setup = nullptr;
     double* pcopy = nullptr;   // panel copy for sbr_panel_qr
@@ -164,10 +168,9 @@ Layout make_layout(int64_t n, int b) {
     L.off_tsqr = take(cur, (size_t)tsqr_workspace_doubles(n > b ? n - b : b, b) * D);
     L.off_bandA = take(cur, (size_t)n * (2 * b + 1) * D);
     L.off_bandB = take(cur, (size_t)n * (b + 1) * D);
-    int grid = 0;
-    L.off_chase = take(cur, (size_t)chase_workspace_doubles(n, b, &grid) * D);
+    L.off_chase = take(cur, (size_t)chase_workspace_doubles(n, b) * D);
     L.off_flags = take(cur, (size_t)(n + 4) * sizeof(int));
-    L.off_status = take(cur, sizeof(int));
+    L.off_status = take(cur, 2 * sizeof(int));
     L.off_d = take(cur, (size_t)n * D);
     L.off_e = take(cur, (size_t)n * D);
     L.off_e2p = take(cur, (size_t)n * D);
@@ -219,7 +222,7 @@ int ensure_workspace(sbr_plan_t p, int64_t n, int b) {
     p->flags = (int*)(base + L.off_flags);
     p->status = (int*)(base + L.off_status);
     {
-        hipError_t ez = hipMemset(p->status, 0, sizeof(int));
+        hipError_t ez = hipMemset(p->status, 0, 2 * sizeof(int));
         if (ez != hipSuccess) return hip_fail(ez);
     }
     p->d = (double*)(base + L.off_d);
@@ -452,8 +455,19 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
     return 0;
 }
 
+StageCtl stage_ctl(sbr_plan_t p) {
+    StageCtl c;
+    c.flags = p->flags;
+    c.status = p->status;
+    c.wait_ticks = p->wait_ticks;
+    c.max_grid = p->chase_max_grid;
+    c.group_max_b = p->group_max_b;
+    return c;
+}
+
 // Band halvings from b0 to 1 starting from the lower band of the dense A.
 int run_band_stages(sbr_plan_t p, int64_t n, const double* A, int64_t lda, int b0, bool f32, hipStream_t s) {
+    const StageCtl ctl = stage_ctl(p);
     double* cur = p->bandA;
     int64_t ld = 2 * b0 + 1;
     launch_dense_to_band(n, A, lda, b0, cur, ld, s);
@@ -461,7 +475,7 @@ int run_band_stages(sbr_plan_t p, int64_t n, const double* A, int64_t lda, int b
     while (b > 1) {
         EventPair ep;
         if (p->timing) { ep.a = p->ev(); p->mark(ep.a, s); }
-        launch_band_halve(n, cur, ld, b, f32, p->chase_scratch, p->flags, p->status, p->chase_max_grid, s);
+        launch_band_halve(n, cur, ld, b, f32, p->chase_scratch, ctl, s);
         if (p->timing) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_stage.push_back(ep); }
         const int h = b / 2;
         double* nxt = (cur == p->bandA) ? p->bandB : p->bandA;
@@ -482,7 +496,6 @@ std::map<int, sbr_plan_t> g_plans;
 
 int init_attributes() {
     int rc = init_tsqr_attributes();
-    rc |= init_band_attributes();
     rc |= init_band_group_attributes();
     rc |= init_band_mfma_attributes();
     rc |= init_batched_attributes();
@@ -591,10 +604,28 @@ int sbr_plan_status(sbr_plan_t plan, int32_t* status) {
     if (!status) return -2;
     *status = 0;
     if (!plan->status) return 0;
-    int v = 0;
-    hipError_t e = hipMemcpy(&v, plan->status, sizeof(int), hipMemcpyDeviceToHost);
+    int v[2] = {0, 0};
+    hipError_t e = hipSetDevice(plan->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(v, plan->status, sizeof(v), hipMemcpyDeviceToHost);
+    const int zero[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpy(plan->status, zero, sizeof(zero), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e);
-    *status = v;
+    *status = v[0] | v[1];
+    return 0;
+}
+
+int sbr_plan_set_wait_limit(sbr_plan_t plan, int64_t ticks) {
+    if (!plan) return -1;
+    if (ticks < 0) return -2;
+    plan->wait_ticks = ticks == 0 ? DEFAULT_WAIT_TICKS : (uint64_t)ticks;
+    return 0;
+}
+
+int sbr_plan_set_group_max_band(sbr_plan_t plan, int32_t b) {
+    if (!plan) return -1;
+    if (b < 0) return -2;
+    plan->group_max_b = b;
     return 0;
 }
 
@@ -655,6 +686,7 @@ int sbr_syev_eigvals_ex(sbr_plan_t plan, int64_t n, double* A, int64_t lda, int3
     int rc = ensure_workspace(plan, n, std::max(b0, 2));
     if (rc) return rc;
     const bool f32 = (prec == SBR_FP32_MFMA);
+    launch_status_rearm(plan->status, s);
     if (plan->timing) {
         plan->reset_timing();
         plan->ev_total.a = plan->ev();
@@ -680,7 +712,7 @@ int sbr_syev_eigvals_ex(sbr_plan_t plan, int64_t n, double* A, int64_t lda, int3
         plan->ev_bis.a = plan->ev();
         plan->mark(plan->ev_bis.a, s);
     }
-    launch_tridiag_eigvals(n, plan->d, plan->e, plan->e2p, plan->setup, w, s);
+    launch_tridiag_eigvals(n, plan->d, plan->e, plan->e2p, plan->setup, w, plan->status, s);
     SBR_CHECK_LAUNCH();
     if (plan->timing) {
         plan->ev_bis.b = plan->ev();
@@ -738,7 +770,7 @@ int sbr_tridiag_eigvals(int64_t n, const double* d, const double* e, sbr_stream_
     }
     const int rc = ensure_workspace(p, n, 2);
     if (rc) return rc;
-    launch_tridiag_eigvals(n, d, e, p->e2p, p->setup, w, (hipStream_t)stream);
+    launch_tridiag_eigvals(n, d, e, p->e2p, p->setup, w, nullptr, (hipStream_t)stream);
     SBR_CHECK_LAUNCH();
     return 0;
 }
@@ -912,10 +944,24 @@ int sbr_band_halve(sbr_plan_t plan, int64_t n, double* band, int64_t ldband, int
     if (check_band(b)) return -5;
     if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -6;
     if (n < 3) return 0;
+    if (n > INT32_MAX) return SBR_ENOTSUP;
     int rc = ensure_workspace(plan, n, b);
     if (rc) return rc;
-    launch_band_halve(n, band, ldband, b, prec == SBR_FP32_MFMA, plan->chase_scratch, plan->flags,
-                      plan->status, plan->chase_max_grid, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    const bool f32 = prec == SBR_FP32_MFMA;
+    const int64_t ld2 = 2 * (int64_t)b + 1;
+    launch_status_rearm(plan->status, s);
+    if (band_halve_supported(n, ldband, b)) {
+        launch_band_halve(n, band, ldband, b, f32, plan->chase_scratch, stage_ctl(plan), s);
+    } else if (band_halve_supported(n, ld2, b)) {
+        // a layout the kernel does not take: through the plan's band buffer
+        // (ld = 2b + 1) and back, with zeros in the rows beyond it
+        launch_band_copy(n, band, ldband, b, plan->bandA, ld2, s);
+        launch_band_halve(n, plan->bandA, ld2, b, f32, plan->chase_scratch, stage_ctl(plan), s);
+        launch_band_copy(n, plan->bandA, ld2, (int)(2 * b), band, ldband, s);
+    } else {
+        return SBR_ENOTSUP;
+    }
     SBR_CHECK_LAUNCH();
     return 0;
 }

@@ -75,10 +75,9 @@ struct GroupArgs {
     int ngroups;
     int* ticket;
     int* done;         // ngroups watermarks
-    int* error;
+    int* error;        // the plan's status word: nonzero stops every block
+    uint64_t wait_ticks;   // a wait gives up after this many ticks of the 100 MHz clock
 };
-
-constexpr uint64_t GROUP_WAIT_LIMIT = 1000000000ull;   // 10 s of the 100 MHz clock
 
 template <int H>
 __device__ __forceinline__ int nchase_of(int n, int i) {
@@ -207,8 +206,8 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                                         abort_sh = 1;
                                         break;
                                     }
-                                    if (wall_clock64() - t0 > GROUP_WAIT_LIMIT) {
-                                        atomicExch(a.error, 2 * H);
+                                    if (wall_clock64() - t0 > a.wait_ticks) {
+                                        atomicOr(a.error, sbr::STATUS_STALLED);
                                         abort_sh = 1;
                                         break;
                                     }
@@ -368,8 +367,8 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                                    (int)n) {
                                 __builtin_amdgcn_s_sleep(2);
                                 if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-                                if (wall_clock64() - t0 > GROUP_WAIT_LIMIT) {
-                                    atomicExch(a.error, 2 * H);
+                                if (wall_clock64() - t0 > a.wait_ticks) {
+                                    atomicOr(a.error, sbr::STATUS_STALLED);
                                     break;
                                 }
                             }
@@ -384,7 +383,7 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
 }
 
 template <int H>
-void launch_group(int64_t n, double* band, int* flags, int* error, int max_grid, hipStream_t s) {
+void launch_group(int64_t n, double* band, const sbr::StageCtl& ctl, hipStream_t s) {
     typedef GroupCfg<H> C;
     const int64_t nsweeps = (n - 2) / H;
     if (nsweeps < 1) return;
@@ -394,12 +393,13 @@ void launch_group(int64_t n, double* band, int* flags, int* error, int max_grid,
     a.band = band;
     a.nsweeps = (int)nsweeps;
     a.ngroups = (int)ngroups;
-    a.ticket = flags;
-    a.done = flags + 1;
-    a.error = error;
-    sbr::launch_fill_int(flags, ngroups + 1, 0, s);
+    a.ticket = ctl.flags;
+    a.done = ctl.flags + 1;
+    a.error = ctl.status;
+    a.wait_ticks = ctl.wait_ticks;
+    sbr::launch_fill_int(ctl.flags, ngroups + 1, 0, s);
     int64_t grid = ngroups < (C::LANE ? 1024 : 256) ? ngroups : (C::LANE ? 1024 : 256);
-    if (max_grid > 0 && grid > max_grid) grid = max_grid;
+    if (ctl.max_grid > 0 && grid > ctl.max_grid) grid = ctl.max_grid;
     const size_t shm = (size_t)C::LDS_DOUBLES * sizeof(double);
     band_group_kernel<H><<<(unsigned)grid, C::NT, shm, s>>>(a);
 }
@@ -418,14 +418,12 @@ namespace sbr {
 
 bool band_group_supported(int b) { return b == 2 || b == 4 || b == 8 || b == 16; }
 
-void launch_band_halve_group(int64_t n, double* band, int64_t ldband, int b, int* flags, int* error, int max_grid,
-                             hipStream_t s) {
-    (void)ldband;   // must equal 2b + 1 (checked by the caller)
+void launch_band_halve_group(int64_t n, double* band, int b, const StageCtl& ctl, hipStream_t s) {
     switch (b) {
-        case 2: launch_group<1>(n, band, flags, error, max_grid, s); break;
-        case 4: launch_group<2>(n, band, flags, error, max_grid, s); break;
-        case 8: launch_group<4>(n, band, flags, error, max_grid, s); break;
-        case 16: launch_group<8>(n, band, flags, error, max_grid, s); break;
+        case 2: launch_group<1>(n, band, ctl, s); break;
+        case 4: launch_group<2>(n, band, ctl, s); break;
+        case 8: launch_group<4>(n, band, ctl, s); break;
+        case 16: launch_group<8>(n, band, ctl, s); break;
         default: break;
     }
 }

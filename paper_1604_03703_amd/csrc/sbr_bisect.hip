@@ -15,6 +15,11 @@
 //
 // One thread per eigenvalue index; d and e^2 are streamed through LDS in
 // chunks that every thread of the block reads at the same address (broadcast).
+//
+// A tridiagonal with a NaN or an infinity has no meaningful Sturm counts: the
+// setup kernel flags it (and raises the non-finite bit of the plan's status
+// word when there is one) and every eigenvalue comes out NaN; so does every
+// eigenvalue of a call whose band stage was abandoned (status word nonzero).
 #include <float.h>
 
 #include "sbr_device.h"
@@ -27,14 +32,16 @@ constexpr int PREP_NT = 256;
 __global__ __launch_bounds__(PREP_NT) void bisect_prep_kernel(int64_t n, const double* __restrict__ d,
                                                                const double* __restrict__ e,
                                                                double* __restrict__ e2p,
-                                                               sbr::BisectSetup* setup) {
+                                                               sbr::BisectSetup* setup, int* status) {
     __shared__ double s_lo[PREP_NT], s_hi[PREP_NT], s_e2[PREP_NT];
     const int t = threadIdx.x;
     double lo = DBL_MAX, hi = -DBL_MAX, emax2 = 1.0;
+    bool bad = false;
     for (int64_t i = t; i < n; i += PREP_NT) {
         const double em = (i > 0) ? e[i - 1] : 0.0;
         const double ep = (i + 1 < n) ? e[i] : 0.0;
         const double r = fabs(em) + fabs(ep);
+        bad |= !isfinite(d[i]) || !isfinite(em);
         lo = fmin(lo, d[i] - r);
         hi = fmax(hi, d[i] + r);
         e2p[i] = em * em;
@@ -43,7 +50,7 @@ __global__ __launch_bounds__(PREP_NT) void bisect_prep_kernel(int64_t n, const d
     s_lo[t] = lo;
     s_hi[t] = hi;
     s_e2[t] = emax2;
-    __syncthreads();
+    const int anybad = __syncthreads_or(bad);
     for (int o = PREP_NT / 2; o > 0; o >>= 1) {
         if (t < o) {
             s_lo[t] = fmin(s_lo[t], s_lo[t + o]);
@@ -69,7 +76,9 @@ __global__ __launch_bounds__(PREP_NT) void bisect_prep_kernel(int64_t n, const d
         setup->lo = l;
         setup->hi = h;
         setup->pivmin = pivmin;
-        setup->iters = iters;
+        setup->iters = anybad ? 0 : iters;
+        setup->nonfinite = anybad;
+        if (anybad && status) atomicOr(status, sbr::STATUS_NONFINITE);
     }
 }
 
@@ -82,7 +91,7 @@ template <int NT, int CH, int G>
 __global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __restrict__ d,
                                                     const double* __restrict__ e2p,
                                                     const sbr::BisectSetup* __restrict__ setup,
-                                                    double* __restrict__ w) {
+                                                    double* __restrict__ w, const int* status) {
     static_assert(G == 4 || G == 8 || G == 16, "lanes per index");
     __shared__ double sd[CH], se[CH];
     const int t = threadIdx.x, g = t % G;
@@ -146,7 +155,10 @@ __global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __r
             }
         }
     }
-    if (k < n && g == 0) w[k] = a + 0.5 * (c - a);
+    if (k < n && g == 0) {
+        const bool failed = setup->nonfinite || (status && *status != 0);
+        w[k] = failed ? __builtin_nan("") : a + 0.5 * (c - a);
+    }
 }
 
 }  // namespace
@@ -154,12 +166,12 @@ __global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __r
 namespace sbr {
 
 void launch_tridiag_eigvals(int64_t n, const double* d, const double* e, double* e2p, BisectSetup* setup,
-                            double* w, hipStream_t s) {
+                            double* w, int* status, hipStream_t s) {
     if (n <= 0) return;
-    bisect_prep_kernel<<<1, PREP_NT, 0, s>>>(n, d, e, e2p, setup);
+    bisect_prep_kernel<<<1, PREP_NT, 0, s>>>(n, d, e, e2p, setup, status);
     constexpr int NT = 256, CH = 2048, G = 4;
     const unsigned blocks = (unsigned)((n + NT / G - 1) / (NT / G));
-    bisect_kernel<NT, CH, G><<<blocks, NT, 0, s>>>(n, d, e2p, setup, w);
+    bisect_kernel<NT, CH, G><<<blocks, NT, 0, s>>>(n, d, e2p, setup, w, status);
 }
 
 }  // namespace sbr

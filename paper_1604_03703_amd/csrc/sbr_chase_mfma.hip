@@ -46,12 +46,12 @@ struct MChaseArgs {
     int* progress;     // nsweeps + 1 ints; progress[i] = chases of sweep i done
     double* gscratch;  // per-block W slices (b = 128)
     int64_t scratch_stride;
-    int* error;
+    int* error;        // the plan's status word: nonzero stops every block
+    uint64_t wait_ticks;   // a wait gives up after this many ticks of the
+                           // 100 MHz clock (it only bounds the kernel's lifetime
+                           // should the schedule's progress guarantee break)
 };
 
-// 10 s of the 100 MHz wall clock; only bounds the kernel's lifetime should
-// the schedule's progress guarantee ever be broken.
-constexpr uint64_t MWAIT_LIMIT_TICKS = 1000000000ull;
 constexpr int MSWEEP_DONE = 1 << 30;
 
 template <int H>
@@ -209,8 +209,8 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                             abort_sh = 1;
                             break;
                         }
-                        if (wall_clock64() - t0 > MWAIT_LIMIT_TICKS) {
-                            atomicExch(a.error, B);   // the stage (its bandwidth b) that stalled
+                        if (wall_clock64() - t0 > a.wait_ticks) {
+                            atomicOr(a.error, sbr::STATUS_STALLED);
                             abort_sh = 1;
                             break;
                         }
@@ -739,8 +739,7 @@ int mchase_grid(int64_t n) {
 }
 
 template <int H>
-void launch_mchase(int64_t n, double* band, int64_t ldb, double* scratch, int* flags, int* error, int max_grid,
-                   hipStream_t s) {
+void launch_mchase(int64_t n, double* band, int64_t ldb, double* scratch, const sbr::StageCtl& ctl, hipStream_t s) {
     const int64_t nsweeps = (n - 2) / H;
     if (nsweeps < 1) return;
     typedef MChase<H> C;
@@ -749,14 +748,15 @@ void launch_mchase(int64_t n, double* band, int64_t ldb, double* scratch, int* f
     a.band = band;
     a.ldb = ldb;
     a.nsweeps = (int)nsweeps;
-    a.ticket = flags;
-    a.progress = flags + 1;
+    a.ticket = ctl.flags;
+    a.progress = ctl.flags + 1;
     a.gscratch = scratch;
     a.scratch_stride = (int64_t)C::B * H;
-    a.error = error;
-    sbr::launch_fill_int(flags, nsweeps + 2, 0, s);
+    a.error = ctl.status;
+    a.wait_ticks = ctl.wait_ticks;
+    sbr::launch_fill_int(ctl.flags, nsweeps + 2, 0, s);
     int grid = mchase_grid<H>(n);
-    if (max_grid > 0 && grid > max_grid) grid = max_grid;
+    if (ctl.max_grid > 0 && grid > ctl.max_grid) grid = ctl.max_grid;
     chase_mfma_kernel<H><<<grid, C::NT, (size_t)C::TOTAL * sizeof(double), s>>>(a);
 }
 
@@ -779,13 +779,13 @@ int64_t band_mfma_workspace_doubles(int64_t n, int b) {
     return (int64_t)mchase_grid<64>(n) * MChase<64>::B * 64;
 }
 
-void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, int* flags,
-                            int* error, int max_grid, hipStream_t s) {
+void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, const StageCtl& ctl,
+                            hipStream_t s) {
     switch (b) {
-        case 16: launch_mchase<8>(n, band, ldband, scratch, flags, error, max_grid, s); break;
-        case 32: launch_mchase<16>(n, band, ldband, scratch, flags, error, max_grid, s); break;
-        case 64: launch_mchase<32>(n, band, ldband, scratch, flags, error, max_grid, s); break;
-        case 128: launch_mchase<64>(n, band, ldband, scratch, flags, error, max_grid, s); break;
+        case 16: launch_mchase<8>(n, band, ldband, scratch, ctl, s); break;
+        case 32: launch_mchase<16>(n, band, ldband, scratch, ctl, s); break;
+        case 64: launch_mchase<32>(n, band, ldband, scratch, ctl, s); break;
+        case 128: launch_mchase<64>(n, band, ldband, scratch, ctl, s); break;
         default: break;
     }
 }

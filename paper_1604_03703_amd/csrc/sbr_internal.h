@@ -90,13 +90,34 @@ void launch_dense_to_band(int64_t n, const double* A, int64_t lda, int b, double
 void launch_band_copy(int64_t n, const double* src, int64_t ldsrc, int keep, double* dst, int64_t lddst,
                       hipStream_t s);
 // Workspace (doubles) of one halving stage for bandwidth b and n.
-int64_t chase_workspace_doubles(int64_t n, int b, int* grid_out);
+int64_t chase_workspace_doubles(int64_t n, int b);
 // Ints of flag/counter storage for one halving stage.
 int64_t chase_flag_ints(int64_t n, int b);
-// `error` is a device int set to 1 if a pipeline wait gave up; max_grid > 0
-// caps the number of chase blocks (1 = the sequential sweep order).
+// Status bits of the plan's device status word (the values of the public
+// SBR_STATUS_* bits).
+constexpr int STATUS_STALLED = 1;     // a pipelined wait gave up; the stage was abandoned
+constexpr int STATUS_NONFINITE = 2;   // the tridiagonal reached by the reductions is not finite
+// Control of one pipelined band stage: flags / tickets (chase_flag_ints of
+// them), the status word (status[0], watched by the kernels: once it is
+// nonzero every block exits), how long one wait may spin (ticks of the
+// 100 MHz clock), and a cap on the grid (0 = automatic, 1 = the sequential
+// sweep order).  Bands b <= group_max_b (and b <= 16) go to the sweep-group
+// kernel when its layout allows, wider ones to the MFMA chase.
+struct StageCtl {
+    int* flags;
+    int* status;
+    uint64_t wait_ticks;
+    int max_grid;
+    int group_max_b;
+};
+constexpr int DEFAULT_GROUP_MAX_B = 8;
+constexpr uint64_t DEFAULT_WAIT_TICKS = 1000000000ull;   // 10 s
+// Whether launch_band_halve handles (n, ldband, b).
+bool band_halve_supported(int64_t n, int64_t ldband, int b);
 void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch,
-                       int* flags, int* error, int max_grid, hipStream_t s);
+                       const StageCtl& ctl, hipStream_t s);
+// status[1] |= status[0]; status[0] = 0 (device side, capturable).
+void launch_status_rearm(int* status, hipStream_t s);
 void launch_fill_int(int* p, int64_t count, int v, hipStream_t s);
 // ---- sbr_batched.hip: many matrices (n <= BATCH_NMAX), one work-group each --
 constexpr int BATCH_NMAX = 512;
@@ -121,26 +142,28 @@ int init_batched_attributes();
 // ---- sbr_chase_mfma.hip: b in {32, 64, 128}, chase products on FP64 MFMA --
 bool band_mfma_supported(int b);
 int64_t band_mfma_workspace_doubles(int64_t n, int b);
-void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, int* flags,
-                            int* error, int max_grid, hipStream_t s);
+void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, const StageCtl& ctl,
+                            hipStream_t s);
 int init_band_mfma_attributes();
 // ---- sbr_band_group.hip: small bandwidths, sweep groups with LDS windows --
 bool band_group_supported(int b);
-void launch_band_halve_group(int64_t n, double* band, int64_t ldband, int b, int* flags, int* error, int max_grid,
-                             hipStream_t s);
+// band ld = 2b + 1, n (2b + 1) < 2^31
+void launch_band_halve_group(int64_t n, double* band, int b, const StageCtl& ctl, hipStream_t s);
 int init_band_group_attributes();
 void launch_band_to_tridiag(int64_t n, const double* band, int64_t ldband, double* d, double* e,
                             hipStream_t s);
-int init_band_attributes();
 
 // ---- sbr_bisect.hip -------------------------------------------------------
 struct BisectSetup {
     double lo, hi, pivmin;
     int iters;
-    int pad;
+    int nonfinite;    // d or e holds a NaN or an infinity
 };
 // e may be null when n == 1.  e2p (n doubles) and setup are workspace.
+// status: null, or the plan's status word: its STATUS_NONFINITE bit is set
+// for a non-finite tridiagonal, and when status[0] is nonzero (a stage of
+// the call was abandoned, or the input is not finite) every w is NaN.
 void launch_tridiag_eigvals(int64_t n, const double* d, const double* e, double* e2p, BisectSetup* setup,
-                            double* w, hipStream_t s);
+                            double* w, int* status, hipStream_t s);
 
 }  // namespace sbr

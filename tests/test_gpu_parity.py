@@ -261,11 +261,13 @@ def test_eigvalsh_batched_replay_and_reshape(sbr, oracle_mod):
         assert np.max(np.abs(w.cpu().numpy() - ref)) <= 1e-11 * _norm2(ref)
 
 
-def test_eigvalsh_batched_fp32_form(sbr, oracle_mod):
+def test_eigvalsh_batched_precision_argument(sbr, oracle_mod):
+    # the batched kernels compute in FP64 whatever the precision argument
+    # says: FP64 accuracy with either value
     mats = si.batch_workload(count=16, lo=32, hi=512)
     refs = [oracle_mod.eigvalsh(M) for M in mats]
     dev = [torch.from_numpy(M.copy()).cuda() for M in mats]
     ws = sbr.eigvalsh_batched(dev, precision="fp32_mfma")
     torch.cuda.synchronize()
     for w, ref in zip(ws, refs):
-        assert np.max(np.abs(w.cpu().numpy() - ref)) <= 2e-5 * _norm2(ref)
+        assert np.max(np.abs(w.cpu().numpy() - ref)) <= 1e-11 * _norm2(ref)

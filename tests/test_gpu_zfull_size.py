@@ -1,20 +1,19 @@
 """GPU parity at the full sizes of the named workloads (n = 8192, 16384 and
 32768), through one plan per solve and the band widths the benchmark uses.
 
-At n = 8192 the CPU oracle finishes in about half a minute and is compared
-element by element.  At n = 16384 and 32768 every case is checked against what
-holds without it:
-
+* n = 8192: the CPU oracle finishes in about half a minute and is compared
+  element by element.
+* the Gaussian inputs at n = 16384 and 32768 (the benchmark's own input):
+  element by element against the oracle's eigenvalues of the same matrix,
+  stored under tests/golden/ by make_oracle_golden.py (the matrix's SHA-256 is
+  checked first, so the values belong to this input); the FP64 path within
+  1e-11 ||A||_2, the FP32-MFMA form within 2e-5 ||A||_2; plus trace and
+  Frobenius invariants;
 * prescribed spectra, A = Q diag(lam) Q^T with Q a product of 64 Gaussian
   reflectors: every computed eigenvalue against the sorted lam, the FP64 path
   within 1e-11 ||A||_2 and the FP32-MFMA form within 2e-5 ||A||_2, where
   ||A||_2 = max |lam| (forming A in floating point moves its eigenvalues by
-  about 64 sqrt(n) eps ||A||_2, far inside the FP64 bound);
-* the Gaussian inputs: the sum of the eigenvalues against trace(A) and the sum
-  of their squares against ||A||_F^2 (both are invariant under orthogonal
-  similarity), within n 1e-11 ||A||_2 and 2 n 1e-11 ||A||_2^2, the most that
-  eigenvalues each within the FP64 tolerance can move them; the FP32-MFMA form
-  of the Gaussian n = 16384 input against the FP64 path, within 2e-5 ||A||_2.
+  about 64 sqrt(n) eps ||A||_2, far inside the FP64 bound).
 
 The file name sorts after the other GPU tests so that these slower cases run
 last.
@@ -25,6 +24,7 @@ import numpy as np
 import pytest
 import torch
 
+import golden_io
 import sbr_inputs as si
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -72,20 +72,32 @@ def test_n32768_clustered_spectrum(sbr, large_clustered, precision, tol):
     assert err.max() <= tol * nrm
 
 
-def test_n32768_gaussian_invariants(sbr):
+@pytest.fixture(scope="module")
+def large_gaussian():
     A, _ = si.workload(si.CFG_LARGE, 0)
+    rec, ref = golden_io.load("n32768")
+    assert golden_io.matrix_sha256(A) == rec["matrix_sha256"], "the stored eigenvalues belong to another matrix"
+    return A, ref
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32_mfma", 2e-5)])
+def test_n32768_gaussian_vs_oracle(sbr, large_gaussian, precision, tol):
+    A, ref = large_gaussian
     n = A.shape[0]
-    tr = float(np.trace(A))
-    flat = A.reshape(-1)
-    fro2 = float(np.dot(flat, flat))
-    w = _solve(sbr, A, 128)
-    nrm = float(np.max(np.abs(w)))
-    d_tr = abs(float(w.sum()) - tr)
-    d_fr = abs(float(np.dot(w, w)) - fro2)
-    print("n=32768 gaussian: |sum w - tr A| = %.3e (bound %.3e), |sum w^2 - ||A||_F^2| = %.3e (bound %.3e)"
-          % (d_tr, n * 1e-11 * nrm, d_fr, 2 * n * 1e-11 * nrm * nrm), flush=True)
-    assert d_tr <= n * 1e-11 * nrm
-    assert d_fr <= 2 * n * 1e-11 * nrm * nrm
+    w = _solve(sbr, A, 128, precision)
+    nrm = float(np.max(np.abs(ref)))
+    err = np.abs(w - ref)
+    _report("n=32768 gaussian %s vs oracle" % precision, err, nrm)
+    assert err.max() <= tol * nrm
+    if precision == "fp64":
+        tr = float(np.trace(A))
+        flat = A.reshape(-1)
+        fro2 = float(np.dot(flat, flat))
+        d_tr = abs(float(w.sum()) - tr)
+        d_fr = abs(float(np.dot(w, w)) - fro2)
+        print("n=32768 gaussian: |sum w - tr A| = %.3e, |sum w^2 - ||A||_F^2| = %.3e" % (d_tr, d_fr), flush=True)
+        assert d_tr <= n * 1e-11 * nrm
+        assert d_fr <= 2 * n * 1e-11 * nrm * nrm
 
 
 def test_n8192_gaussian_vs_oracle(sbr, oracle_mod):
@@ -117,11 +129,13 @@ def test_n16384_fp32_form_uniform_spectrum(sbr):
     assert err.max() <= 2e-5 * nrm
 
 
-def test_n16384_fp32_form_gaussian_vs_fp64(sbr):
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32_mfma", 2e-5)])
+def test_n16384_gaussian_vs_oracle(sbr, precision, tol):
     A, _ = si.workload(si.CFG_FP32, 0)
-    w64 = _solve(sbr, A, 0, "fp64")
-    w32 = _solve(sbr, A, 0, "fp32_mfma")
-    nrm = float(np.max(np.abs(w64)))
-    err = np.abs(w32 - w64)
-    _report("n=16384 gaussian fp32_mfma vs fp64", err, nrm)
-    assert err.max() <= 2e-5 * nrm
+    rec, ref = golden_io.load("n16384")
+    assert golden_io.matrix_sha256(A) == rec["matrix_sha256"], "the stored eigenvalues belong to another matrix"
+    w = _solve(sbr, A, 0, precision)
+    nrm = float(np.max(np.abs(ref)))
+    err = np.abs(w - ref)
+    _report("n=16384 gaussian %s vs oracle" % precision, err, nrm)
+    assert err.max() <= tol * nrm

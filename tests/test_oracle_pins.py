@@ -146,3 +146,45 @@ def test_semicircle_range(oracle_mod):
     w = oracle_mod.eigvalsh(A)
     edge = math.sqrt(2 * n)
     assert -1.15 * edge < w[0] < -0.85 * edge and 0.85 * edge < w[-1] < 1.15 * edge
+
+
+def test_oracle_bisection_on_adversarial_tridiagonals(oracle_mod):
+    # graded, glued Wilkinson, exact zero pivots, underflowing couplings:
+    # the oracle's bisection against LAPACK's tridiagonal eigensolver
+    from scipy.linalg import eigvalsh_tridiagonal
+
+    from bisect_cases import CASES
+    eps = np.finfo(np.float64).eps
+    for name, (d, e) in CASES.items():
+        ref = oracle_mod.tridiag_eigvals(d, e)
+        lap = eigvalsh_tridiagonal(d, e)
+        nrm = max(float(np.max(np.abs(lap))), 1e-300)
+        assert np.all(np.diff(ref) >= 0.0), name
+        assert np.max(np.abs(ref - lap)) <= 8 * len(d) * eps * nrm, name
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", ["n16384", "n32768"])
+def test_stored_oracle_eigenvalues(name):
+    # the stored eigenvalues of the full-size Gaussian inputs: the generator
+    # still produces the matrix they were computed on (SHA-256 of its bytes),
+    # and they satisfy what the spectrum of that matrix must: sum = trace,
+    # sum of squares = ||A||_F^2, ascending, inside the Gershgorin interval
+    import golden_io
+    rec, w = golden_io.load(name)
+    cfg = {"n16384": si.CFG_FP32, "n32768": si.CFG_LARGE}[name]
+    A, _ = si.workload(cfg, 0)
+    n = A.shape[0]
+    assert w.shape == (n,)
+    assert golden_io.matrix_sha256(A) == rec["matrix_sha256"]
+    nrm = float(np.max(np.abs(w)))
+    eps = np.finfo(np.float64).eps
+    assert np.all(np.diff(w) >= 0.0)
+    assert abs(float(w.sum()) - float(np.trace(A))) <= n * eps * nrm * 100
+    flat = A.reshape(-1)
+    fro2 = float(np.dot(flat, flat))
+    assert abs(float(np.dot(w, w)) - fro2) <= n * eps * fro2 * 10
+    radius = float(np.max(np.sum(np.abs(A), axis=1)))
+    assert nrm <= radius
+    # Wigner semicircle: the spectrum of (G + G^T)/2 fills about [-sqrt(2n), sqrt(2n)]
+    assert 0.97 * math.sqrt(2 * n) <= nrm <= 1.03 * math.sqrt(2 * n)
