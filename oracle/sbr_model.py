@@ -205,18 +205,20 @@ def full_to_band(A: np.ndarray, b: int, leaves: int = 4) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# Algorithm 4.2 (band-to-band), k = 2
+# Algorithm 4.2 (band-to-band), b -> h = b / k
 # --------------------------------------------------------------------------
-def chase_list(n: int, b: int):
-    """All chases (i, j) of one halving b -> h = b/2 in sequential order, with
-    their offsets and exact index ranges (0-based, half-open).
+def chase_list(n: int, b: int, h: int | None = None):
+    """All chases (i, j) of one reduction b -> h (h = b / k, default k = 2) in
+    sequential order, with their offsets and exact index ranges (0-based,
+    half-open).
 
     Loop bounds (reading G4): sweep i exists while i*h <= n - 2; chase j
     exists while o_qr.r <= n - 2 (at least two rows to factor).
     Update columns (G5/G6): j = 1 -> [o_qr.r, o_qr.r + 2b); j > 1 ->
     [o_qr.c + h, o_qr.c + 3b), clipped at n.
     """
-    h = b // 2
+    h = b // 2 if h is None else h
+    assert 1 <= h < b and b % h == 0
     out = []
     i = 1
     while i * h <= n - 2:
@@ -257,8 +259,9 @@ def chase_touched(ch) -> set:
     return s
 
 
-def band_to_band(B: np.ndarray, b: int, check_window: bool = True) -> np.ndarray:
-    """One halving b -> h = b/2 of the symmetric band matrix B (dense storage).
+def band_to_band(B: np.ndarray, b: int, check_window: bool = True, h: int | None = None) -> np.ndarray:
+    """One reduction b -> h (h = b / k, default k = 2: a halving) of the
+    symmetric band matrix B (dense storage).
 
     For each chase: [U, T, R] = QR(B[I_qr.rs, I_qr.cs]); the block becomes
     [R; 0]; W = B[I_up.cs, I_qr.rs] U T; V = -W;
@@ -267,8 +270,7 @@ def band_to_band(B: np.ndarray, b: int, check_window: bool = True) -> np.ndarray
     """
     B = np.array(B, dtype=np.float64, copy=True)
     n = B.shape[0]
-    h = b // 2
-    for ch in chase_list(n, b):
+    for ch in chase_list(n, b, h):
         r0, r1 = ch["qr_rows"]
         c0, c1 = ch["qr_cols"]
         u0, u1 = ch["up_cols"]

@@ -219,12 +219,12 @@ def test_chase_schedule_after_previous_qr_orders_every_conflict(n, b):
     assert _phase_conflicts_not_ordered(n, b) == 0
 
 
-def _lockstep_phase_conflicts(n, b, lag):
+def _lockstep_phase_conflicts(n, b, lag, h=None):
     # the small-band pipeline: at step tau every sweep s of a group does chase
     # j = tau - lag*s, first all the QR blocks (phase 0), then the rest (phase 1);
     # a conflicting pair of phases must run at different times, in the order of
     # the sequential loop nest (sweep-major, QR phase first)
-    chases = M.chase_list(n, b)
+    chases = M.chase_list(n, b, h)
     first_i = min(c["i"] for c in chases)
     nodes = []
     for c in chases:
@@ -250,3 +250,64 @@ def test_lockstep_two_phase_lag2_orders_every_conflict(n, b):
 
 def test_lockstep_two_phase_lag1_is_not_enough():
     assert _lockstep_phase_conflicts(64, 8, 1) > 0
+
+
+@pytest.mark.parametrize("n,b,h", [(64, 8, 1), (67, 8, 2), (50, 4, 1), (100, 16, 1), (100, 16, 4), (33, 8, 1),
+                                   (20, 16, 1), (40, 2, 1), (130, 32, 1)])
+def test_band_to_band_general_k(oracle_mod, n, b, h):
+    # Algorithm 4.2 with k = b / h > 2: the same offsets and extents with
+    # h = b / k; the band shrinks to exactly h (k = b: straight to the
+    # tridiagonal) and the spectrum is kept
+    rng = np.random.default_rng(n * b + h)
+    A = rng.standard_normal((n, n))
+    A = 0.5 * (A + A.T)
+    i, j = np.indices((n, n))
+    A[np.abs(i - j) > b] = 0.0
+    ref = oracle_mod.eigvalsh(A)
+    B = M.band_to_band(A, b, h=h)       # also asserts the window reading per chase
+    assert M.bandwidth(B) <= h
+    fro = math.sqrt(float(np.sum(A * A)))
+    assert abs(math.sqrt(float(np.sum(B * B))) - fro) <= 1e-13 * fro * n
+    assert np.max(np.abs(oracle_mod.eigvalsh(B) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n,b", [(35, 4), (67, 8), (100, 16)])
+def test_lockstep_two_phase_lag2_direct_to_tridiagonal(n, b):
+    # the two-phase lock-step schedule with a lag of two chases also orders
+    # every conflict of the direct b -> 1 reduction; a lag of one does not
+    assert _lockstep_phase_conflicts(n, b, 2, h=1) == 0
+    assert _lockstep_phase_conflicts(n, b, 1, h=1) > 0
+
+
+def _carry_violations(n, b, h, lag):
+    # a sweep keeps its chase's below block (rows [o+b, o+2b) x cols [o, o+b))
+    # in registers for its next chase; no phase of another sweep may write
+    # those entries between the two (lock-step schedule, two phases per step)
+    chases = M.chase_list(n, b, h)
+    first_i = min(c["i"] for c in chases)
+    when = {}
+    written = []
+    for c in chases:
+        q, r = _phase_touched(c)
+        tau = c["j"] + lag * (c["i"] - first_i)
+        when[(c["i"], c["j"])] = tau
+        written.append(((tau, 0), c["i"], q))
+        written.append(((tau, 1), c["i"], r))
+    bad = 0
+    for c in chases:
+        i, j = c["i"], c["j"]
+        if (i, j + 1) not in when:
+            continue
+        r0, r1 = c["qr_rows"]
+        o = r0
+        blk = {(r, cc) for r in range(o + b, min(n, o + 2 * b)) for cc in range(o, min(n, o + b)) if r >= cc}
+        t0, t1 = (when[(i, j)], 1), (when[(i, j + 1)], 0)
+        for t, ii, ent in written:
+            if ii != i and t0 < t < t1 and (ent & blk):
+                bad += 1
+    return bad
+
+
+@pytest.mark.parametrize("n,b,h", [(35, 4, 1), (67, 8, 1), (100, 16, 1), (64, 8, 4), (60, 4, 2)])
+def test_lockstep_lag2_keeps_the_carried_below_block(n, b, h):
+    assert _carry_violations(n, b, h, 2) == 0
