@@ -131,6 +131,20 @@ int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n,
 int sbr_tridiag_eigvals(int64_t n, const double* d, const double* e,
                         sbr_stream_t stream, double* w);
 
+/*
+ * sbr_tridiag_eigvals without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, kernels and results as
+ * sbr_tridiag_eigvals; its scratch (e^2 and the bisection setup, about
+ * 2 MiB) is a fixed array in the library's device image, one per GPU, held
+ * until the process ends.  n <= 262144 (2^18), else SBR_ENOTSUP before
+ * anything is enqueued.  All calls on one GPU share that array: calls that
+ * overlap on one GPU (concurrent streams or threads) race and must be
+ * serialised by the caller.
+ */
+int sbr_tridiag_eigvals_noalloc(int64_t n, const double* d, const double* e,
+                                sbr_stream_t stream, double* w);
+
 /* Plan owning the device workspace for problems up to n_max (and batches up
  * to batch_max matrices).  Creating a plan allocates; calls made through an
  * existing plan within its limits do not. */

@@ -55,6 +55,7 @@ def _load():
                                       ctypes.POINTER(_i64), _i32, ctypes.c_int, _vp,
                                       ctypes.POINTER(_vp)], ctypes.c_int),
         "sbr_tridiag_eigvals": ([_i64, _vp, _vp, _vp, _vp], ctypes.c_int),
+        "sbr_tridiag_eigvals_noalloc": ([_i64, _vp, _vp, _vp, _vp], ctypes.c_int),
         "sbr_plan_create": ([ctypes.POINTER(_vp), _i64, _i32, ctypes.c_int], ctypes.c_int),
         "sbr_plan_destroy": ([_vp], ctypes.c_int),
         "sbr_workspace_size": ([_i64, _i32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -90,7 +91,7 @@ EXPORTED = (
     "sbr_last_hip_error", "sbr_full_to_band", "sbr_dense_to_band", "sbr_band_halve", "sbr_panel_qr",
     "sbr_gemm", "sbr_syr2k_lower", "sbr_symm_lower", "sbr_plan_set_timing", "sbr_plan_get_timing",
     "sbr_plan_set_chase_blocks", "sbr_plan_set_panel_cus", "sbr_plan_status",
-    "sbr_plan_set_wait_limit", "sbr_plan_set_group_max_band",
+    "sbr_plan_set_wait_limit", "sbr_plan_set_group_max_band", "sbr_tridiag_eigvals_noalloc",
 )
 
 STATUS_STALLED = 1      # SBR_STATUS_STALLED
@@ -262,6 +263,16 @@ def tridiag_eigvals(d: torch.Tensor, e: torch.Tensor | None, stream=None) -> tor
     _check(_lib.sbr_tridiag_eigvals(n, _dev_f64(d, "d"), ep, _stream(stream), _dev_f64(w, "w")),
            "sbr_tridiag_eigvals")
     return w
+
+
+def tridiag_eigvals_noalloc(d: torch.Tensor, e: torch.Tensor | None, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """sbr_tridiag_eigvals_noalloc: the library allocates nothing (n <= 2^18);
+    the caller provides the output vector."""
+    n = d.shape[0]
+    ep = _dev_f64(e, "e") if (e is not None and n > 1) else ctypes.c_void_p(0)
+    _check(_lib.sbr_tridiag_eigvals_noalloc(n, _dev_f64(d, "d"), ep, _stream(stream), _dev_f64(out, "w")),
+           "sbr_tridiag_eigvals_noalloc")
+    return out
 
 
 def full_to_band(A: torch.Tensor, b: int, plan: Plan, precision="fp64", stream=None) -> torch.Tensor:

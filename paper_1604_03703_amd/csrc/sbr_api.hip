@@ -775,6 +775,25 @@ int sbr_tridiag_eigvals(int64_t n, const double* d, const double* e, sbr_stream_
     return 0;
 }
 
+int sbr_tridiag_eigvals_noalloc(int64_t n, const double* d, const double* e, sbr_stream_t stream, double* w) {
+    if (n < 0) return -1;
+    if (n > 0 && !d) return -2;
+    if (n > 1 && !e) return -3;
+    if (n > 0 && !w) return -5;
+    if (n == 0) return 0;
+    if (n > NOALLOC_MAX_N) return SBR_ENOTSUP;
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return hip_fail(he);
+    double* e2p = nullptr;
+    BisectSetup* setup = nullptr;
+    const int rc = noalloc_scratch(dev, &e2p, &setup);
+    if (rc) return hip_fail((hipError_t)rc);
+    launch_tridiag_eigvals(n, d, e, e2p, setup, w, nullptr, (hipStream_t)stream);
+    SBR_CHECK_LAUNCH();
+    return 0;
+}
+
 int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n, double* const* A,
                              const int64_t* lda, int32_t b0, sbr_precision prec, sbr_stream_t stream,
                              double* const* w) {

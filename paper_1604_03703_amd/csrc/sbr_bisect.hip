@@ -22,8 +22,19 @@
 // eigenvalue of a call whose band stage was abandoned (status word nonzero).
 #include <float.h>
 
+#include <mutex>
+
 #include "sbr_device.h"
 #include "sbr_internal.h"
+
+// Fixed device scratch of the allocation-free tridiagonal entry point: e^2
+// (NOALLOC_MAX_N doubles), then the setup record.  One copy per GPU, held
+// until the process ends.  Host code must not use this name as an address (it
+// names a host-side stand-in): the device address comes from
+// hipGetSymbolAddress, see noalloc_scratch below.
+constexpr int64_t NOALLOC_E2_DOUBLES = sbr::NOALLOC_MAX_N;
+constexpr int64_t NOALLOC_SETUP_DOUBLES = (sizeof(sbr::BisectSetup) + sizeof(double) - 1) / sizeof(double);
+static __device__ __align__(256) double scratch[NOALLOC_E2_DOUBLES + NOALLOC_SETUP_DOUBLES];
 
 namespace {
 
@@ -161,9 +172,28 @@ __global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __r
     }
 }
 
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
 }  // namespace
 
 namespace sbr {
+
+int noalloc_scratch(int device, double** e2p, BisectSetup** setup) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        // the caller has made `device` current: its own copy of the array
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        g_scratch_ptr[device] = (double*)ptr;
+    }
+    *e2p = g_scratch_ptr[device];
+    *setup = (BisectSetup*)(g_scratch_ptr[device] + NOALLOC_E2_DOUBLES);
+    return 0;
+}
 
 void launch_tridiag_eigvals(int64_t n, const double* d, const double* e, double* e2p, BisectSetup* setup,
                             double* w, int* status, hipStream_t s) {

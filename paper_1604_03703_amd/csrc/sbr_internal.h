@@ -165,5 +165,11 @@ struct BisectSetup {
 // the call was abandoned, or the input is not finite) every w is NaN.
 void launch_tridiag_eigvals(int64_t n, const double* d, const double* e, double* e2p, BisectSetup* setup,
                             double* w, int* status, hipStream_t s);
+// Largest order of the allocation-free tridiagonal entry point.
+constexpr int64_t NOALLOC_MAX_N = 1 << 18;
+// Device addresses (for `device`, which must be current) of the fixed scratch
+// of the allocation-free entry point: e^2 (NOALLOC_MAX_N doubles) and the
+// setup record.  Looked up once per device.  0 or a hipError_t.
+int noalloc_scratch(int device, double** e2p, BisectSetup** setup);
 
 }  // namespace sbr
