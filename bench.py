@@ -145,6 +145,7 @@ def run_batch(sbr, torch, si, count, steps, warmup):
     out["fp32_mfma"] = "not measured: the batched kernels compute in FP64"
     for prec in ("fp64",):
         plan = sbr.Plan(512, count, prec)
+        out["tuned_bands"] = [list(x) for x in plan.use_tuned_batch_bands(prec)]
         times = []
         for it in range(max(1, warmup) + steps):
             for d, d0 in zip(dev, dev0):
@@ -179,11 +180,66 @@ def run_batch(sbr, torch, si, count, steps, warmup):
     tr = max(abs(float(w.sum().item()) - float(np.trace(M))) / max(1.0, float(np.abs(M).max()) * M.shape[0])
              for w, M in zip(ws[:64], mats[:64]))
     out["trace_check_rel"] = tr
+    # roofline of the batch: sum over phases of max(flops / peak, bytes / BW)
+    # with the method's own work: full-to-band 4/3 n^3 flops per matrix on
+    # the FP64 MFMA peak, the halvings' band traffic (32 n^2 bytes per
+    # stage) on HBM, and the bisection's n^2 I Sturm steps of 12 FP64 lane
+    # operations (a reciprocal, its refinement, the recurrence) on the FP64
+    # vector rate (78.6 TFLOP/s = 39.3 T lane-op/s)
+    ns = [M.shape[0] for M in mats]
+    t_f2b = sum(4.0 / 3.0 * m ** 3 for m in ns) / (PEAK_FP64_MFMA * 1e12)
+    t_band = sum(32.0 * m * m * max(1, int(math.log2(max(2, min(16, m))))) for m in ns) / (PEAK_HBM * 1e9)
+    t_bis = sum(m * m * 56 * 12 for m in ns) / 39.3e12
+    t_roof = t_f2b + t_band + t_bis
+    out["roofline"] = {"t_roof_ms": round(t_roof * 1e3, 3), "f2b_ms": round(t_f2b * 1e3, 3),
+                       "band_ms": round(t_band * 1e3, 3), "bisect_ms": round(t_bis * 1e3, 3),
+                       "frac": round(t_roof / (out["fp64"]["ms"] * 1e-3), 4)}
     return out
 
 
 def mean(xs):
     return sum(xs) / max(1, len(xs))
+
+
+def time_band_stage(sbr, torch, n, b, direct, variant, steps, warmup):
+    """One band stage alone: a seeded random symmetric band of width b (lower
+    band storage, ld 2b + 1) halved (sbr_band_halve) or, with direct, taken
+    straight to the tridiagonal (sbr_band_to_tridiag); the band is restored
+    from a device copy before every launch (outside the timed region)."""
+    g = torch.Generator(device="cuda").manual_seed(1604 + b)
+    ld = 2 * b + 1
+    src = torch.zeros((n, ld), dtype=torch.float64, device="cuda")
+    src[:, : b + 1] = torch.randn((n, b + 1), dtype=torch.float64, device="cuda", generator=g)
+    for d in range(1, b + 1):
+        src[n - d:, d] = 0.0
+    plan = sbr.Plan(0)
+    plan.set_tridiag_band(0, variant)
+    bd = torch.empty_like(src)
+    ms = []
+    for it in range(warmup + steps):
+        bd.copy_(src)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        if direct:
+            sbr.band_to_tridiag(bd, b, plan)
+        else:
+            sbr.band_halve(bd, b, plan)
+        e1.record()
+        torch.cuda.synchronize()
+        if plan.status() != 0:
+            raise RuntimeError("band stage reported a stalled wait")
+        if it >= warmup:
+            ms.append(e0.elapsed_time(e1))
+    by = band_stage_bytes(n, b) if not direct else None
+    out = {"n": n, "b": b, "stage": ("%d->1" % b) if direct else ("%d->%d" % (b, b // 2)),
+           "variant": variant if direct else None, "ms": [round(x, 3) for x in ms]}
+    if by:
+        out["alg_GB"] = round(by / 1e9, 3)
+        out["GBps"] = round(by / (mean(ms) * 1e-3) / 1e9, 1)
+    plan.close()
+    return out
 
 
 def golden_eigenvalues(A_host, n):
@@ -254,6 +310,11 @@ def main():
                     help="only run the batched form and print its results (profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run three device-to-device copies of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--band-stage", type=int, default=0, metavar="B",
+                    help="only time one band stage of width B on a seeded random band of order --n "
+                         "(a halving, or with --direct the reduction straight to tridiagonal) and exit")
+    ap.add_argument("--direct", action="store_true", help="with --band-stage: the direct B -> 1 stage")
+    ap.add_argument("--variant", type=int, default=0, help="with --band-stage --direct: launch shape")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the eigensolver here runs on a single device "
@@ -276,6 +337,11 @@ def main():
 
     import sbr_inputs as si
     import paper_1604_03703_amd as sbr
+
+    if args.band_stage:
+        print(json.dumps(time_band_stage(sbr, torch, args.n, args.band_stage, args.direct, args.variant,
+                                         args.steps, args.warmup)), flush=True)
+        return
 
     if args.batch_only:
         print(json.dumps({"batch": run_batch(sbr, torch, si, args.batch_count, args.steps, args.warmup)}), flush=True)

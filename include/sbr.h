@@ -106,7 +106,8 @@ int sbr_syev_eigvals_ex(sbr_plan_t plan, int64_t n, double* A, int64_t lda,
  *   w        HOST array of batch DEVICE pointers, w[k] holds n[k] doubles.
  * Matrices with n[k] <= 512 (and b0 <= 16) are reduced by the batched
  * kernels, one work-group per matrix, largest first: full-to-band with
- * panels of width b (8 for n <= 96, 16 above, when b0 = 0), the halvings
+ * panels of width b (when b0 = 0: the plan's band table, see
+ * sbr_plan_set_batch_bands, else 8 for n <= 96 and 16 above), the halvings
  * b -> 1 and bisection.  Their launch sequence is captured once per batch
  * shape (the pointers, orders and bands) and replayed by later calls with the
  * same shape; a new shape uploads the descriptors and captures again (the
@@ -120,6 +121,17 @@ int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n,
                              double* const* A, const int64_t* lda, int32_t b0,
                              sbr_precision prec, sbr_stream_t stream,
                              double* const* w);
+
+/*
+ * Band per size bucket for the batched form with b0 = 0 (the tuned choice):
+ * a matrix of order n gets bands[q] for the first q with n <= n_max[q]
+ * (n_max ascending, bands powers of two <= 16), the built-in rule (8 up to
+ * n = 96, 16 above) beyond the last bucket; nbuckets = 0 restores the
+ * built-in rule.  Host-side only (the next batched call captures its launch
+ * again when a band changes).  -3 / -4 for a malformed table.
+ */
+int sbr_plan_set_batch_bands(sbr_plan_t plan, int32_t nbuckets, const int32_t* n_max,
+                             const int32_t* bands);
 
 /*
  * Eigenvalues of the symmetric tridiagonal matrix with diagonal d[0..n-1]

@@ -49,6 +49,17 @@ int sbr_band_halve(sbr_plan_t plan, int64_t n, double* band, int64_t ldband,
                    int32_t b, sbr_precision prec, sbr_stream_t stream);
 
 /*
+ * Band of width b straight to tridiagonal form (Algorithm 4.2 with k = b,
+ * i.e. h = 1: every chase is one Householder reflector of length b).  Same
+ * storage conventions as sbr_band_halve (ldband >= 2b + 1, rows b+1 .. 2b
+ * zero on entry); on return the entries at distance > 1 are exactly zero.
+ * b in {4, 8, 16} (-5 otherwise); FP64.  SBR_ENOTSUP when n (2b + 1) reaches
+ * 2^31.
+ */
+int sbr_band_to_tridiag(sbr_plan_t plan, int64_t n, double* band, int64_t ldband, int32_t b,
+                        sbr_stream_t stream);
+
+/*
  * Panel QR of the m x b panel P (m >= b) by the TSQR tree of Algorithm 3.2
  * followed by Householder reconstruction (Corollary 3.7).  Outputs (device):
  *   Q  m x b explicit orthonormal factor (ld = m), P = Q R,
@@ -122,6 +133,13 @@ int sbr_plan_set_chase_blocks(sbr_plan_t plan, int32_t max_blocks);
  * kernel (bulges in registers, live band in LDS), wider ones by the MFMA
  * chase kernel (default 8). */
 int sbr_plan_set_group_max_band(sbr_plan_t plan, int32_t b);
+
+/* In a solve, bands b <= this value (b in {4, 8, 16}) are reduced straight
+ * to the tridiagonal by one stage of sbr_band_to_tridiag's kind instead of
+ * further halvings (0: halve down to 1; the default is 4).  variant (0 .. 2) picks the launch
+ * shape of that kernel (lanes per sweep, sweeps per work-group) for it and
+ * for sbr_band_to_tridiag; 0 is the default.  -3 for an unknown variant. */
+int sbr_plan_set_tridiag_band(sbr_plan_t plan, int32_t b, int32_t variant);
 
 /* How long (ticks of the 100 MHz device clock) a pipelined band kernel waits
  * for the previous sweep before it abandons the stage and raises

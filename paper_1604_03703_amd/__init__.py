@@ -76,6 +76,9 @@ def _load():
         "sbr_plan_status": ([_vp, ctypes.POINTER(_i32)], ctypes.c_int),
         "sbr_plan_set_wait_limit": ([_vp, _i64], ctypes.c_int),
         "sbr_plan_set_group_max_band": ([_vp, _i32], ctypes.c_int),
+        "sbr_plan_set_tridiag_band": ([_vp, _i32, _i32], ctypes.c_int),
+        "sbr_band_to_tridiag": ([_vp, _i64, _vp, _i64, _i32, _vp], ctypes.c_int),
+        "sbr_plan_set_batch_bands": ([_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -92,6 +95,7 @@ EXPORTED = (
     "sbr_gemm", "sbr_syr2k_lower", "sbr_symm_lower", "sbr_plan_set_timing", "sbr_plan_get_timing",
     "sbr_plan_set_chase_blocks", "sbr_plan_set_panel_cus", "sbr_plan_status",
     "sbr_plan_set_wait_limit", "sbr_plan_set_group_max_band", "sbr_tridiag_eigvals_noalloc",
+    "sbr_plan_set_tridiag_band", "sbr_band_to_tridiag", "sbr_plan_set_batch_bands",
 )
 
 STATUS_STALLED = 1      # SBR_STATUS_STALLED
@@ -165,6 +169,25 @@ class Plan:
 
     def set_group_max_band(self, b: int):
         _check(_lib.sbr_plan_set_group_max_band(self._h, int(b)), "sbr_plan_set_group_max_band")
+
+    def set_tridiag_band(self, b: int, variant: int = 0):
+        _check(_lib.sbr_plan_set_tridiag_band(self._h, int(b), int(variant)), "sbr_plan_set_tridiag_band")
+
+    def set_batch_bands(self, table):
+        """Band per size bucket for the batched form with b0 = 0: a list of
+        (n_max, band) pairs, ascending n_max ([] = the built-in rule)."""
+        k = len(table)
+        nm = (_i32 * max(k, 1))(*[int(x) for x, _ in table])
+        bd = (_i32 * max(k, 1))(*[int(y) for _, y in table])
+        _check(_lib.sbr_plan_set_batch_bands(self._h, k, nm, bd), "sbr_plan_set_batch_bands")
+
+    def use_tuned_batch_bands(self, precision="fp64") -> list:
+        """Apply the band table a tuning run stored for this device (see
+        autotune.py); returns the table ([] when there is none)."""
+        from . import autotune
+        table = autotune.batch_table(precision)
+        self.set_batch_bands(table)
+        return table
 
     def set_wait_limit(self, ticks: int):
         _check(_lib.sbr_plan_set_wait_limit(self._h, int(ticks)), "sbr_plan_set_wait_limit")
@@ -250,6 +273,8 @@ def eigvalsh_batched(mats, b0: int = 0, precision="fp64", plan: Plan | None = No
     wps = (_vp * k)(*[_dev_f64(x, "w").value for x in ws])
     if plan is None:
         plan = Plan(max(int(m.shape[0]) for m in mats) if k else 0, k, precision)
+        if b0 == 0:
+            plan.use_tuned_batch_bands(precision)
     rc = _lib.sbr_syev_eigvals_batched(plan.handle, k, ns, aps, ldas, int(b0), _prec(precision),
                                        _stream(stream), wps)
     _check(rc, "sbr_syev_eigvals_batched")
@@ -300,6 +325,14 @@ def band_halve(band: torch.Tensor, b: int, plan: Plan, precision="fp64", stream=
     n, ld = band.shape
     _check(_lib.sbr_band_halve(plan.handle, n, _dev_f64(band, "band"), ld, int(b), _prec(precision),
                                _stream(stream)), "sbr_band_halve")
+    return band
+
+
+def band_to_tridiag(band: torch.Tensor, b: int, plan: Plan, stream=None) -> torch.Tensor:
+    """Band of width b (4, 8, 16) straight to tridiagonal form, in place."""
+    n, ld = band.shape
+    _check(_lib.sbr_band_to_tridiag(plan.handle, n, _dev_f64(band, "band"), ld, int(b), _stream(stream)),
+           "sbr_band_to_tridiag")
     return band
 
 

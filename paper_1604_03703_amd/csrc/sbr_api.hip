@@ -92,6 +92,11 @@ struct sbr_plan_s {
     int chase_max_grid = 0;
     uint64_t wait_ticks = DEFAULT_WAIT_TICKS;
     int group_max_b = DEFAULT_GROUP_MAX_B;
+    int tridiag_from_b = DEFAULT_TRIDIAG_FROM_B;
+    int tri_variant = 0;
+    // batched form, b0 = 0: band per size bucket (ascending order limits);
+    // empty = the built-in rule
+    std::vector<int32_t> bt_nmax, bt_band;
     double *d = nullptr, *e = nullptr, *e2p = nullptr;
     BisectSetup* setup = nullptr;
     double* pcopy = nullptr;   // panel copy for sbr_panel_qr
@@ -462,6 +467,7 @@ StageCtl stage_ctl(sbr_plan_t p) {
     c.wait_ticks = p->wait_ticks;
     c.max_grid = p->chase_max_grid;
     c.group_max_b = p->group_max_b;
+    c.tri_variant = p->tri_variant;
     return c;
 }
 
@@ -475,6 +481,13 @@ int run_band_stages(sbr_plan_t p, int64_t n, const double* A, int64_t lda, int b
     while (b > 1) {
         EventPair ep;
         if (p->timing) { ep.a = p->ev(); p->mark(ep.a, s); }
+        if (b <= p->tridiag_from_b && band_tridiag_supported(b) && n * ld < (int64_t)INT32_MAX) {
+            // Algorithm 4.2 with k = b: the rest of the way in one stage
+            launch_band_tridiag(n, cur, b, ctl, s);
+            if (p->timing) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_stage.push_back(ep); }
+            SBR_CHECK_LAUNCH();
+            break;
+        }
         launch_band_halve(n, cur, ld, b, f32, p->chase_scratch, ctl, s);
         if (p->timing) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_stage.push_back(ep); }
         const int h = b / 2;
@@ -498,6 +511,7 @@ int init_attributes() {
     int rc = init_tsqr_attributes();
     rc |= init_band_group_attributes();
     rc |= init_band_mfma_attributes();
+    rc |= init_band_tridiag_attributes();
     rc |= init_batched_attributes();
     return rc;
 }
@@ -615,6 +629,20 @@ int sbr_plan_status(sbr_plan_t plan, int32_t* status) {
     return 0;
 }
 
+int sbr_plan_set_batch_bands(sbr_plan_t plan, int32_t nbuckets, const int32_t* n_max, const int32_t* bands) {
+    if (!plan) return -1;
+    if (nbuckets < 0) return -2;
+    if (nbuckets > 0 && !n_max) return -3;
+    if (nbuckets > 0 && !bands) return -4;
+    for (int32_t q = 0; q < nbuckets; ++q) {
+        if (n_max[q] < 1 || (q > 0 && n_max[q] <= n_max[q - 1])) return -3;
+        if (bands[q] < 1 || bands[q] > 16 || (bands[q] & (bands[q] - 1))) return -4;
+    }
+    plan->bt_nmax.assign(n_max, n_max + nbuckets);
+    plan->bt_band.assign(bands, bands + nbuckets);
+    return 0;
+}
+
 int sbr_plan_set_wait_limit(sbr_plan_t plan, int64_t ticks) {
     if (!plan) return -1;
     if (ticks < 0) return -2;
@@ -626,6 +654,15 @@ int sbr_plan_set_group_max_band(sbr_plan_t plan, int32_t b) {
     if (!plan) return -1;
     if (b < 0) return -2;
     plan->group_max_b = b;
+    return 0;
+}
+
+int sbr_plan_set_tridiag_band(sbr_plan_t plan, int32_t b, int32_t variant) {
+    if (!plan) return -1;
+    if (b < 0) return -2;
+    if (variant < 0 || variant >= band_tridiag_variants()) return -3;
+    plan->tridiag_from_b = b;
+    plan->tri_variant = variant;
     return 0;
 }
 
@@ -827,8 +864,17 @@ int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n, d
         key.push_back(cnt);
         for (int32_t q = 0; q < cnt; ++q) {
             const int64_t nk = n[order[q]];
-            // band per size bucket: 8 for small matrices, 16 above
-            int bk = b0 ? b0 : (nk <= 96 ? 8 : 16);
+            // band per size bucket: the plan's table (set from a tuning run)
+            // or the built-in rule, 8 for small matrices, 16 above
+            int bk = b0;
+            if (!bk) {
+                bk = (nk <= 96 ? 8 : 16);
+                for (size_t q2 = 0; q2 < plan->bt_nmax.size(); ++q2)
+                    if (nk <= plan->bt_nmax[q2]) {
+                        bk = plan->bt_band[q2];
+                        break;
+                    }
+            }
             while (bk > 1 && bk / 2 >= nk - 1) bk /= 2;
             if (nk <= 2) bk = 1;
             band[q] = bk;
@@ -980,6 +1026,31 @@ int sbr_band_halve(sbr_plan_t plan, int64_t n, double* band, int64_t ldband, int
         launch_band_copy(n, plan->bandA, ld2, (int)(2 * b), band, ldband, s);
     } else {
         return SBR_ENOTSUP;
+    }
+    SBR_CHECK_LAUNCH();
+    return 0;
+}
+
+int sbr_band_to_tridiag(sbr_plan_t plan, int64_t n, double* band, int64_t ldband, int32_t b, sbr_stream_t stream) {
+    if (!plan) return -1;
+    if (n < 0) return -2;
+    if (n > 0 && !band) return -3;
+    if (ldband < 2 * (int64_t)b + 1) return -4;
+    if (!band_tridiag_supported(b)) return -5;
+    if (n < 3) return 0;
+    if (n > INT32_MAX) return SBR_ENOTSUP;
+    const int64_t ld2 = 2 * (int64_t)b + 1;
+    if (n * ld2 >= (int64_t)INT32_MAX) return SBR_ENOTSUP;
+    int rc = ensure_workspace(plan, n, b);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    launch_status_rearm(plan->status, s);
+    if (ldband == ld2) {
+        launch_band_tridiag(n, band, b, stage_ctl(plan), s);
+    } else {
+        launch_band_copy(n, band, ldband, b, plan->bandA, ld2, s);
+        launch_band_tridiag(n, plan->bandA, b, stage_ctl(plan), s);
+        launch_band_copy(n, plan->bandA, ld2, (int)(2 * b), band, ldband, s);
     }
     SBR_CHECK_LAUNCH();
     return 0;

@@ -109,8 +109,14 @@ struct StageCtl {
     uint64_t wait_ticks;
     int max_grid;
     int group_max_b;
+    int tri_variant;     // launch shape of the direct band-to-tridiagonal kernel
 };
 constexpr int DEFAULT_GROUP_MAX_B = 8;
+// Bands b <= this (and b in {4, 8, 16}) go straight to the tridiagonal in one
+// stage instead of being halved further (0: always halve).  Measured at
+// n = 32768: 4 -> 1 direct 129 ms against 4 -> 2 -> 1 138 ms; 8 -> 1 direct
+// 237 ms against 238 ms; 16 -> 1 direct 517 ms against 385 ms.
+constexpr int DEFAULT_TRIDIAG_FROM_B = 4;
 constexpr uint64_t DEFAULT_WAIT_TICKS = 1000000000ull;   // 10 s
 // Whether launch_band_halve handles (n, ldband, b).
 bool band_halve_supported(int64_t n, int64_t ldband, int b);
@@ -145,6 +151,12 @@ int64_t band_mfma_workspace_doubles(int64_t n, int b);
 void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, const StageCtl& ctl,
                             hipStream_t s);
 int init_band_mfma_attributes();
+// ---- sbr_band_tridiag.hip: band b in {4, 8, 16} straight to tridiagonal ----
+// (Algorithm 4.2 with k = b).  Band ld = 2b + 1, n (2b + 1) < 2^31.
+bool band_tridiag_supported(int b);
+int band_tridiag_variants();
+void launch_band_tridiag(int64_t n, double* band, int b, const StageCtl& ctl, hipStream_t s);
+int init_band_tridiag_attributes();
 // ---- sbr_band_group.hip: small bandwidths, sweep groups with LDS windows --
 bool band_group_supported(int b);
 // band ld = 2b + 1, n (2b + 1) < 2^31
