@@ -39,19 +39,20 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def band_stage_bytes(n: int, b: int) -> float:
-    """Algorithmic bytes of one halving b -> b/2 (FP64): every chase reads and
-    writes the entries it touches once (QR block, left block, lower half of
-    the diagonal block, below block), summed over all chases."""
+def band_stage_bytes(n: int, b: int, h: int | None = None) -> float:
+    """Algorithmic bytes of one band stage b -> h (FP64; h = b/2 a halving):
+    every chase reads and writes the entries it touches once (QR block b x h,
+    left block b x (b - h), lower half of the diagonal block, below block),
+    summed over all chases."""
     import numpy as np
-    h = b // 2
+    h = b // 2 if h is None else h
     total = 0
     for i in range(1, (n - 2) // h + 1):
         o = i * h + b * np.arange(0, (n - 2 - i * h) // b + 1, dtype=np.int64)
         nr = np.minimum(n - o, b)
         nbr = np.maximum(0, np.minimum(n, o + 2 * b) - (o + b))
         ent = nr * h + nr * (nr + 1) // 2 + nbr * b
-        ent[1:] += nr[1:] * h            # left block for j > 1
+        ent[1:] += nr[1:] * (b - h)      # left block for j > 1
         total += int(ent.sum())
     return 16.0 * total   # 8 B read + 8 B written per entry
 
@@ -201,11 +202,13 @@ def mean(xs):
     return sum(xs) / max(1, len(xs))
 
 
-def time_band_stage(sbr, torch, n, b, direct, variant, steps, warmup):
+def time_band_stage(sbr, torch, n, b, h, direct, variant, steps, warmup):
     """One band stage alone: a seeded random symmetric band of width b (lower
-    band storage, ld 2b + 1) halved (sbr_band_halve) or, with direct, taken
-    straight to the tridiagonal (sbr_band_to_tridiag); the band is restored
-    from a device copy before every launch (outside the timed region)."""
+    band storage, ld 2b + 1) reduced to width h (sbr_band_reduce; h = b/2 by
+    default) or, with direct, taken straight to the tridiagonal
+    (sbr_band_to_tridiag, launch shape variant); the band is restored from a
+    device copy before every launch (outside the timed region)."""
+    h = 1 if direct else (h or b // 2)
     g = torch.Generator(device="cuda").manual_seed(1604 + b)
     ld = 2 * b + 1
     src = torch.zeros((n, ld), dtype=torch.float64, device="cuda")
@@ -225,19 +228,18 @@ def time_band_stage(sbr, torch, n, b, direct, variant, steps, warmup):
         if direct:
             sbr.band_to_tridiag(bd, b, plan)
         else:
-            sbr.band_halve(bd, b, plan)
+            sbr.band_reduce(bd, b, h, plan)
         e1.record()
         torch.cuda.synchronize()
         if plan.status() != 0:
             raise RuntimeError("band stage reported a stalled wait")
         if it >= warmup:
             ms.append(e0.elapsed_time(e1))
-    by = band_stage_bytes(n, b) if not direct else None
-    out = {"n": n, "b": b, "stage": ("%d->1" % b) if direct else ("%d->%d" % (b, b // 2)),
+    by = band_stage_bytes(n, b, h)
+    out = {"n": n, "b": b, "stage": "%d->%d" % (b, h),
            "variant": variant if direct else None, "ms": [round(x, 3) for x in ms]}
-    if by:
-        out["alg_GB"] = round(by / 1e9, 3)
-        out["GBps"] = round(by / (mean(ms) * 1e-3) / 1e9, 1)
+    out["alg_GB"] = round(by / 1e9, 3)
+    out["GBps"] = round(by / (mean(ms) * 1e-3) / 1e9, 1)
     plan.close()
     return out
 
@@ -312,7 +314,8 @@ def main():
                     help="only run three device-to-device copies of MIB MiB (counter calibration) and exit")
     ap.add_argument("--band-stage", type=int, default=0, metavar="B",
                     help="only time one band stage of width B on a seeded random band of order --n "
-                         "(a halving, or with --direct the reduction straight to tridiagonal) and exit")
+                         "(to width --to, a halving by default, or with --direct straight to tridiagonal) and exit")
+    ap.add_argument("--to", type=int, default=0, metavar="H", help="with --band-stage: the width to reduce to")
     ap.add_argument("--direct", action="store_true", help="with --band-stage: the direct B -> 1 stage")
     ap.add_argument("--variant", type=int, default=0, help="with --band-stage --direct: launch shape")
     args = ap.parse_args()
@@ -339,7 +342,7 @@ def main():
     import paper_1604_03703_amd as sbr
 
     if args.band_stage:
-        print(json.dumps(time_band_stage(sbr, torch, args.n, args.band_stage, args.direct, args.variant,
+        print(json.dumps(time_band_stage(sbr, torch, args.n, args.band_stage, args.to, args.direct, args.variant,
                                          args.steps, args.warmup)), flush=True)
         return
 
@@ -359,6 +362,7 @@ def main():
     fro2 = float(np.sum(A_host * A_host))
 
     plan = sbr.Plan(n, 0, "fp64")
+    widths = plan.band_stages(n, b0)
     times, tims, w, btims = run_form(sbr, torch, A0, n, b0, "fp64", args.steps, args.warmup, plan)
     wh = w.cpu().numpy()
     # properties that hold at any size: sum of eigenvalues = trace, sum of squares = ||A||_F^2
@@ -392,14 +396,15 @@ def main():
     stage_ms = [mean([t["ms_stage"][i] for t in tims]) for i in range(len(tims[0]["ms_stage"]))]
     stages = []
     b = b0
-    for sms in stage_ms:
-        by = band_stage_bytes(n, b)
+    band_bytes = 0.0
+    for sms, h in zip(stage_ms, widths):
+        by = band_stage_bytes(n, b, h)
+        band_bytes += by
         gbps = by / (sms * 1e-3) / 1e9 if sms > 0 else None
-        stages.append({"b": b, "ms": round(sms, 3), "alg_GB": round(by / 1e9, 3),
+        stages.append({"b": b, "h": h, "ms": round(sms, 3), "alg_GB": round(by / 1e9, 3),
                        "GBps": round(gbps, 1) if gbps else None,
                        "frac_hbm": round(gbps / PEAK_HBM, 4) if gbps else None})
-        b //= 2
-    band_bytes = sum(band_stage_bytes(n, 2 ** k) for k in range(1, int(math.log2(b0)) + 1))
+        b = h
 
     result = {
         "metric": METRIC,
@@ -415,7 +420,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "symmetric eigenvalues, n=%d (G+G^T)/2 Gaussian, full-to-band b0=%d, "
-                               "halvings %d->1, Sturm bisection (all n), FP64" % (n, b0, b0),
+                               "band stages %s, Sturm bisection (all n), FP64"
+                               % (n, b0, "->".join(str(x) for x in [b0] + widths)),
                    "n": n, "b0": b0},
         "s_per_solve": round(ms_per_step / 1e3, 4),
         "phases_ms": {"f2b": round(f2b_ms, 3), "band": round(band_ms, 3), "bisect": round(bis_ms, 3)},

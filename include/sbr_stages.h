@@ -60,6 +60,21 @@ int sbr_band_to_tridiag(sbr_plan_t plan, int64_t n, double* band, int64_t ldband
                         sbr_stream_t stream);
 
 /*
+ * One band-to-band reduction b -> h (Algorithm 4.2 with k = b / h, Section
+ * 4.2): same storage conventions as sbr_band_halve (ldband >= 2b + 1, rows
+ * b+1 .. 2b zero on entry); on return the entries at distance > h are
+ * exactly zero.  Kernels exist for h = b/2 (as sbr_band_halve), for h = 1
+ * with b in {4, 8, 16} (as sbr_band_to_tridiag) and for b in {16, 32, 64, 128}
+ * with h = b/k >= 8 (one work-group per sweep, chase products on FP64 MFMA);
+ * -5 for any other (b, h).  Every sweep eliminates h columns, so a stage with
+ * k > 2 does in one pipeline what log2(k) halvings do in several.  FP64 in
+ * both precision forms.  SBR_ENOTSUP for n >= 2^31, and for h = 1 when
+ * n (2b + 1) reaches 2^31.
+ */
+int sbr_band_reduce(sbr_plan_t plan, int64_t n, double* band, int64_t ldband, int32_t b, int32_t h,
+                    sbr_precision prec, sbr_stream_t stream);
+
+/*
  * Panel QR of the m x b panel P (m >= b) by the TSQR tree of Algorithm 3.2
  * followed by Householder reconstruction (Corollary 3.7).  Outputs (device):
  *   Q  m x b explicit orthonormal factor (ld = m), P = Q R,
@@ -106,7 +121,8 @@ typedef struct {
     int64_t syr2k_launches;
     double ms_symm;           /* SYMM launches only */
     int64_t symm_launches;
-    double ms_stage[8];       /* per halving stage (b0, b0/2, ...) */
+    double ms_stage[8];       /* per band-to-band stage, in order (the widths
+                                 come from sbr_plan_get_band_stages) */
     int32_t n_stages;
     double ms_syr2k_big;      /* the bulk SYR2K launches on 128 x 128 tiles
                                  (the first ones; the last, small trailing
@@ -140,6 +156,20 @@ int sbr_plan_set_group_max_band(sbr_plan_t plan, int32_t b);
  * shape of that kernel (lanes per sweep, sweeps per work-group) for it and
  * for sbr_band_to_tridiag; 0 is the default.  -3 for an unknown variant. */
 int sbr_plan_set_tridiag_band(sbr_plan_t plan, int32_t b, int32_t variant);
+
+/* Band widths of a solve's band-to-band stages (Algorithm 4.3 leaves the
+ * choice of k per stage to the machine): widths[0 .. count) strictly
+ * decreasing powers of two.  From the current width b a solve goes to the
+ * largest listed width below b that sbr_band_reduce takes for b (halving when
+ * none does), and it ends with a width of 1.  count = 0 restores the built-in
+ * sequence (chosen by measurement on gfx950).  -2 for a bad count, -3 for a
+ * list that is not strictly decreasing powers of two >= 1. */
+int sbr_plan_set_band_stages(sbr_plan_t plan, int32_t count, const int32_t* widths);
+
+/* The band widths after each band-to-band stage of a solve of order n from
+ * band b0 with the plan's current settings (at most cap of them written to
+ * widths); returns the number of stages or a negative argument error. */
+int sbr_plan_get_band_stages(sbr_plan_t plan, int64_t n, int32_t b0, int32_t* widths, int32_t cap);
 
 /* How long (ticks of the 100 MHz device clock) a pipelined band kernel waits
  * for the previous sweep before it abandons the stage and raises

@@ -79,6 +79,9 @@ def _load():
         "sbr_plan_set_tridiag_band": ([_vp, _i32, _i32], ctypes.c_int),
         "sbr_band_to_tridiag": ([_vp, _i64, _vp, _i64, _i32, _vp], ctypes.c_int),
         "sbr_plan_set_batch_bands": ([_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)], ctypes.c_int),
+        "sbr_band_reduce": ([_vp, _i64, _vp, _i64, _i32, _i32, ctypes.c_int, _vp], ctypes.c_int),
+        "sbr_plan_set_band_stages": ([_vp, _i32, ctypes.POINTER(_i32)], ctypes.c_int),
+        "sbr_plan_get_band_stages": ([_vp, _i64, _i32, ctypes.POINTER(_i32), _i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -96,6 +99,7 @@ EXPORTED = (
     "sbr_plan_set_chase_blocks", "sbr_plan_set_panel_cus", "sbr_plan_status",
     "sbr_plan_set_wait_limit", "sbr_plan_set_group_max_band", "sbr_tridiag_eigvals_noalloc",
     "sbr_plan_set_tridiag_band", "sbr_band_to_tridiag", "sbr_plan_set_batch_bands",
+    "sbr_band_reduce", "sbr_plan_set_band_stages", "sbr_plan_get_band_stages",
 )
 
 STATUS_STALLED = 1      # SBR_STATUS_STALLED
@@ -188,6 +192,22 @@ class Plan:
         table = autotune.batch_table(precision)
         self.set_batch_bands(table)
         return table
+
+    def set_band_stages(self, widths):
+        """Band widths a solve reduces to, in decreasing order (powers of two);
+        [] restores the built-in sequence."""
+        k = len(widths)
+        arr = (_i32 * max(k, 1))(*[int(x) for x in widths])
+        _check(_lib.sbr_plan_set_band_stages(self._h, k, arr), "sbr_plan_set_band_stages")
+
+    def band_stages(self, n: int, b0: int) -> list:
+        """The band width after each band-to-band stage of a solve of order n
+        from band b0 with the current settings."""
+        arr = (_i32 * 32)()
+        rc = _lib.sbr_plan_get_band_stages(self._h, int(n), int(b0), arr, 32)
+        if rc < 0:
+            raise SbrError("sbr_plan_get_band_stages failed with code %d" % rc)
+        return [int(arr[i]) for i in range(min(rc, 32))]
 
     def set_wait_limit(self, ticks: int):
         _check(_lib.sbr_plan_set_wait_limit(self._h, int(ticks)), "sbr_plan_set_wait_limit")
@@ -325,6 +345,14 @@ def band_halve(band: torch.Tensor, b: int, plan: Plan, precision="fp64", stream=
     n, ld = band.shape
     _check(_lib.sbr_band_halve(plan.handle, n, _dev_f64(band, "band"), ld, int(b), _prec(precision),
                                _stream(stream)), "sbr_band_halve")
+    return band
+
+
+def band_reduce(band: torch.Tensor, b: int, h: int, plan: Plan, precision="fp64", stream=None) -> torch.Tensor:
+    """Band of width b reduced to width h = b / k in place (one stage)."""
+    n, ld = band.shape
+    _check(_lib.sbr_band_reduce(plan.handle, n, _dev_f64(band, "band"), ld, int(b), int(h), _prec(precision),
+                                _stream(stream)), "sbr_band_reduce")
     return band
 
 

@@ -93,6 +93,8 @@ struct sbr_plan_s {
     uint64_t wait_ticks = DEFAULT_WAIT_TICKS;
     int group_max_b = DEFAULT_GROUP_MAX_B;
     int tridiag_from_b = DEFAULT_TRIDIAG_FROM_B;
+    // band widths after the band stages (descending; empty = built-in rule)
+    std::vector<int32_t> band_widths;
     int tri_variant = 0;
     // batched form, b0 = 0: band per size bucket (ascending order limits);
     // empty = the built-in rule
@@ -471,7 +473,34 @@ StageCtl stage_ctl(sbr_plan_t p) {
     return c;
 }
 
-// Band halvings from b0 to 1 starting from the lower band of the dense A.
+// Built-in choice of the next band width (the k of each stage of Algorithm
+// 4.3), measured at n = 32768 on gfx950: every stage's pipeline has about
+// 2.5 n / h chase steps on its critical path whatever b is, and a b x h chase
+// on one work-group costs roughly b^2 h MFMA work plus a latency that does not
+// shrink with h, so large bands go down by k > 2 at once.
+int default_next_band(int b) {
+    switch (b) {
+        case 128: return DEFAULT_NEXT_FROM_128;
+        case 64: return DEFAULT_NEXT_FROM_64;
+        case 32: return DEFAULT_NEXT_FROM_32;
+        default: return b / 2;
+    }
+}
+
+// The width a solve reduces band b to next.
+int next_band(sbr_plan_t p, int64_t n, int b) {
+    const int64_t ld = 2 * (int64_t)b + 1;
+    if (!p->band_widths.empty()) {
+        for (int32_t h : p->band_widths)
+            if (h < b && band_reduce_supported(n, ld, b, h)) return h;
+        return b / 2;
+    }
+    if (b <= p->tridiag_from_b && band_reduce_supported(n, ld, b, 1)) return 1;
+    const int h = default_next_band(b);
+    return band_reduce_supported(n, ld, b, h) ? h : b / 2;
+}
+
+// Band-to-band stages from b0 to 1 starting from the lower band of the dense A.
 int run_band_stages(sbr_plan_t p, int64_t n, const double* A, int64_t lda, int b0, bool f32, hipStream_t s) {
     const StageCtl ctl = stage_ctl(p);
     double* cur = p->bandA;
@@ -481,16 +510,11 @@ int run_band_stages(sbr_plan_t p, int64_t n, const double* A, int64_t lda, int b
     while (b > 1) {
         EventPair ep;
         if (p->timing) { ep.a = p->ev(); p->mark(ep.a, s); }
-        if (b <= p->tridiag_from_b && band_tridiag_supported(b) && n * ld < (int64_t)INT32_MAX) {
-            // Algorithm 4.2 with k = b: the rest of the way in one stage
-            launch_band_tridiag(n, cur, b, ctl, s);
-            if (p->timing) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_stage.push_back(ep); }
-            SBR_CHECK_LAUNCH();
-            break;
-        }
-        launch_band_halve(n, cur, ld, b, f32, p->chase_scratch, ctl, s);
+        const int h = next_band(p, n, b);
+        launch_band_reduce(n, cur, ld, b, h, f32, p->chase_scratch, ctl, s);
         if (p->timing) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_stage.push_back(ep); }
-        const int h = b / 2;
+        SBR_CHECK_LAUNCH();
+        if (h == 1 && 2 * h != b) break;   // the direct stage reduced the band in place
         double* nxt = (cur == p->bandA) ? p->bandB : p->bandA;
         const int64_t ldn = 2 * h + 1;
         launch_band_copy(n, cur, ld, h, nxt, ldn, s);
@@ -664,6 +688,32 @@ int sbr_plan_set_tridiag_band(sbr_plan_t plan, int32_t b, int32_t variant) {
     plan->tridiag_from_b = b;
     plan->tri_variant = variant;
     return 0;
+}
+
+int sbr_plan_set_band_stages(sbr_plan_t plan, int32_t count, const int32_t* widths) {
+    if (!plan) return -1;
+    if (count < 0 || count > 16 || (count > 0 && !widths)) return -2;
+    for (int32_t q = 0; q < count; ++q) {
+        const int32_t h = widths[q];
+        if (h < 1 || (h & (h - 1)) || (q > 0 && h >= widths[q - 1])) return -3;
+    }
+    plan->band_widths.assign(widths, widths + count);
+    return 0;
+}
+
+int sbr_plan_get_band_stages(sbr_plan_t plan, int64_t n, int32_t b0, int32_t* widths, int32_t cap) {
+    if (!plan) return -1;
+    if (n < 0) return -2;
+    if (check_band(b0)) return -3;
+    if (cap > 0 && !widths) return -4;
+    int count = 0;
+    for (int b = b0; b > 1;) {
+        const int h = next_band(plan, n, b);
+        if (count < cap) widths[count] = h;
+        ++count;
+        b = h;
+    }
+    return count;
 }
 
 int sbr_plan_set_timing(sbr_plan_t plan, int enable) {
@@ -1027,6 +1077,31 @@ int sbr_band_halve(sbr_plan_t plan, int64_t n, double* band, int64_t ldband, int
     } else {
         return SBR_ENOTSUP;
     }
+    SBR_CHECK_LAUNCH();
+    return 0;
+}
+
+int sbr_band_reduce(sbr_plan_t plan, int64_t n, double* band, int64_t ldband, int32_t b, int32_t h,
+                    sbr_precision prec, sbr_stream_t stream) {
+    if (!plan) return -1;
+    if (n < 0) return -2;
+    if (n > 0 && !band) return -3;
+    if (ldband < 2 * (int64_t)b + 1) return -4;
+    if (check_band(b) || h < 1 || h >= b || b % h) return -5;
+    if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -6;
+    if (2 * h == b) return sbr_band_halve(plan, n, band, ldband, b, prec, stream);
+    if (h == 1) {
+        if (!band_tridiag_supported(b)) return -5;
+        return sbr_band_to_tridiag(plan, n, band, ldband, b, stream);
+    }
+    if (!band_reduce_mfma_supported(b, h)) return -5;
+    if (n < 3) return 0;
+    if (n > INT32_MAX) return SBR_ENOTSUP;
+    int rc = ensure_workspace(plan, n, b);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    launch_status_rearm(plan->status, s);
+    launch_band_reduce_mfma(n, band, ldband, b, h, plan->chase_scratch, stage_ctl(plan), s);
     SBR_CHECK_LAUNCH();
     return 0;
 }

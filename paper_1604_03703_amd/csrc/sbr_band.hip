@@ -1,30 +1,32 @@
-// sbr_band.hip -- band-to-band reduction (Algorithm 4.2 with k = 2) and the
-// band storage helpers.
+// sbr_band.hip -- band-to-band reductions (Algorithm 4.2, b -> h = b / k) and
+// the band storage helpers.
 //
 // Band storage: lower band, column-major by column: band[d + j*ldb] holds
-// B(j + d, j).  A halving stage on bandwidth b = 2h needs ldb >= 2b + 1: a
-// chase fills entries up to distance 2b - 1 below the diagonal.
+// B(j + d, j).  A stage on bandwidth b needs ldb >= 2b + 1: a chase fills
+// entries up to distance 2b - 1 below the diagonal.
 //
-// One halving b -> h.  Sweep i (1-based) eliminates columns [(i-1)h, ih)
+// One reduction b -> h.  Sweep i (1-based) eliminates columns [(i-1)h, ih)
 // below the h-th sub-diagonal and chases the bulge down; chase (i, j) has
 //   o = o_qr.r = ih + (j-1)b,
 //   QR block  rows [o, o + n_r) x cols [o - h, o) for j = 1, [o - b, o - b + h)
 //             for j > 1, n_r = min(n - o, b);
 //   update    rows [o, o + n_r) x cols [o, o + 2b) for j = 1 and
-//             [o - h, o + 2b) for j > 1 (the exact extents; clipped at n);
+//             [o - b + h, o + 2b) for j > 1 (the exact extents; clipped at n);
 // with [U, T, R] = QR(block), the block set to [R; 0], W = B[upd, qr] U T,
 // V = -W, V[qr rows] += 1/2 U T^T U^T W[qr rows], B[qr, upd] += U V^T and
 // B[upd, qr] += V U^T.  Sweep i has chases while o <= n - 2; sweeps run
 // while ih <= n - 2.
 //
-// In lower storage the update splits into the "left" block B[qr, o-h:o]
+// In lower storage the update splits into the "left" block B[qr, o-b+h:o]
 // (j > 1), the diagonal block B[qr, qr] and the "below" block
 // B[o+b:o+2b, qr].
 //
 // The chase kernels themselves are in sbr_chase_mfma.hip (b >= 16, one
-// work-group per sweep, products on MFMA) and sbr_band_group.hip (b <= 8, a
-// group of consecutive sweeps per work-group with the live band in LDS); this
-// file holds the storage kernels and the dispatch.
+// work-group per sweep, products on MFMA, any k with h >= 8),
+// sbr_band_group.hip (halvings of b <= 8, a group of consecutive sweeps per
+// work-group with the live band in LDS) and sbr_band_tridiag.hip (b <= 16
+// straight to the tridiagonal); this file holds the storage kernels and the
+// dispatch.
 #include "sbr_device.h"
 #include "sbr_internal.h"
 
@@ -115,6 +117,23 @@ void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32,
         launch_band_halve_group(n, band, b, ctl, s);
     else if (band_mfma_supported(b))
         launch_band_halve_mfma(n, band, ldband, b, scratch, ctl, s);
+}
+
+bool band_reduce_supported(int64_t n, int64_t ldband, int b, int h) {
+    if (h < 1 || h >= b || b % h) return false;
+    if (2 * h == b) return band_halve_supported(n, ldband, b);
+    if (h == 1) return band_tridiag_supported(b) && ldband == 2 * (int64_t)b + 1 && n * ldband < (int64_t)INT32_MAX;
+    return band_reduce_mfma_supported(b, h);
+}
+
+void launch_band_reduce(int64_t n, double* band, int64_t ldband, int b, int h, bool f32, double* scratch,
+                        const StageCtl& ctl, hipStream_t s) {
+    if (2 * h == b)
+        launch_band_halve(n, band, ldband, b, f32, scratch, ctl, s);
+    else if (h == 1)
+        launch_band_tridiag(n, band, b, ctl, s);
+    else
+        launch_band_reduce_mfma(n, band, ldband, b, h, scratch, ctl, s);
 }
 
 void launch_fill_int(int* p, int64_t count, int v, hipStream_t s) {

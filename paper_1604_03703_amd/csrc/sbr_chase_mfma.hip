@@ -1,22 +1,27 @@
-// sbr_chase_mfma.hip -- one halving b -> h = b/2 of the band (Algorithm 4.2
-// with k = 2) for b in {32, 64, 128}, every product of a chase on FP64 MFMA.
+// sbr_chase_mfma.hip -- one reduction b -> h of the band (Algorithm 4.2,
+// h = b / k) for b in {16, 32, 64, 128} and h in {b/2, b/4, b/8, b/16} (h >= 8),
+// every product of a chase on FP64 MFMA.
 //
 // A chase (i, j) works on the rows [o, o + n_r) of the band, o = ih + (j-1)b
 // (the same offsets and extents as the small-b kernels; chase (i, j) starts
 // after chase (i, j-1) of the same block and after chase (i-1, j+2) has
 // finished its QR block, the only entries the two chases share, so a sweep
-// overlaps the second half of the chase two ahead of it in the previous sweep).
-// With [U, T, R] = QR(QR block) and
-// Q = I - U T U^T:
-//   left block  X_L  (rows [o, o+n_r), cols [o-h, o), j > 1):  X_L <- Q^T X_L
-//   below block X_B  (rows [o+b, o+2b), cols [o, o+n_r)):      X_B <- X_B Q
-//   diagonal    D    (rows and cols [o, o+n_r), symmetric):    D   <- Q^T D Q
+// overlaps the rest of the chase two ahead of it in the previous sweep; this
+// holds for every k: chases of consecutive sweeps three or more apart are
+// 3b - h >= 2b rows apart and touch no common entry).
+// With [U, T, R] = QR(QR block, b x h) and Q = I - U T U^T:
+//   left block  X_L  (rows [o, o+n_r), cols [o-b+h, o), j > 1): X_L <- Q^T X_L
+//   below block X_B  (rows [o+b, o+2b), cols [o, o+n_r)):       X_B <- X_B Q
+//   diagonal    D    (rows and cols [o, o+n_r), symmetric):     D   <- Q^T D Q
 // computed as
 //   X_L -= (U T^T)(U^T X_L)
 //   X_B -= ((X_B U) T) U^T
 //   W = (D U) T,  G = U^T W,  V = 1/2 (U T^T) G - W,  D += U V^T + V U^T.
 // T comes from the identity T^{-1} = diag(1/tau) + strict upper part of U^T U
 // (the compact WY form of a product of reflectors), inverted column by column.
+// The left block is b - h columns wide (h for a halving); the QR block of chase
+// j + 1 and its left block are the first h and the last b - h columns of chase
+// j's below block.
 //
 // Wave w of the block owns the rows [16w, 16w + 16) of every b x h quantity.
 // MFMA 16x16x4 lane layout: with a = R(k0 + l/16, c0 + l%16) and
@@ -25,8 +30,9 @@
 // layout) is, element for element, the b operand of a following product
 // L' R' with L' = that tile; so the chains X_B U -> (.) T -> (.) U^T and
 // D U -> (.) T stay in registers.  Cross-wave quantities (U, T, U^T X_L,
-// U^T W) go through LDS; W goes through LDS (b <= 64) or a per-block global
-// scratch slice (b = 128).
+// U^T W) go through LDS; W goes through LDS or, when LDS is short (b = 128
+// with h >= 32), a per-block global scratch slice.  h < 16 is padded to
+// 16-wide tiles with zero columns.
 //
 // The update of D is split in two wave-local phases separated by a barrier:
 // wave w adds V_w U_X^T to its own tiles (w, X <= w), then U_X V_w^T to the
@@ -54,35 +60,46 @@ struct MChaseArgs {
 
 constexpr int MSWEEP_DONE = 1 << 30;
 
-template <int H>
+template <int B_, int H>
 struct MChase {
-    static constexpr int B = 2 * H;
+    static constexpr int B = B_;
     static constexpr int HP = H < 16 ? 16 : H;   // h rounded up to whole 16-wide tiles
+    static constexpr int HL = B - H;             // width of the left block
+    static constexpr int CL = (HL + 15) / 16;    // its 16-wide tiles
     static constexpr int NW = B / 16;          // one wave per 16-row tile
     static constexpr int NT = 64 * NW;
     static constexpr int RT = B / 16, CT = HP / 16;
     static constexpr int LDU = B + 1, LDH = HP + 1;
-    static constexpr bool WR_LDS = H <= 32;
     // CARRY: the updated below block stays in LDS for the next chase of the
     // sweep (its QR and left blocks), the diagonal and below blocks are loaded
     // into registers right after the wait, and the diagonal update is applied
     // to those registers (V goes through LDS).  One round trip to memory per
     // chase instead of one per block.
-    static constexpr bool CARRY = H <= 32;
+    static constexpr bool CARRY = B <= 64;
     static constexpr int LDX = B + 1;
+    // W (b x h) in LDS unless the block's LDS would run short
+    static constexpr bool WR_LDS = B * HP <= 2048;
     // LDS (doubles): U (b x h), T (h x h; QR staging before T exists), one
-    // h x h exchange buffer (L = T^{-1}, then U^T X_L, then U^T W), W (b x h;
-    // V after G is formed), the carried below block (b x b);
+    // exchange buffer (L = T^{-1}, then U^T X_L (h x (b - h)), then U^T W), W
+    // (b x h; V after G is formed), the carried below block (b x b);
     // for h < 16 the columns h .. 15 are zero padding
+    static constexpr int RW = CL * 16 > HP ? CL * 16 : HP;   // exchange buffer columns
     static constexpr int US = 0;
     static constexpr int TS = US + LDU * HP;
     static constexpr int RS = TS + LDH * HP;
-    static constexpr int WS = RS + LDH * HP;
+    static constexpr int WS = RS + LDH * RW;
     static constexpr int XS = WS + (WR_LDS ? B * HP : 0);
     static constexpr int TOTAL = XS + (CARRY ? B * LDX : 0);
-    static constexpr int TPCQ = 8, RPT = B / TPCQ;   // QR: 8 lanes per column
-    static_assert(H * TPCQ == NT, "QR layout");
+    // QR: TPCQ lanes per column (8 for a halving, at most 16), the threads
+    // t < h TPCQ take part
+    static constexpr int TPCQ = (NT / H) < 16 ? (NT / H) : 16, RPT = B / TPCQ;
+    static constexpr int QRT = H * TPCQ;
+    static_assert(QRT <= NT && QRT % 64 == 0 && RPT * TPCQ == B, "QR layout");
     static_assert(2 * B + H <= LDH * HP, "QR staging fits in the T region");
+    static_assert(TOTAL * 8 <= 160 * 1024, "LDS");
+    // the QR staging (2 b + h doubles from the start of the T region) spills
+    // into T's padding columns, which must be zero again before T is used
+    static constexpr bool TPAD_DIRTY = HP > H && 2 * B + H > LDH * H;
 };
 
 __device__ __forceinline__ sbr_d4 mma(double a, double b, sbr_d4 c) {
@@ -155,11 +172,11 @@ __device__ __forceinline__ void kloop_plain(const LoadF& load, const UseF& use) 
     for (int k0 = 0; k0 < B; k0 += 4) use(k0, load(k0));
 }
 
-template <int H>
-__global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a) {
-    typedef MChase<H> C;
+template <int B_, int H>
+__global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseArgs a) {
+    typedef MChase<B_, H> C;
     constexpr int B = C::B, HP = C::HP, NW = C::NW, RT = C::RT, CT = C::CT, LDU = C::LDU, LDH = C::LDH;
-    constexpr int TPCQ = C::TPCQ, RPT = C::RPT, LDX = C::LDX;
+    constexpr int TPCQ = C::TPCQ, RPT = C::RPT, LDX = C::LDX, HL = C::HL, CL = C::CL;
     constexpr bool CARRY = C::CARRY;
     extern __shared__ double sm[];
     double* Us = sm + C::US;
@@ -238,9 +255,10 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
             // registers of the reflector loop are only ever filled from LDS and
             // the loop never waits on the memory counter, which would also wait
             // for the previous chase's stores.
+            const bool inqr = qc < H;   // wave-uniform (h TPCQ is a multiple of 64)
             {
                 double x[RPT];
-                if (CARRY && j == 1) {
+                if (CARRY && j == 1 && inqr) {
 #pragma unroll
                     for (int r = 0; r < RPT; ++r) {
                         const int row = qs + TPCQ * r;
@@ -250,7 +268,9 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
                     const int row = qs + TPCQ * r;
-                    if (CARRY)
+                    if (!inqr)
+                        x[r] = 0.0;
+                    else if (CARRY)
                         x[r] = (row < nr) ? Xs[row + qc * LDX] : 0.0;
                     else
                         x[r] = (row < nr) ? B_at(o + row, cq + qc) : 0.0;
@@ -300,7 +320,7 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                         if (qs == 0) tau[k] = tk;
                     }
                     __syncthreads();
-                    if (qc > k) {
+                    if (qc > k && inqr) {
                         // tau and v in one round trip to LDS: a zero tau (v is
                         // then finite, its tail zero) leaves x as it is
                         const double tk = tau[k];
@@ -317,14 +337,16 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 }
                 // U (unit lower; a zero column where no reflector was applied)
                 // into LDS, [R; 0] into the band
-                const double tq = tau[qc];
+                if (inqr) {
+                    const double tq = tau[qc];
 #pragma unroll
-                for (int r = 0; r < RPT; ++r) {
-                    const int row = qs + TPCQ * r;
-                    double u = 0.0;
-                    if (tq != 0.0) u = (row == qc) ? 1.0 : ((row > qc) ? x[r] : 0.0);
-                    Us[row + qc * LDU] = u;
-                    if (row < nr) B_at(o + row, cq + qc) = (row <= qc) ? x[r] : 0.0;
+                    for (int r = 0; r < RPT; ++r) {
+                        const int row = qs + TPCQ * r;
+                        double u = 0.0;
+                        if (tq != 0.0) u = (row == qc) ? 1.0 : ((row > qc) ? x[r] : 0.0);
+                        Us[row + qc * LDU] = u;
+                        if (row < nr) B_at(o + row, cq + qc) = (row <= qc) ? x[r] : 0.0;
+                    }
                 }
             }
             // ---- publish the QR block: it is the only part of this chase that
@@ -395,7 +417,7 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
             // the hand-over.  Adding L[i][k] T[k][j] for i >= k is harmless:
             // L is zero below its diagonal and a row's sum is no longer read
             // once its entry is formed.
-            {
+            if (t < 8 * H) {   // wave-uniform: 8 h is a multiple of 64
                 constexpr int M = H / 8;
                 const int jc = t >> 3, s = t & 7;
                 double p[M], tr[M];
@@ -420,6 +442,9 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                     }
                 }
             }
+            if constexpr (C::TPAD_DIRTY) {
+                for (int idx = t; idx < (HP - H) * HP; idx += C::NT) Ts[(idx % HP) + (H + idx / HP) * LDH] = 0.0;
+            }
             __syncthreads();
 
             // ---- 4. Z_w = U_w T^T (row-in-lane, rows of this wave)
@@ -434,10 +459,10 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 
             // ---- 5. left block (j > 1): M_L = U^T X_L into LDS, then X_L -= Z M_L
             if (j > 1) {
-                for (int idx = w; idx < CT * CT; idx += NW) {
+                for (int idx = w; idx < CT * CL; idx += NW) {
                     const int I = idx % CT, J = idx / CT;
-                    const int64_t gc = o - H + J * 16 + li;
-                    const bool colv = J * 16 + li < H;
+                    const int64_t gc = o - HL + J * 16 + li;
+                    const bool colv = J * 16 + li < HL;
                     sbr_d4 acc = zero4();
                     if constexpr (CARRY) {
                         acc = mma_chain<B / 4>(
@@ -461,7 +486,7 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
                 __syncthreads();
                 if (w * 16 < nr) {
 #pragma unroll
-                    for (int J = 0; J < CT; ++J) {
+                    for (int J = 0; J < CL; ++J) {
                         sbr_d4 acc = zero4();
                         if constexpr (CARRY) {
                             acc = mma_chain<CT * 4>(
@@ -479,11 +504,11 @@ __global__ __launch_bounds__(MChase<H>::NT) void chase_mfma_kernel(MChaseArgs a)
 #pragma unroll
                             for (int r = 0; r < 4; ++r) {
                                 const int col = J * 16 + 4 * r + lk;
-                                if (col < H) {
+                                if (col < HL) {
                                     if (CARRY)
-                                        B_at(o + row, o - H + col) = Xs[row + (H + col) * LDX] - acc[r];
+                                        B_at(o + row, o - HL + col) = Xs[row + (H + col) * LDX] - acc[r];
                                     else
-                                        B_at(o + row, o - H + col) -= acc[r];
+                                        B_at(o + row, o - HL + col) -= acc[r];
                                 }
                             }
                         }
@@ -738,11 +763,11 @@ int mchase_grid(int64_t n) {
     return (int)(g < 1 ? 1 : g);
 }
 
-template <int H>
+template <int B, int H>
 void launch_mchase(int64_t n, double* band, int64_t ldb, double* scratch, const sbr::StageCtl& ctl, hipStream_t s) {
     const int64_t nsweeps = (n - 2) / H;
     if (nsweeps < 1) return;
-    typedef MChase<H> C;
+    typedef MChase<B, H> C;
     MChaseArgs a;
     a.n = n;
     a.band = band;
@@ -751,21 +776,28 @@ void launch_mchase(int64_t n, double* band, int64_t ldb, double* scratch, const 
     a.ticket = ctl.flags;
     a.progress = ctl.flags + 1;
     a.gscratch = scratch;
-    a.scratch_stride = (int64_t)C::B * H;
+    a.scratch_stride = (int64_t)C::B * C::HP;
     a.error = ctl.status;
     a.wait_ticks = ctl.wait_ticks;
     sbr::launch_fill_int(ctl.flags, nsweeps + 2, 0, s);
     int grid = mchase_grid<H>(n);
     if (ctl.max_grid > 0 && grid > ctl.max_grid) grid = ctl.max_grid;
-    chase_mfma_kernel<H><<<grid, C::NT, (size_t)C::TOTAL * sizeof(double), s>>>(a);
+    chase_mfma_kernel<B, H><<<grid, C::NT, (size_t)C::TOTAL * sizeof(double), s>>>(a);
 }
 
-template <int H>
+template <int B, int H>
 int set_mchase_attr() {
-    const int bytes = MChase<H>::TOTAL * (int)sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void*)chase_mfma_kernel<H>,
+    const int bytes = MChase<B, H>::TOTAL * (int)sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void*)chase_mfma_kernel<B, H>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e == hipSuccess ? 0 : (int)e;
+}
+
+// global W scratch (doubles) of one (b, h) kernel: its grid's slices
+template <int B, int H>
+int64_t mchase_scratch(int64_t n) {
+    typedef MChase<B, H> C;
+    return C::WR_LDS ? 0 : (int64_t)mchase_grid<H>(n) * C::B * C::HP;
 }
 
 }  // namespace
@@ -774,28 +806,51 @@ namespace sbr {
 
 bool band_mfma_supported(int b) { return b == 16 || b == 32 || b == 64 || b == 128; }
 
-int64_t band_mfma_workspace_doubles(int64_t n, int b) {
-    if (b != 128) return 0;
-    return (int64_t)mchase_grid<64>(n) * MChase<64>::B * 64;
+bool band_reduce_mfma_supported(int b, int h) {
+    if (!band_mfma_supported(b) || h < 8 || h >= b || b % h) return false;
+    return true;
 }
 
-void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, const StageCtl& ctl,
-                            hipStream_t s) {
-    switch (b) {
-        case 16: launch_mchase<8>(n, band, ldband, scratch, ctl, s); break;
-        case 32: launch_mchase<16>(n, band, ldband, scratch, ctl, s); break;
-        case 64: launch_mchase<32>(n, band, ldband, scratch, ctl, s); break;
-        case 128: launch_mchase<64>(n, band, ldband, scratch, ctl, s); break;
+int64_t band_mfma_workspace_doubles(int64_t n, int b) {
+    if (b < 128) return 0;
+    const int64_t a = mchase_scratch<128, 64>(n), c = mchase_scratch<128, 32>(n);
+    return a > c ? a : c;
+}
+
+void launch_band_reduce_mfma(int64_t n, double* band, int64_t ldband, int b, int h, double* scratch,
+                             const StageCtl& ctl, hipStream_t s) {
+    switch (b * 1000 + h) {
+        case 16008: launch_mchase<16, 8>(n, band, ldband, scratch, ctl, s); break;
+        case 32016: launch_mchase<32, 16>(n, band, ldband, scratch, ctl, s); break;
+        case 32008: launch_mchase<32, 8>(n, band, ldband, scratch, ctl, s); break;
+        case 64032: launch_mchase<64, 32>(n, band, ldband, scratch, ctl, s); break;
+        case 64016: launch_mchase<64, 16>(n, band, ldband, scratch, ctl, s); break;
+        case 64008: launch_mchase<64, 8>(n, band, ldband, scratch, ctl, s); break;
+        case 128064: launch_mchase<128, 64>(n, band, ldband, scratch, ctl, s); break;
+        case 128032: launch_mchase<128, 32>(n, band, ldband, scratch, ctl, s); break;
+        case 128016: launch_mchase<128, 16>(n, band, ldband, scratch, ctl, s); break;
+        case 128008: launch_mchase<128, 8>(n, band, ldband, scratch, ctl, s); break;
         default: break;
     }
 }
 
+void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, const StageCtl& ctl,
+                            hipStream_t s) {
+    launch_band_reduce_mfma(n, band, ldband, b, b / 2, scratch, ctl, s);
+}
+
 int init_band_mfma_attributes() {
     int rc = 0;
-    rc |= set_mchase_attr<8>();
-    rc |= set_mchase_attr<16>();
-    rc |= set_mchase_attr<32>();
-    rc |= set_mchase_attr<64>();
+    rc |= set_mchase_attr<16, 8>();
+    rc |= set_mchase_attr<32, 16>();
+    rc |= set_mchase_attr<32, 8>();
+    rc |= set_mchase_attr<64, 32>();
+    rc |= set_mchase_attr<64, 16>();
+    rc |= set_mchase_attr<64, 8>();
+    rc |= set_mchase_attr<128, 64>();
+    rc |= set_mchase_attr<128, 32>();
+    rc |= set_mchase_attr<128, 16>();
+    rc |= set_mchase_attr<128, 8>();
     return rc;
 }
 

@@ -117,11 +117,26 @@ constexpr int DEFAULT_GROUP_MAX_B = 8;
 // n = 32768: 4 -> 1 direct 129 ms against 4 -> 2 -> 1 138 ms; 8 -> 1 direct
 // 237 ms against 238 ms; 16 -> 1 direct 517 ms against 385 ms.
 constexpr int DEFAULT_TRIDIAG_FROM_B = 4;
+// Built-in next band width from 128, 64 and 32 (the rest halve, and bands
+// <= DEFAULT_TRIDIAG_FROM_B go straight to the tridiagonal).  Measured at
+// n = 32768 (ms per stage): 128 -> 64 / 32 / 16 / 8: 209 / 231 / 336 / 625;
+// 64 -> 32 / 16 / 8: 94 / 95 / 150; 32 -> 16 / 8: 83 / 119; 16 -> 8: 146.
+// So 128 -> 32 -> 8 -> 4 -> 1 (569 ms with 8 -> 4 and 4 -> 1) against 750 ms
+// for the halvings.
+constexpr int DEFAULT_NEXT_FROM_128 = 32;
+constexpr int DEFAULT_NEXT_FROM_64 = 8;
+constexpr int DEFAULT_NEXT_FROM_32 = 8;
 constexpr uint64_t DEFAULT_WAIT_TICKS = 1000000000ull;   // 10 s
 // Whether launch_band_halve handles (n, ldband, b).
 bool band_halve_supported(int64_t n, int64_t ldband, int b);
 void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch,
                        const StageCtl& ctl, hipStream_t s);
+// One reduction b -> h (Algorithm 4.2 with k = b / h): a halving (any kernel
+// above), h = 1 (the direct band-to-tridiagonal kernel, ld = 2b + 1) or
+// another k on the MFMA chase kernel.  Band ld >= 2b + 1.
+bool band_reduce_supported(int64_t n, int64_t ldband, int b, int h);
+void launch_band_reduce(int64_t n, double* band, int64_t ldband, int b, int h, bool f32, double* scratch,
+                        const StageCtl& ctl, hipStream_t s);
 // status[1] |= status[0]; status[0] = 0 (device side, capturable).
 void launch_status_rearm(int* status, hipStream_t s);
 void launch_fill_int(int* p, int64_t count, int v, hipStream_t s);
@@ -145,11 +160,15 @@ int batch_f2b_grid();
 void launch_batched(const BatchDesc* desc, int count, int max_b0, int* tickets, double* scratch, hipStream_t s);
 int init_batched_attributes();
 
-// ---- sbr_chase_mfma.hip: b in {32, 64, 128}, chase products on FP64 MFMA --
+// ---- sbr_chase_mfma.hip: b in {16, 32, 64, 128}, chase products on FP64 MFMA
 bool band_mfma_supported(int b);
+// b -> h with h = b / k, k a power of two, h >= 8
+bool band_reduce_mfma_supported(int b, int h);
 int64_t band_mfma_workspace_doubles(int64_t n, int b);
 void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, const StageCtl& ctl,
                             hipStream_t s);
+void launch_band_reduce_mfma(int64_t n, double* band, int64_t ldband, int b, int h, double* scratch,
+                             const StageCtl& ctl, hipStream_t s);
 int init_band_mfma_attributes();
 // ---- sbr_band_tridiag.hip: band b in {4, 8, 16} straight to tridiagonal ----
 // (Algorithm 4.2 with k = b).  Band ld = 2b + 1, n (2b + 1) < 2^31.

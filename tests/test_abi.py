@@ -52,6 +52,9 @@ def test_invalid_arguments_rejected_on_host(sbr):
     assert lib.sbr_plan_create(None, 10, 0, 0) == -1
     assert lib.sbr_gemm(2, 0, 1, 1, 1, 1.0, dummy, 1, dummy, 1, 0.0, dummy, 1, 0, null) == -1
     assert lib.sbr_band_halve(null, 10, dummy, 3, 2, 0, null) == -1
+    assert lib.sbr_band_reduce(null, 10, dummy, 65, 32, 8, 0, null) == -1
+    assert lib.sbr_plan_set_band_stages(null, 0, None) == -1
+    assert lib.sbr_plan_get_band_stages(null, 10, 32, None, 0) == -1
 
 
 def test_unsupported_sizes_rejected_on_host(sbr):

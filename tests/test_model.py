@@ -172,11 +172,11 @@ def _phase_touched(ch):
     return q, M.chase_touched(ch) - q
 
 
-def _phase_conflicts_not_ordered(n, b):
+def _phase_conflicts_not_ordered(n, b, h=None):
     # chase (i, j): its QR phase waits for (i, j-1) complete and for the QR
     # phase of (i-1, j+2) (the whole sweep i-1 when it has no chase j+2);
     # its other phase follows its own QR phase
-    chases = M.chase_list(n, b)
+    chases = M.chase_list(n, b, h)
     last = {}
     for c in chases:
         last[c["i"]] = max(last.get(c["i"], 0), c["j"])
@@ -217,6 +217,17 @@ def test_chase_schedule_after_previous_qr_orders_every_conflict(n, b):
     # chase (i-1, j+2) has finished its QR block (the only entries the two
     # share); every pair of phases that touch a common entry stays ordered
     assert _phase_conflicts_not_ordered(n, b) == 0
+
+
+@pytest.mark.parametrize("n,b,h", [(64, 16, 4), (67, 16, 2), (130, 32, 8), (100, 32, 4), (129, 64, 8),
+                                   (200, 64, 16), (45, 8, 2)])
+def test_chase_schedule_after_previous_qr_general_k(n, b, h):
+    # the same pipeline for b -> h = b / k with k > 2 (one work-group per
+    # sweep, chase (i, j) after the QR phase of (i-1, j+2)): every pair of
+    # phases touching a common entry is still ordered as in the loop nest, so
+    # the below block a work-group keeps for its next chase is not written by
+    # another sweep in between
+    assert _phase_conflicts_not_ordered(n, b, h) == 0
 
 
 def _lockstep_phase_conflicts(n, b, lag, h=None):
