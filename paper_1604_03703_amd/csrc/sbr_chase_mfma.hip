@@ -3,12 +3,16 @@
 // every product of a chase on FP64 MFMA.
 //
 // A chase (i, j) works on the rows [o, o + n_r) of the band, o = ih + (j-1)b
-// (the same offsets and extents as the small-b kernels; chase (i, j) starts
-// after chase (i, j-1) of the same block and after chase (i-1, j+2) has
-// finished its QR block, the only entries the two chases share, so a sweep
-// overlaps the rest of the chase two ahead of it in the previous sweep; this
-// holds for every k: chases of consecutive sweeps three or more apart are
-// 3b - h >= 2b rows apart and touch no common entry).
+// (the same offsets and extents as the small-b kernels).  One work-group runs
+// the chases of a sweep in order.  Chase (i, j > 1) factors its QR block and
+// updates its left block right after chase (i, j-1): both lie in the previous
+// chase's below block and no unfinished chase of sweep i-1 touches them
+// (h <= b/2); chase (i, 1) first waits for the QR block of (i-1, 2).  The
+// diagonal and below blocks wait until chase (i-1, j+2) has finished its QR
+// block (the only entries the two chases share; the left block of (i-1, j+1)
+// is done by then), so a sweep overlaps the rest of the chase two ahead of it
+// in the previous sweep.  This holds for every k: chases of consecutive sweeps
+// three or more apart are 3b - h >= 2b rows apart and touch no common entry.
 // With [U, T, R] = QR(QR block, b x h) and Q = I - U T U^T:
 //   left block  X_L  (rows [o, o+n_r), cols [o-b+h, o), j > 1): X_L <- Q^T X_L
 //   below block X_B  (rows [o+b, o+2b), cols [o, o+n_r)):       X_B <- X_B Q
@@ -214,30 +218,40 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
         __syncthreads();
         if (i > a.nsweeps) break;
         const int64_t nchase = (n - 2 - (int64_t)i * H) / B + 1;
-        for (int64_t j = 1; j <= nchase; ++j) {
-            if (i > 1) {
-                if (t == 0) {
-                    const int need = (int)(j + 2);
-                    const uint64_t t0 = wall_clock64();
-                    while (__hip_atomic_load(&a.progress[i - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                           need) {
-                        __builtin_amdgcn_s_sleep(2);
-                        if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                            abort_sh = 1;
-                            break;
-                        }
-                        if (wall_clock64() - t0 > a.wait_ticks) {
-                            atomicOr(a.error, sbr::STATUS_STALLED);
-                            abort_sh = 1;
-                            break;
-                        }
+        // Wait until sweep i - 1 has published chase `need` (its QR block, or
+        // the whole sweep); true when the stage is abandoned.
+        auto wait_prev = [&](int need) -> bool {
+            if (t == 0) {
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(&a.progress[i - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        abort_sh = 1;
+                        break;
                     }
-                    // one acquire for the block: it invalidates this CU's L1 and
-                    // the XCD's L2, which every wave of the block reads through
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    if (wall_clock64() - t0 > a.wait_ticks) {
+                        atomicOr(a.error, sbr::STATUS_STALLED);
+                        abort_sh = 1;
+                        break;
+                    }
                 }
-                __syncthreads();
-                if (abort_sh) return;
+                // one acquire for the block: it invalidates this CU's L1 and
+                // the XCD's L2, which every wave of the block reads through
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            __syncthreads();
+            return abort_sh != 0;
+        };
+        for (int64_t j = 1; j <= nchase; ++j) {
+            // Schedule (every conflict ordered as in the loop nest; checked on
+            // the model for every k): the QR block of chase (i, j > 1) is the
+            // first h columns of this block's own previous below block and the
+            // left block the rest, which no pending chase of sweep i - 1
+            // touches, so both go ahead at once; chase (i, 1) first waits for
+            // the QR block of (i - 1, 2).  The diagonal and below blocks wait
+            // for the QR block of (i - 1, j + 2).
+            if (i > 1 && j == 1) {
+                if (wait_prev(2)) return;
             }
             const int64_t o = (int64_t)i * H + (j - 1) * B;
             const int nr = (int)((n - o < B) ? (n - o) : B);
@@ -358,27 +372,6 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (t == 0) sbr_store_release(&a.progress[i], (int)j);
-
-            // ---- (CARRY) the chase's diagonal block (full, from the lower
-            // triangle) and below block, row-in-lane: element q of lane l is
-            // (16 w + l%16, 4 q + l/16), loaded together behind the QR block's
-            // publication (loads issued before the QR would make its first
-            // wait on the memory counter wait for them, and for the previous
-            // chase's stores)
-            constexpr int NQ = CARRY ? B / 4 : 1;
-            double dr[NQ], xb[NQ];
-            if (CARRY) {
-                const int row = w * 16 + li;
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    const int col = 4 * q + lk;
-                    double dv = 0.0, bv = 0.0;
-                    if (row < nr && col < nr) dv = (row >= col) ? B_at(o + row, o + col) : B_at(o + col, o + row);
-                    if (row < nbr && col < nr) bv = B_at(o + B + row, o + col);
-                    dr[q] = dv;
-                    xb[q] = bv;
-                }
-            }
 
             // ---- 2. L = T^{-1}: strict upper part of U^T U, tau on the diagonal
             // (the multiplier that replaces 1/tau below; a zero tau gives a zero
@@ -513,6 +506,30 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
                             }
                         }
                     }
+                }
+            }
+
+            // ---- the diagonal and below blocks meet the QR block of chase
+            // (i-1, j+2) and the left block of (i-1, j+1)
+            if (i > 1) {
+                if (wait_prev((int)(j + 2))) return;
+            }
+
+            // ---- (CARRY) the chase's diagonal block (full, from the lower
+            // triangle) and below block, row-in-lane: element q of lane l is
+            // (16 w + l%16, 4 q + l/16), loaded together
+            constexpr int NQ = CARRY ? B / 4 : 1;
+            double dr[NQ], xb[NQ];
+            if (CARRY) {
+                const int row = w * 16 + li;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const int col = 4 * q + lk;
+                    double dv = 0.0, bv = 0.0;
+                    if (row < nr && col < nr) dv = (row >= col) ? B_at(o + row, o + col) : B_at(o + col, o + row);
+                    if (row < nbr && col < nr) bv = B_at(o + B + row, o + col);
+                    dr[q] = dv;
+                    xb[q] = bv;
                 }
             }
 

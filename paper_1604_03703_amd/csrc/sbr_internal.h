@@ -119,11 +119,11 @@ constexpr int DEFAULT_GROUP_MAX_B = 8;
 constexpr int DEFAULT_TRIDIAG_FROM_B = 4;
 // Built-in next band width from 128, 64 and 32 (the rest halve, and bands
 // <= DEFAULT_TRIDIAG_FROM_B go straight to the tridiagonal).  Measured at
-// n = 32768 (ms per stage): 128 -> 64 / 32 / 16 / 8: 209 / 231 / 336 / 625;
-// 64 -> 32 / 16 / 8: 94 / 95 / 150; 32 -> 16 / 8: 83 / 119; 16 -> 8: 146.
-// So 128 -> 32 -> 8 -> 4 -> 1 (569 ms with 8 -> 4 and 4 -> 1) against 750 ms
-// for the halvings.
-constexpr int DEFAULT_NEXT_FROM_128 = 32;
+// n = 32768 (ms per stage): 128 -> 64 / 32 / 16: 164 / 188 / 283; 64 -> 32 /
+// 16 / 8: 70 / 73 / 122; 32 -> 16 / 8: 77 / 117; 16 -> 8: 155; 8 -> 4: 99;
+// 4 -> 1: 117.  So 128 -> 64 -> 8 -> 4 -> 1 (502 ms) against 566 ms for
+// 128 -> 64 -> 32 -> 8 -> ... and 520 ms for 128 -> 32 -> 8 -> ...
+constexpr int DEFAULT_NEXT_FROM_128 = 64;
 constexpr int DEFAULT_NEXT_FROM_64 = 8;
 constexpr int DEFAULT_NEXT_FROM_32 = 8;
 constexpr uint64_t DEFAULT_WAIT_TICKS = 1000000000ull;   // 10 s

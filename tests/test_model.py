@@ -230,6 +230,63 @@ def test_chase_schedule_after_previous_qr_general_k(n, b, h):
     assert _phase_conflicts_not_ordered(n, b, h) == 0
 
 
+def _three_phase_conflicts(n, b, h, lag):
+    # the wide-band kernel's schedule: chase (i, j) in three phases, its QR
+    # block (Q), its left block (L) and its diagonal and below blocks (D).
+    # Q(i, j) follows D(i, j-1) of the same work-group (Q(i, 1) also waits
+    # for Q(i-1, 2)); L follows Q; D follows L and the QR phase of
+    # (i-1, j+lag) (the whole sweep i-1 when it has no such chase)
+    chases = M.chase_list(n, b, h)
+    last = {}
+    for c in chases:
+        last[c["i"]] = max(last.get(c["i"], 0), c["j"])
+
+    def prev_q(i, j):
+        return (i, j, "Q") if j <= last[i] else (i, last[i], "D")
+
+    anc = {}
+
+    def add(node, preds):
+        s = set()
+        for p in preds:
+            s |= anc[p]
+            s.add(p)
+        anc[node] = s
+
+    nodes, sets = [], []
+    for c in chases:
+        i, j = c["i"], c["j"]
+        qp = [(i, j - 1, "D")] if j > 1 else []
+        if i > 1 and j == 1:
+            qp.append(prev_q(i - 1, 2))
+        add((i, j, "Q"), qp)
+        add((i, j, "L"), [(i, j, "Q")])
+        add((i, j, "D"), [(i, j, "L")] + ([prev_q(i - 1, j + lag)] if i > 1 else []))
+        q, r = _phase_touched(c)
+        o = c["qr_rows"][0]
+        left = {e for e in r if e[1] < o}
+        for ph, st in (("Q", q), ("L", left), ("D", r - left)):
+            nodes.append((i, j, ph))
+            sets.append(st)
+    bad = 0
+    for a, c in itertools.combinations(range(len(nodes)), 2):
+        if nodes[a][:2] == nodes[c][:2]:
+            continue
+        if sets[a] & sets[c]:
+            bad += nodes[a] not in anc[nodes[c]] and nodes[c] not in anc[nodes[a]]
+    return bad
+
+
+@pytest.mark.parametrize("n,b,h", [(64, 8, 4), (67, 4, 2), (128, 16, 8), (200, 32, 16), (130, 32, 8),
+                                   (100, 32, 4), (129, 64, 8), (200, 64, 16), (300, 128, 32), (250, 128, 16)])
+def test_chase_schedule_early_qr_and_left_block(n, b, h):
+    # the QR and left blocks of a chase go ahead of the wait for sweep i-1:
+    # every pair of phases touching a common entry is still ordered as in the
+    # loop nest; waiting for (i-1, j+1) instead of (i-1, j+2) is not enough
+    assert _three_phase_conflicts(n, b, h, 2) == 0
+    assert _three_phase_conflicts(n, b, h, 1) > 0
+
+
 def _lockstep_phase_conflicts(n, b, lag, h=None):
     # the small-band pipeline: at step tau every sweep s of a group does chase
     # j = tau - lag*s, first all the QR blocks (phase 0), then the rest (phase 1);
