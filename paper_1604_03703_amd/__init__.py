@@ -269,36 +269,51 @@ def eigvalsh(A: torch.Tensor, b0: int = 0, precision="fp64", plan: Plan | None =
     return w
 
 
+class BatchedSolve:
+    """A prepared batched call: the matrices (solved in place), the output
+    vectors and the plan are checked and marshalled once; every ``run()``
+    hands the same pointer arrays to ``sbr_syev_eigvals_batched``, which then
+    replays its captured launch (the pattern of a self-consistent-field loop
+    that refills the same buffers every iteration)."""
+
+    def __init__(self, mats, b0: int = 0, precision="fp64", plan: Plan | None = None, out=None):
+        k = len(mats)
+        for m in mats:
+            if m.dim() != 2 or m.shape[0] != m.shape[1]:
+                raise ValueError("every matrix must be square")
+            if not _leading_dim(m):
+                raise ValueError("every matrix needs contiguous rows at least n apart (it is solved in place)")
+        if out is None:
+            out = [torch.empty(int(m.shape[0]), dtype=torch.float64, device=m.device) for m in mats]
+        elif len(out) != k:
+            raise ValueError("out must have one vector per matrix")
+        self.mats, self.out = list(mats), list(out)
+        self._k = k
+        self._ns = (_i64 * k)(*[int(m.shape[0]) for m in mats])
+        self._ldas = (_i64 * k)(*[_leading_dim(m) for m in mats])
+        self._aps = (_vp * k)(*[_dev_f64(m, "A").value for m in mats])
+        self._wps = (_vp * k)(*[_dev_f64(x, "w").value for x in self.out])
+        if plan is None:
+            plan = Plan(max(int(m.shape[0]) for m in mats) if k else 0, k, precision)
+            if b0 == 0:
+                plan.use_tuned_batch_bands(precision)
+        self.plan, self._b0, self._prec = plan, int(b0), _prec(precision)
+
+    def run(self, stream=None):
+        rc = _lib.sbr_syev_eigvals_batched(self.plan.handle, self._k, self._ns, self._aps, self._ldas, self._b0,
+                                           self._prec, _stream(stream), self._wps)
+        _check(rc, "sbr_syev_eigvals_batched")
+        return self.out
+
+
 def eigvalsh_batched(mats, b0: int = 0, precision="fp64", plan: Plan | None = None, stream=None, out=None):
     """Eigenvalues of a list of symmetric CUDA float64 matrices (overwritten).
 
     ``out``: optional list of float64 CUDA vectors (one per matrix) to write
     into; with the same matrices and outputs a plan replays its captured
-    launch instead of rebuilding it."""
-    k = len(mats)
-    for m in mats:
-        if m.dim() != 2 or m.shape[0] != m.shape[1]:
-            raise ValueError("every matrix must be square")
-        if not _leading_dim(m):
-            raise ValueError("every matrix needs contiguous rows at least n apart (it is solved in place)")
-    ns = (_i64 * k)(*[int(m.shape[0]) for m in mats])
-    ldas = (_i64 * k)(*[_leading_dim(m) for m in mats])
-    if out is None:
-        ws = [torch.empty(int(m.shape[0]), dtype=torch.float64, device=m.device) for m in mats]
-    else:
-        if len(out) != k:
-            raise ValueError("out must have one vector per matrix")
-        ws = list(out)
-    aps = (_vp * k)(*[_dev_f64(m, "A").value for m in mats])
-    wps = (_vp * k)(*[_dev_f64(x, "w").value for x in ws])
-    if plan is None:
-        plan = Plan(max(int(m.shape[0]) for m in mats) if k else 0, k, precision)
-        if b0 == 0:
-            plan.use_tuned_batch_bands(precision)
-    rc = _lib.sbr_syev_eigvals_batched(plan.handle, k, ns, aps, ldas, int(b0), _prec(precision),
-                                       _stream(stream), wps)
-    _check(rc, "sbr_syev_eigvals_batched")
-    return ws
+    launch instead of rebuilding it (``BatchedSolve`` also keeps the
+    marshalled arguments)."""
+    return BatchedSolve(mats, b0, precision, plan, out).run(stream)
 
 
 def tridiag_eigvals(d: torch.Tensor, e: torch.Tensor | None, stream=None) -> torch.Tensor:
