@@ -45,9 +45,14 @@ typedef enum {
                             FP64 storage with FP32 products if it cannot be
                             allocated); each panel's column block returns to
                             FP64 before its QR, so the panel QR, Householder
-                            norms, R factor and Sturm counts stay FP64.  The
-                            band stages and the batched kernels compute in
-                            FP64 in both forms. */
+                            norms, R factor and Sturm counts stay FP64.  In
+                            the band stages of width b >= 16 the WY
+                            applications of every chase (the products after
+                            T is formed) run on FP32 MFMA with FP32
+                            accumulation; the QR of the bulge, tau and T stay
+                            FP64, the band stays FP64 storage.  Bands b <= 8
+                            (no matrix products) and the batched kernels
+                            compute in FP64 in both forms. */
 } sbr_precision;
 
 enum {

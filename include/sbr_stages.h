@@ -41,7 +41,9 @@ int sbr_dense_to_band(int64_t n, const double* A, int64_t lda, int32_t b,
  * at distances b+1 .. 2b must hold zeros on entry, as sbr_dense_to_band
  * leaves them) is reduced in place to bandwidth b/2.  On return the entries
  * at distance > b/2 are exactly zero.  b: power of two, 2 <= b <= 128.
- * The chases run in FP64 in both precision forms.  For b <= 8 with
+ * prec = SBR_FP32_MFMA: for b >= 16 the WY applications of every chase
+ * run on FP32 MFMA with FP32 accumulation (QR, tau and T in FP64); b <= 8
+ * is FP64 in both forms.  For b <= 8 with
  * ldband != 2b + 1 the band goes through the plan's band buffer (two
  * copies).  SBR_ENOTSUP for n >= 2^31.
  */
@@ -65,10 +67,10 @@ int sbr_band_to_tridiag(sbr_plan_t plan, int64_t n, double* band, int64_t ldband
  * b+1 .. 2b zero on entry); on return the entries at distance > h are
  * exactly zero.  Kernels exist for h = b/2 (as sbr_band_halve), for h = 1
  * with b in {4, 8, 16} (as sbr_band_to_tridiag) and for b in {16, 32, 64, 128}
- * with h = b/k >= 8 (one work-group per sweep, chase products on FP64 MFMA);
+ * with h = b/k >= 8 (one work-group per sweep, chase products on MFMA);
  * -5 for any other (b, h).  Every sweep eliminates h columns, so a stage with
- * k > 2 does in one pipeline what log2(k) halvings do in several.  FP64 in
- * both precision forms.  SBR_ENOTSUP for n >= 2^31, and for h = 1 when
+ * k > 2 does in one pipeline what log2(k) halvings do in several.  prec as
+ * for sbr_band_halve (h = 1 is FP64 in both forms).  SBR_ENOTSUP for n >= 2^31, and for h = 1 when
  * n (2b + 1) reaches 2^31.
  */
 int sbr_band_reduce(sbr_plan_t plan, int64_t n, double* band, int64_t ldband, int32_t b, int32_t h,

@@ -1101,7 +1101,7 @@ int sbr_band_reduce(sbr_plan_t plan, int64_t n, double* band, int64_t ldband, in
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     launch_status_rearm(plan->status, s);
-    launch_band_reduce_mfma(n, band, ldband, b, h, plan->chase_scratch, stage_ctl(plan), s);
+    launch_band_reduce_mfma(n, band, ldband, b, h, prec == SBR_FP32_MFMA, plan->chase_scratch, stage_ctl(plan), s);
     SBR_CHECK_LAUNCH();
     return 0;
 }

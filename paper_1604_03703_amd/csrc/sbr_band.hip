@@ -111,12 +111,13 @@ bool band_halve_supported(int64_t n, int64_t ldband, int b) {
 
 void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch,
                        const StageCtl& ctl, hipStream_t s) {
-    (void)f32;
+    // f32: the MFMA chase's WY applications on FP32 MFMA; the small-b group
+    // kernels (no matrix products) are FP64 in both forms
     const bool group = group_fits(n, ldband, b) && (b <= ctl.group_max_b || !band_mfma_supported(b));
     if (group)
         launch_band_halve_group(n, band, b, ctl, s);
     else if (band_mfma_supported(b))
-        launch_band_halve_mfma(n, band, ldband, b, scratch, ctl, s);
+        launch_band_halve_mfma(n, band, ldband, b, f32, scratch, ctl, s);
 }
 
 bool band_reduce_supported(int64_t n, int64_t ldband, int b, int h) {
@@ -133,7 +134,7 @@ void launch_band_reduce(int64_t n, double* band, int64_t ldband, int b, int h, b
     else if (h == 1)
         launch_band_tridiag(n, band, b, ctl, s);
     else
-        launch_band_reduce_mfma(n, band, ldband, b, h, scratch, ctl, s);
+        launch_band_reduce_mfma(n, band, ldband, b, h, f32, scratch, ctl, s);
 }
 
 void launch_fill_int(int* p, int64_t count, int v, hipStream_t s) {

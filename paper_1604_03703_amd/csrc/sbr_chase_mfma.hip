@@ -42,6 +42,8 @@
 // wave w adds V_w U_X^T to its own tiles (w, X <= w), then U_X V_w^T to the
 // tiles (X >= w, w) of its column; every tile is read-modified-written by at
 // most one wave per phase.
+#include <type_traits>
+
 #include "sbr_device.h"
 #include "sbr_internal.h"
 
@@ -110,13 +112,25 @@ __device__ __forceinline__ sbr_d4 mma(double a, double b, sbr_d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ sbr_d4 zero4() { return sbr_d4{0.0, 0.0, 0.0, 0.0}; }
+// The products of the WY applications take their precision from the
+// accumulator: FP64 MFMA into sbr_d4, or (the FP32-MFMA form) operands
+// rounded to FP32 and FP32 MFMA with FP32 accumulation into sbr_f4.  Both
+// instructions have the same lane layout.
+__device__ __forceinline__ sbr_d4 mmx(double a, double b, sbr_d4 c) { return mma(a, b, c); }
+__device__ __forceinline__ sbr_f4 mmx(double a, double b, sbr_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+}
+template <class Acc>
+__device__ __forceinline__ Acc zacc() {
+    return Acc{0, 0, 0, 0};
+}
 
 // acc + the chain of N products mma(fa(i), fb(i)), i = 0 .. N-1, in that order,
 // with every operand read before the first product: left to itself the
 // compiler issues each product right after its operand's LDS read and a wait
 // for it.  Only where the registers allow it (two operands per step).
-template <int N, class FA, class FB>
-__device__ __forceinline__ sbr_d4 mma_chain(sbr_d4 acc, const FA& fa, const FB& fb) {
+template <int N, class Acc, class FA, class FB>
+__device__ __forceinline__ Acc mma_chain(Acc acc, const FA& fa, const FB& fb) {
     double a[N], b[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -124,7 +138,7 @@ __device__ __forceinline__ sbr_d4 mma_chain(sbr_d4 acc, const FA& fa, const FB& 
         b[i] = fb(i);
     }
 #pragma unroll
-    for (int i = 0; i < N; ++i) acc = mma(a[i], b[i], acc);
+    for (int i = 0; i < N; ++i) acc = mmx(a[i], b[i], acc);
     return acc;
 }
 
@@ -176,9 +190,12 @@ __device__ __forceinline__ void kloop_plain(const LoadF& load, const UseF& use) 
     for (int k0 = 0; k0 < B; k0 += 4) use(k0, load(k0));
 }
 
-template <int B_, int H>
+template <int B_, int H, bool F32>
 __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseArgs a) {
     typedef MChase<B_, H> C;
+    // accumulators of the WY applications (steps 4 - 10); the QR, L = U^T U
+    // and T are FP64 in both forms
+    typedef typename std::conditional<F32, sbr_f4, sbr_d4>::type Acc;
     constexpr int B = C::B, HP = C::HP, NW = C::NW, RT = C::RT, CT = C::CT, LDU = C::LDU, LDH = C::LDH;
     constexpr int TPCQ = C::TPCQ, RPT = C::RPT, LDX = C::LDX, HL = C::HL, CL = C::CL;
     constexpr bool CARRY = C::CARRY;
@@ -195,6 +212,13 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int li = lane & 15, lk = lane >> 4;
+    // Accumulator element r of a WY product lies in column ocol(r) of its
+    // 16 x 16 tile (row li): 4 r + lk for FP64 MFMA, 4 lk + r for FP32 MFMA.
+    // A register-held operand (an accumulator, or a block loaded in that
+    // layout) feeds k-step q of a following product, whose other operand is
+    // then read at k = kq(q): the same k in both operands of every step.
+    auto ocol = [&](int r) { return F32 ? 4 * lk + r : 4 * r + lk; };
+    auto kq = [&](int q) { return 16 * (q >> 2) + ocol(q & 3); };
     const int qc = t / TPCQ, qs = t % TPCQ;
     const int64_t n = a.n, ldb = a.ldb;
     double* band = a.band;
@@ -441,13 +465,13 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
             __syncthreads();
 
             // ---- 4. Z_w = U_w T^T (row-in-lane, rows of this wave)
-            sbr_d4 Z[CT];
+            Acc Z[CT];
 #pragma unroll
             for (int J = 0; J < CT; ++J) {
-                Z[J] = zero4();
+                Z[J] = zacc<Acc>();
 #pragma unroll
                 for (int k0 = J * 16; k0 < HP; k0 += 4)     // T^T(k, c) = 0 for k < c
-                    Z[J] = mma(Ts[(J * 16 + li) + (k0 + lk) * LDH], Us[(w * 16 + li) + (k0 + lk) * LDU], Z[J]);
+                    Z[J] = mmx(Ts[(J * 16 + li) + (k0 + lk) * LDH], Us[(w * 16 + li) + (k0 + lk) * LDU], Z[J]);
             }
 
             // ---- 5. left block (j > 1): M_L = U^T X_L into LDS, then X_L -= Z M_L
@@ -456,7 +480,7 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
                     const int I = idx % CT, J = idx / CT;
                     const int64_t gc = o - HL + J * 16 + li;
                     const bool colv = J * 16 + li < HL;
-                    sbr_d4 acc = zero4();
+                    Acc acc = zacc<Acc>();
                     if constexpr (CARRY) {
                         acc = mma_chain<B / 4>(
                             acc,
@@ -471,32 +495,32 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
                                 const int row = k0 + lk;
                                 return (row < nr && colv) ? B_at(o + row, gc) : 0.0;
                             },
-                            [&](int k0, double av) { acc = mma(av, Us[(k0 + lk) + (I * 16 + li) * LDU], acc); });
+                            [&](int k0, double av) { acc = mmx(av, Us[(k0 + lk) + (I * 16 + li) * LDU], acc); });
                     }
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) Rs[(I * 16 + li) + (J * 16 + 4 * r + lk) * LDH] = acc[r];
+                    for (int r = 0; r < 4; ++r) Rs[(I * 16 + li) + (J * 16 + ocol(r)) * LDH] = acc[r];
                 }
                 __syncthreads();
                 if (w * 16 < nr) {
 #pragma unroll
                     for (int J = 0; J < CL; ++J) {
-                        sbr_d4 acc = zero4();
+                        Acc acc = zacc<Acc>();
                         if constexpr (CARRY) {
                             acc = mma_chain<CT * 4>(
-                                acc, [&](int i) { return Rs[(4 * i + lk) + (J * 16 + li) * LDH]; },
+                                acc, [&](int i) { return Rs[kq(i) + (J * 16 + li) * LDH]; },
                                 [&](int i) { return Z[i / 4][i % 4]; });
                         } else {
 #pragma unroll
                             for (int K = 0; K < CT; ++K)
 #pragma unroll
                                 for (int r4 = 0; r4 < 4; ++r4)
-                                    acc = mma(Rs[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], Z[K][r4], acc);
+                                    acc = mmx(Rs[(K * 16 + ocol(r4)) + (J * 16 + li) * LDH], Z[K][r4], acc);
                         }
                         const int row = w * 16 + li;
                         if (row < nr) {
 #pragma unroll
                             for (int r = 0; r < 4; ++r) {
-                                const int col = J * 16 + 4 * r + lk;
+                                const int col = J * 16 + ocol(r);
                                 if (col < HL) {
                                     if (CARRY)
                                         B_at(o + row, o - HL + col) = Xs[row + (H + col) * LDX] - acc[r];
@@ -524,7 +548,7 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
                 const int row = w * 16 + li;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
-                    const int col = 4 * q + lk;
+                    const int col = kq(q);
                     double dv = 0.0, bv = 0.0;
                     if (row < nr && col < nr) dv = (row >= col) ? B_at(o + row, o + col) : B_at(o + col, o + row);
                     if (row < nbr && col < nr) bv = B_at(o + B + row, o + col);
@@ -536,20 +560,20 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
             // ---- 6. below block: P = X_B U, W_B = P T, X_B -= W_B U^T
             if (w * 16 < nbr) {
                 const int row = w * 16 + li;
-                sbr_d4 P[CT];
+                Acc P[CT];
 #pragma unroll
-                for (int J = 0; J < CT; ++J) P[J] = zero4();
+                for (int J = 0; J < CT; ++J) P[J] = zacc<Acc>();
                 if constexpr (CARRY) {
                     // every U operand read from LDS before the first product
                     double ua[B / 4][CT];
 #pragma unroll
                     for (int q = 0; q < B / 4; ++q)
 #pragma unroll
-                        for (int J = 0; J < CT; ++J) ua[q][J] = Us[(4 * q + lk) + (J * 16 + li) * LDU];
+                        for (int J = 0; J < CT; ++J) ua[q][J] = Us[kq(q) + (J * 16 + li) * LDU];
 #pragma unroll
                     for (int q = 0; q < B / 4; ++q)
 #pragma unroll
-                        for (int J = 0; J < CT; ++J) P[J] = mma(ua[q][J], xb[q], P[J]);
+                        for (int J = 0; J < CT; ++J) P[J] = mmx(ua[q][J], xb[q], P[J]);
                 } else {
                     kloop_plain<B>(
                         [&](int k0) {
@@ -558,32 +582,32 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
                         },
                         [&](int k0, double bv) {
 #pragma unroll
-                            for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
+                            for (int J = 0; J < CT; ++J) P[J] = mmx(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
                         });
                 }
-                sbr_d4 WB[CT];
+                Acc WB[CT];
 #pragma unroll
                 for (int J = 0; J < CT; ++J) {
-                    WB[J] = zero4();
+                    WB[J] = zacc<Acc>();
 #pragma unroll
                     for (int K = 0; K <= J; ++K)                // T(k, c) = 0 for k > c
 #pragma unroll
                         for (int r4 = 0; r4 < 4; ++r4)
-                            WB[J] = mma(Ts[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], P[K][r4], WB[J]);
+                            WB[J] = mmx(Ts[(K * 16 + ocol(r4)) + (J * 16 + li) * LDH], P[K][r4], WB[J]);
                 }
                 for (int X = 0; X < RT; ++X) {
                     if (X * 16 >= nr) break;
-                    sbr_d4 acc = zero4();
+                    Acc acc = zacc<Acc>();
                     if constexpr (CARRY) {
                         acc = mma_chain<CT * 4>(
-                            acc, [&](int i) { return Us[(X * 16 + li) + (4 * i + lk) * LDU]; },
+                            acc, [&](int i) { return Us[(X * 16 + li) + kq(i) * LDU]; },
                             [&](int i) { return WB[i / 4][i % 4]; });
                     } else {
 #pragma unroll
                         for (int K = 0; K < CT; ++K)
 #pragma unroll
                             for (int r4 = 0; r4 < 4; ++r4)
-                                acc = mma(Us[(X * 16 + li) + (K * 16 + 4 * r4 + lk) * LDU], WB[K][r4], acc);
+                                acc = mmx(Us[(X * 16 + li) + (K * 16 + ocol(r4)) * LDU], WB[K][r4], acc);
                     }
                     if (CARRY) {
 #pragma unroll
@@ -591,7 +615,7 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
                     } else if (row < nbr) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            const int col = X * 16 + 4 * r + lk;
+                            const int col = X * 16 + ocol(r);
                             if (col < nr) B_at(o + B + row, o + col) -= acc[r];
                         }
                     }
@@ -599,23 +623,23 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
             }
 
             // ---- 7. diagonal block: W_w = (D_w U) T, to the exchange buffer
-            sbr_d4 WR[CT];
+            Acc WR[CT];
             {
                 const int row = w * 16 + li;
-                sbr_d4 P[CT];
+                Acc P[CT];
 #pragma unroll
-                for (int J = 0; J < CT; ++J) P[J] = zero4();
+                for (int J = 0; J < CT; ++J) P[J] = zacc<Acc>();
                 if constexpr (CARRY) {
                     // every U operand read from LDS before the first product
                     double ua[B / 4][CT];
 #pragma unroll
                     for (int q = 0; q < B / 4; ++q)
 #pragma unroll
-                        for (int J = 0; J < CT; ++J) ua[q][J] = Us[(4 * q + lk) + (J * 16 + li) * LDU];
+                        for (int J = 0; J < CT; ++J) ua[q][J] = Us[kq(q) + (J * 16 + li) * LDU];
 #pragma unroll
                     for (int q = 0; q < B / 4; ++q)
 #pragma unroll
-                        for (int J = 0; J < CT; ++J) P[J] = mma(ua[q][J], dr[q], P[J]);
+                        for (int J = 0; J < CT; ++J) P[J] = mmx(ua[q][J], dr[q], P[J]);
                 } else {
                     kloop_plain<B>(
                         [&](int k0) {
@@ -626,19 +650,19 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
                         },
                         [&](int k0, double bv) {
 #pragma unroll
-                            for (int J = 0; J < CT; ++J) P[J] = mma(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
+                            for (int J = 0; J < CT; ++J) P[J] = mmx(Us[(k0 + lk) + (J * 16 + li) * LDU], bv, P[J]);
                         });
                 }
 #pragma unroll
                 for (int J = 0; J < CT; ++J) {
-                    WR[J] = zero4();
+                    WR[J] = zacc<Acc>();
 #pragma unroll
                     for (int K = 0; K <= J; ++K)
 #pragma unroll
                         for (int r4 = 0; r4 < 4; ++r4)
-                            WR[J] = mma(Ts[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], P[K][r4], WR[J]);
+                            WR[J] = mmx(Ts[(K * 16 + ocol(r4)) + (J * 16 + li) * LDH], P[K][r4], WR[J]);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) Wsc[row + (J * 16 + 4 * r + lk) * B] = WR[J][r];
+                    for (int r = 0; r < 4; ++r) Wsc[row + (J * 16 + ocol(r)) * B] = WR[J][r];
                 }
             }
             __syncthreads();
@@ -650,7 +674,7 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
                 const int row = w * 16 + li;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
-                    const int col = 4 * q + lk;
+                    const int col = kq(q);
                     Xs[row + col * LDX] = xb[q];
                     if (j == nchase && row < nbr && col < nr) B_at(o + B + row, o + col) = xb[q];
                 }
@@ -659,7 +683,7 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
             // ---- 8. G = U^T W into LDS (the left block is done with it)
             for (int idx = w; idx < CT * CT; idx += NW) {
                 const int I = idx % CT, J = idx / CT;
-                sbr_d4 acc = zero4();
+                Acc acc = zacc<Acc>();
                 if constexpr (CARRY) {
                     acc = mma_chain<B / 4>(
                         acc, [&](int i) { return Wsc[(4 * i + lk) + (J * 16 + li) * B]; },
@@ -667,28 +691,28 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
                 } else {
 #pragma unroll 8
                     for (int k0 = 0; k0 < B; k0 += 4)
-                        acc = mma(Wsc[(k0 + lk) + (J * 16 + li) * B], Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
+                        acc = mmx(Wsc[(k0 + lk) + (J * 16 + li) * B], Us[(k0 + lk) + (I * 16 + li) * LDU], acc);
                 }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) Rs[(I * 16 + li) + (J * 16 + 4 * r + lk) * LDH] = acc[r];
+                for (int r = 0; r < 4; ++r) Rs[(I * 16 + li) + (J * 16 + ocol(r)) * LDH] = acc[r];
             }
             __syncthreads();
 
             // ---- 9. V_w = 1/2 Z_w G - W_w
-            sbr_d4 V[CT];
+            Acc V[CT];
 #pragma unroll
             for (int J = 0; J < CT; ++J) {
-                sbr_d4 acc = zero4();
+                Acc acc = zacc<Acc>();
                 if constexpr (CARRY) {
                     acc = mma_chain<CT * 4>(
-                        acc, [&](int i) { return Rs[(4 * i + lk) + (J * 16 + li) * LDH]; },
+                        acc, [&](int i) { return Rs[kq(i) + (J * 16 + li) * LDH]; },
                         [&](int i) { return Z[i / 4][i % 4]; });
                 } else {
 #pragma unroll
                     for (int K = 0; K < CT; ++K)
 #pragma unroll
                         for (int r4 = 0; r4 < 4; ++r4)
-                            acc = mma(Rs[(K * 16 + 4 * r4 + lk) + (J * 16 + li) * LDH], Z[K][r4], acc);
+                            acc = mmx(Rs[(K * 16 + ocol(r4)) + (J * 16 + li) * LDH], Z[K][r4], acc);
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) V[J][r] = 0.5 * acc[r] - WR[J][r];
@@ -703,20 +727,20 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
 #pragma unroll
                 for (int J = 0; J < CT; ++J)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) Vs[row + (J * 16 + 4 * r + lk) * B] = V[J][r];
+                    for (int r = 0; r < 4; ++r) Vs[row + (J * 16 + ocol(r)) * B] = V[J][r];
                 __syncthreads();
 #pragma unroll
                 for (int X = 0; X < RT; ++X) {
                     if (X > w || X * 16 >= nr) break;
-                    sbr_d4 acc = mma_chain<CT * 4>(
-                        zero4(), [&](int i) { return Us[(X * 16 + li) + (4 * i + lk) * LDU]; },
+                    Acc acc = mma_chain<CT * 4>(
+                        zacc<Acc>(), [&](int i) { return Us[(X * 16 + li) + kq(i) * LDU]; },
                         [&](int i) { return V[i / 4][i % 4]; });
                     acc = mma_chain<HP / 4>(
                         acc, [&](int i) { return Vs[(X * 16 + li) + (4 * i + lk) * B]; },
                         [&](int i) { return Us[row + (4 * i + lk) * LDU]; });
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int col = X * 16 + 4 * r + lk;
+                        const int col = X * 16 + ocol(r);
                         if (row < nr && col <= row) B_at(o + row, o + col) = dr[4 * X + r] + acc[r];
                     }
                 }
@@ -726,16 +750,16 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
             if (w * 16 < nr) {
                 const int row = w * 16 + li;
                 for (int X = 0; X <= w; ++X) {
-                    sbr_d4 acc = zero4();
+                    Acc acc = zacc<Acc>();
 #pragma unroll
                     for (int K = 0; K < CT; ++K)
 #pragma unroll
                         for (int r4 = 0; r4 < 4; ++r4)
-                            acc = mma(Us[(X * 16 + li) + (K * 16 + 4 * r4 + lk) * LDU], V[K][r4], acc);
+                            acc = mmx(Us[(X * 16 + li) + (K * 16 + ocol(r4)) * LDU], V[K][r4], acc);
                     if (row < nr) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            const int col = X * 16 + 4 * r + lk;
+                            const int col = X * 16 + ocol(r);
                             if (col <= row) B_at(o + row, o + col) += acc[r];
                         }
                     }
@@ -744,17 +768,17 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
             __syncthreads();
             for (int X = w; X < RT; ++X) {
                 if (X * 16 >= nr) break;
-                sbr_d4 acc = zero4();
+                Acc acc = zacc<Acc>();
 #pragma unroll
                 for (int K = 0; K < CT; ++K)
 #pragma unroll
                     for (int r4 = 0; r4 < 4; ++r4)
-                        acc = mma(V[K][r4], Us[(X * 16 + li) + (K * 16 + 4 * r4 + lk) * LDU], acc);
+                        acc = mmx(V[K][r4], Us[(X * 16 + li) + (K * 16 + ocol(r4)) * LDU], acc);
                 const int row = X * 16 + li;
                 if (row < nr) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int col = w * 16 + 4 * r + lk;
+                        const int col = w * 16 + ocol(r);
                         if (col <= row) B_at(o + row, o + col) += acc[r];
                     }
                 }
@@ -780,7 +804,7 @@ int mchase_grid(int64_t n) {
     return (int)(g < 1 ? 1 : g);
 }
 
-template <int B, int H>
+template <int B, int H, bool F32>
 void launch_mchase(int64_t n, double* band, int64_t ldb, double* scratch, const sbr::StageCtl& ctl, hipStream_t s) {
     const int64_t nsweeps = (n - 2) / H;
     if (nsweeps < 1) return;
@@ -799,14 +823,17 @@ void launch_mchase(int64_t n, double* band, int64_t ldb, double* scratch, const 
     sbr::launch_fill_int(ctl.flags, nsweeps + 2, 0, s);
     int grid = mchase_grid<H>(n);
     if (ctl.max_grid > 0 && grid > ctl.max_grid) grid = ctl.max_grid;
-    chase_mfma_kernel<B, H><<<grid, C::NT, (size_t)C::TOTAL * sizeof(double), s>>>(a);
+    chase_mfma_kernel<B, H, F32><<<grid, C::NT, (size_t)C::TOTAL * sizeof(double), s>>>(a);
 }
 
 template <int B, int H>
 int set_mchase_attr() {
     const int bytes = MChase<B, H>::TOTAL * (int)sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void*)chase_mfma_kernel<B, H>,
+    hipError_t e = hipFuncSetAttribute((const void*)chase_mfma_kernel<B, H, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)chase_mfma_kernel<B, H, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e == hipSuccess ? 0 : (int)e;
 }
 
@@ -834,26 +861,35 @@ int64_t band_mfma_workspace_doubles(int64_t n, int b) {
     return a > c ? a : c;
 }
 
-void launch_band_reduce_mfma(int64_t n, double* band, int64_t ldband, int b, int h, double* scratch,
-                             const StageCtl& ctl, hipStream_t s) {
+template <bool F32>
+void launch_band_reduce_mfma_t(int64_t n, double* band, int64_t ldband, int b, int h, double* scratch,
+                               const StageCtl& ctl, hipStream_t s) {
     switch (b * 1000 + h) {
-        case 16008: launch_mchase<16, 8>(n, band, ldband, scratch, ctl, s); break;
-        case 32016: launch_mchase<32, 16>(n, band, ldband, scratch, ctl, s); break;
-        case 32008: launch_mchase<32, 8>(n, band, ldband, scratch, ctl, s); break;
-        case 64032: launch_mchase<64, 32>(n, band, ldband, scratch, ctl, s); break;
-        case 64016: launch_mchase<64, 16>(n, band, ldband, scratch, ctl, s); break;
-        case 64008: launch_mchase<64, 8>(n, band, ldband, scratch, ctl, s); break;
-        case 128064: launch_mchase<128, 64>(n, band, ldband, scratch, ctl, s); break;
-        case 128032: launch_mchase<128, 32>(n, band, ldband, scratch, ctl, s); break;
-        case 128016: launch_mchase<128, 16>(n, band, ldband, scratch, ctl, s); break;
-        case 128008: launch_mchase<128, 8>(n, band, ldband, scratch, ctl, s); break;
+        case 16008: launch_mchase<16, 8, F32>(n, band, ldband, scratch, ctl, s); break;
+        case 32016: launch_mchase<32, 16, F32>(n, band, ldband, scratch, ctl, s); break;
+        case 32008: launch_mchase<32, 8, F32>(n, band, ldband, scratch, ctl, s); break;
+        case 64032: launch_mchase<64, 32, F32>(n, band, ldband, scratch, ctl, s); break;
+        case 64016: launch_mchase<64, 16, F32>(n, band, ldband, scratch, ctl, s); break;
+        case 64008: launch_mchase<64, 8, F32>(n, band, ldband, scratch, ctl, s); break;
+        case 128064: launch_mchase<128, 64, F32>(n, band, ldband, scratch, ctl, s); break;
+        case 128032: launch_mchase<128, 32, F32>(n, band, ldband, scratch, ctl, s); break;
+        case 128016: launch_mchase<128, 16, F32>(n, band, ldband, scratch, ctl, s); break;
+        case 128008: launch_mchase<128, 8, F32>(n, band, ldband, scratch, ctl, s); break;
         default: break;
     }
 }
 
-void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, const StageCtl& ctl,
-                            hipStream_t s) {
-    launch_band_reduce_mfma(n, band, ldband, b, b / 2, scratch, ctl, s);
+void launch_band_reduce_mfma(int64_t n, double* band, int64_t ldband, int b, int h, bool f32, double* scratch,
+                             const StageCtl& ctl, hipStream_t s) {
+    if (f32)
+        launch_band_reduce_mfma_t<true>(n, band, ldband, b, h, scratch, ctl, s);
+    else
+        launch_band_reduce_mfma_t<false>(n, band, ldband, b, h, scratch, ctl, s);
+}
+
+void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch,
+                            const StageCtl& ctl, hipStream_t s) {
+    launch_band_reduce_mfma(n, band, ldband, b, b / 2, f32, scratch, ctl, s);
 }
 
 int init_band_mfma_attributes() {

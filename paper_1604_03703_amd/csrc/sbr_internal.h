@@ -165,9 +165,11 @@ bool band_mfma_supported(int b);
 // b -> h with h = b / k, k a power of two, h >= 8
 bool band_reduce_mfma_supported(int b, int h);
 int64_t band_mfma_workspace_doubles(int64_t n, int b);
-void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, double* scratch, const StageCtl& ctl,
-                            hipStream_t s);
-void launch_band_reduce_mfma(int64_t n, double* band, int64_t ldband, int b, int h, double* scratch,
+// f32: the WY applications (every product after T is formed) on FP32 MFMA
+// with FP32 accumulation; QR, tau, U^T U and T stay FP64
+void launch_band_halve_mfma(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch,
+                            const StageCtl& ctl, hipStream_t s);
+void launch_band_reduce_mfma(int64_t n, double* band, int64_t ldband, int b, int h, bool f32, double* scratch,
                              const StageCtl& ctl, hipStream_t s);
 int init_band_mfma_attributes();
 // ---- sbr_band_tridiag.hip: band b in {4, 8, 16} straight to tridiagonal ----

@@ -123,3 +123,26 @@ def test_solver_with_band_stage_sequence(sbr, oracle_mod, n, b0, widths, expect)
     err = np.max(np.abs(w.cpu().numpy() - ref))
     print("stages %s max err %.3e" % (seq, err / _norm2(ref)), flush=True)
     assert err <= 1e-11 * _norm2(ref)
+
+
+@pytest.mark.parametrize("b,h", PAIRS)
+@pytest.mark.parametrize("n", [300, 1337])
+def test_band_reduce_fp32_form(sbr, oracle_mod, b, h, n):
+    # the FP32-MFMA form: the WY applications of every chase on FP32 MFMA
+    # (QR, tau and T in FP64); the band structure stays exact and the
+    # spectrum is kept to the FP32 form's bar
+    print("band reduce fp32 n=%d b=%d h=%d" % (n, b, h), flush=True)
+    rng = np.random.default_rng(52000 + 3 * b + h + n)
+    A = random_band(n, b, rng)
+    ref = oracle_mod.eigvalsh(A)
+    plan = sbr.Plan(0)
+    bd = torch.from_numpy(_band_storage(A, b, 2 * b + 1)).cuda()
+    sbr.band_reduce(bd, b, h, plan, precision="fp32_mfma")
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    out = bd.cpu().numpy()
+    assert np.all(out[:, h + 1:] == 0.0)
+    w = oracle_mod.eigvalsh(band_to_dense(out, n, keep=h))
+    err = np.max(np.abs(w - ref)) / _norm2(ref)
+    print("  max err %.3e (x ||A||_2)" % err, flush=True)
+    assert err <= 2e-5
