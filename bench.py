@@ -367,6 +367,9 @@ def main():
     fro2 = float(np.sum(A_host * A_host))
 
     plan = sbr.Plan(n, 0, "fp64")
+    # band-stage sequence: the autotuner's table for this device when there
+    # is one (tuning/stages.json), else the library's built-in choice
+    stage_src = "tuned" if plan.use_tuned_stages(n, b0, "fp64") else "built-in"
     widths = plan.band_stages(n, b0)
     times, tims, w, btims = run_form(sbr, torch, A0, n, b0, "fp64", args.steps, args.warmup, plan)
     wh = w.cpu().numpy()
@@ -436,6 +439,7 @@ def main():
                            "panel_and_other": round(mean([t["ms_f2b"] for t in btims]) - symm_ms - syr2k_ms, 3),
                            "measured_in": "warmup steps (every event pair recorded)"},
         "band_stages": stages,
+        "band_stage_source": stage_src,
         "band_GBps_alg": round(band_bytes / (band_ms * 1e-3) / 1e9, 1) if band_ms > 0 else None,
         "checks": {"trace_rel": tr_err, "frobenius_rel": fr_err},
         "band_frac_hbm": round(band_bytes / (band_ms * 1e-3) / 1e9 / PEAK_HBM, 4) if band_ms > 0 else None,
@@ -454,6 +458,8 @@ def main():
 
     if not args.no_fp32:
         plan32 = sbr.Plan(n, 0, "fp32_mfma")
+        if not plan32.use_tuned_stages(n, b0, "fp32_mfma"):
+            plan32.use_tuned_stages(n, b0, "fp64")
         t32, tim32, w32, wt32 = run_form(sbr, torch, A0, n, b0, "fp32_mfma", args.steps, args.warmup, plan32)
         f2b32 = mean([t["ms_f2b"] for t in tim32])
         d = np.abs(w32.cpu().numpy() - wh)
@@ -468,6 +474,9 @@ def main():
             "speedup_f2b": round(f2b_ms / f2b32, 3) if f2b32 > 0 else None,
             "speedup_solve": round(mean(times) / mean(t32), 3),
             "speedup_band": round(band_ms / mean([t["ms_band"] for t in tim32]), 3),
+            "band_stage_widths": plan32.band_stages(n, b0),
+            "band_stage_ms": [round(mean([t["ms_stage"][i] for t in tim32]), 3)
+                              for i in range(len(tim32[0]["ms_stage"]))],
         }
         # the FP32 trailing-update kernels against the FP32 MFMA peak (same
         # bookkeeping as the FP64 roofline: warmup steps give the SYMM /

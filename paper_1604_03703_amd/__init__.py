@@ -209,6 +209,18 @@ class Plan:
             raise SbrError("sbr_plan_get_band_stages failed with code %d" % rc)
         return [int(arr[i]) for i in range(min(rc, 32))]
 
+    def use_tuned_stages(self, n: int, b0: int, precision="fp64") -> list:
+        """Apply the band-stage sequence (and direct-stage launch shape) a
+        tuning run stored for this device and the nearest order to n (see
+        autotune.py); returns the widths ([] when there is none: the built-in
+        sequence stays)."""
+        from . import autotune
+        widths, variant = autotune.stage_sequence(n, b0, precision)
+        if widths:
+            self.set_band_stages(widths)
+            self.set_tridiag_band(4, variant)
+        return widths
+
     def set_wait_limit(self, ticks: int):
         _check(_lib.sbr_plan_set_wait_limit(self._h, int(ticks)), "sbr_plan_set_wait_limit")
 

@@ -17,6 +17,16 @@ architecture and the precision form:
 it to the plans it creates.  Run on the target GPU:
 
     python -m paper_1604_03703_amd.autotune [--count 1024] [--reps 5]
+
+The single-matrix path has a second table, tuning/stages.json: the band
+widths of its band-to-band stages (the k of each stage of Algorithm 4.3)
+and the launch shape of the direct band-to-tridiagonal stage.  For an order
+n, `tune_stages` times every stage b -> h the library has a kernel for on a
+seeded random band of that order (each direct b -> 1 stage in each launch
+shape) and picks, for every starting band b0, the sequence b0 -> ... -> 1
+with the least total time (a shortest path over the measured stages):
+
+    python -m paper_1604_03703_amd.autotune --stages [--n 8192 16384 32768]
 """
 from __future__ import annotations
 
@@ -126,16 +136,143 @@ def tune(precision="fp64", count: int = 1024, reps: int = 5, warmup: int = 2, pa
     return db
 
 
+# ---- band-to-band stage sequence of the single-matrix path ----------------
+
+STAGE_DB = os.path.join(_PKG, "tuning", "stages.json")
+# every (b, h) with a kernel: halvings, b -> b/k on the wide-band MFMA chase
+# (h >= 8) and the direct b -> 1 stages
+STAGE_PAIRS = ((128, 64), (128, 32), (128, 16), (64, 32), (64, 16), (64, 8), (32, 16), (32, 8), (16, 8),
+               (8, 4), (4, 2), (2, 1), (4, 1), (8, 1), (16, 1))
+TRI_VARIANTS = 3
+
+
+def time_stage(sbr, n: int, b: int, h: int, reps: int = 2, warmup: int = 1, variant: int = 0,
+               precision="fp64") -> float:
+    """Median ms of one band stage b -> h on a seeded random band of order n
+    (band restored from a device copy before every launch)."""
+    g = torch.Generator(device="cuda").manual_seed(1604 + b)
+    ld = 2 * b + 1
+    src = torch.zeros((n, ld), dtype=torch.float64, device="cuda")
+    src[:, : b + 1] = torch.randn((n, b + 1), dtype=torch.float64, device="cuda", generator=g)
+    for d in range(1, b + 1):
+        src[n - d:, d] = 0.0
+    plan = sbr.Plan(0)
+    plan.set_tridiag_band(0, variant)
+    bd = torch.empty_like(src)
+    ts = []
+    for it in range(warmup + reps):
+        bd.copy_(src)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sbr.band_reduce(bd, b, h, plan, precision=precision)
+        e1.record()
+        torch.cuda.synchronize()
+        if plan.status() != 0:
+            raise RuntimeError("band stage %d -> %d reported a stalled wait" % (b, h))
+        if it >= warmup:
+            ts.append(e0.elapsed_time(e1))
+    plan.close()
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def best_sequence(ms: dict, b0: int):
+    """Fastest b0 -> ... -> 1 over the measured stages ms[(b, h)] (a shortest
+    path on the powers of two); (widths after each stage, total ms)."""
+    best = {1: (0.0, [])}
+    b = 2
+    while b <= b0:
+        cands = [(ms[(b, h)] + best[h][0], [h] + best[h][1]) for (bb, h) in ms if bb == b and h in best]
+        if cands:
+            best[b] = min(cands, key=lambda c: c[0])
+        b *= 2
+    if b0 not in best:
+        return None, None
+    return best[b0][1], best[b0][0]
+
+
+def tune_stages(ns=(8192, 16384, 32768), reps: int = 2, warmup: int = 1, precision="fp64", path: str = STAGE_DB,
+                log=print) -> dict:
+    import paper_1604_03703_amd as sbr
+    arch = device_arch()
+    prec = "fp64" if precision in ("fp64", 0) else "fp32_mfma"
+    db = _load_db(path)
+    rec = db.setdefault(arch, {}).setdefault(prec, {})
+    for n in ns:
+        ms, variant = {}, {}
+        for b, h in STAGE_PAIRS:
+            if b >= n:
+                continue
+            if h == 1 and b > 2:
+                per = [time_stage(sbr, n, b, h, reps, warmup, v, precision) for v in range(TRI_VARIANTS)]
+                variant[b] = min(range(TRI_VARIANTS), key=lambda v: per[v])
+                ms[(b, h)] = per[variant[b]]
+                log("n = %d: %d -> 1: %s ms (launch shapes 0..%d)" % (n, b, ["%.2f" % x for x in per],
+                                                                      TRI_VARIANTS - 1))
+            else:
+                ms[(b, h)] = time_stage(sbr, n, b, h, reps, warmup, 0, precision)
+                log("n = %d: %d -> %d: %.2f ms" % (n, b, h, ms[(b, h)]))
+        seqs = {}
+        for b0 in (16, 32, 64, 128):
+            widths, total = best_sequence(ms, b0)
+            if widths:
+                direct = [b for b, h in zip([b0] + widths, widths) if h == 1 and b > 2]
+                seqs[str(b0)] = {"widths": widths, "ms": round(total, 3),
+                                 "tri_variant": variant.get(direct[0], 0) if direct else 0}
+                log("n = %d, b0 = %d: %s (%.1f ms)" % (n, b0, " -> ".join(str(x) for x in [b0] + widths), total))
+        rec[str(n)] = {"ms": {"%d->%d" % k: round(v, 3) for k, v in ms.items()},
+                       "tri_variant": {str(k): v for k, v in variant.items()}, "sequences": seqs,
+                       "reps": reps}
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+        f.write("\n")
+    return db
+
+
+def stage_sequence(n: int, b0: int, precision="fp64", arch: str | None = None, path: str = STAGE_DB):
+    """(widths, launch shape of the direct stage) tuned for the stored order
+    nearest to n (by ratio) and this b0; ([], 0) when there is none."""
+    import math
+    prec = "fp64" if precision in ("fp64", 0) else "fp32_mfma"
+    if arch is None:
+        if not torch.cuda.is_available():
+            return [], 0
+        arch = device_arch()
+    rec = _load_db(path).get(arch, {}).get(prec) or {}
+    best = None
+    for key, r in rec.items():
+        if str(b0) not in r.get("sequences", {}):
+            continue
+        d = abs(math.log(max(n, 2) / int(key)))
+        if best is None or d < best[0]:
+            best = (d, r["sequences"][str(b0)])
+    if best is None:
+        return [], 0
+    return list(best[1]["widths"]), int(best[1]["tri_variant"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--count", type=int, default=1024)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp64")
-    ap.add_argument("--db", default=DB)
+    ap.add_argument("--db", default=None)
+    ap.add_argument("--stages", action="store_true", help="tune the band-stage sequence of the single-matrix path")
+    ap.add_argument("--n", type=int, nargs="*", default=[8192, 16384, 32768])
     args = ap.parse_args()
-    tune(args.precision, args.count, args.reps, args.warmup, args.db)
-    print(json.dumps({"arch": device_arch(), "table": batch_table(args.precision, path=args.db)}))
+    if args.stages:
+        path = args.db or STAGE_DB
+        tune_stages(args.n, reps=min(args.reps, 3), warmup=1, precision=args.precision, path=path)
+        print(json.dumps({"arch": device_arch(),
+                          "sequences": {n: stage_sequence(n, 128, args.precision, path=path) for n in args.n}}))
+        return
+    path = args.db or DB
+    tune(args.precision, args.count, args.reps, args.warmup, path)
+    print(json.dumps({"arch": device_arch(), "table": batch_table(args.precision, path=path)}))
 
 
 if __name__ == "__main__":

@@ -1,6 +1,12 @@
-"""The batched form with the tuned band per size bucket: the stored tuning
-table is well formed (CPU), and a batch solved with it, or with any valid
-table, matches the oracle matrix by matrix (GPU)."""
+"""The autotuner's tables.  Batched form: the tuned band per size bucket is
+well formed (CPU), and a batch solved with it, or with any valid table,
+matches the oracle matrix by matrix (GPU).  Single-matrix path: the
+shortest-path choice of the band-stage sequence equals brute force over
+every sequence (CPU), the stored sequences are consistent with their
+measured stage times (CPU), and solves with them match the oracle (GPU)."""
+import itertools
+import json
+import os
 import numpy as np
 import pytest
 
@@ -11,9 +17,10 @@ def _norm2(ref):
     return max(1e-300, float(np.max(np.abs(ref))))
 
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
 def test_tuning_database_is_well_formed():
-    import json
-    import os
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                         "paper_1604_03703_amd", "tuning", "batched.json")
     db = json.load(open(path))
@@ -61,3 +68,65 @@ def test_batch_band_table_rejects_malformed():
     with pytest.raises(sbr.SbrError):
         plan.set_batch_bands([(100, 32)])               # wider than the batched kernels take
     plan.set_batch_bands([])
+
+
+def _all_sequences(ms, b0):
+    # every chain b0 -> ... -> 1 through measured stages, by enumeration
+    out = []
+    def walk(b, acc, t):
+        if b == 1:
+            out.append((t, acc))
+            return
+        for (bb, h), v in ms.items():
+            if bb == b:
+                walk(h, acc + [h], t + v)
+    walk(b0, [], 0.0)
+    return out
+
+
+def test_stage_sequence_is_the_shortest_path():
+    from paper_1604_03703_amd import autotune
+    import random
+    rng = random.Random(3)
+    for trial in range(50):
+        ms = {k: rng.uniform(10, 300) for k in autotune.STAGE_PAIRS if rng.random() < 0.8 or k[1] == k[0] // 2}
+        for b0 in (16, 32, 64, 128):
+            widths, total = autotune.best_sequence(ms, b0)
+            brute = min(_all_sequences(ms, b0))
+            assert abs(total - brute[0]) < 1e-9
+            assert abs(sum(ms[(b, h)] for b, h in zip([b0] + widths, widths)) - total) < 1e-9
+
+
+def test_stage_table_is_well_formed():
+    from paper_1604_03703_amd import autotune
+    db = json.load(open(autotune.STAGE_DB))
+    assert db, "no stage tuning stored"
+    for arch, forms in db.items():
+        for prec, per_n in forms.items():
+            for n, rec in per_n.items():
+                ms = {tuple(int(x) for x in k.split("->")): v for k, v in rec["ms"].items()}
+                for b0, seq in rec["sequences"].items():
+                    w = seq["widths"]
+                    chain = [int(b0)] + w
+                    assert w[-1] == 1 and all(x > y for x, y in zip(chain, w))
+                    total = sum(ms[(b, h)] for b, h in zip(chain, w))
+                    assert abs(total - seq["ms"]) < 1e-2
+                    assert total <= min(t for t, _ in _all_sequences(ms, int(b0))) + 1e-2
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,b0", [(3000, 128), (2000, 64), (1500, 32)])
+def test_solver_with_tuned_stages(oracle_mod, n, b0):
+    import torch
+    import paper_1604_03703_amd as sbr
+    A = si.gaussian_symmetric(n, si.make_rng(si.CFG_SMALL, 31))
+    ref = oracle_mod.eigvalsh(A)
+    plan = sbr.Plan(n)
+    widths = plan.use_tuned_stages(n, b0)
+    assert widths, "no stage tuning stored for this device"
+    assert plan.band_stages(n, b0) == widths
+    print("tuned stages n=%d b0=%d: %s" % (n, b0, widths), flush=True)
+    w = sbr.eigvalsh(torch.from_numpy(A).cuda(), b0=b0, plan=plan)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    assert np.max(np.abs(w.cpu().numpy() - ref)) <= 1e-11 * _norm2(ref)
