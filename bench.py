@@ -141,12 +141,12 @@ def run_batch(sbr, torch, si, count, steps, warmup):
     dev = [torch.empty_like(d) for d in dev0]
     ws = [torch.empty(d.shape[0], dtype=torch.float64, device=d.device) for d in dev0]
     out = {"count": count, "n_range": [int(min(M.shape[0] for M in mats)), int(max(M.shape[0] for M in mats))]}
-    # the batched kernels compute in FP64 whatever the precision argument says,
-    # so there is one batched form to time
-    out["fp32_mfma"] = "not measured: the batched kernels compute in FP64"
-    for prec in ("fp64",):
+    wsave = {}
+    for prec in ("fp64", "fp32_mfma"):
         plan = sbr.Plan(512, count, prec)
-        out["tuned_bands"] = [list(x) for x in plan.use_tuned_batch_bands(prec)]
+        # band per size bucket: the form's own tuning table, else the FP64 one
+        table = plan.use_tuned_batch_bands(prec) or plan.use_tuned_batch_bands("fp64")
+        out.setdefault("tuned_bands", {})[prec] = [list(x) for x in table]
         # arguments marshalled once, as an SCF loop that refills the same
         # buffers would; each step is one call (one replay of the captured
         # launch), timed on the host clock around the call and a sync
@@ -165,8 +165,14 @@ def run_batch(sbr, torch, si, count, steps, warmup):
                 times.append(t1 - t0)
         tm = mean(times)
         out[prec] = {"ms": round(tm * 1e3, 3), "solves_per_s": round(count / tm, 1)}
+        wsave[prec] = [w.cpu().numpy() for w in ws[:256]]
         del call
         plan.close()
+    # FP32-MFMA form against the FP64 form, matrix by matrix (first 256)
+    errs = [float(np.max(np.abs(a - b)) / max(1e-300, float(np.max(np.abs(b)))))
+            for a, b in zip(wsave["fp32_mfma"], wsave["fp64"])]
+    out["fp32_mfma"]["err_vs_fp64_max_rel"] = max(errs)
+    out["fp32_speedup"] = round(out["fp64"]["ms"] / out["fp32_mfma"]["ms"], 3)
     # the plain FP64 solver called once per matrix (one plan, the same stream)
     # on the first `plain` matrices: what the batched launch replaces
     plain = min(count, 512)
@@ -182,9 +188,10 @@ def run_batch(sbr, torch, si, count, steps, warmup):
     plan.close()
     out["plain_fp64_loop"] = {"count": plain, "solves_per_s": round(plain / tp, 1)}
     out["batched_speedup_vs_plain"] = round(out["fp64"]["solves_per_s"] / (plain / tp), 2)
-    # every matrix's eigenvalues sum to its trace (cheap check at full size)
-    tr = max(abs(float(w.sum().item()) - float(np.trace(M))) / max(1.0, float(np.abs(M).max()) * M.shape[0])
-             for w, M in zip(ws[:64], mats[:64]))
+    # every matrix's eigenvalues (batched FP64 form) sum to its trace (cheap
+    # check at full size)
+    tr = max(abs(float(w.sum()) - float(np.trace(M))) / max(1.0, float(np.abs(M).max()) * M.shape[0])
+             for w, M in zip(wsave["fp64"][:64], mats[:64]))
     out["trace_check_rel"] = tr
     # roofline of the batch: sum over phases of max(flops / peak, bytes / BW)
     # with the method's own work: full-to-band 4/3 n^3 flops per matrix on

@@ -119,8 +119,11 @@ int sbr_syev_eigvals_ex(sbr_plan_t plan, int64_t n, double* A, int64_t lda,
  * host then waits for the previous upload).  Larger matrices, or b0 >= 32,
  * go through sbr_syev_eigvals_ex one after another on the same stream.  The
  * per-matrix band buffers grow on demand (allocation on the first call of a
- * larger batch).  The batched kernels compute in FP64 whatever prec says;
- * prec applies to the matrices that go through sbr_syev_eigvals_ex.
+ * larger batch).  prec = SBR_FP32_MFMA: the batched full-to-band runs
+ * its trailing updates (W = A22 U T, U^T W, V and A22 += U V^T + V U^T) on
+ * FP32 MFMA with FP32 accumulation, added into the FP64 matrix; its panel QR,
+ * tau and T, the halvings and the bisection stay FP64.  prec also applies to
+ * the matrices that go through sbr_syev_eigvals_ex.
  */
 int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n,
                              double* const* A, const int64_t* lda, int32_t b0,

@@ -912,6 +912,7 @@ int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n, d
         std::vector<int64_t> key;
         key.reserve(5 * (size_t)cnt + 2);
         key.push_back(cnt);
+        key.push_back((int64_t)prec);     // the captured launch depends on the form
         for (int32_t q = 0; q < cnt; ++q) {
             const int64_t nk = n[order[q]];
             // band per size bucket: the plan's table (set from a tuning run)
@@ -1006,7 +1007,8 @@ int sbr_syev_eigvals_batched(sbr_plan_t plan, int32_t batch, const int64_t* n, d
             hipGraph_t g = nullptr;
             e = hipStreamBeginCapture(plan->side, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e);
-            launch_batched(plan->bdesc_dev, cnt, max_b0, plan->btickets, plan->bscratch, plan->side);
+            launch_batched(plan->bdesc_dev, cnt, max_b0, prec == SBR_FP32_MFMA, plan->btickets, plan->bscratch,
+                           plan->side);
             e = hipStreamEndCapture(plan->side, &g);
             if (e == hipSuccess) e = hipGraphInstantiate(&plan->bgraph, g, nullptr, nullptr, 0);
             if (g) (void)hipGraphDestroy(g);

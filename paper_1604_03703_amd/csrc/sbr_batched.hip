@@ -22,6 +22,7 @@
 //   * batched_bisect_kernel: one wavefront per matrix, d and e^2 in LDS, each
 //     lane bisecting up to 8 eigenvalue indices in lockstep.
 #include <float.h>
+#include <type_traits>
 
 #include "sbr_device.h"
 #include "sbr_internal.h"
@@ -53,6 +54,17 @@ __device__ __forceinline__ sbr_d4 mma(double a, double b, sbr_d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ sbr_d4 zero4() { return sbr_d4{0.0, 0.0, 0.0, 0.0}; }
+// Products of the trailing update in the precision of their accumulator:
+// FP64 MFMA into sbr_d4, or operands rounded to FP32 and FP32 MFMA with FP32
+// accumulation into sbr_f4 (the FP32-MFMA form).
+__device__ __forceinline__ sbr_d4 mmx(double a, double b, sbr_d4 c) { return mma(a, b, c); }
+__device__ __forceinline__ sbr_f4 mmx(double a, double b, sbr_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+}
+template <class Acc>
+__device__ __forceinline__ Acc zacc() {
+    return Acc{0, 0, 0, 0};
+}
 
 // All-reduce over the 32 lanes of an aligned half-wave: 16-lane DPP sums, then
 // the two halves exchanged.
@@ -63,9 +75,15 @@ __device__ __forceinline__ double sum32(double v) {
 
 // MFMA lane layout used below: with a = R(k0 + l/16, c0 + l%16) and
 // b = L(r0 + l%16, k0 + l/16), element r of the accumulator of lane l is
-// (L R)(r0 + l%16, c0 + 4r + l/16).
+// (L R)(r0 + l%16, c0 + 4r + l/16) for FP64 MFMA and (L R)(r0 + l%16,
+// c0 + 4 (l/16) + r) for FP32 MFMA (ocol below).
+// F32: the trailing update (W, Z, V and the A22 update) on FP32 MFMA with
+// FP32 accumulation, the results added into the FP64 matrix; the panel QR,
+// tau, U^T U and T stay FP64.
+template <bool F32>
 __global__ __launch_bounds__(BF_NT) void batched_f2b_kernel(const BatchDesc* __restrict__ desc, int count,
                                                             int* ticket, double* scratch) {
+    typedef typename std::conditional<F32, sbr_f4, sbr_d4>::type Acc;
     extern __shared__ double sm[];
     double* Us = sm + BF_US;
     double* Ts = sm + BF_TS;
@@ -77,6 +95,9 @@ __global__ __launch_bounds__(BF_NT) void batched_f2b_kernel(const BatchDesc* __r
     __shared__ int mat_sh;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int li = lane & 15, lk = lane >> 4;
+    // tile column of accumulator element r (the FP32 instruction's layout
+    // differs from the FP64 one)
+    auto ocol = [&](int r) { return F32 ? 4 * lk + r : 4 * r + lk; };
     double* Wg = scratch + (int64_t)blockIdx.x * (2 * BF_MP * 16);   // W, column-major, ld BF_MP
     double* Vg = Wg + BF_MP * 16;                                    // V, same layout
 
@@ -202,14 +223,14 @@ __global__ __launch_bounds__(BF_NT) void batched_f2b_kernel(const BatchDesc* __r
             // ---- 4. W = (A22 U) T by row tiles; W kept in registers (at most
             // 4 row tiles per wave) and written to the scratch slice
             const int nI = (m + 15) / 16;
-            sbr_d4 Wr[4];
+            Acc Wr[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                Wr[q] = zero4();
+                Wr[q] = zacc<Acc>();
                 const int I = w + q * BF_NW;
                 if (I < nI) {
                     const int row = I * 16 + li;
-                    sbr_d4 acc = zero4();
+                    Acc acc = zacc<Acc>();
 #pragma unroll 4
                     for (int k0 = 0; k0 < m; k0 += 4) {
                         const int col = k0 + lk;
@@ -217,13 +238,13 @@ __global__ __launch_bounds__(BF_NT) void batched_f2b_kernel(const BatchDesc* __r
                         if (row < m && col < m)
                             bv = (row >= col) ? A22[row + (int64_t)col * lda] : A22[col + (int64_t)row * lda];
                         const double av = (col < m) ? Us[col + li * BF_LDU] : 0.0;
-                        acc = mma(av, bv, acc);
+                        acc = mmx(av, bv, acc);
                     }
 #pragma unroll
                     for (int r4 = 0; r4 < 4; ++r4)
-                        Wr[q] = mma(Ts[(4 * r4 + lk) + li * BF_LDT], acc[r4], Wr[q]);
+                        Wr[q] = mmx(Ts[ocol(r4) + li * BF_LDT], acc[r4], Wr[q]);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) Wg[row + (4 * r + lk) * BF_MP] = Wr[q][r];
+                    for (int r = 0; r < 4; ++r) Wg[row + ocol(r) * BF_MP] = Wr[q][r];
                 }
             }
             __syncthreads();
@@ -232,15 +253,15 @@ __global__ __launch_bounds__(BF_NT) void batched_f2b_kernel(const BatchDesc* __r
             if (w < 4) {
                 const int kb = (m + 3) / 4;
                 const int ka = w * kb, ke = (ka + kb < m) ? ka + kb : m;
-                sbr_d4 acc = zero4();
+                Acc acc = zacc<Acc>();
                 for (int k0 = ka; k0 < ke; k0 += 4) {
                     const int k = k0 + lk;
                     const double wv = (k < ke) ? Wg[k + li * BF_MP] : 0.0;
                     const double ub = (k < ke) ? Us[k + li * BF_LDU] : 0.0;
-                    acc = mma(wv, ub, acc);
+                    acc = mmx(wv, ub, acc);
                 }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) Zp[w * 256 + li + (4 * r + lk) * 16] = acc[r];
+                for (int r = 0; r < 4; ++r) Zp[w * 256 + li + ocol(r) * 16] = acc[r];
             }
             __syncthreads();
             if (t < 256) {
@@ -260,12 +281,12 @@ __global__ __launch_bounds__(BF_NT) void batched_f2b_kernel(const BatchDesc* __r
                 const int I = w + q * BF_NW;
                 if (I < nI) {
                     const int row = I * 16 + li;
-                    sbr_d4 acc = zero4();
+                    Acc acc = zacc<Acc>();
 #pragma unroll
                     for (int k0 = 0; k0 < 16; k0 += 4)
-                        acc = mma(Ms[(k0 + lk) + li * BF_LDT], Us[row + (k0 + lk) * BF_LDU], acc);
+                        acc = mmx(Ms[(k0 + lk) + li * BF_LDT], Us[row + (k0 + lk) * BF_LDU], acc);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) Vg[row + (4 * r + lk) * BF_MP] = 0.5 * acc[r] - Wr[q][r];
+                    for (int r = 0; r < 4; ++r) Vg[row + ocol(r) * BF_MP] = 0.5 * acc[r] - Wr[q][r];
                 }
             }
             __syncthreads();
@@ -278,7 +299,7 @@ __global__ __launch_bounds__(BF_NT) void batched_f2b_kernel(const BatchDesc* __r
                 while ((I + 1) * (I + 2) / 2 <= x) ++I;
                 const int J = x - I * (I + 1) / 2;
                 const int ri = I * 16 + li, rj = J * 16 + li;
-                sbr_d4 acc = zero4();
+                Acc acc = zacc<Acc>();
 #pragma unroll
                 for (int k0 = 0; k0 < 32; k0 += 4) {
                     const int k = k0 + lk;
@@ -290,12 +311,12 @@ __global__ __launch_bounds__(BF_NT) void batched_f2b_kernel(const BatchDesc* __r
                         av = Us[rj + (k - 16) * BF_LDU];
                         bv = Vg[ri + (k - 16) * BF_MP];
                     }
-                    acc = mma(av, bv, acc);
+                    acc = mmx(av, bv, acc);
                 }
                 if (ri < m) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int cj = J * 16 + 4 * r + lk;
+                        const int cj = J * 16 + ocol(r);
                         if (cj <= ri) A22[ri + (int64_t)cj * lda] += acc[r];
                     }
                 }
@@ -550,11 +571,15 @@ int64_t batch_scratch_doubles(int grid) { return (int64_t)grid * 2 * BF_MP * 16;
 
 int batch_f2b_grid() { return 512; }
 
-void launch_batched(const BatchDesc* desc, int count, int max_b0, int* tickets, double* scratch, hipStream_t s) {
+void launch_batched(const BatchDesc* desc, int count, int max_b0, bool f32, int* tickets, double* scratch,
+                    hipStream_t s) {
     if (count <= 0) return;
     batch_reset_kernel<<<1, 64, 0, s>>>(tickets, 8);
     const int gf = count < batch_f2b_grid() ? count : batch_f2b_grid();
-    batched_f2b_kernel<<<gf, BF_NT, BF_TOTAL * sizeof(double), s>>>(desc, count, tickets + 0, scratch);
+    if (f32)
+        batched_f2b_kernel<true><<<gf, BF_NT, BF_TOTAL * sizeof(double), s>>>(desc, count, tickets + 0, scratch);
+    else
+        batched_f2b_kernel<false><<<gf, BF_NT, BF_TOTAL * sizeof(double), s>>>(desc, count, tickets + 0, scratch);
     const int gb = count < 4096 ? count : 4096;
     if (max_b0 >= 16) batched_band_kernel<8><<<gb, 64, 0, s>>>(desc, count, tickets + 1);
     if (max_b0 >= 8) batched_band_kernel<4><<<gb, 64, 0, s>>>(desc, count, tickets + 2);
@@ -565,8 +590,11 @@ void launch_batched(const BatchDesc* desc, int count, int max_b0, int* tickets, 
 }
 
 int init_batched_attributes() {
-    hipError_t e = hipFuncSetAttribute((const void*)batched_f2b_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       BF_TOTAL * (int)sizeof(double));
+    hipError_t e = hipFuncSetAttribute((const void*)batched_f2b_kernel<false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, BF_TOTAL * (int)sizeof(double));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)batched_f2b_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                BF_TOTAL * (int)sizeof(double));
     return e == hipSuccess ? 0 : (int)e;
 }
 

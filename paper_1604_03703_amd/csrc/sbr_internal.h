@@ -157,7 +157,10 @@ int batch_f2b_grid();
 // Every kernel of the batched form, in order, on stream s (capturable: the
 // tickets are reset by a kernel).  desc is a device array of count entries,
 // ordered by decreasing n; tickets: 8 ints.
-void launch_batched(const BatchDesc* desc, int count, int max_b0, int* tickets, double* scratch, hipStream_t s);
+// f32: the full-to-band trailing updates on FP32 MFMA (panel QR, T, the
+// halvings and the bisection FP64)
+void launch_batched(const BatchDesc* desc, int count, int max_b0, bool f32, int* tickets, double* scratch,
+                    hipStream_t s);
 int init_batched_attributes();
 
 // ---- sbr_chase_mfma.hip: b in {16, 32, 64, 128}, chase products on FP64 MFMA
