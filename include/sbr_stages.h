@@ -159,15 +159,6 @@ int sbr_plan_set_group_max_band(sbr_plan_t plan, int32_t b);
  * for sbr_band_to_tridiag; 0 is the default.  -3 for an unknown variant. */
 int sbr_plan_set_tridiag_band(sbr_plan_t plan, int32_t b, int32_t variant);
 
-/* Whether a solve runs its band-to-band stages side by side (1, the
- * default) or one after another (0).  Side by side, every stage works in
- * place on one band buffer and starts on the columns the stage before it has
- * finished (that stage's progress words gate it), the stages alternating
- * between the caller's stream and a second stream of the plan; the results
- * are the same bits either way (every chase sees the same data).  -1 for a
- * null plan. */
-int sbr_plan_set_band_pipeline(sbr_plan_t plan, int32_t enable);
-
 /* Band widths of a solve's band-to-band stages (Algorithm 4.3 leaves the
  * choice of k per stage to the machine): widths[0 .. count) strictly
  * decreasing powers of two.  From the current width b a solve goes to the

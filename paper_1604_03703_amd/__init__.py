@@ -82,7 +82,6 @@ def _load():
         "sbr_band_reduce": ([_vp, _i64, _vp, _i64, _i32, _i32, ctypes.c_int, _vp], ctypes.c_int),
         "sbr_plan_set_band_stages": ([_vp, _i32, ctypes.POINTER(_i32)], ctypes.c_int),
         "sbr_plan_get_band_stages": ([_vp, _i64, _i32, ctypes.POINTER(_i32), _i32], ctypes.c_int),
-        "sbr_plan_set_band_pipeline": ([_vp, _i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -100,7 +99,7 @@ EXPORTED = (
     "sbr_plan_set_chase_blocks", "sbr_plan_set_panel_cus", "sbr_plan_status",
     "sbr_plan_set_wait_limit", "sbr_plan_set_group_max_band", "sbr_tridiag_eigvals_noalloc",
     "sbr_plan_set_tridiag_band", "sbr_band_to_tridiag", "sbr_plan_set_batch_bands",
-    "sbr_band_reduce", "sbr_plan_set_band_stages", "sbr_plan_get_band_stages", "sbr_plan_set_band_pipeline",
+    "sbr_band_reduce", "sbr_plan_set_band_stages", "sbr_plan_get_band_stages",
 )
 
 STATUS_STALLED = 1      # SBR_STATUS_STALLED
@@ -200,11 +199,6 @@ class Plan:
         k = len(widths)
         arr = (_i32 * max(k, 1))(*[int(x) for x in widths])
         _check(_lib.sbr_plan_set_band_stages(self._h, k, arr), "sbr_plan_set_band_stages")
-
-    def set_band_pipeline(self, enable: bool):
-        """Band-to-band stages side by side (True, the default) or one after
-        another (False); the eigenvalues are the same bits either way."""
-        _check(_lib.sbr_plan_set_band_pipeline(self._h, 1 if enable else 0), "sbr_plan_set_band_pipeline")
 
     def band_stages(self, n: int, b0: int) -> list:
         """The band width after each band-to-band stage of a solve of order n

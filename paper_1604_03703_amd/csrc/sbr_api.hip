@@ -44,7 +44,6 @@ struct EventPair {
 
 struct sbr_plan_s {
     int device = 0;
-    int ncu = 0;       // compute units of the device
     int64_t n_cap = 0;
     int b_cap = 0;
     sbr_precision prec = SBR_FP64;
@@ -58,11 +57,6 @@ struct sbr_plan_s {
     // of the current trailing update runs on the caller's stream
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    // band stages side by side (each on the columns the previous one has
-    // finished): completion events per stage
-    int band_pipeline = 1;
-    std::vector<hipEvent_t> ev_bstage;
-    int64_t flag_stride = 0;    // ints per stage flag region (BAND_FLAG_REGIONS regions)
     // the bulk update runs on `upd`, a stream barred from `panel_cus` CUs, so
     // that the panel kernels always find free CUs instead of queueing behind
     // a grid that fills the whole chip (upd = nullptr: caller's stream)
@@ -182,7 +176,7 @@ Layout make_layout(int64_t n, int b) {
     L.off_bandA = take(cur, (size_t)n * (2 * b + 1) * D);
     L.off_bandB = take(cur, (size_t)n * (b + 1) * D);
     L.off_chase = take(cur, (size_t)chase_workspace_doubles(n, b) * D);
-    L.off_flags = take(cur, (size_t)BAND_FLAG_REGIONS * (n + 4) * sizeof(int));   // one region per band stage
+    L.off_flags = take(cur, (size_t)(n + 4) * sizeof(int));
     L.off_status = take(cur, 2 * sizeof(int));
     L.off_d = take(cur, (size_t)n * D);
     L.off_e = take(cur, (size_t)n * D);
@@ -233,7 +227,6 @@ int ensure_workspace(sbr_plan_t p, int64_t n, int b) {
     p->bandB = (double*)(base + L.off_bandB);
     p->chase_scratch = (double*)(base + L.off_chase);
     p->flags = (int*)(base + L.off_flags);
-    p->flag_stride = nn + 4;
     p->status = (int*)(base + L.off_status);
     {
         hipError_t ez = hipMemset(p->status, 0, 2 * sizeof(int));
@@ -508,101 +501,16 @@ int next_band(sbr_plan_t p, int64_t n, int b) {
 }
 
 // Band-to-band stages from b0 to 1 starting from the lower band of the dense A.
-//
-// Side by side (plan->band_pipeline, the default): every stage works in place
-// on the first band buffer (ld 2 b0 + 1; the entries beyond a stage's band
-// are exact zeros, which is what the next stage expects), consecutive stages
-// on alternate streams, and a stage starts on the columns the previous stage
-// has finished (the previous stage's progress words gate it, UpGate), so
-// consecutive stages overlap (except after a b = 128 stage).  Stage k has flag region k of its own, all of them zeroed
-// on the caller's stream before the fork, so a stage never sees a word left
-// by an earlier stage or call, whichever stream runs first.  Otherwise the
-// stages run one after another, each on a copy of the band narrowed to its
-// own width.
 int run_band_stages(sbr_plan_t p, int64_t n, const double* A, int64_t lda, int b0, bool f32, hipStream_t s) {
     const StageCtl ctl = stage_ctl(p);
     double* cur = p->bandA;
     int64_t ld = 2 * b0 + 1;
     launch_dense_to_band(n, A, lda, b0, cur, ld, s);
-    std::vector<std::pair<int, int>> stages;
-    for (int b = b0; b > 1;) {
-        const int h = next_band(p, n, b);
-        stages.push_back({b, h});
-        b = h;
-    }
-    bool pipe = p->band_pipeline && stages.size() > 1 && stages.size() <= (size_t)BAND_FLAG_REGIONS &&
-                n * ld < (int64_t)INT32_MAX;
-    for (auto& bh : stages) pipe = pipe && band_reduce_supported(n, ld, bh.first, bh.second);
-    if (pipe) {
-        int rc = ensure_side_stream(p);
-        if (rc) return rc;
-        while (p->ev_bstage.size() < stages.size()) {
-            hipEvent_t e;
-            const hipError_t he = hipEventCreateWithFlags(&e, hipEventDisableTiming);
-            if (he != hipSuccess) return hip_fail(he);
-            p->ev_bstage.push_back(e);
-        }
-        hipStream_t str[2] = {s, p->side};
-        launch_fill_int(p->flags, (int64_t)stages.size() * p->flag_stride, 0, s);
-        hipError_t e = hipEventRecord(p->ev_fork, s);      // the band is in place, the flags zero
-        if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
-        if (e != hipSuccess) return hip_fail(e);
-        UpGate prev;
-        int si = 0;
-        for (size_t k = 0; k < stages.size(); ++k) {
-            const int b = stages[k].first, h = stages[k].second;
-            // A stage runs beside the one before it unless that one is a
-            // b = 128 stage: its blocks fill a CU each and it keeps about 128
-            // sweeps in flight, so a consumer beside it only takes CUs from it
-            // (measured: 128 -> 64 beside 64 -> 8 ran 400 ms against 163).
-            const bool overlap = k > 0 && stages[k - 1].first < PIPE_SOLO_B;
-            si = (k == 0) ? 0 : (overlap ? 1 - si : si);
-            hipStream_t sk = str[si];
-            // never more than two stages at once: stage k - 2 is complete
-            if (k >= 2) {
-                e = hipStreamWaitEvent(sk, p->ev_bstage[k - 2], 0);
-                if (e != hipSuccess) return hip_fail(e);
-            }
-            StageCtl c = ctl;
-            c.flags = p->flags + (int64_t)k * p->flag_stride;
-            c.up = overlap ? prev : UpGate();
-            if (overlap) {
-                // The consumer's blocks must never take every CU: a producer
-                // block may need a CU of its own, and a consumer that has not
-                // seen its producer start would wait for good.  Work-groups
-                // go to the XCDs in turn, so a grid of at most ncu - ncu / 8
-                // leaves every XCD an eighth of its CUs whatever the
-                // consumer's blocks hold.  (The producer already has blocks
-                // running: it started beside, or after, its own producer.)
-                // Beyond that the consumer gets the work-groups it keeps busy
-                // at once and no more: the kernels hold most of a SIMD's
-                // registers, so a consumer block and a producer block seldom
-                // share a CU, and idle consumer blocks take CUs from the
-                // producer.
-                int cap = p->ncu > 8 ? p->ncu - p->ncu / 8 : 1;
-                cap = std::min(cap, band_stage_busy_blocks(n, ld, b, h, c));
-                if (c.max_grid <= 0 || c.max_grid > cap) c.max_grid = cap;
-            }
-            EventPair ep;
-            if (p->timing) { ep.a = p->ev(); p->mark(ep.a, sk); }
-            launch_band_reduce(n, cur, ld, b, h, f32, p->chase_scratch, c, sk);
-            if (p->timing) { ep.b = p->ev(); p->mark(ep.b, sk); p->ev_stage.push_back(ep); }
-            e = hipEventRecord(p->ev_bstage[k], sk);
-            if (e != hipSuccess) return hip_fail(e);
-            SBR_CHECK_LAUNCH();
-            prev = band_stage_gate(n, ld, b, h, c);
-        }
-        // join: every stage is done
-        for (size_t k = 0; k < stages.size() && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, p->ev_bstage[k], 0);
-        if (e != hipSuccess) return hip_fail(e);
-        launch_band_to_tridiag(n, cur, ld, p->d, p->e, s);
-        SBR_CHECK_LAUNCH();
-        return 0;
-    }
-    for (size_t k = 0; k < stages.size(); ++k) {
-        const int b = stages[k].first, h = stages[k].second;
+    int b = b0;
+    while (b > 1) {
         EventPair ep;
         if (p->timing) { ep.a = p->ev(); p->mark(ep.a, s); }
+        const int h = next_band(p, n, b);
         launch_band_reduce(n, cur, ld, b, h, f32, p->chase_scratch, ctl, s);
         if (p->timing) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_stage.push_back(ep); }
         SBR_CHECK_LAUNCH();
@@ -612,6 +520,7 @@ int run_band_stages(sbr_plan_t p, int64_t n, const double* A, int64_t lda, int b
         launch_band_copy(n, cur, ld, h, nxt, ldn, s);
         cur = nxt;
         ld = ldn;
+        b = h;
         SBR_CHECK_LAUNCH();
     }
     launch_band_to_tridiag(n, cur, ld, p->d, p->e, s);
@@ -651,7 +560,6 @@ int sbr_plan_create(sbr_plan_t* plan, int64_t n_max, int32_t batch_max, sbr_prec
     sbr_plan_t p = new (std::nothrow) sbr_plan_s();
     if (!p) return SBR_ENOMEM;
     hipError_t e = hipGetDevice(&p->device);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, p->device);
     if (e != hipSuccess) {
         delete p;
         return hip_fail(e);
@@ -682,7 +590,6 @@ int sbr_plan_destroy(sbr_plan_t plan) {
     (void)hipSetDevice(plan->device);
     (void)hipDeviceSynchronize();
     for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
-    for (hipEvent_t e : plan->ev_bstage) (void)hipEventDestroy(e);
     if (plan->as_buf) (void)hipFree(plan->as_buf);
     if (plan->bgraph) (void)hipGraphExecDestroy(plan->bgraph);
     if (plan->bupload_ev) (void)hipEventDestroy(plan->bupload_ev);
@@ -780,12 +687,6 @@ int sbr_plan_set_tridiag_band(sbr_plan_t plan, int32_t b, int32_t variant) {
     if (variant < 0 || variant >= band_tridiag_variants()) return -3;
     plan->tridiag_from_b = b;
     plan->tri_variant = variant;
-    return 0;
-}
-
-int sbr_plan_set_band_pipeline(sbr_plan_t plan, int32_t enable) {
-    if (!plan) return -1;
-    plan->band_pipeline = enable ? 1 : 0;
     return 0;
 }
 
@@ -1221,11 +1122,11 @@ int sbr_band_to_tridiag(sbr_plan_t plan, int64_t n, double* band, int64_t ldband
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     launch_status_rearm(plan->status, s);
-    if (n * ldband < (int64_t)INT32_MAX) {
-        launch_band_tridiag(n, band, ldband, b, stage_ctl(plan), s);
+    if (ldband == ld2) {
+        launch_band_tridiag(n, band, b, stage_ctl(plan), s);
     } else {
         launch_band_copy(n, band, ldband, b, plan->bandA, ld2, s);
-        launch_band_tridiag(n, plan->bandA, ld2, b, stage_ctl(plan), s);
+        launch_band_tridiag(n, plan->bandA, b, stage_ctl(plan), s);
         launch_band_copy(n, plan->bandA, ld2, (int)(2 * b), band, ldband, s);
     }
     SBR_CHECK_LAUNCH();

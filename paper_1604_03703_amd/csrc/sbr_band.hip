@@ -99,9 +99,10 @@ int64_t chase_flag_ints(int64_t n, int b) {
     return (n - 2) / h + 2 > 2 ? (n - 2) / h + 2 : 2;
 }
 
-// the small-b group kernel indexes its window with 32-bit integers
+// the small-b group kernel indexes the band with 32-bit integers and expects
+// ld = 2b + 1
 static bool group_fits(int64_t n, int64_t ldband, int b) {
-    return band_group_supported(b) && ldband >= 2 * (int64_t)b + 1 && n * ldband < (int64_t)INT32_MAX;
+    return band_group_supported(b) && ldband == 2 * (int64_t)b + 1 && n * ldband < (int64_t)INT32_MAX;
 }
 
 bool band_halve_supported(int64_t n, int64_t ldband, int b) {
@@ -114,7 +115,7 @@ void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32,
     // kernels (no matrix products) are FP64 in both forms
     const bool group = group_fits(n, ldband, b) && (b <= ctl.group_max_b || !band_mfma_supported(b));
     if (group)
-        launch_band_halve_group(n, band, ldband, b, ctl, s);
+        launch_band_halve_group(n, band, b, ctl, s);
     else if (band_mfma_supported(b))
         launch_band_halve_mfma(n, band, ldband, b, f32, scratch, ctl, s);
 }
@@ -122,7 +123,7 @@ void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32,
 bool band_reduce_supported(int64_t n, int64_t ldband, int b, int h) {
     if (h < 1 || h >= b || b % h) return false;
     if (2 * h == b) return band_halve_supported(n, ldband, b);
-    if (h == 1) return band_tridiag_supported(b) && ldband >= 2 * (int64_t)b + 1 && n * ldband < (int64_t)INT32_MAX;
+    if (h == 1) return band_tridiag_supported(b) && ldband == 2 * (int64_t)b + 1 && n * ldband < (int64_t)INT32_MAX;
     return band_reduce_mfma_supported(b, h);
 }
 
@@ -131,53 +132,9 @@ void launch_band_reduce(int64_t n, double* band, int64_t ldband, int b, int h, b
     if (2 * h == b)
         launch_band_halve(n, band, ldband, b, f32, scratch, ctl, s);
     else if (h == 1)
-        launch_band_tridiag(n, band, ldband, b, ctl, s);
+        launch_band_tridiag(n, band, b, ctl, s);
     else
         launch_band_reduce_mfma(n, band, ldband, b, h, f32, scratch, ctl, s);
-}
-
-int band_stage_busy_blocks(int64_t n, int64_t ldband, int b, int h, const StageCtl& ctl) {
-    const int64_t nsweeps = (n - 2) / h;
-    if (nsweeps < 1) return 1;
-    const bool group = 2 * h == b && group_fits(n, ldband, b) && (b <= ctl.group_max_b || !band_mfma_supported(b));
-    int64_t S, lag;
-    if (h == 1 && 2 * h != b) {
-        S = band_tridiag_sweeps(b, ctl.tri_variant);
-        lag = 2;
-    } else if (group) {
-        S = band_group_sweeps(b);
-        lag = (h <= 4) ? 2 : 3;
-    } else {
-        return (int)(nsweeps < 256 ? nsweeps : 256);   // one work-group per sweep in flight
-    }
-    // a group of S sweeps runs about n / b + lag S steps and starts lag S
-    // steps after the one before it
-    const int64_t ngroups = (nsweeps + S - 1) / S;
-    int64_t busy = (n / b + lag * S) / (lag * S) + 4;
-    if (busy > ngroups) busy = ngroups;
-    return (int)busy;
-}
-
-UpGate band_stage_gate(int64_t n, int64_t ldband, int b, int h, const StageCtl& ctl) {
-    UpGate g;
-    g.b = b;
-    g.h = h;
-    g.n = n;
-    g.flags = ctl.flags + 1;     // progress[i] / done[g] follow the ticket
-    g.nsweeps = (int)((n - 2) / h);
-    if (g.nsweeps < 1) return UpGate();   // the stage does nothing: no gate
-    const bool group = 2 * h == b && group_fits(n, ldband, b) && (b <= ctl.group_max_b || !band_mfma_supported(b));
-    if (h == 1 && 2 * h != b) {
-        g.kind = 2;
-        g.S = band_tridiag_sweeps(b, ctl.tri_variant);
-    } else if (group) {
-        g.kind = 2;
-        g.S = band_group_sweeps(b);
-    } else {
-        g.kind = 1;
-    }
-    g.ngroups = (g.nsweeps + g.S - 1) / g.S;
-    return g;
 }
 
 void launch_fill_int(int* p, int64_t count, int v, hipStream_t s) {

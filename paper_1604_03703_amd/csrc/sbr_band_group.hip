@@ -70,15 +70,13 @@ struct GroupCfg {
 
 struct GroupArgs {
     int64_t n;
-    double* band;      // global band, ld = ldg >= 4h + 1
-    int64_t ldg;
+    double* band;      // global band, ld = 4h + 1
     int nsweeps;
     int ngroups;
     int* ticket;
     int* done;         // ngroups watermarks
     int* error;        // the plan's status word: nonzero stops every block
     uint64_t wait_ticks;   // a wait gives up after this many ticks of the 100 MHz clock
-    sbr::UpGate up;        // the previous band stage, when it runs beside this one
 };
 
 template <int H>
@@ -94,7 +92,6 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
     double* ring = smem;
     __shared__ int g_sh, abort_sh, fresh_sh;
     __shared__ int vis_sh;
-    __shared__ int upvis_sh;   // columns below it are final in the previous stage
     const int t = threadIdx.x;
     const int tm = t / TEAM, u = t % TEAM;
     double* scr = smem + WC * LDW + tm * C::SCR;
@@ -117,7 +114,6 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
             g_sh = failed ? a.ngroups : atomicAdd(a.ticket, 1);
             abort_sh = 0;
             vis_sh = 0;
-            upvis_sh = 0;
         }
         __syncthreads();
         // uniform across the block: keep the schedule arithmetic scalar
@@ -197,32 +193,10 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                 }
                 if (need > loaded) {
                     // wait until the previous group has released the columns
-                    // (and the previous stage, when it runs beside this one,
-                    // has finished them)
-                    if (g > 0 || a.up.kind != 0) {
+                    if (g > 0) {
                         if (t == 0) {
                             fresh_sh = 0;
-                            // (group 0 only: the columns a later group loads
-                            // were released by the group before it, which
-                            // loaded them after this check)
-                            if (g == 0 && a.up.kind != 0 && upvis_sh < need) {
-                                const uint64_t t0 = wall_clock64();
-                                while (!sbr::up_ready(a.up, need)) {
-                                    __builtin_amdgcn_s_sleep(2);
-                                    if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                                        abort_sh = 1;
-                                        break;
-                                    }
-                                    if (wall_clock64() - t0 > a.wait_ticks) {
-                                        atomicOr(a.error, sbr::STATUS_STALLED);
-                                        abort_sh = 1;
-                                        break;
-                                    }
-                                }
-                                upvis_sh = need;
-                                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                            }
-                            if (g > 0 && vis_sh < need) {
+                            if (vis_sh < need) {
                                 const uint64_t t0 = wall_clock64();
                                 int d;
                                 while ((d = __hip_atomic_load(&a.done[g - 1], __ATOMIC_RELAXED,
@@ -254,7 +228,7 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                         const int k = idx / LDW, d = idx - k * LDW;
                         int sl = sl0 + k;
                         if (sl >= WC) sl -= WC;
-                        ring[sl * LDW + d] = (loaded + k + d < n) ? gband[(loaded + k) * a.ldg + d] : 0.0;
+                        ring[sl * LDW + d] = (loaded + k + d < n) ? gband[(loaded + k) * (int64_t)LDW + d] : 0.0;
                     }
                     loaded = need;
                 }
@@ -264,10 +238,8 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                     const int sl2 = lowest_active(s_lo, tau_s + C::BATCH);
                     int want = need_through(sl2, tau_s + 2 * C::BATCH - 1);
                     if (want > loaded + C::PFC) want = loaded + C::PFC;
-                    if (want > loaded && (g > 0 || a.up.kind != 0)) {
-                        // (group 0 asks the previous stage, the others the
-                        // group before them)
-                        if (t == 0 && g > 0 && vis_sh < want) {
+                    if (want > loaded && g > 0) {
+                        if (t == 0 && vis_sh < want) {
                             const int d = __hip_atomic_load(&a.done[g - 1], __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
                             if (d > vis_sh) {
@@ -275,13 +247,8 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                             }
                         }
-                        if (t == 0 && g == 0 && a.up.kind != 0 && upvis_sh < want && sbr::up_ready(a.up, want)) {
-                            upvis_sh = want;
-                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                        }
                         __syncthreads();
-                        if (g > 0 && want > vis_sh) want = vis_sh;
-                        if (g == 0 && a.up.kind != 0 && want > upvis_sh) want = upvis_sh;
+                        if (want > vis_sh) want = vis_sh;
                     }
                     if (want > loaded) {
                         const int cnt = (int)(want - loaded) * LDW;
@@ -291,7 +258,7 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                             if (idx < cnt) {
                                 const int k = idx / LDW, d = idx - k * LDW;
                                 // entries past the matrix end read as zero
-                                pf[p] = (loaded + k + d < n) ? gband[(loaded + k) * a.ldg + d] : 0.0;
+                                pf[p] = (loaded + k + d < n) ? gband[(loaded + k) * (int64_t)LDW + d] : 0.0;
                             }
                         }
                         pf_lo = loaded;
@@ -382,7 +349,7 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
                         const int k = idx / LDW, d = idx - k * LDW;
                         int sl = sl0 + k;
                         if (sl >= WC) sl -= WC;
-                        gband[(written + k) * a.ldg + d] = ring[sl * LDW + d];
+                        gband[(written + k) * (int64_t)LDW + d] = ring[sl * LDW + d];
                     }
                     written = done;
                     pub_pending = written;
@@ -416,7 +383,7 @@ __global__ __launch_bounds__(GroupCfg<H>::NT) void band_group_kernel(GroupArgs a
 }
 
 template <int H>
-void launch_group(int64_t n, double* band, int64_t ld, const sbr::StageCtl& ctl, hipStream_t s) {
+void launch_group(int64_t n, double* band, const sbr::StageCtl& ctl, hipStream_t s) {
     typedef GroupCfg<H> C;
     const int64_t nsweeps = (n - 2) / H;
     if (nsweeps < 1) return;
@@ -424,14 +391,12 @@ void launch_group(int64_t n, double* band, int64_t ld, const sbr::StageCtl& ctl,
     GroupArgs a;
     a.n = n;
     a.band = band;
-    a.ldg = ld;
     a.nsweeps = (int)nsweeps;
     a.ngroups = (int)ngroups;
     a.ticket = ctl.flags;
     a.done = ctl.flags + 1;
     a.error = ctl.status;
     a.wait_ticks = ctl.wait_ticks;
-    a.up = ctl.up;
     sbr::launch_fill_int(ctl.flags, ngroups + 1, 0, s);
     int64_t grid = ngroups < (C::LANE ? 1024 : 256) ? ngroups : (C::LANE ? 1024 : 256);
     if (ctl.max_grid > 0 && grid > ctl.max_grid) grid = ctl.max_grid;
@@ -453,23 +418,13 @@ namespace sbr {
 
 bool band_group_supported(int b) { return b == 2 || b == 4 || b == 8 || b == 16; }
 
-void launch_band_halve_group(int64_t n, double* band, int64_t ld, int b, const StageCtl& ctl, hipStream_t s) {
+void launch_band_halve_group(int64_t n, double* band, int b, const StageCtl& ctl, hipStream_t s) {
     switch (b) {
-        case 2: launch_group<1>(n, band, ld, ctl, s); break;
-        case 4: launch_group<2>(n, band, ld, ctl, s); break;
-        case 8: launch_group<4>(n, band, ld, ctl, s); break;
-        case 16: launch_group<8>(n, band, ld, ctl, s); break;
+        case 2: launch_group<1>(n, band, ctl, s); break;
+        case 4: launch_group<2>(n, band, ctl, s); break;
+        case 8: launch_group<4>(n, band, ctl, s); break;
+        case 16: launch_group<8>(n, band, ctl, s); break;
         default: break;
-    }
-}
-
-int band_group_sweeps(int b) {
-    switch (b) {
-        case 2: return GroupCfg<1>::S;
-        case 4: return GroupCfg<2>::S;
-        case 8: return GroupCfg<4>::S;
-        case 16: return GroupCfg<8>::S;
-        default: return 1;
     }
 }
 

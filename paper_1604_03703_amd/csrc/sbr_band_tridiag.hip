@@ -76,15 +76,14 @@ struct TriCfg {
 
 struct TriArgs {
     int64_t n;
-    double* band;          // global band, ld = ldg >= 2b + 1
-    int ldg;
+    double* band;          // global band, ld = 2b + 1
+    int ldg;               // 2b + 1
     int nsweeps;
     int ngroups;
     int* ticket;
     int* done;             // ngroups watermarks
     int* error;            // the plan's status word: nonzero stops every block
     uint64_t wait_ticks;
-    sbr::UpGate up;        // the previous band stage, when it runs beside this one
 };
 
 template <int B>
@@ -321,7 +320,6 @@ __global__ __launch_bounds__((TriCfg<B, V>::NT)) void band_tridiag_kernel(TriArg
     constexpr int S = C::S, WC = C::WC, LDW = C::LDW, LAG = C::LAG, T = C::T, R = C::R;
     extern __shared__ double ring[];
     __shared__ int g_sh, abort_sh, vis_sh;
-    __shared__ int upvis_sh;   // columns below it are final in the previous stage
     const int t = threadIdx.x;
     // sweep of the group: the teams of one wavefront take every NW-th sweep
     // (NW = wavefronts of the block), so their chase windows, NW (2b - 1)
@@ -339,7 +337,6 @@ __global__ __launch_bounds__((TriCfg<B, V>::NT)) void band_tridiag_kernel(TriArg
             g_sh = failed ? a.ngroups : atomicAdd(a.ticket, 1);
             abort_sh = 0;
             vis_sh = 0;
-            upvis_sh = 0;
         }
         __syncthreads();
         const int g = __builtin_amdgcn_readfirstlane(g_sh);
@@ -409,29 +406,8 @@ __global__ __launch_bounds__((TriCfg<B, V>::NT)) void band_tridiag_kernel(TriArg
                     pf_lo = pf_hi = 0;
                 }
                 if (need > loaded) {
-                    if (g > 0 || a.up.kind != 0) {
-                        // the previous stage, when it runs beside this one,
-                        // must have finished the columns (group 0 asks it;
-                        // a later group loads what the group before it
-                        // released, which that group loaded after asking)
-                        if (t == 0 && g == 0 && a.up.kind != 0 && upvis_sh < need) {
-                            const uint64_t t0 = wall_clock64();
-                            while (!sbr::up_ready(a.up, need)) {
-                                __builtin_amdgcn_s_sleep(1);
-                                if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                                    abort_sh = 1;
-                                    break;
-                                }
-                                if (wall_clock64() - t0 > a.wait_ticks) {
-                                    atomicOr(a.error, sbr::STATUS_STALLED);
-                                    abort_sh = 1;
-                                    break;
-                                }
-                            }
-                            upvis_sh = need;
-                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                        }
-                        if (t == 0 && g > 0 && vis_sh < need) {
+                    if (g > 0) {
+                        if (t == 0 && vis_sh < need) {
                             const uint64_t t0 = wall_clock64();
                             int d;
                             while ((d = __hip_atomic_load(&a.done[g - 1], __ATOMIC_RELAXED,
@@ -468,8 +444,8 @@ __global__ __launch_bounds__((TriCfg<B, V>::NT)) void band_tridiag_kernel(TriArg
                     const int sl2 = lowest_active(s_lo, tau_s + C::BATCH);
                     int want = need_through(sl2, tau_s + 2 * C::BATCH - 1);
                     if (want > loaded + C::PFC) want = loaded + C::PFC;
-                    if (want > loaded && (g > 0 || a.up.kind != 0)) {
-                        if (t == 0 && g > 0 && vis_sh < want) {
+                    if (want > loaded && g > 0) {
+                        if (t == 0 && vis_sh < want) {
                             const int d = __hip_atomic_load(&a.done[g - 1], __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
                             if (d > vis_sh) {
@@ -477,13 +453,8 @@ __global__ __launch_bounds__((TriCfg<B, V>::NT)) void band_tridiag_kernel(TriArg
                                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                             }
                         }
-                        if (t == 0 && g == 0 && a.up.kind != 0 && upvis_sh < want && sbr::up_ready(a.up, want)) {
-                            upvis_sh = want;
-                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                        }
                         __syncthreads();
-                        if (g > 0 && want > vis_sh) want = vis_sh;
-                        if (g == 0 && a.up.kind != 0 && want > upvis_sh) want = upvis_sh;
+                        if (want > vis_sh) want = vis_sh;
                     }
                     if (want > loaded) {
                         const int cnt = (want - loaded) * LDW;
@@ -586,7 +557,7 @@ __global__ __launch_bounds__((TriCfg<B, V>::NT)) void band_tridiag_kernel(TriArg
 }
 
 template <int B, int V>
-void launch_tri(int64_t n, double* band, int64_t ld, const sbr::StageCtl& ctl, hipStream_t s) {
+void launch_tri(int64_t n, double* band, const sbr::StageCtl& ctl, hipStream_t s) {
     typedef TriCfg<B, V> C;
     const int64_t nsweeps = n - 2;
     if (nsweeps < 1) return;
@@ -594,14 +565,13 @@ void launch_tri(int64_t n, double* band, int64_t ld, const sbr::StageCtl& ctl, h
     TriArgs a;
     a.n = n;
     a.band = band;
-    a.ldg = (int)ld;
+    a.ldg = 2 * B + 1;
     a.nsweeps = (int)nsweeps;
     a.ngroups = (int)ngroups;
     a.ticket = ctl.flags;
     a.done = ctl.flags + 1;
     a.error = ctl.status;
     a.wait_ticks = ctl.wait_ticks;
-    a.up = ctl.up;
     sbr::launch_fill_int(ctl.flags, ngroups + 1, 0, s);
     int64_t grid = ngroups < 1024 ? ngroups : 1024;
     if (ctl.max_grid > 0 && grid > ctl.max_grid) grid = ctl.max_grid;
@@ -609,11 +579,11 @@ void launch_tri(int64_t n, double* band, int64_t ld, const sbr::StageCtl& ctl, h
 }
 
 template <int B>
-void launch_tri_variant(int64_t n, double* band, int64_t ld, const sbr::StageCtl& ctl, hipStream_t s) {
+void launch_tri_variant(int64_t n, double* band, const sbr::StageCtl& ctl, hipStream_t s) {
     switch (ctl.tri_variant) {
-        case 1: launch_tri<B, 1>(n, band, ld, ctl, s); break;
-        case 2: launch_tri<B, 2>(n, band, ld, ctl, s); break;
-        default: launch_tri<B, 0>(n, band, ld, ctl, s); break;
+        case 1: launch_tri<B, 1>(n, band, ctl, s); break;
+        case 2: launch_tri<B, 2>(n, band, ctl, s); break;
+        default: launch_tri<B, 0>(n, band, ctl, s); break;
     }
 }
 
@@ -638,30 +608,12 @@ bool band_tridiag_supported(int b) { return b == 4 || b == 8 || b == 16; }
 
 int band_tridiag_variants() { return TRI_VARIANTS; }
 
-void launch_band_tridiag(int64_t n, double* band, int64_t ld, int b, const StageCtl& ctl, hipStream_t s) {
+void launch_band_tridiag(int64_t n, double* band, int b, const StageCtl& ctl, hipStream_t s) {
     switch (b) {
-        case 4: launch_tri_variant<4>(n, band, ld, ctl, s); break;
-        case 8: launch_tri_variant<8>(n, band, ld, ctl, s); break;
-        case 16: launch_tri_variant<16>(n, band, ld, ctl, s); break;
+        case 4: launch_tri_variant<4>(n, band, ctl, s); break;
+        case 8: launch_tri_variant<8>(n, band, ctl, s); break;
+        case 16: launch_tri_variant<16>(n, band, ctl, s); break;
         default: break;
-    }
-}
-
-template <int B>
-int tri_sweeps(int variant) {
-    switch (variant) {
-        case 1: return TriCfg<B, 1>::S;
-        case 2: return TriCfg<B, 2>::S;
-        default: return TriCfg<B, 0>::S;
-    }
-}
-
-int band_tridiag_sweeps(int b, int variant) {
-    switch (b) {
-        case 4: return tri_sweeps<4>(variant);
-        case 8: return tri_sweeps<8>(variant);
-        case 16: return tri_sweeps<16>(variant);
-        default: return 1;
     }
 }
 

@@ -62,11 +62,9 @@ struct MChaseArgs {
     uint64_t wait_ticks;   // a wait gives up after this many ticks of the
                            // 100 MHz clock (it only bounds the kernel's lifetime
                            // should the schedule's progress guarantee break)
-    sbr::UpGate up;        // the previous band stage, when it runs beside this one
 };
 
 constexpr int MSWEEP_DONE = 1 << 30;
-static_assert(MSWEEP_DONE == sbr::UP_SWEEP_DONE, "complete-sweep word");
 
 template <int B_, int H>
 struct MChase {
@@ -211,11 +209,9 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
     double* Xs = sm + C::XS;      // carried below block (CARRY only)
     __shared__ int sweep_sh;
     __shared__ int abort_sh;
-    __shared__ int64_t upcol_sh;   // columns below it are final in the previous stage
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    if (t == 0) upcol_sh = 0;    // read first after the first ticket's barrier
     // Accumulator element r of a WY product lies in column ocol(r) of its
     // 16 x 16 tile (row li): 4 r + lk for FP64 MFMA, 4 lk + r for FP32 MFMA.
     // A register-held operand (an accumulator, or a block loaded in that
@@ -287,42 +283,6 @@ __global__ __launch_bounds__((MChase<B_, H>::NT)) void chase_mfma_kernel(MChaseA
             int64_t nb64 = n - (o + B);
             if (nb64 > B) nb64 = B;
             const int nbr = nb64 > 0 ? (int)nb64 : 0;
-
-            // ---- the previous stage, when it runs beside this one, must be
-            // done with every column this chase touches (< o + b).  Only
-            // sweep 1 asks: chase (i > 1, j) follows the QR block of chase
-            // (i - 1, j + 1) (through chase (i, j - 1)) or of (i - 1, 2), which
-            // asked for columns < (i - 1) h + (j + 1) b >= o + b.  upcol_sh is
-            // uniform here (written only after the barrier below, and read
-            // again only a chase later)
-            if (a.up.kind != 0 && i == 1) {
-                const int64_t needc = (o + B < n) ? o + B : n;
-                if (needc > upcol_sh) {
-                    int64_t got = needc;
-                    if (t == 0) {
-                        const uint64_t t0 = wall_clock64();
-                        while (!sbr::up_ready(a.up, needc)) {
-                            __builtin_amdgcn_s_sleep(2);
-                            if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                                abort_sh = 1;
-                                break;
-                            }
-                            if (wall_clock64() - t0 > a.wait_ticks) {
-                                atomicOr(a.error, sbr::STATUS_STALLED);
-                                abort_sh = 1;
-                                break;
-                            }
-                        }
-                        // ask for a stretch ahead too, so most chases skip this
-                        const int64_t ahead = needc + 16 * (int64_t)B;
-                        if (sbr::up_ready(a.up, ahead)) got = ahead;
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    }
-                    __syncthreads();
-                    if (abort_sh) return;
-                    if (t == 0) upcol_sh = got;
-                }
-            }
 
             // ---- 1. Householder QR of the QR block (rows [o, o+nr), cols
             // [cq, cq+h)): 8 lanes per column, one barrier per reflector.
@@ -860,7 +820,6 @@ void launch_mchase(int64_t n, double* band, int64_t ldb, double* scratch, const 
     a.scratch_stride = (int64_t)C::B * C::HP;
     a.error = ctl.status;
     a.wait_ticks = ctl.wait_ticks;
-    a.up = ctl.up;
     sbr::launch_fill_int(ctl.flags, nsweeps + 2, 0, s);
     int grid = mchase_grid<H>(n);
     if (ctl.max_grid > 0 && grid > ctl.max_grid) grid = ctl.max_grid;

@@ -103,56 +103,6 @@ constexpr int STATUS_NONFINITE = 2;   // the tridiagonal reached by the reductio
 // 100 MHz clock), and a cap on the grid (0 = automatic, 1 = the sequential
 // sweep order).  Bands b <= group_max_b (and b <= 16) go to the sweep-group
 // kernel when its layout allows, wider ones to the MFMA chase.
-// Gate on the stage before a band stage that runs beside it (the stages of
-// a solve overlap: a stage starts on the columns the previous one has
-// finished).  kind 0: no gate.  kind 1: the previous stage runs on the
-// wide-band chase kernel and flags[i] is the progress word of its sweep i
-// (the last chase whose QR block is published, MSWEEP_DONE when the sweep is
-// complete; sweeps finish in order).  kind 2: it runs on a sweep-group kernel
-// and flags[g] is the watermark of group g (every column below it is final as
-// far as that group's sweeps are concerned, and it is reached only after the
-// groups before it released those columns).  In both cases the previous
-// stage's sweep i = c / h + 1 is the last one to touch column c.
-struct UpGate {
-    const int* flags = nullptr;
-    int kind = 0;
-    int b = 0, h = 0;       // the previous stage reduces b -> h
-    int S = 1;              // kind 2: sweeps per group
-    int nsweeps = 0, ngroups = 0;
-    int64_t n = 0;
-};
-constexpr int UP_SWEEP_DONE = 1 << 30;   // the wide-band kernel's complete-sweep word
-
-// Whether every column < c is final with respect to the previous stage (one
-// relaxed load; the caller issues the acquire once it sees true).
-__device__ __forceinline__ bool up_ready(const UpGate& g, int64_t c) {
-    if (g.kind == 0 || c <= 0) return true;
-    const int64_t cc = (c < g.n ? c : g.n) - 1;           // highest column needed
-    const int64_t is = cc / g.h + 1;                     // last sweep touching it
-    if (g.kind == 1) {
-        int64_t i = is, need;
-        if (i > g.nsweeps) {
-            i = g.nsweeps;
-            need = UP_SWEEP_DONE;
-        } else {
-            // chase (i, j > 1) touches columns [o - b + h, o + b), o = i h +
-            // (j - 1) b; chase (i, 1) columns [(i - 1) h, i h + b)
-            const int64_t rel = cc - is * g.h - g.h;
-            const int64_t jl = rel < 0 ? 1 : rel / g.b + 2;
-            const int64_t nch = (g.n - 2 - is * g.h) / g.b + 1;
-            need = (jl >= nch) ? UP_SWEEP_DONE : jl + 1;   // chase jl complete
-        }
-        return __hip_atomic_load(g.flags + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
-    }
-    int64_t gi = (is - 1) / g.S;
-    int64_t need = cc + 1;
-    if (is > g.nsweeps || gi >= g.ngroups) {
-        gi = g.ngroups - 1;
-        need = g.n;
-    }
-    return __hip_atomic_load(g.flags + gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
-}
-
 struct StageCtl {
     int* flags;
     int* status;
@@ -160,7 +110,6 @@ struct StageCtl {
     int max_grid;
     int group_max_b;
     int tri_variant;     // launch shape of the direct band-to-tridiagonal kernel
-    UpGate up;           // the previous stage when the two run side by side
 };
 constexpr int DEFAULT_GROUP_MAX_B = 8;
 // Bands b <= this (and b in {4, 8, 16}) go straight to the tridiagonal in one
@@ -178,12 +127,6 @@ constexpr int DEFAULT_NEXT_FROM_128 = 64;
 constexpr int DEFAULT_NEXT_FROM_64 = 8;
 constexpr int DEFAULT_NEXT_FROM_32 = 8;
 constexpr uint64_t DEFAULT_WAIT_TICKS = 1000000000ull;   // 10 s
-// flag regions of the plan: one per band stage of a solve (b0 <= 128 gives at
-// most 7 stages)
-constexpr int BAND_FLAG_REGIONS = 8;
-// band stages from this width on run alone (their blocks fill a CU each and
-// they keep about 128 sweeps in flight): the next stage waits for them
-constexpr int PIPE_SOLO_B = 128;
 // Whether launch_band_halve handles (n, ldband, b).
 bool band_halve_supported(int64_t n, int64_t ldband, int b);
 void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32, double* scratch,
@@ -194,10 +137,6 @@ void launch_band_halve(int64_t n, double* band, int64_t ldband, int b, bool f32,
 bool band_reduce_supported(int64_t n, int64_t ldband, int b, int h);
 void launch_band_reduce(int64_t n, double* band, int64_t ldband, int b, int h, bool f32, double* scratch,
                         const StageCtl& ctl, hipStream_t s);
-// The gate a stage after this one (b -> h, launched with ctl) waits on.
-UpGate band_stage_gate(int64_t n, int64_t ldband, int b, int h, const StageCtl& ctl);
-// Work-groups a stage b -> h keeps busy at once (more only wait for tickets).
-int band_stage_busy_blocks(int64_t n, int64_t ldband, int b, int h, const StageCtl& ctl);
 // status[1] |= status[0]; status[0] = 0 (device side, capturable).
 void launch_status_rearm(int* status, hipStream_t s);
 void launch_fill_int(int* p, int64_t count, int v, hipStream_t s);
@@ -237,19 +176,15 @@ void launch_band_reduce_mfma(int64_t n, double* band, int64_t ldband, int b, int
                              const StageCtl& ctl, hipStream_t s);
 int init_band_mfma_attributes();
 // ---- sbr_band_tridiag.hip: band b in {4, 8, 16} straight to tridiagonal ----
-// (Algorithm 4.2 with k = b).  Band ld >= 2b + 1, n ld < 2^31.
+// (Algorithm 4.2 with k = b).  Band ld = 2b + 1, n (2b + 1) < 2^31.
 bool band_tridiag_supported(int b);
 int band_tridiag_variants();
-void launch_band_tridiag(int64_t n, double* band, int64_t ld, int b, const StageCtl& ctl, hipStream_t s);
-// sweeps per work-group of the direct kernel for b and a launch shape
-int band_tridiag_sweeps(int b, int variant);
+void launch_band_tridiag(int64_t n, double* band, int b, const StageCtl& ctl, hipStream_t s);
 int init_band_tridiag_attributes();
 // ---- sbr_band_group.hip: small bandwidths, sweep groups with LDS windows --
 bool band_group_supported(int b);
-// band ld >= 2b + 1, n ld < 2^31
-void launch_band_halve_group(int64_t n, double* band, int64_t ld, int b, const StageCtl& ctl, hipStream_t s);
-// sweeps per work-group of the halving b -> b/2
-int band_group_sweeps(int b);
+// band ld = 2b + 1, n (2b + 1) < 2^31
+void launch_band_halve_group(int64_t n, double* band, int b, const StageCtl& ctl, hipStream_t s);
 int init_band_group_attributes();
 void launch_band_to_tridiag(int64_t n, const double* band, int64_t ldband, double* d, double* e,
                             hipStream_t s);

@@ -146,30 +146,3 @@ def test_band_reduce_fp32_form(sbr, oracle_mod, b, h, n):
     err = np.max(np.abs(w - ref)) / _norm2(ref)
     print("  max err %.3e (x ||A||_2)" % err, flush=True)
     assert err <= 2e-5
-
-
-@pytest.mark.parametrize("n,b0,widths", [(3000, 128, []), (2049, 128, [32, 8, 4, 1]), (1500, 64, [16, 8, 4, 2, 1]),
-                                         (4000, 128, [64, 16, 4, 1]), (777, 32, [8, 1]), (5000, 128, [64, 8, 4, 1])])
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mfma"])
-def test_band_stages_side_by_side_equal_sequential(sbr, oracle_mod, n, b0, widths, precision):
-    # the band stages run side by side (each on the columns the stage before
-    # it has finished, in place in one buffer) or one after another (each on
-    # a narrowed copy): every chase sees the same data, so the eigenvalues
-    # are the same bits; and they match the oracle
-    print("side by side n=%d b0=%d widths=%s %s" % (n, b0, widths, precision), flush=True)
-    A = si.gaussian_symmetric(n, si.make_rng(si.CFG_SMALL, 40 + n % 7))
-    ref = oracle_mod.eigvalsh(A)
-    outs = []
-    for pipe, blocks in ((False, 0), (True, 0), (True, 1)):
-        plan = sbr.Plan(n, 0, precision)
-        plan.set_band_stages(widths)
-        plan.set_band_pipeline(pipe)
-        plan.set_chase_blocks(blocks)
-        w = sbr.eigvalsh(torch.from_numpy(A).cuda(), b0=b0, precision=precision, plan=plan)
-        torch.cuda.synchronize()
-        assert plan.status() == 0
-        outs.append(w.cpu().numpy())
-    assert np.array_equal(outs[0], outs[1]), np.max(np.abs(outs[0] - outs[1]))
-    assert np.array_equal(outs[0], outs[2]), np.max(np.abs(outs[0] - outs[2]))
-    tol = 1e-11 if precision == "fp64" else 2e-5
-    assert np.max(np.abs(outs[1] - ref)) <= tol * _norm2(ref)
