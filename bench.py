@@ -499,8 +499,8 @@ def main():
             "syr2k_TFLOPs": round(sum(syr2k_f) / (syr2k32 * 1e-3) / 1e12, 2) if syr2k32 > 0 else None,
             "panel_and_other": round(mean([t["ms_f2b"] for t in wt32]) - symm32 - syr2k32, 3)}
         result["fp32_mfma"]["roofline"] = {
-            "bound": "mfma", "kernel": "syr2k_lower_kernel<float, 128, 2, 4, 2, float> (bulk trailing update, "
-                                       "FP32 storage)",
+            "bound": "mfma", "kernel": "syr2k_lower_kernel<float, 128, 2, 4, 2, float, true, float> (bulk trailing update, "
+                                       "FP32 storage and operands)",
             "achieved": round(ach32, 3), "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
             "frac": round(ach32 / PEAK_FP32_MFMA, 4), "traffic": None, "launches": nbig32,
             "avg_launch_ms": round(kms32 / max(1, nbig32), 4)}

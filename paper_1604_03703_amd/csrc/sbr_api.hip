@@ -76,9 +76,11 @@ struct sbr_plan_s {
     hipEvent_t bupload_ev = nullptr;
     hipGraphExec_t bgraph = nullptr;
     std::vector<int64_t> bkey;
-    // FP32-storage copy of the trailing matrix for the FP32-MFMA form
+    // FP32-storage copy of the trailing matrix for the FP32-MFMA form, then
+    // FP32 copies of the panel's U, V and Y (n_cap x b_cap each, ld n_cap)
     float* as_buf = nullptr;
     int64_t as_cap = 0;
+    float *Uf = nullptr, *Vf = nullptr, *Yf = nullptr;
     double *part = nullptr;
     int64_t part_doubles = 0;
     double *T = nullptr, *W1inv = nullptr, *Mm = nullptr, *Zm = nullptr, *S = nullptr;
@@ -333,19 +335,29 @@ void release_upd_stream(sbr_plan_t p) {
 // FP32 copy of the trailing matrix for the FP32-MFMA form; false when it
 // cannot be allocated (the form then keeps FP64 storage).
 bool ensure_f32_storage(sbr_plan_t p, int64_t n) {
-    if (p->as_cap >= n * n) return true;
+    const int64_t skinny = p->n_cap * (int64_t)p->b_cap;
+    const int64_t need = n * n + 3 * skinny;
+    if (p->as_cap >= need) {
+        p->Uf = p->as_buf + n * n;
+        p->Vf = p->Uf + skinny;
+        p->Yf = p->Vf + skinny;
+        return true;
+    }
     if (p->as_buf) {
         (void)hipFree(p->as_buf);
         p->as_buf = nullptr;
         p->as_cap = 0;
     }
     void* q = nullptr;
-    if (hipMalloc(&q, (size_t)n * n * sizeof(float)) != hipSuccess) {
+    if (hipMalloc(&q, (size_t)need * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         return false;
     }
     p->as_buf = (float*)q;
-    p->as_cap = n * n;
+    p->as_cap = need;
+    p->Uf = p->as_buf + n * n;
+    p->Vf = p->Uf + skinny;
+    p->Yf = p->Vf + skinny;
     return true;
 }
 
@@ -375,6 +387,7 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
         if (f32s) launch_lower_to_f32(n - b, A + b + b * lda, lda, As + b + b * lds, lds, s);
         factor_panel(p, n - b, b, A + b, lda, p->Ub[0], s);
         launch_gemm(false, false, false, n - b, b, b, 1.0, p->Ub[0], ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, s);
+        if (f32s) launch_block_to_f32(n - b, b, p->Y, ldq, p->Yf, ldq, s);
     }
     for (;; ++k) {
         const int64_t c0 = k * b, r0 = c0 + b, m = n - r0;
@@ -386,13 +399,19 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
         EventPair ep;
         if (p->timing == 1) { ep.a = p->ev(); p->mark(ep.a, s); }
         const int ss = symm_splits(m, b);
-        if (f32s) launch_symm_lower_f32s(m, b, A22s, lds, p->Y, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
+        if (f32s) launch_symm_lower_f32s(m, b, A22s, lds, p->Yf, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
         else launch_symm_lower(f32, m, b, A22, lda, p->Y, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
         if (p->timing == 1) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_symm.push_back(ep); }
         // Z = U^T W ; M = T^T Z ; V = 1/2 U M - W
         const int gs = gemm_splits(b, b, m);
         launch_ttuw(b, m, U, ldq, p->W, ldq, p->T, b, p->Mm, p->part, gs, s);
         launch_gemm(false, false, false, m, b, b, 0.5, U, ldq, p->Mm, b, -1.0, p->W, ldq, p->V, ldq, s);
+        // FP32 form: the update's operands rounded once (its products round
+        // them anyway), half the bytes for every tile that reads them
+        if (f32s) {
+            launch_block_to_f32(m, b, U, ldq, p->Uf, ldq, s);
+            launch_block_to_f32(m, b, p->V, ldq, p->Vf, ldq, s);
+        }
         // A22 += U V^T + V U^T (the timed pair brackets the bulk launch only)
         EventPair eq;
         const int64_t mn = m - b;          // rows of the next panel
@@ -409,7 +428,7 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
             if (e != hipSuccess) return hip_fail(e);
             auto bulk = [&](hipStream_t us) {
                 if (p->timing) { eq.a = p->ev(); p->mark(eq.a, us); }
-                if (f32s) launch_syr2k_lower_f32s(mn, b, U + b, ldq, p->V + b, ldq, A22s + b + b * lds, lds, us);
+                if (f32s) launch_syr2k_lower_f32s(mn, b, p->Uf + b, ldq, p->Vf + b, ldq, A22s + b + b * lds, lds, us);
                 else launch_syr2k_lower(f32, mn, b, U + b, ldq, p->V + b, ldq, A22 + b + b * lda, lda, us);
                 if (p->timing) {
                     eq.b = p->ev();
@@ -424,7 +443,7 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
                 if (e != hipSuccess) return hip_fail(e);
             }
             if (f32s) {
-                launch_syr2k_lower_cols_f32s(m, b, b, U, ldq, p->V, ldq, A22s, lds, p->side);
+                launch_syr2k_lower_cols_f32s(m, b, b, p->Uf, ldq, p->Vf, ldq, A22s, lds, p->side);
                 launch_cols_to_f64(m, b, A22s, lds, A22, lda, p->side);
             } else {
                 launch_syr2k_lower_cols(f32, m, b, b, U, ldq, p->V, ldq, A22, lda, p->side);
@@ -432,6 +451,7 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
             double* Un = p->Ub[cur ^ 1];
             factor_panel(p, mn, b, A22 + b, lda, Un, p->side);
             launch_gemm(false, false, false, mn, b, b, 1.0, Un, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, p->side);
+            if (f32s) launch_block_to_f32(mn, b, p->Y, ldq, p->Yf, ldq, p->side);
             e = hipEventRecord(p->ev_join, p->side);
             if (e != hipSuccess) return hip_fail(e);
             if (p->upd) e = hipStreamWaitEvent(s, p->ev_ujoin, 0);
@@ -441,7 +461,7 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
             cur ^= 1;
         } else {
             if (p->timing) { eq.a = p->ev(); p->mark(eq.a, s); }
-            if (f32s) launch_syr2k_lower_f32s(m, b, U, ldq, p->V, ldq, A22s, lds, s);
+            if (f32s) launch_syr2k_lower_f32s(m, b, p->Uf, ldq, p->Vf, ldq, A22s, lds, s);
             else launch_syr2k_lower(f32, m, b, U, ldq, p->V, ldq, A22, lda, s);
             if (p->timing) {
                 eq.b = p->ev();
@@ -614,7 +634,8 @@ int sbr_workspace_size(int64_t n, int32_t b0, sbr_precision prec, size_t* bytes)
     if (prec != SBR_FP64 && prec != SBR_FP32_MFMA) return -3;
     if (!bytes) return -4;
     *bytes = make_layout(std::max<int64_t>(n, 1), b0).bytes;
-    if (prec == SBR_FP32_MFMA) *bytes += (size_t)n * n * sizeof(float);   // FP32 copy of the trailing matrix
+    if (prec == SBR_FP32_MFMA)   // FP32 copies of the trailing matrix and of U, V, Y
+        *bytes += ((size_t)n * n + 3 * (size_t)std::max<int64_t>(n, 1) * b0) * sizeof(float);
     return 0;
 }
 

@@ -222,11 +222,14 @@ __device__ __forceinline__ void lower_tile_banded(int64_t x, int64_t T, int64_t&
 // The result is added into C with atomic adds that return nothing: with
 // K' = 256 a tile is only 16 chunks long, and a read-modify-write epilogue
 // would hold the block for a full C read latency.
-// ST: storage type of C (double, or float for the FP32-storage form).
-template <typename CT, int BM, int WM, int WN, int PAD = 2, typename ST = double, bool FAST = true>
+// ST: storage type of C (double, or float for the FP32-storage form); OT:
+// type of U and V (double, or FP32 copies of them in the FP32 form, half the
+// bytes per operand).
+template <typename CT, int BM, int WM, int WN, int PAD = 2, typename ST = double, bool FAST = true,
+          typename OT = double>
 __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
-    int64_t m, int64_t nc, int64_t jt, int64_t K, const double* __restrict__ U, int64_t ldu,
-    const double* __restrict__ V, int64_t ldv, ST* C, int64_t ldc, int64_t ntiles) {
+    int64_t m, int64_t nc, int64_t jt, int64_t K, const OT* __restrict__ U, int64_t ldu,
+    const OT* __restrict__ V, int64_t ldv, ST* C, int64_t ldc, int64_t ntiles) {
     typedef TileEngine<CT, BM, BM, WM, WN, PAD, false> E;
     typedef TileMap<BM, E::NT, false> MA;   // row fastest (column-major U, V)
     typedef TileMap<BM, E::NT, false> MB;
@@ -255,32 +258,33 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     // (block-uniform) buffer base, and rows past m read zero through an
     // out-of-range offset.  No branches and no 64-bit address arithmetic per
     // element.  Otherwise element-wise loads with bounds checks.
-    const uint32_t span = (uint32_t)((m + (int64_t)(SBR_BK - 1) * ldu) * (int64_t)sizeof(double));
+    constexpr int64_t SO = sizeof(OT);
+    const uint32_t span = (uint32_t)((m + (int64_t)(SBR_BK - 1) * ldu) * SO);
     uint32_t offa[MA::E], offb[MB::E];
     if constexpr (FAST) {
 #pragma unroll
         for (int e = 0; e < MA::E; ++e) {
             int i, k;
             MA::coords(t, e, i, k);
-            offa[e] = (i0 + i < m) ? (uint32_t)(((i0 + i) + (int64_t)k * ldu) * 8) : SBR_BUF_OOB;
+            offa[e] = (i0 + i < m) ? (uint32_t)(((i0 + i) + (int64_t)k * ldu) * SO) : SBR_BUF_OOB;
         }
 #pragma unroll
         for (int e = 0; e < MB::E; ++e) {
             int j, k;
             MB::coords(t, e, j, k);
-            offb[e] = (j0 + j < m) ? (uint32_t)(((j0 + j) + (int64_t)k * ldu) * 8) : SBR_BUF_OOB;
+            offb[e] = (j0 + j < m) ? (uint32_t)(((j0 + j) + (int64_t)k * ldu) * SO) : SBR_BUF_OOB;
         }
     }
     auto load = [&](int64_t k0) {
         if constexpr (FAST) {
-            const double* pa = (k0 < K) ? U + k0 * ldu : V + (k0 - K) * ldu;
-            const double* pb = (k0 < K) ? V + k0 * ldu : U + (k0 - K) * ldu;
+            const OT* pa = (k0 < K) ? U + k0 * ldu : V + (k0 - K) * ldu;
+            const OT* pb = (k0 < K) ? V + k0 * ldu : U + (k0 - K) * ldu;
             const __amdgpu_buffer_rsrc_t rsa = sbr_buffer(pa, span);
             const __amdgpu_buffer_rsrc_t rsb = sbr_buffer(pb, span);
 #pragma unroll
-            for (int e = 0; e < MA::E; ++e) ra[e] = (CT)sbr_buffer_load(rsa, offa[e], 0.0);
+            for (int e = 0; e < MA::E; ++e) ra[e] = (CT)sbr_buffer_load(rsa, offa[e], OT());
 #pragma unroll
-            for (int e = 0; e < MB::E; ++e) rb[e] = (CT)sbr_buffer_load(rsb, offb[e], 0.0);
+            for (int e = 0; e < MB::E; ++e) rb[e] = (CT)sbr_buffer_load(rsb, offb[e], OT());
             return;
         }
 #pragma unroll
@@ -288,7 +292,7 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
             int i, k;
             MA::coords(t, e, i, k);
             const int64_t gi = i0 + i, gk = k0 + k;
-            double v = 0.0;
+            OT v = 0;
             if (gi < m && gk < K2) v = (gk < K) ? U[gi + gk * ldu] : V[gi + (gk - K) * ldv];
             ra[e] = (CT)v;
         }
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
             int j, k;
             MB::coords(t, e, j, k);
             const int64_t gj = j0 + j, gk = k0 + k;
-            double v = 0.0;
+            OT v = 0;
             if (gj < m && gk < K2) v = (gk < K) ? V[gj + gk * ldv] : U[gj + (gk - K) * ldu];
             rb[e] = (CT)v;
         }
@@ -357,10 +361,11 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
 // block-uniform base that a chunk moves, rows past m, columns past nb and k
 // past kend read zero through an out-of-range offset.  Every offset is below
 // 2^31 (the launcher checks (m + BM lda) sizeof(ST) and BN ldy 8 against it).
-template <typename CT, int BM, int BN, int WM, int WN, int PAD = 2, typename ST = double>
+// YT: type of Y (double, or an FP32 copy of it in the FP32 form).
+template <typename CT, int BM, int BN, int WM, int WN, int PAD = 2, typename ST = double, typename YT = double>
 __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(BM == 128 ? 4 : 1))) void symm_lower_kernel(
     int64_t m, int64_t nb, int64_t kchunk, const ST* __restrict__ A, int64_t lda,
-    const double* __restrict__ Y, int64_t ldy, double* W, int64_t ldw, int64_t slice_stride) {
+    const YT* __restrict__ Y, int64_t ldy, double* W, int64_t ldw, int64_t slice_stride) {
     typedef TileEngine<CT, BM, BN, WM, WN, PAD, false> E;   // long K: no operand prefetch (registers)
     typedef TileMap<BM, E::NT, false> MAi;   // row fastest
     typedef TileMap<BM, E::NT, true> MAk;    // k fastest
@@ -381,7 +386,8 @@ __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(BM
     const uint32_t spanD = (uint32_t)((BM + (int64_t)(SBR_BK - 1) * lda) * SA);
     const uint32_t spanM = (uint32_t)((SBR_BK + (int64_t)(BM - 1) * lda) * SA);
     const uint32_t spanS = (uint32_t)((m + (int64_t)BM * lda) * SA);
-    const uint32_t spanY = (uint32_t)((SBR_BK + (int64_t)(BN - 1) * ldy) * 8);
+    constexpr uint32_t SY = sizeof(YT);
+    const uint32_t spanY = (uint32_t)((SBR_BK + (int64_t)(BN - 1) * ldy) * SY);
     const uint32_t mrows = (uint32_t)(m - i0 < BM ? m - i0 : BM);      // valid rows of the tile
     const uint32_t ncols = (uint32_t)(nb - j0 < BN ? nb - j0 : BN);    // valid columns of Y
 
@@ -393,7 +399,7 @@ __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(BM
             int j, k;
             MB::coords(t, e, j, k);
             const bool ok = (uint32_t)j < ncols && k < kv;
-            rb[e] = (CT)sbr_buffer_load(ry, ok ? ((uint32_t)k + (uint32_t)j * ldy32) * 8u : SBR_BUF_OOB, 0.0);
+            rb[e] = (CT)sbr_buffer_load(ry, ok ? ((uint32_t)k + (uint32_t)j * ldy32) * SY : SBR_BUF_OOB, YT());
         }
     };
     // below the diagonal block: A[i0 + i + (k0 + k) lda]
@@ -539,26 +545,26 @@ void gemm_dispatch_t(bool ta, bool tb, int64_t M, int64_t N, int64_t K, int64_t 
     else gemm_dispatch<CT, true, true>(M, N, K, kchunk, splits, alpha, A, lda, B, ldb, beta, Cin, ldci, Cout, ldco, slice_stride, s);
 }
 
-template <typename CT, typename ST>
+template <typename CT, typename ST, typename YT = double>
 void symm_dispatch(int64_t m, int64_t nb, int64_t kchunk, int splits, const ST* A, int64_t lda,
-                   const double* Y, int64_t ldy, double* W, int64_t ldw, int64_t slice_stride, hipStream_t s) {
+                   const YT* Y, int64_t ldy, double* W, int64_t ldw, int64_t slice_stride, hipStream_t s) {
     if (nb > 64) {
         if (m >= 2048) {
             dim3 g(cdiv(m, 128), cdiv(nb, 128), splits);
-            symm_lower_kernel<CT, 128, 128, 2, 4, 2, ST><<<g, 512, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+            symm_lower_kernel<CT, 128, 128, 2, 4, 2, ST, YT><<<g, 512, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
         } else {
             dim3 g(cdiv(m, 64), cdiv(nb, 128), splits);
-            symm_lower_kernel<CT, 64, 128, 2, 2, 2, ST><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+            symm_lower_kernel<CT, 64, 128, 2, 2, 2, ST, YT><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
         }
     } else if (nb > 32) {
         dim3 g(cdiv(m, 64), cdiv(nb, 64), splits);
-        symm_lower_kernel<CT, 64, 64, 2, 2, 2, ST><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+        symm_lower_kernel<CT, 64, 64, 2, 2, 2, ST, YT><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
     } else if (nb > 16) {
         dim3 g(cdiv(m, 64), cdiv(nb, 32), splits);
-        symm_lower_kernel<CT, 64, 32, 4, 1, 2, ST><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+        symm_lower_kernel<CT, 64, 32, 4, 1, 2, ST, YT><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
     } else {
         dim3 g(cdiv(m, 64), cdiv(nb, 16), splits);
-        symm_lower_kernel<CT, 64, 16, 4, 1, 2, ST><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
+        symm_lower_kernel<CT, 64, 16, 4, 1, 2, ST, YT><<<g, 256, 0, s>>>(m, nb, kchunk, A, lda, Y, ldy, W, ldw, slice_stride);
     }
 }
 
@@ -569,6 +575,12 @@ __global__ void lower_to_f32_kernel(int64_t m, const double* __restrict__ A, int
     const int64_t j = blockIdx.y;
     for (int64_t i = j + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
         As[i + j * lds] = (float)A[i + j * lda];
+}
+// The m x nc block of X (ld ldx) rounded to FP32 into Xs (ld lds).
+__global__ void block_to_f32_kernel(int64_t m, const double* __restrict__ X, int64_t ldx, float* Xs, int64_t lds) {
+    const int64_t j = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        Xs[i + j * lds] = (float)X[i + j * ldx];
 }
 __global__ void cols_to_f64_kernel(int64_t m, const float* __restrict__ As, int64_t lds, double* A, int64_t lda) {
     const int64_t j = blockIdx.y;
@@ -640,17 +652,17 @@ bool syr2k_big_tiles(int64_t m) {
 
 // One launch of syr2k_lower_kernel over nt tiles: the buffer-load form when
 // its conditions hold, the element-wise form otherwise.
-template <typename CT, int BM, int WM, int WN, typename ST>
-void syr2k_go(int64_t nt, int64_t m, int64_t nc, int64_t jt, int64_t K, const double* U, int64_t ldu,
-              const double* V, int64_t ldv, ST* C, int64_t ldc, hipStream_t s) {
+template <typename CT, int BM, int WM, int WN, typename ST, typename OT = double>
+void syr2k_go(int64_t nt, int64_t m, int64_t nc, int64_t jt, int64_t K, const OT* U, int64_t ldu,
+              const OT* V, int64_t ldv, ST* C, int64_t ldc, hipStream_t s) {
     const bool fast = (ldu == ldv) && (K % SBR_BK == 0) &&
-                      (m + (int64_t)(SBR_BK - 1) * ldu) * (int64_t)sizeof(double) < (int64_t)SBR_BUF_OOB;
+                      (m + (int64_t)(SBR_BK - 1) * ldu) * (int64_t)sizeof(OT) < (int64_t)SBR_BUF_OOB;
     if (fast)
-        syr2k_lower_kernel<CT, BM, WM, WN, 2, ST, true><<<(unsigned)nt, 64 * WM * WN, 0, s>>>(m, nc, jt, K, U, ldu, V,
-                                                                                          ldv, C, ldc, nt);
+        syr2k_lower_kernel<CT, BM, WM, WN, 2, ST, true, OT><<<(unsigned)nt, 64 * WM * WN, 0, s>>>(m, nc, jt, K, U, ldu,
+                                                                                              V, ldv, C, ldc, nt);
     else
-        syr2k_lower_kernel<CT, BM, WM, WN, 2, ST, false><<<(unsigned)nt, 64 * WM * WN, 0, s>>>(m, nc, jt, K, U, ldu, V,
-                                                                                           ldv, C, ldc, nt);
+        syr2k_lower_kernel<CT, BM, WM, WN, 2, ST, false, OT><<<(unsigned)nt, 64 * WM * WN, 0, s>>>(m, nc, jt, K, U, ldu,
+                                                                                               V, ldv, C, ldc, nt);
 }
 
 void launch_syr2k_lower(bool f32, int64_t m, int64_t K, const double* U, int64_t ldu, const double* V,
@@ -752,6 +764,49 @@ void launch_lower_to_f32(int64_t m, const double* A, int64_t lda, float* As, int
     if (m <= 0) return;
     dim3 g((unsigned)cdiv(m, 1024) < 64 ? (unsigned)cdiv(m, 1024) : 64, (unsigned)m);
     lower_to_f32_kernel<<<g, 256, 0, s>>>(m, A, lda, As, lds);
+}
+
+void launch_block_to_f32(int64_t m, int64_t nc, const double* X, int64_t ldx, float* Xs, int64_t lds, hipStream_t s) {
+    if (m <= 0 || nc <= 0) return;
+    dim3 g((unsigned)cdiv(m, 1024) < 64 ? (unsigned)cdiv(m, 1024) : 64, (unsigned)nc);
+    block_to_f32_kernel<<<g, 256, 0, s>>>(m, X, ldx, Xs, lds);
+}
+
+// FP32-storage form with FP32 copies of the operands (U, V; Y)
+void launch_syr2k_lower_f32s(int64_t m, int64_t K, const float* U, int64_t ldu, const float* V, int64_t ldv,
+                             float* C, int64_t ldc, hipStream_t s) {
+    if (m <= 0 || K <= 0) return;
+    const int64_t T128 = (m + 127) / 128;
+    if (syr2k_big_tiles(m)) {
+        const int64_t nt = T128 * (T128 + 1) / 2;
+        syr2k_go<float, 128, 2, 4, float, float>(nt, m, m, 0, K, U, ldu, V, ldv, C, ldc, s);
+        return;
+    }
+    const int64_t T = (m + 63) / 64;
+    const int64_t nt = T * (T + 1) / 2;
+    syr2k_go<float, 64, 2, 2, float, float>(nt, m, m, 0, K, U, ldu, V, ldv, C, ldc, s);
+}
+
+void launch_syr2k_lower_cols_f32s(int64_t m, int64_t nc, int64_t K, const float* U, int64_t ldu, const float* V,
+                                  int64_t ldv, float* C, int64_t ldc, hipStream_t s) {
+    if (m <= 0 || K <= 0 || nc <= 0) return;
+    if (nc > m) nc = m;
+    const int64_t T = (m + 63) / 64, jt = (nc + 63) / 64;
+    const int64_t nt = T * jt;
+    syr2k_go<float, 64, 2, 2, float, float>(nt, m, nc, jt, K, U, ldu, V, ldv, C, ldc, s);
+}
+
+void launch_symm_lower_f32s(int64_t m, int64_t nb, const float* A, int64_t lda, const float* Y, int64_t ldy,
+                            double* W, int64_t ldw, double* part, int splits, hipStream_t s) {
+    if (m <= 0 || nb <= 0) return;
+    if (splits <= 1 || part == nullptr) {
+        symm_dispatch<float, float, float>(m, nb, m, 1, A, lda, Y, ldy, W, ldw, 0, s);
+        return;
+    }
+    int64_t kchunk = (m + splits - 1) / splits;
+    kchunk = (kchunk + SBR_BK - 1) / SBR_BK * SBR_BK;
+    symm_dispatch<float, float, float>(m, nb, kchunk, splits, A, lda, Y, ldy, part, m, m * nb, s);
+    reduce_slices(m, nb, splits, part, 1.0, 0.0, nullptr, 0, W, ldw, s);
 }
 
 void launch_cols_to_f64(int64_t m, int64_t nc, const float* As, int64_t lds, double* A, int64_t lda, hipStream_t s) {

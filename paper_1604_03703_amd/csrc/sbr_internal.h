@@ -39,6 +39,16 @@ void launch_syr2k_lower_cols_f32s(int64_t m, int64_t nc, int64_t K, const double
                                   int64_t ldv, float* C, int64_t ldc, hipStream_t s);
 void launch_symm_lower_f32s(int64_t m, int64_t nb, const float* A, int64_t lda, const double* Y, int64_t ldy,
                             double* W, int64_t ldw, double* part, int splits, hipStream_t s);
+// The same with FP32 copies of the skinny operands (half the bytes per
+// operand load; the products round to FP32 anyway).
+void launch_syr2k_lower_f32s(int64_t m, int64_t K, const float* U, int64_t ldu, const float* V, int64_t ldv,
+                             float* C, int64_t ldc, hipStream_t s);
+void launch_syr2k_lower_cols_f32s(int64_t m, int64_t nc, int64_t K, const float* U, int64_t ldu, const float* V,
+                                  int64_t ldv, float* C, int64_t ldc, hipStream_t s);
+void launch_symm_lower_f32s(int64_t m, int64_t nb, const float* A, int64_t lda, const float* Y, int64_t ldy,
+                            double* W, int64_t ldw, double* part, int splits, hipStream_t s);
+// X (m x nc, ld ldx) rounded to FP32 into Xs (ld lds).
+void launch_block_to_f32(int64_t m, int64_t nc, const double* X, int64_t ldx, float* Xs, int64_t lds, hipStream_t s);
 // Lower triangle of A's m x m block -> As (FP32); the first nc columns of As's
 // m x m block (lower part) -> A (FP64).
 void launch_lower_to_f32(int64_t m, const double* A, int64_t lda, float* As, int64_t lds, hipStream_t s);
