@@ -155,8 +155,8 @@ int sbr_tridiag_eigvals(int64_t n, const double* d, const double* e,
  * sbr_tridiag_eigvals without any allocation, for callers that cannot
  * allocate device memory: code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc.  Same arguments, kernels and results as
- * sbr_tridiag_eigvals; its scratch (e^2 and the bisection setup, about
- * 2 MiB) is a fixed array in the library's device image, one per GPU, held
+ * sbr_tridiag_eigvals; its scratch (e^2, the Sturm counts of the first grid
+ * and the bisection setup, about 4 MiB) is a fixed array in the library's device image, one per GPU, held
  * until the process ends.  n <= 262144 (2^18), else SBR_ENOTSUP before
  * anything is enqueued.  All calls on one GPU share that array: calls that
  * overlap on one GPU (concurrent streams or threads) race and must be

@@ -182,7 +182,7 @@ Layout make_layout(int64_t n, int b) {
     L.off_status = take(cur, 2 * sizeof(int));
     L.off_d = take(cur, (size_t)n * D);
     L.off_e = take(cur, (size_t)n * D);
-    L.off_e2p = take(cur, (size_t)n * D);
+    L.off_e2p = take(cur, (size_t)bisect_workspace_doubles(n) * D);
     L.off_setup = take(cur, sizeof(BisectSetup));
     L.off_pcopy = take(cur, nb * D);
     L.bytes = cur + 256;

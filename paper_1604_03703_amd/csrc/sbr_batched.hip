@@ -430,8 +430,8 @@ __global__ __launch_bounds__(64) void batched_band_kernel(const BatchDesc* __res
 }
 
 // ---------------------------------------------------------------------------
-// Sturm bisection per matrix (same counting, guard, interval and iteration
-// rule as the single-matrix kernels).
+// Sturm bisection per matrix (the same counts, interval and final width as
+// the single-matrix kernels, by plain bisection from the whole interval).
 
 constexpr int BB_NT = 64;   // one wavefront per matrix
 
@@ -447,11 +447,13 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // KQ eigenvalue indices per lane (k = lane + 64 q), bisected in lockstep: KQ
-// independent count recurrences per step hide the latency of each chain's
-// divisions.
+// independent count recurrences per step (SturmChain on the scaled d, e^2
+// in LDS; a wave with a chain whose minors came near underflow recounts all
+// its chains with the guarded ratio recurrence).
 template <int KQ>
 __device__ __forceinline__ void bisect_lanes(int n, const double* sd, const double* se, double lo, double hi,
-                                             double piv, int iters, double* w, int lane) {
+                                             double sc, int iters, double* w, int lane) {
+    constexpr int U = 16;
     double a[KQ], c[KQ];
     bool live[KQ];
 #pragma unroll
@@ -461,28 +463,54 @@ __device__ __forceinline__ void bisect_lanes(int n, const double* sd, const doub
         live[q] = lane + 64 * q < n;
     }
     for (int it = 0; it < iters; ++it) {
-        double x[KQ], qv[KQ];
-        int cnt[KQ];
+        double x[KQ], xs[KQ];
+        SturmChain ch[KQ];
         bool anyl = false;
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
             x[q] = a[q] + 0.5 * (c[q] - a[q]);
             if (live[q] && (x[q] == a[q] || x[q] == c[q])) live[q] = false;
             anyl |= live[q];
-            qv[q] = 1.0;
-            cnt[q] = 0;
+            xs[q] = x[q] * sc;
+            ch[q].start();
         }
         if (!__any(anyl)) break;
-#pragma unroll 4
-        for (int i = 0; i < n; ++i) {
+        int i = 0;
+        for (; i + U <= n; i += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double di = sd[i + u], ei = se[i + u];
+#pragma unroll
+                for (int q = 0; q < KQ; ++q) ch[q].step(di - xs[q], ei);
+            }
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) ch[q].template close_block<U>();
+        }
+        for (; i < n; ++i) {
             const double di = sd[i], ei = se[i];
 #pragma unroll
-            for (int q = 0; q < KQ; ++q) {
-                double v = (di - x[q]) - ei * sbr_recip(qv[q]);   // pivmin >= DBL_MIN: finite
-                v = (fabs(v) < piv) ? -piv : v;
-                qv[q] = v;
-                cnt[q] += (v < 0.0);
+            for (int q = 0; q < KQ; ++q) ch[q].step_tail(di - xs[q], ei);
+        }
+        bool low = false;
+        int cnt[KQ];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            ch[q].finish();
+            low |= ch[q].low;
+            cnt[q] = ch[q].cnt;
+        }
+        if (__any(low)) {
+            SturmRatio r[KQ];
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) r[q].start();
+            for (int j = 0; j < n; ++j) {
+                const double di = sd[j], ei = se[j];
+#pragma unroll
+                for (int q = 0; q < KQ; ++q) r[q].step(di - xs[q], ei);
             }
+#pragma unroll
+            for (int q = 0; q < KQ; ++q)
+                if (ch[q].low) cnt[q] = r[q].cnt;
         }
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
@@ -533,10 +561,9 @@ __global__ __launch_bounds__(BB_NT) void batched_bisect_kernel(const BatchDesc* 
         lo = wave_min(lo);
         hi = wave_max(hi);
         emax2 = wave_max(emax2);
-        team_sync<64>();
-        const double pivmin = DBL_MIN * emax2;
         const double eps = DBL_EPSILON * 0.5;
         double tnorm = fmax(fabs(lo), fabs(hi));
+        const double pivmin = DBL_MIN * emax2;
         const double widen = 2.1 * ((double)n * eps * tnorm + 2.0 * pivmin);
         const double l = lo - widen, h = hi + widen;
         tnorm = fmax(fabs(l), fabs(h));
@@ -545,15 +572,23 @@ __global__ __launch_bounds__(BB_NT) void batched_bisect_kernel(const BatchDesc* 
             iters = (int)ceil(log2((h - l) / (eps * tnorm))) + 2;
             if (iters < 0) iters = 0;
         }
+        // the Sturm data scaled so that the interval width is below one
+        const double sc = (h > l) ? sturm_scale(h - l) : 1.0;
+        team_sync<64>();
+        for (int i = t; i < n; i += BB_NT) {
+            sd[i] *= sc;
+            se[i] *= sc * sc;
+        }
+        team_sync<64>();
         switch ((n + 63) / 64) {
-            case 1: bisect_lanes<1>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
-            case 2: bisect_lanes<2>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
-            case 3: bisect_lanes<3>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
-            case 4: bisect_lanes<4>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
-            case 5: bisect_lanes<5>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
-            case 6: bisect_lanes<6>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
-            case 7: bisect_lanes<7>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
-            default: bisect_lanes<8>(n, sd, se, l, h, pivmin, iters, dm.w, t); break;
+            case 1: bisect_lanes<1>(n, sd, se, l, h, sc, iters, dm.w, t); break;
+            case 2: bisect_lanes<2>(n, sd, se, l, h, sc, iters, dm.w, t); break;
+            case 3: bisect_lanes<3>(n, sd, se, l, h, sc, iters, dm.w, t); break;
+            case 4: bisect_lanes<4>(n, sd, se, l, h, sc, iters, dm.w, t); break;
+            case 5: bisect_lanes<5>(n, sd, se, l, h, sc, iters, dm.w, t); break;
+            case 6: bisect_lanes<6>(n, sd, se, l, h, sc, iters, dm.w, t); break;
+            case 7: bisect_lanes<7>(n, sd, se, l, h, sc, iters, dm.w, t); break;
+            default: bisect_lanes<8>(n, sd, se, l, h, sc, iters, dm.w, t); break;
         }
         team_sync<64>();
     }

@@ -2,19 +2,23 @@
 // bisection (the last step of Algorithm 4.3, "compute the eigenvalues of the
 // thin band", done here on the tridiagonal reached by the halvings).
 //
-// Sturm count of T - x I: q_0 = d_0 - x, q_i = (d_i - x) - e_{i-1}^2 / q_{i-1};
-// a pivot with |q| < pivmin is replaced by -pivmin (Kahan's guard); the count
-// is the number of negative pivots.  pivmin >= DBL_MIN, so 1/q is finite and
-// is taken as a Newton-refined reciprocal (about one ulp, like the division
-// it replaces: the count is exact for T with each e^2 perturbed by a few ulps,
-// the backward error the eigenvalue tolerance allows for).  The interval
-// is the Gershgorin interval widened by 2.1 (n eps |T| + 2 pivmin), and every
-// index runs the same fixed number of halvings
-// I = ceil(log2((hi - lo) / (eps max(|lo|, |hi|)))) + 2, stopping early when
-// the midpoint equals an end point.
+// The count of eigenvalues below x is the number of sign changes of the
+// leading principal minors of T - x I (SturmChain: the three-term recurrence
+// on data scaled by a power of two, rescaled every 16 steps; a chain whose
+// minors come near underflow is recounted with the guarded ratio recurrence
+// q_i = (d_i - x) - e_{i-1}^2 / q_{i-1}, SturmRatio).  The interval is the
+// Gershgorin interval widened by 2.1 (n eps |T| + 2 pivmin); every index ends
+// no wider than the bisection of that interval by
+// I = ceil(log2((hi - lo) / (eps max(|lo|, |hi|)))) + 2 halvings would leave
+// it, stopping early when no point falls strictly inside.
 //
-// One thread per eigenvalue index; d and e^2 are streamed through LDS in
-// chunks that every thread of the block reads at the same address (broadcast).
+// Two passes share the work of the first halvings, which is the same for all
+// indices: the counts at 2n evenly spaced points of the interval (one thread
+// a point), after which each index starts from the grid cell that holds its
+// eigenvalue (a binary search in the counts), about log2(2n) halvings in one
+// pass; then multisection inside the cell (G lanes per index).  d and e^2 are
+// streamed through LDS in chunks that every thread of the block reads at the
+// same address (broadcast).
 //
 // A tridiagonal with a NaN or an infinity has no meaningful Sturm counts: the
 // setup kernel flags it (and raises the non-finite bit of the plan's status
@@ -28,17 +32,20 @@
 #include "sbr_internal.h"
 
 // Fixed device scratch of the allocation-free tridiagonal entry point: e^2
-// (NOALLOC_MAX_N doubles), then the setup record.  One copy per GPU, held
+// (NOALLOC_MAX_N doubles) and the grid counts (2 NOALLOC_MAX_N ints), then
+// the setup record.  One copy per GPU, held
 // until the process ends.  Host code must not use this name as an address (it
 // names a host-side stand-in): the device address comes from
 // hipGetSymbolAddress, see noalloc_scratch below.
-constexpr int64_t NOALLOC_E2_DOUBLES = sbr::NOALLOC_MAX_N;
+constexpr int64_t NOALLOC_E2_DOUBLES = 2 * sbr::NOALLOC_MAX_N;
 constexpr int64_t NOALLOC_SETUP_DOUBLES = (sizeof(sbr::BisectSetup) + sizeof(double) - 1) / sizeof(double);
 static __device__ __align__(256) double scratch[NOALLOC_E2_DOUBLES + NOALLOC_SETUP_DOUBLES];
 
 namespace {
 
 constexpr int PREP_NT = 256;
+// lanes per eigenvalue index in the multisection pass
+constexpr int BISECT_LANES = 2;
 
 __global__ __launch_bounds__(PREP_NT) void bisect_prep_kernel(int64_t n, const double* __restrict__ d,
                                                                const double* __restrict__ e,
@@ -87,71 +94,143 @@ __global__ __launch_bounds__(PREP_NT) void bisect_prep_kernel(int64_t n, const d
         setup->lo = l;
         setup->hi = h;
         setup->pivmin = pivmin;
+        setup->scale = (h > l) ? sturm_scale(h - l) : 1.0;
         setup->iters = anybad ? 0 : iters;
         setup->nonfinite = anybad;
         if (anybad && status) atomicOr(status, sbr::STATUS_NONFINITE);
     }
 }
 
-// Multisection: G lanes per eigenvalue index, lane g evaluates the Sturm count
-// at x_g = a + (g + 1) (c - a) / (G + 1); the interval then shrinks to the
-// piece between the last point with count <= k and the next one, a factor
-// G + 1 per round.  More lanes per index keep every SIMD busy when there are
-// few indices per SIMD (the count recurrence is a serial chain of divisions).
+// Sturm count at xs (scaled) for every thread of the block: d and e^2 pass
+// through LDS scaled by sc, sc^2 in chunks of CH, each thread runs one
+// chain; if any chain of the block came near underflow, the block recounts
+// with the guarded ratio recurrence and those chains take that count.
+// Called by every thread of the block (it synchronises).
+template <int NT, int CH>
+__device__ __forceinline__ int sturm_count(int n, const double* __restrict__ d, const double* __restrict__ e2p,
+                                           double sc, double xs, double2* sde) {
+    constexpr int U = 16;
+    static_assert(CH % U == 0, "chunks hold whole blocks");
+    const int t = threadIdx.x;
+    const double sc2 = sc * sc;
+    SturmChain ch;
+    ch.start();
+    for (int s0 = 0; s0 < n; s0 += CH) {
+        const int len = (n - s0 < CH) ? (n - s0) : CH;
+        __syncthreads();
+        for (int i = t; i < len; i += NT) sde[i] = make_double2(d[s0 + i] * sc, e2p[s0 + i] * sc2);
+        __syncthreads();
+        int i = 0;
+        for (; i + U <= len; i += U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double2 de = sde[i + u];
+                ch.step(de.x - xs, de.y);
+            }
+            ch.template close_block<U>();
+        }
+        for (; i < len; ++i) {   // only the last chunk has a partial block
+            const double2 de = sde[i];
+            ch.step_tail(de.x - xs, de.y);
+        }
+    }
+    ch.finish();
+    if (!__syncthreads_or(ch.low)) return ch.cnt;
+    SturmRatio r;
+    r.start();
+    for (int s0 = 0; s0 < n; s0 += CH) {
+        const int len = (n - s0 < CH) ? (n - s0) : CH;
+        __syncthreads();
+        for (int i = t; i < len; i += NT) sde[i] = make_double2(d[s0 + i] * sc, e2p[s0 + i] * sc2);
+        __syncthreads();
+        for (int i = 0; i < len; ++i) {
+            const double2 de = sde[i];
+            r.step(de.x - xs, de.y);
+        }
+    }
+    return ch.low ? r.cnt : ch.cnt;
+}
+
+// Point j (0 <= j < M) of the grid of M interior points of [lo, hi]; the
+// same expression in both passes, so a cell's ends are the points counted.
+__device__ __forceinline__ double grid_point(double lo, double hi, int M, int j) {
+    return lo + (double)(j + 1) * ((hi - lo) / (double)(M + 1));
+}
+
+// First pass: counts at the M grid points, one thread each.
+template <int NT, int CH>
+__global__ __launch_bounds__(NT) void sturm_grid_kernel(int64_t n, int M, const double* __restrict__ d,
+                                                        const double* __restrict__ e2p,
+                                                        const sbr::BisectSetup* __restrict__ setup,
+                                                        int* __restrict__ gcnt) {
+    __shared__ double2 sde[CH];
+    if (setup->iters == 0) return;   // the whole grid: no interval to search
+    const int j = (int)blockIdx.x * NT + (int)threadIdx.x;
+    const double x = grid_point(setup->lo, setup->hi, M, j < M ? j : M - 1);
+    const double sc = setup->scale;
+    const int cnt = sturm_count<NT, CH>((int)n, d, e2p, sc, x * sc, sde);
+    if (j < M) gcnt[j] = cnt;
+}
+
+// Second pass, multisection: G lanes per eigenvalue index, lane g counts at
+// x_g = a + (g + 1) (c - a) / (G + 1); the interval then shrinks to the piece
+// between the last point with count <= k and the next one, a factor G + 1
+// per round.  Several lanes per index keep every SIMD busy when there are few
+// indices per SIMD.  The start interval is the grid cell [x_jl, x_jh] with
+// count(x_jl) <= k < count(x_jh) (x_{-1} = lo, x_M = hi), found by binary
+// search; it holds the eigenvalue whatever rounding did to the counts.
 template <int NT, int CH, int G>
-__global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, const double* __restrict__ d,
+__global__ __launch_bounds__(NT) void bisect_kernel(int64_t n, int M, const double* __restrict__ d,
                                                     const double* __restrict__ e2p,
                                                     const sbr::BisectSetup* __restrict__ setup,
-                                                    double* __restrict__ w, const int* status) {
-    static_assert(G == 4 || G == 8 || G == 16, "lanes per index");
-    __shared__ double sd[CH], se[CH];
+                                                    const int* __restrict__ gcnt, double* __restrict__ w,
+                                                    const int* status) {
+    static_assert(G == 2 || G == 4 || G == 8, "lanes per index");
+    __shared__ double2 sde[CH];
     const int t = threadIdx.x, g = t % G;
     const int64_t k = (int64_t)blockIdx.x * (NT / G) + t / G;   // 0-based: the (k+1)-th smallest
-    const double lo = setup->lo, hi = setup->hi, piv = setup->pivmin;
-    // rounds so that (hi - lo) / (G + 1)^rounds is below the bisection's
-    // final width (hi - lo) / 2^iters
+    const double lo = setup->lo, hi = setup->hi, sc = setup->scale;
     const int iters = setup->iters;
-    const int rounds = (int)ceil((double)iters / log2((double)(G + 1)));
     double a = lo, c = hi;
     bool live = (k < n);
+    int rounds = 0;
+    if (iters > 0) {
+        if (live) {
+            int jl = -1, jh = M;
+            while (jh - jl > 1) {
+                const int mid = (jl + jh) >> 1;
+                if (gcnt[mid] > k) jh = mid;
+                else jl = mid;
+            }
+            a = (jl < 0) ? lo : grid_point(lo, hi, M, jl);
+            c = (jh >= M) ? hi : grid_point(lo, hi, M, jh);
+        }
+        // rounds so that (hi - lo) / ((M + 1) (G + 1)^rounds) is below the
+        // bisection's final width (hi - lo) / 2^iters
+        const double need = (double)iters - log2((double)M + 1.0);
+        rounds = need > 0.0 ? (int)ceil(need / log2((double)(G + 1))) : 0;
+    }
     for (int it = 0; it < rounds; ++it) {
         const double x = a + (double)(g + 1) * ((c - a) / (double)(G + 1));
         const bool act = live && (c - a) > 0.0 && (x > a) && (x < c);
         if (!__syncthreads_or(act)) break;
-        int cnt = 0;   // n < 2^31 (checked at the entry points)
-        double q = 1.0;
-        for (int64_t s0 = 0; s0 < n; s0 += CH) {
-            const int len = (int)((n - s0 < CH) ? (n - s0) : CH);
-            __syncthreads();
-            for (int i = t; i < len; i += NT) {
-                sd[i] = d[s0 + i];
-                se[i] = e2p[s0 + i];
-            }
-            __syncthreads();
-#pragma unroll 8
-            for (int i = 0; i < len; ++i) {
-                q = (sd[i] - x) - se[i] * sbr_recip(q);
-                if (fabs(q) < piv) q = -piv;
-                cnt += (q < 0.0);
-            }
-        }
+        const int cnt = sturm_count<NT, CH>((int)n, d, e2p, sc, x * sc, sde);   // n < 2^31 (entry points)
         // p = number of points left of the eigenvalue (count <= k); the
-        // counts are monotone in x, so the eigenvalue lies in [x_{p-1}, x_p]
-        // (x_{-1} = a, x_G = c).  The lanes of a group hold the same a, c and
-        // evaluate the same formula for the points, so they agree on the ends.
+        // counts are monotone in x up to rounding, so the eigenvalue lies in
+        // [x_{p-1}, x_p] (x_{-1} = a, x_G = c).  The lanes of a group hold
+        // the same a, c and evaluate the same formula for the points, so
+        // they agree on the ends.
         double left = (cnt <= k) ? 1.0 : 0.0;
         double any = act ? 1.0 : 0.0;
         left += dpp_d<0xB1>(left);
         any += dpp_d<0xB1>(any);
-        left += dpp_d<0x4E>(left);
-        any += dpp_d<0x4E>(any);
+        if (G >= 4) {
+            left += dpp_d<0x4E>(left);
+            any += dpp_d<0x4E>(any);
+        }
         if (G >= 8) {
             left += dpp_d<0x141>(left);
             any += dpp_d<0x141>(any);
-        }
-        if (G >= 16) {
-            left += dpp_d<0x140>(left);
-            any += dpp_d<0x140>(any);
         }
         if (live) {
             if (any > 0.0) {
@@ -199,9 +278,13 @@ void launch_tridiag_eigvals(int64_t n, const double* d, const double* e, double*
                             double* w, int* status, hipStream_t s) {
     if (n <= 0) return;
     bisect_prep_kernel<<<1, PREP_NT, 0, s>>>(n, d, e, e2p, setup, status);
-    constexpr int NT = 256, CH = 2048, G = 4;
+    constexpr int NT = 256, CH = 2048, G = BISECT_LANES;
+    // the grid counts fill the workspace's second n doubles (2n ints)
+    const int M = (int)(n < (int64_t{1} << 29) ? 2 * n : (int64_t{1} << 30));
+    int* gcnt = (int*)(e2p + n);
+    sturm_grid_kernel<NT, CH><<<(unsigned)((M + NT - 1) / NT), NT, 0, s>>>(n, M, d, e2p, setup, gcnt);
     const unsigned blocks = (unsigned)((n + NT / G - 1) / (NT / G));
-    bisect_kernel<NT, CH, G><<<blocks, NT, 0, s>>>(n, d, e2p, setup, w, status);
+    bisect_kernel<NT, CH, G><<<blocks, NT, 0, s>>>(n, M, d, e2p, setup, gcnt, w, status);
 }
 
 }  // namespace sbr

@@ -2,6 +2,7 @@
 // (gfx950 / CDNA4, wave64).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <float.h>
 #include <stdint.h>
 
 typedef double sbr_d4 __attribute__((ext_vector_type(4)));
@@ -158,6 +159,91 @@ __device__ __forceinline__ double sbr_rsqrt(double a) {
     y = fma(0.5 * y, fma(-a, y * y, 1.0), y);
     y = fma(0.5 * y, fma(-a, y * y, 1.0), y);
     return y;
+}
+
+// Sturm count of T - x I by the three-term recurrence of the leading
+// principal minors, p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2} (p_0 = 1,
+// e_0 = 0): the number of eigenvalues below x is the number of sign changes
+// along p_0, ..., p_n (an exact zero counts by its sign bit, which gives the
+// same total over two steps as Kahan's guard).  The data are scaled by a power
+// of two so that |d_i - x| <= 1 and e^2 <= 1/4, so the larger of two
+// consecutive minors grows by at most 1.25 a step; every U steps both are
+// rescaled by a power of two (no rounding), so nothing overflows.  If the
+// pair falls below 2^-600 at a block end (a split with x on an eigenvalue of
+// the leading block, or couplings near underflow), some step of the block may
+// have lost accuracy to underflow: `low` is set and the caller recounts with
+// the guarded ratio recurrence.  Otherwise the count is exact for T with each
+// d_i - x and e^2 perturbed by a few ulps, the same backward error as the
+// ratio form (Barth, Martin and Wilkinson's scaled form of the recurrence).
+// A step is three FP64 operations and one bit append, against a division or
+// a refined reciprocal, a guard and a compare in the ratio form.
+struct SturmChain {
+    double pm, pc;   // p_{i-2}, p_{i-1}
+    unsigned bits;   // sign bits of the current block, newest in bit 0, the last sign before it above them
+    int cnt;
+    bool low;
+
+    __device__ __forceinline__ void start() {
+        pm = 0.0;
+        pc = 1.0;
+        bits = 0u;
+        cnt = 0;
+        low = false;
+    }
+    // one step inside a block: dx = d_i - x, e2 = e_{i-1}^2 (scaled)
+    __device__ __forceinline__ void step(double dx, double e2) {
+        const double pn = fma(dx, pc, -(e2 * pm));
+        pm = pc;
+        pc = pn;
+        bits = __builtin_amdgcn_alignbit(bits, (unsigned)__double2hiint(pn), 31u);   // (bits << 1) | sign
+    }
+    // end of a block of U steps: count its sign changes, rescale the pair
+    template <int U>
+    __device__ __forceinline__ void close_block() {
+        static_assert(U >= 1 && U <= 31, "block length");
+        cnt += __builtin_popcount((bits ^ (bits >> 1)) & ((1u << U) - 1u));
+        bits &= 1u;
+        const double m = fmax(fabs(pm), fabs(pc));
+        low |= !(m >= 0x1p-600);
+        const int ex = __builtin_amdgcn_frexp_exp(m);
+        pm = __builtin_amdgcn_ldexp(pm, -ex);
+        pc = __builtin_amdgcn_ldexp(pc, -ex);
+    }
+    // a step after the last full block (bits holds the last sign in bit 0)
+    __device__ __forceinline__ void step_tail(double dx, double e2) {
+        const double pn = fma(dx, pc, -(e2 * pm));
+        pm = pc;
+        pc = pn;
+        const unsigned sg = (unsigned)__double2hiint(pn) >> 31;
+        cnt += (int)(sg ^ bits);
+        bits = sg;
+    }
+    __device__ __forceinline__ void finish() { low |= !(fmax(fabs(pm), fabs(pc)) >= 0x1p-600); }
+};
+
+// The ratio form q_i = (d_i - x) - e_{i-1}^2 / q_{i-1} with a correctly
+// rounded division and Kahan's guard (|q| < pivmin -> -pivmin), counting the
+// negative pivots: the recount for a chain whose scaled minors came near
+// underflow.  On the scaled data pivmin = DBL_MIN keeps e^2 / q finite.
+struct SturmRatio {
+    double q;
+    int cnt;
+    __device__ __forceinline__ void start() {
+        q = 1.0;
+        cnt = 0;
+    }
+    __device__ __forceinline__ void step(double dx, double e2) {
+        double v = dx - e2 / q;
+        if (fabs(v) < DBL_MIN) v = -DBL_MIN;
+        q = v;
+        cnt += (v < 0.0);
+    }
+};
+
+// Power of two 2^-E with w 2^-E in [1/2, 1): the scale of the Sturm data for
+// a Gershgorin interval of width w > 0.
+__device__ __forceinline__ double sturm_scale(double w) {
+    return __builtin_amdgcn_ldexp(1.0, -__builtin_amdgcn_frexp_exp(w));
 }
 
 // Sum of N values by pairs (a tree of depth log2 N instead of a chain of N).

@@ -202,10 +202,15 @@ void launch_band_to_tridiag(int64_t n, const double* band, int64_t ldband, doubl
 // ---- sbr_bisect.hip -------------------------------------------------------
 struct BisectSetup {
     double lo, hi, pivmin;
+    double scale;     // power of two putting the interval width in [1/2, 1)
     int iters;
     int nonfinite;    // d or e holds a NaN or an infinity
 };
-// e may be null when n == 1.  e2p (n doubles) and setup are workspace.
+// Doubles of bisection workspace for order n: e^2 (n) and the Sturm counts
+// at the 2n points of the shared first grid (2n ints).
+inline int64_t bisect_workspace_doubles(int64_t n) { return 2 * n; }
+// e may be null when n == 1.  e2p (bisect_workspace_doubles(n)) and setup
+// are workspace.
 // status: null, or the plan's status word: its STATUS_NONFINITE bit is set
 // for a non-finite tridiagonal, and when status[0] is nonzero (a stage of
 // the call was abandoned, or the input is not finite) every w is NaN.
