@@ -191,6 +191,22 @@ int sbr_plan_set_wait_limit(sbr_plan_t plan, int64_t ticks);
  * CU-masked streams are unavailable the setting has no effect. */
 int sbr_plan_set_panel_cus(sbr_plan_t plan, int32_t cus);
 
+/* Number of consecutive full-to-band panels whose two-sided updates are
+ * aggregated before one trailing update (default 1).  Section 4, Eq. (4.2):
+ * the update X + U V^T + V U^T need not be applied before the next panel,
+ * since the product that panel needs is (X + U V^T + V U^T) Y =
+ * X Y + U (V^T Y) + V (U^T Y).  With depth D, the panels of a group take
+ * their W = A22 Y from the matrix as it stood at the start of the group plus
+ * those skinny corrections, each next panel's columns get the pending
+ * updates before its factorization, and one SYR2K of rank 2 D b per group
+ * updates the trailing matrix (the next group's first panel is factored
+ * beside it, as with depth 1).  Applies to the FP64 form (the FP32-MFMA form
+ * keeps depth 1).  Depth > 1 allocates 4 n_max D b + 2 D b^2 doubles of
+ * aggregation buffers, here for the plan's current size and again when a
+ * larger problem grows the plan.  Returns 0, -1 (null plan), -2 (depth
+ * outside 1 .. 4) or SBR_ENOMEM. */
+int sbr_plan_set_update_depth(sbr_plan_t plan, int32_t depth);
+
 /* Blocking (waits for the device): the SBR_STATUS_* bits raised by the calls
  * made through the plan since the previous sbr_plan_status, then clears
  * them.  Every call starts with a clear live word, so a stage abandoned by

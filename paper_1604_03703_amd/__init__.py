@@ -82,6 +82,7 @@ def _load():
         "sbr_band_reduce": ([_vp, _i64, _vp, _i64, _i32, _i32, ctypes.c_int, _vp], ctypes.c_int),
         "sbr_plan_set_band_stages": ([_vp, _i32, ctypes.POINTER(_i32)], ctypes.c_int),
         "sbr_plan_get_band_stages": ([_vp, _i64, _i32, ctypes.POINTER(_i32), _i32], ctypes.c_int),
+        "sbr_plan_set_update_depth": ([_vp, _i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -99,7 +100,7 @@ EXPORTED = (
     "sbr_plan_set_chase_blocks", "sbr_plan_set_panel_cus", "sbr_plan_status",
     "sbr_plan_set_wait_limit", "sbr_plan_set_group_max_band", "sbr_tridiag_eigvals_noalloc",
     "sbr_plan_set_tridiag_band", "sbr_band_to_tridiag", "sbr_plan_set_batch_bands",
-    "sbr_band_reduce", "sbr_plan_set_band_stages", "sbr_plan_get_band_stages",
+    "sbr_band_reduce", "sbr_plan_set_band_stages", "sbr_plan_get_band_stages", "sbr_plan_set_update_depth",
 )
 
 STATUS_STALLED = 1      # SBR_STATUS_STALLED
@@ -170,6 +171,10 @@ class Plan:
 
     def set_panel_cus(self, cus: int):
         _check(_lib.sbr_plan_set_panel_cus(self._h, int(cus)), "sbr_plan_set_panel_cus")
+
+    def set_update_depth(self, depth: int):
+        """Panels whose two-sided updates are aggregated (Eq. (4.2)); 1 = per panel."""
+        _check(_lib.sbr_plan_set_update_depth(self._h, int(depth)), "sbr_plan_set_update_depth")
 
     def set_group_max_band(self, b: int):
         _check(_lib.sbr_plan_set_group_max_band(self._h, int(b)), "sbr_plan_set_group_max_band")

@@ -81,6 +81,12 @@ struct sbr_plan_s {
     float* as_buf = nullptr;
     int64_t as_cap = 0;
     float *Uf = nullptr, *Vf = nullptr, *Yf = nullptr;
+    // aggregated updates (Eq. (4.2), update_depth > 1): two sets (one per
+    // group in flight) of U and V for update_depth panels, n_cap x depth b
+    // each with absolute row numbering, then two small products
+    int32_t update_depth = 1;
+    double* gbuf = nullptr;
+    int64_t gbuf_cap = 0;
     double *part = nullptr;
     int64_t part_doubles = 0;
     double *T = nullptr, *W1inv = nullptr, *Mm = nullptr, *Zm = nullptr, *S = nullptr;
@@ -361,6 +367,152 @@ bool ensure_f32_storage(sbr_plan_t p, int64_t n) {
     return true;
 }
 
+// Doubles of the aggregation buffers for depth D panels of width b, order up
+// to ldq: U and V sets for two groups, then Z1, Z2 ((D - 1) b x b each).
+int64_t group_buffer_doubles(int64_t ldq, int b, int D) {
+    return 4 * ldq * (int64_t)D * b + 2 * (int64_t)D * b * b;
+}
+
+bool ensure_group_buffers(sbr_plan_t p, int b, int D) {
+    const int64_t need = group_buffer_doubles(p->n_cap, b, D);
+    if (p->gbuf_cap >= need) return true;
+    if (p->gbuf) {
+        (void)hipFree(p->gbuf);
+        p->gbuf = nullptr;
+        p->gbuf_cap = 0;
+    }
+    void* q = nullptr;
+    if (hipMalloc(&q, (size_t)need * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    p->gbuf = (double*)q;
+    p->gbuf_cap = need;
+    return true;
+}
+
+// Full-to-band with the two-sided updates of D consecutive panels aggregated
+// (Eq. (4.1) appended panel by panel, applied left-looking as in Eq. (4.2)):
+// inside a group, panel j's product with the trailing matrix is taken from
+// the matrix as it stood at the start of the group plus the pending updates,
+//   W_j = A22 Y_j + U_g (V_g^T Y_j) + V_g (U_g^T Y_j),
+// where U_g, V_g hold the group's earlier panels (rows of panel j's trailing
+// matrix); the next panel's columns receive the pending updates before they
+// are factored; and once per group one SYR2K of rank 2 D b applies them all.
+// U and V are stored with absolute row numbers (row r of A at row r of the
+// buffer), so the rows of panel j's trailing matrix are one pointer offset
+// for every panel of the group.  Across groups the work forks as in the
+// per-panel form: the next group's first panel is updated and factored on
+// the side stream while the group's bulk update runs.  FP64 storage only.
+int run_full_to_band_grouped(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, int D, hipStream_t s) {
+    const int64_t ldq = p->n_cap;
+    if (!ensure_group_buffers(p, b, D)) return SBR_ENOMEM;
+    const int64_t setsz = ldq * (int64_t)D * b;
+    double* Ucs[2] = {p->gbuf, p->gbuf + 2 * setsz};
+    double* Vcs[2] = {p->gbuf + setsz, p->gbuf + 3 * setsz};
+    double* Z1 = p->gbuf + 4 * setsz;
+    double* Z2 = Z1 + (int64_t)D * b * b;
+    int gi = 0, g = 0;
+    int64_t k = 0;
+    if (n - b >= b) {
+        const int rc = ensure_side_stream(p);
+        if (rc) return rc;
+        factor_panel(p, n - b, b, A + b, lda, Ucs[0] + b, s);
+        launch_gemm(false, false, false, n - b, b, b, 1.0, Ucs[0] + b, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, s);
+    }
+    // split-K slices for the small reductions, within the partials buffer
+    auto splits_for = [&](int64_t M, int64_t N, int64_t K) {
+        int sp = gemm_splits(M, N, K);
+        while (sp > 1 && (int64_t)sp * M * N > p->part_doubles) sp /= 2;
+        return sp;
+    };
+    for (;; ++k) {
+        const int64_t c0 = k * b, r0 = c0 + b, m = n - r0;
+        if (m < b) break;
+        double* Ug = Ucs[gi] + r0;                 // the group's panels, rows r0 ..
+        double* Vg = Vcs[gi] + r0;
+        double* U = Ug + (int64_t)g * b * ldq;     // this panel
+        double* V = Vg + (int64_t)g * b * ldq;
+        double* A22 = A + r0 + r0 * lda;
+        EventPair ep;
+        if (p->timing == 1) { ep.a = p->ev(); p->mark(ep.a, s); }
+        const int ss = symm_splits(m, b);
+        launch_symm_lower(false, m, b, A22, lda, p->Y, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
+        if (p->timing == 1) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_symm.push_back(ep); }
+        if (g > 0) {
+            // W += U_g (V_g^T Y) + V_g (U_g^T Y): the group's pending updates
+            const int64_t gb = (int64_t)g * b;
+            launch_gemm_splitk(false, true, false, gb, b, m, 1.0, Vg, ldq, p->Y, ldq, 0.0, nullptr, 0, Z1, gb,
+                               p->part, splits_for(gb, b, m), s);
+            launch_gemm_splitk(false, true, false, gb, b, m, 1.0, Ug, ldq, p->Y, ldq, 0.0, nullptr, 0, Z2, gb,
+                               p->part, splits_for(gb, b, m), s);
+            launch_gemm(false, false, false, m, b, gb, 1.0, Ug, ldq, Z1, gb, 1.0, p->W, ldq, p->W, ldq, s);
+            launch_gemm(false, false, false, m, b, gb, 1.0, Vg, ldq, Z2, gb, 1.0, p->W, ldq, p->W, ldq, s);
+        }
+        // V = 1/2 U (T^T U^T W) - W
+        const int gs = gemm_splits(b, b, m);
+        launch_ttuw(b, m, U, ldq, p->W, ldq, p->T, b, p->Mm, p->part, gs, s);
+        launch_gemm(false, false, false, m, b, b, 0.5, U, ldq, p->Mm, b, -1.0, p->W, ldq, V, ldq, s);
+        const int G = g + 1;                        // panels pending in the group
+        const int64_t K = (int64_t)G * b;
+        const int64_t mn = m - b;
+        if (mn >= b && G < D) {
+            // the next panel joins the group: its columns get the pending
+            // updates, then it is factored (U at absolute row r0 + b)
+            launch_syr2k_lower_cols(false, m, b, K, Ug, ldq, Vg, ldq, A22, lda, s);
+            double* Un = Ug + b + K * ldq;
+            factor_panel(p, mn, b, A22 + b, lda, Un, s);
+            launch_gemm(false, false, false, mn, b, b, 1.0, Un, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, s);
+            g = G;
+        } else if (mn >= b) {
+            // end of the group: bulk update of rank 2 K beside the next
+            // group's first panel (its columns updated, then factored)
+            hipError_t e = hipEventRecord(p->ev_fork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+            if (e == hipSuccess && p->upd) e = hipStreamWaitEvent(p->upd, p->ev_fork, 0);
+            if (e != hipSuccess) return hip_fail(e);
+            EventPair eq;
+            auto bulk = [&](hipStream_t us) {
+                if (p->timing) { eq.a = p->ev(); p->mark(eq.a, us); }
+                launch_syr2k_lower(false, mn, K, Ug + b, ldq, Vg + b, ldq, A22 + b + b * lda, lda, us);
+                if (p->timing) {
+                    eq.b = p->ev();
+                    p->mark(eq.b, us);
+                    p->ev_syr2k.push_back(eq);
+                    p->syr2k_big.push_back(syr2k_big_tiles(mn) ? 1 : 0);
+                }
+            };
+            if (p->upd) {
+                bulk(p->upd);
+                e = hipEventRecord(p->ev_ujoin, p->upd);
+                if (e != hipSuccess) return hip_fail(e);
+            }
+            launch_syr2k_lower_cols(false, m, b, K, Ug, ldq, Vg, ldq, A22, lda, p->side);
+            double* Un = Ucs[gi ^ 1] + r0 + b;
+            factor_panel(p, mn, b, A22 + b, lda, Un, p->side);
+            launch_gemm(false, false, false, mn, b, b, 1.0, Un, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, p->side);
+            e = hipEventRecord(p->ev_join, p->side);
+            if (e != hipSuccess) return hip_fail(e);
+            if (p->upd) e = hipStreamWaitEvent(s, p->ev_ujoin, 0);
+            else bulk(s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join, 0);
+            if (e != hipSuccess) return hip_fail(e);
+            gi ^= 1;
+            g = 0;
+        } else {
+            // no next panel: the pending updates on the whole rest
+            launch_syr2k_lower(false, m, K, Ug, ldq, Vg, ldq, A22, lda, s);
+        }
+        SBR_CHECK_LAUNCH();
+    }
+    const int64_t c0 = k * b, r0 = c0 + b, m = n - r0;
+    if (m >= 2) {
+        launch_f2b_tail(m, b, A + r0 + c0 * lda, lda, A + r0 + r0 * lda, lda, s);
+        SBR_CHECK_LAUNCH();
+    }
+    return 0;
+}
+
 // Panel k (columns c0 .. c0+b-1, rows below the band) and its trailing
 // update.  The update of panel k's trailing matrix is split: the columns of
 // panel k+1, then the rest.  Once V is known the work forks: the rest of the
@@ -379,6 +531,7 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
     int64_t k = 0;
     int cur = 0;
     const bool f32s = f32 && n - b >= b && ensure_f32_storage(p, n);
+    if (!f32s && p->update_depth > 1) return run_full_to_band_grouped(p, n, A, lda, b, p->update_depth, s);
     float* As = f32s ? p->as_buf : nullptr;
     const int64_t lds = n;
     if (n - b >= b) {
@@ -611,6 +764,7 @@ int sbr_plan_destroy(sbr_plan_t plan) {
     (void)hipDeviceSynchronize();
     for (hipEvent_t e : plan->pool) (void)hipEventDestroy(e);
     if (plan->as_buf) (void)hipFree(plan->as_buf);
+    if (plan->gbuf) (void)hipFree(plan->gbuf);
     if (plan->bgraph) (void)hipGraphExecDestroy(plan->bgraph);
     if (plan->bupload_ev) (void)hipEventDestroy(plan->bupload_ev);
     if (plan->bdesc_host) (void)hipHostFree(plan->bdesc_host);
@@ -655,6 +809,14 @@ int sbr_plan_set_panel_cus(sbr_plan_t plan, int32_t cus) {
     if (e != hipSuccess) return hip_fail(e);
     release_upd_stream(plan);
     plan->panel_cus = cus;
+    return 0;
+}
+
+int sbr_plan_set_update_depth(sbr_plan_t plan, int32_t depth) {
+    if (!plan) return -1;
+    if (depth < 1 || depth > 4) return -2;
+    if (depth > 1 && plan->ws && !ensure_group_buffers(plan, plan->b_cap, depth)) return SBR_ENOMEM;
+    plan->update_depth = depth;
     return 0;
 }
 

@@ -55,6 +55,7 @@ def test_invalid_arguments_rejected_on_host(sbr):
     assert lib.sbr_band_reduce(null, 10, dummy, 65, 32, 8, 0, null) == -1
     assert lib.sbr_plan_set_band_stages(null, 0, None) == -1
     assert lib.sbr_plan_get_band_stages(null, 10, 32, None, 0) == -1
+    assert lib.sbr_plan_set_update_depth(null, 2) == -1
 
 
 def test_unsupported_sizes_rejected_on_host(sbr):
