@@ -446,25 +446,99 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// KQ eigenvalue indices per lane (k = lane + 64 q), bisected in lockstep: KQ
-// independent count recurrences per step (SturmChain on the scaled d, e^2
-// in LDS; a wave with a chain whose minors came near underflow recounts all
-// its chains with the guarded ratio recurrence).
+// Sturm counts at xs[q] (scaled) for KQ chains per lane: SturmChain on the
+// scaled d, e^2 in LDS; a wave with a chain whose minors came near underflow
+// recounts all its chains with the guarded ratio recurrence.
 template <int KQ>
-__device__ __forceinline__ void bisect_lanes(int n, const double* sd, const double* se, double lo, double hi,
-                                             double sc, int iters, double* w, int lane) {
+__device__ __forceinline__ void sturm_counts_lanes(int n, const double* sd, const double* se, const double* xs,
+                                                   int* cnt) {
     constexpr int U = 16;
-    double a[KQ], c[KQ];
-    bool live[KQ];
+    SturmChain ch[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) ch[q].start();
+    int i = 0;
+    for (; i + U <= n; i += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double di = sd[i + u], ei = se[i + u];
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) ch[q].step(di - xs[q], ei);
+        }
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) ch[q].template close_block<U>();
+    }
+    for (; i < n; ++i) {
+        const double di = sd[i], ei = se[i];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) ch[q].step_tail(di - xs[q], ei);
+    }
+    bool low = false;
 #pragma unroll
     for (int q = 0; q < KQ; ++q) {
+        ch[q].finish();
+        low |= ch[q].low;
+        cnt[q] = ch[q].cnt;
+    }
+    if (__any(low)) {
+        SturmRatio r[KQ];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) r[q].start();
+        for (int j = 0; j < n; ++j) {
+            const double di = sd[j], ei = se[j];
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) r[q].step(di - xs[q], ei);
+        }
+#pragma unroll
+        for (int q = 0; q < KQ; ++q)
+            if (ch[q].low) cnt[q] = r[q].cnt;
+    }
+}
+
+// KQ eigenvalue indices per lane (k = lane + 64 q), bisected in lockstep (KQ
+// independent count recurrences per step).  First the counts at the M = 64 KQ
+// points lo + (j + 1) (hi - lo) / (M + 1) (lane l, chain q: point l + 64 q),
+// kept in LDS; each index starts from the cell whose end counts bracket it
+// (a binary search), which holds its eigenvalue whatever rounding did to the
+// counts, and bisects it for the halvings left.
+template <int KQ>
+__device__ __forceinline__ void bisect_lanes(int n, const double* sd, const double* se, double lo, double hi,
+                                             double sc, int iters, double* w, int lane, int* gcnt) {
+    constexpr int M = 64 * KQ;
+    double a[KQ], c[KQ];
+    bool live[KQ];
+    const double gw = (hi - lo) / (double)(M + 1);
+    if (iters > 0) {
+        double xs[KQ];
+        int cnt[KQ];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) xs[q] = (lo + (double)(lane + 64 * q + 1) * gw) * sc;
+        sturm_counts_lanes<KQ>(n, sd, se, xs, cnt);
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) gcnt[lane + 64 * q] = cnt[q];
+    }
+    team_sync<64>();
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+        const int k = lane + 64 * q;
         a[q] = lo;
         c[q] = hi;
-        live[q] = lane + 64 * q < n;
+        live[q] = k < n;
+        if (live[q] && iters > 0) {
+            int jl = -1, jh = M;
+            while (jh - jl > 1) {
+                const int mid = (jl + jh) >> 1;
+                if (gcnt[mid] > k) jh = mid;
+                else jl = mid;
+            }
+            if (jl >= 0) a[q] = lo + (double)(jl + 1) * gw;
+            if (jh < M) c[q] = lo + (double)(jh + 1) * gw;
+        }
     }
-    for (int it = 0; it < iters; ++it) {
+    team_sync<64>();   // gcnt is rewritten by the next matrix
+    // halvings left: (hi - lo) / ((M + 1) 2^r) below (hi - lo) / 2^iters
+    const int rounds = iters > 0 ? (int)ceil((double)iters - log2((double)(M + 1))) : 0;
+    for (int it = 0; it < rounds; ++it) {
         double x[KQ], xs[KQ];
-        SturmChain ch[KQ];
         bool anyl = false;
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
@@ -472,46 +546,10 @@ __device__ __forceinline__ void bisect_lanes(int n, const double* sd, const doub
             if (live[q] && (x[q] == a[q] || x[q] == c[q])) live[q] = false;
             anyl |= live[q];
             xs[q] = x[q] * sc;
-            ch[q].start();
         }
         if (!__any(anyl)) break;
-        int i = 0;
-        for (; i + U <= n; i += U) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const double di = sd[i + u], ei = se[i + u];
-#pragma unroll
-                for (int q = 0; q < KQ; ++q) ch[q].step(di - xs[q], ei);
-            }
-#pragma unroll
-            for (int q = 0; q < KQ; ++q) ch[q].template close_block<U>();
-        }
-        for (; i < n; ++i) {
-            const double di = sd[i], ei = se[i];
-#pragma unroll
-            for (int q = 0; q < KQ; ++q) ch[q].step_tail(di - xs[q], ei);
-        }
-        bool low = false;
         int cnt[KQ];
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-            ch[q].finish();
-            low |= ch[q].low;
-            cnt[q] = ch[q].cnt;
-        }
-        if (__any(low)) {
-            SturmRatio r[KQ];
-#pragma unroll
-            for (int q = 0; q < KQ; ++q) r[q].start();
-            for (int j = 0; j < n; ++j) {
-                const double di = sd[j], ei = se[j];
-#pragma unroll
-                for (int q = 0; q < KQ; ++q) r[q].step(di - xs[q], ei);
-            }
-#pragma unroll
-            for (int q = 0; q < KQ; ++q)
-                if (ch[q].low) cnt[q] = r[q].cnt;
-        }
+        sturm_counts_lanes<KQ>(n, sd, se, xs, cnt);
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
             if (live[q]) {
@@ -528,6 +566,7 @@ __device__ __forceinline__ void bisect_lanes(int n, const double* sd, const doub
 __global__ __launch_bounds__(BB_NT) void batched_bisect_kernel(const BatchDesc* __restrict__ desc, int count,
                                                                int* ticket) {
     __shared__ double sd[sbr::BATCH_NMAX], se[sbr::BATCH_NMAX];
+    __shared__ int gcnt[sbr::BATCH_NMAX];
     __shared__ int mat_sh;
     const int t = threadIdx.x;
     while (true) {
@@ -581,14 +620,14 @@ __global__ __launch_bounds__(BB_NT) void batched_bisect_kernel(const BatchDesc* 
         }
         team_sync<64>();
         switch ((n + 63) / 64) {
-            case 1: bisect_lanes<1>(n, sd, se, l, h, sc, iters, dm.w, t); break;
-            case 2: bisect_lanes<2>(n, sd, se, l, h, sc, iters, dm.w, t); break;
-            case 3: bisect_lanes<3>(n, sd, se, l, h, sc, iters, dm.w, t); break;
-            case 4: bisect_lanes<4>(n, sd, se, l, h, sc, iters, dm.w, t); break;
-            case 5: bisect_lanes<5>(n, sd, se, l, h, sc, iters, dm.w, t); break;
-            case 6: bisect_lanes<6>(n, sd, se, l, h, sc, iters, dm.w, t); break;
-            case 7: bisect_lanes<7>(n, sd, se, l, h, sc, iters, dm.w, t); break;
-            default: bisect_lanes<8>(n, sd, se, l, h, sc, iters, dm.w, t); break;
+            case 1: bisect_lanes<1>(n, sd, se, l, h, sc, iters, dm.w, t, gcnt); break;
+            case 2: bisect_lanes<2>(n, sd, se, l, h, sc, iters, dm.w, t, gcnt); break;
+            case 3: bisect_lanes<3>(n, sd, se, l, h, sc, iters, dm.w, t, gcnt); break;
+            case 4: bisect_lanes<4>(n, sd, se, l, h, sc, iters, dm.w, t, gcnt); break;
+            case 5: bisect_lanes<5>(n, sd, se, l, h, sc, iters, dm.w, t, gcnt); break;
+            case 6: bisect_lanes<6>(n, sd, se, l, h, sc, iters, dm.w, t, gcnt); break;
+            case 7: bisect_lanes<7>(n, sd, se, l, h, sc, iters, dm.w, t, gcnt); break;
+            default: bisect_lanes<8>(n, sd, se, l, h, sc, iters, dm.w, t, gcnt); break;
         }
         team_sync<64>();
     }
