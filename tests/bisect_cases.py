@@ -49,5 +49,37 @@ def toeplitz_odd(n=1001):
     return si.toeplitz_tridiagonal(n, 0.0, 1.0)
 
 
+def identity(n=300):
+    # one eigenvalue of multiplicity n: every count jumps from 0 to n at 1,
+    # so every index shares the same grid cell
+    return np.ones(n), np.zeros(n - 1)
+
+
+def diagonal_only(n=257):
+    # no couplings: the count is the number of d_i below x, each step a split
+    rng = np.random.default_rng(5)
+    return rng.standard_normal(n), np.zeros(n - 1)
+
+
+def scaled(n, scale, seed):
+    # a random tridiagonal scaled far from 1 in either direction (the Sturm
+    # data are rescaled by a power of two, so the counts must not move)
+    rng = np.random.default_rng(seed)
+    return scale * rng.standard_normal(n), scale * rng.standard_normal(n - 1)
+
+
+def pair_clusters(n=400):
+    # 2 x 2 blocks [[c, t], [t, c]] with t = 1e-13 |c| glued by 1e-3: tight
+    # pairs of eigenvalues c +- t spread over the spectrum
+    rng = np.random.default_rng(17)
+    c = np.repeat(rng.uniform(-1.0, 1.0, n // 2), 2)
+    e = np.empty(n - 1)
+    e[0::2] = 1e-13 * np.abs(c[0::2][: (n - 1 + 1) // 2])
+    e[1::2] = 1e-3
+    return c, e
+
+
 CASES = {"graded": graded(400), "glued_wilkinson": glued_wilkinson(), "integer_zero_pivots": integer_zero_pivots(),
-         "underflowing_pivots": underflowing_pivots(), "toeplitz_odd": toeplitz_odd()}
+         "underflowing_pivots": underflowing_pivots(), "toeplitz_odd": toeplitz_odd(), "identity": identity(),
+         "diagonal_only": diagonal_only(), "scaled_1e150": scaled(500, 1e150, 3), "scaled_1e-140": scaled(500, 1e-140, 4),
+         "pair_clusters": pair_clusters()}

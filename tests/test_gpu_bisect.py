@@ -1,18 +1,23 @@
 """Sturm bisection on adversarial tridiagonals, GPU against the oracle.
 
-The count recurrence on the GPU takes 1/q from a Newton-refined hardware
-reciprocal instead of a division; the oracle divides.  Kahan's argument that
-the count is monotone in x assumes correctly rounded, monotone arithmetic, so
-these cases aim at the places where a count could break: eigenvalues spread
-over many orders of magnitude (graded diagonal), tight pairs of eigenvalues
-(Wilkinson matrices glued by 1e-14), exact zero pivots (integer diagonals with
-zero couplings), and pivots that underflow.  Both entry points run them: the
-tridiagonal call (bisect_kernel) and the batched solver on the same matrices
-in dense form, whose reductions leave a tridiagonal input as it is, so its
-bisection (batched_bisect_kernel) sees the same (d, e).
+The GPU counts eigenvalues below x as the sign changes of the leading
+principal minors (their three-term recurrence on data scaled by a power of
+two, rescaled every 16 steps, with a recount by the guarded ratio recurrence
+when the minors come near underflow), starting each index from a cell of a
+shared first grid; the oracle counts negative pivots of the ratio recurrence
+with a division and bisects the whole interval.  These cases aim at the
+places where either could break: eigenvalues spread over many orders of
+magnitude (graded diagonal), tight pairs (Wilkinson matrices glued by 1e-14,
+2 x 2 blocks split by 1e-13), exact zero pivots (integer diagonals with zero
+couplings), pivots that underflow, one eigenvalue of multiplicity n (every
+index in one grid cell), no couplings at all (a split at every step), and
+matrices scaled by 1e150 and 1e-140.  Both entry points run them: the
+tridiagonal call (sturm_grid_kernel, bisect_kernel) and the batched solver on
+the same matrices in dense form, whose reductions leave a tridiagonal input
+as it is, so its bisection (batched_bisect_kernel) sees the same (d, e).
 
 Bar: max |lam - lam_oracle| <= 4 eps ||T||_2, the accuracy of bisection
-itself (both sides stop at the same width).
+itself (both sides stop no wider than the same width).
 """
 import numpy as np
 import pytest
@@ -45,7 +50,8 @@ def test_tridiag_eigvals_adversarial(sbr, oracle_mod, name):
     assert err <= 4 * EPS64 * nrm
 
 
-@pytest.mark.parametrize("name", ["glued_wilkinson", "integer_zero_pivots", "graded", "underflowing_pivots"])
+@pytest.mark.parametrize("name", ["glued_wilkinson", "integer_zero_pivots", "graded", "underflowing_pivots",
+                                  "identity", "diagonal_only", "scaled_1e150", "scaled_1e-140", "pair_clusters"])
 def test_batched_bisection_adversarial(sbr, oracle_mod, name):
     d, e = CASES[name]
     n = len(d)
