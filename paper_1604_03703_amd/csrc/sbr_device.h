@@ -109,6 +109,24 @@ struct TileEngine {
         }
     }
 
+    // The chunk with the scheduler fenced between k-steps: the operand reads
+    // of a step are not hoisted above the products of the previous one (no
+    // more registers live than one step's operands).
+    __device__ __forceinline__ void chunk_fenced(const CT* As, const CT* Bs, int wm, int wn, int lane) {
+        const int kr = lane >> 4, c = lane & 15;
+        constexpr int KS = SBR_BK / 4;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            CT p[TN], q[TM];
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) p[tn] = Bs[(4 * s + kr) * LDB + wn * WTN + tn * 16 + c];
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) q[tm] = As[(4 * s + kr) * LDA + wm * WTM + tm * 16 + c];
+            products(p, q);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
     __device__ __forceinline__ void products(const CT (&p)[TN], const CT (&q)[TM]) {
 #pragma unroll
         for (int tn = 0; tn < TN; ++tn)

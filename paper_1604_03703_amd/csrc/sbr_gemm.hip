@@ -9,6 +9,8 @@
 //                  form for the tall reductions U^T W.
 // CT = double uses v_mfma_f64_16x16x4_f64; CT = float is the precision form
 // (operands rounded to FP32 in LDS, FP32 accumulation, FP64 result).
+#include <type_traits>
+
 #include "sbr_device.h"
 #include "sbr_internal.h"
 
@@ -225,16 +227,26 @@ __device__ __forceinline__ void lower_tile_banded(int64_t x, int64_t T, int64_t&
 // ST: storage type of C (double, or float for the FP32-storage form); OT:
 // type of U and V (double, or FP32 copies of them in the FP32 form, half the
 // bytes per operand).
+// DL (FP64, 128 x 128 tiles on 8 waves, every tile inside the matrix, ldu
+// even; the launcher checks): operands go from memory straight into LDS
+// (16-byte buffer loads with an LDS destination; lane l's two doubles land at
+// the window base + 16 l, so one load moves one 128-row k-column of a tile).
+// Wave w moves k-columns 2w and 2w + 1 of both operands; the loads of chunk
+// c + 1 run behind the products of chunk c, and each wave waits for its own
+// loads before the chunk's closing barrier.  The two buffers are separate LDS
+// objects and the chunk loop runs in pairs, so a load into one buffer is seen
+// not to alias the reads of the other.
 template <typename CT, int BM, int WM, int WN, int PAD = 2, typename ST = double, bool FAST = true,
-          typename OT = double>
+          typename OT = double, bool DL = false>
 __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     int64_t m, int64_t nc, int64_t jt, int64_t K, const OT* __restrict__ U, int64_t ldu,
     const OT* __restrict__ V, int64_t ldv, ST* C, int64_t ldc, int64_t ntiles) {
     typedef TileEngine<CT, BM, BM, WM, WN, PAD, false> E;
     typedef TileMap<BM, E::NT, false> MA;   // row fastest (column-major U, V)
     typedef TileMap<BM, E::NT, false> MB;
-    __shared__ CT As[2][SBR_BK * E::LDA];
-    __shared__ CT Bs[2][SBR_BK * E::LDB];
+    static_assert(!DL || (FAST && std::is_same<CT, double>::value && std::is_same<OT, double>::value && BM == 128 &&
+                          WM * WN == 8 && SBR_BK == 16),
+                  "direct LDS loads: FP64 128 x 128 tiles on 8 waves");
     const int64_t x = xcd_logical_tile(blockIdx.x, ntiles);
     int64_t I, J;
     if (jt == 0) {
@@ -250,6 +262,44 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     const int64_t K2 = 2 * K;
     E eng;
     eng.zero();
+    constexpr int64_t SO = sizeof(OT);
+    const uint32_t span = (uint32_t)((m + (int64_t)(SBR_BK - 1) * ldu) * SO);
+    const int64_t nch = (K2 + SBR_BK - 1) / SBR_BK;
+    if constexpr (DL) {
+        __shared__ __align__(16) CT As0[SBR_BK * E::LDA], As1[SBR_BK * E::LDA];
+        __shared__ __align__(16) CT Bs0[SBR_BK * E::LDB], Bs1[SBR_BK * E::LDB];
+        const uint32_t la = (uint32_t)(((i0 + 2 * lane) + (int64_t)(2 * wave) * ldu) * SO);
+        const uint32_t lb = (uint32_t)(((j0 + 2 * lane) + (int64_t)(2 * wave) * ldu) * SO);
+        const uint32_t ldub = (uint32_t)(ldu * SO);
+        auto dload = [&](int64_t k0, CT* as, CT* bs) {
+            const OT* pa = (k0 < K) ? U + k0 * ldu : V + (k0 - K) * ldu;
+            const OT* pb = (k0 < K) ? V + k0 * ldu : U + (k0 - K) * ldu;
+            const __amdgpu_buffer_rsrc_t rsa = sbr_buffer(pa, span);
+            const __amdgpu_buffer_rsrc_t rsb = sbr_buffer(pb, span);
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const int k = 2 * wave + kk;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rsa, (__attribute__((address_space(3))) void*)(as + k * E::LDA), 16, la + kk * ldub, 0, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rsb, (__attribute__((address_space(3))) void*)(bs + k * E::LDB), 16, lb + kk * ldub, 0, 0, 0);
+            }
+        };
+        // K is a multiple of the chunk depth, so K' = 2K holds an even
+        // number of chunks
+        dload(0, As0, Bs0);
+        __syncthreads();
+        for (int64_t c = 0; c < nch; c += 2) {
+            dload((c + 1) * SBR_BK, As1, Bs1);   // last read before the previous barrier
+            eng.chunk_fenced(As0, Bs0, wm, wn, lane);
+            __syncthreads();
+            if (c + 2 < nch) dload((c + 2) * SBR_BK, As0, Bs0);
+            eng.chunk_fenced(As1, Bs1, wm, wn, lane);
+            __syncthreads();
+        }
+    } else {
+    __shared__ CT As[2][SBR_BK * E::LDA];
+    __shared__ CT Bs[2][SBR_BK * E::LDB];
     CT ra[MA::E], rb[MB::E];
     // FAST (U and V share the leading dimension, K is a multiple of the chunk
     // depth, so a chunk lies wholly in the U or the V half of K', and
@@ -258,8 +308,6 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     // (block-uniform) buffer base, and rows past m read zero through an
     // out-of-range offset.  No branches and no 64-bit address arithmetic per
     // element.  Otherwise element-wise loads with bounds checks.
-    constexpr int64_t SO = sizeof(OT);
-    const uint32_t span = (uint32_t)((m + (int64_t)(SBR_BK - 1) * ldu) * SO);
     uint32_t offa[MA::E], offb[MB::E];
     if constexpr (FAST) {
 #pragma unroll
@@ -320,7 +368,6 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
             Bs[buf][k * E::LDB + j] = rb[e];
         }
     };
-    const int64_t nch = (K2 + SBR_BK - 1) / SBR_BK;
     load(0);
     store(0);
     __syncthreads();
@@ -331,6 +378,7 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
         eng.chunk(As[cur], Bs[cur], wm, wn, lane);
         if (more) store(cur ^ 1);     // that buffer was last read before the previous barrier
         __syncthreads();
+    }
     }
 #pragma unroll
     for (int tn = 0; tn < E::TN; ++tn)
@@ -657,6 +705,15 @@ void syr2k_go(int64_t nt, int64_t m, int64_t nc, int64_t jt, int64_t K, const OT
               const OT* V, int64_t ldv, ST* C, int64_t ldc, hipStream_t s) {
     const bool fast = (ldu == ldv) && (K % SBR_BK == 0) &&
                       (m + (int64_t)(SBR_BK - 1) * ldu) * (int64_t)sizeof(OT) < (int64_t)SBR_BUF_OOB;
+    if constexpr (std::is_same<CT, double>::value && std::is_same<OT, double>::value && BM == 128 && WM * WN == 8) {
+        // every tile inside the matrix (full lower tiles only) and 16-byte
+        // aligned columns: operands straight into LDS
+        if (fast && jt == 0 && m % BM == 0 && (ldu & 1) == 0) {
+            syr2k_lower_kernel<CT, BM, WM, WN, 2, ST, true, OT, true><<<(unsigned)nt, 64 * WM * WN, 0, s>>>(
+                m, nc, jt, K, U, ldu, V, ldv, C, ldc, nt);
+            return;
+        }
+    }
     if (fast)
         syr2k_lower_kernel<CT, BM, WM, WN, 2, ST, true, OT><<<(unsigned)nt, 64 * WM * WN, 0, s>>>(m, nc, jt, K, U, ldu,
                                                                                               V, ldv, C, ldc, nt);

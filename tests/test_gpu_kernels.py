@@ -74,6 +74,32 @@ def test_syr2k_lower(sbr, prec, m, k):
     assert np.all(out[up] == C[up])           # strict upper triangle not written
 
 
+@pytest.mark.parametrize("m,k", [(4096, 128), (4224, 64), (8192, 16)])
+def test_syr2k_lower_direct_lds_path(sbr, m, k):
+    # FP64, m a multiple of 128 with 128 x 128 tiles: with an even leading
+    # dimension the operands go from memory straight into LDS, with an odd
+    # one through registers; the two forms run the same products in the same
+    # order, so C must come out the same bit for bit, and right
+    print("syr2k direct lds", m, k, flush=True)
+    rng = np.random.default_rng(m + 3 * k)
+    U = rng.standard_normal((m, k))
+    V = rng.standard_normal((m, k))
+    C = rng.standard_normal((m, m))
+    outs = []
+    for ld in (m + 2, m + 3):
+        Ud, Vd, Cd = to_col(U, ld), to_col(V, ld), to_col(C, m + 1)
+        sbr.syr2k_lower(m, k, Ud, ld, Vd, ld, Cd, m + 1, precision="fp64")
+        torch.cuda.synchronize()
+        outs.append(from_col(Cd, m))
+    assert np.array_equal(outs[0], outs[1])
+    ref = C + U @ V.T + V @ U.T
+    low = np.tril_indices(m)
+    up = np.triu_indices(m, 1)
+    scale = 2 * k * np.abs(U).max() * np.abs(V).max() + np.abs(C).max()
+    assert np.max(np.abs(outs[0][low] - ref[low])) <= 8 * k * EPS64 * scale
+    assert np.all(outs[0][up] == C[up])
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32_mfma"])
 @pytest.mark.parametrize("m,k", [(17, 16), (1000, 64), (4100, 128)])
 def test_syr2k_lower_buffer_path(sbr, prec, m, k):
