@@ -87,6 +87,8 @@ struct sbr_plan_s {
     int32_t update_depth = 1;
     double* gbuf = nullptr;
     int64_t gbuf_cap = 0;
+    // Y^T (b x n_cap, ld b) for the FP64 product W = A22 Y on full tiles
+    double* Yt = nullptr;
     double *part = nullptr;
     int64_t part_doubles = 0;
     double *T = nullptr, *W1inv = nullptr, *Mm = nullptr, *Zm = nullptr, *S = nullptr;
@@ -143,7 +145,7 @@ namespace {
 
 struct Layout {
     size_t bytes = 0;
-    size_t off_Q, off_U, off_Y, off_W, off_V, off_part, off_T, off_W1inv, off_Mm, off_Zm, off_S, off_tsqr,
+    size_t off_Q, off_U, off_Y, off_Yt, off_W, off_V, off_part, off_T, off_W1inv, off_Mm, off_Zm, off_S, off_tsqr,
         off_bandA, off_bandB, off_chase, off_flags, off_status, off_d, off_e, off_e2p, off_setup, off_pcopy;
     int64_t part_doubles = 0;
 };
@@ -172,6 +174,7 @@ Layout make_layout(int64_t n, int b) {
     L.off_Q = take(cur, nb * D);
     L.off_U = take(cur, 2 * nb * D);
     L.off_Y = take(cur, nb * D);
+    L.off_Yt = take(cur, nb * D);
     L.off_W = take(cur, nb * D);
     L.off_V = take(cur, nb * D);
     L.off_part = take(cur, part * D);
@@ -221,6 +224,7 @@ int ensure_workspace(sbr_plan_t p, int64_t n, int b) {
     p->Ub[0] = p->U;
     p->Ub[1] = p->U + nn * bb;
     p->Y = (double*)(base + L.off_Y);
+    p->Yt = (double*)(base + L.off_Yt);
     p->W = (double*)(base + L.off_W);
     p->V = (double*)(base + L.off_V);
     p->part = (double*)(base + L.off_part);
@@ -534,13 +538,20 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
     if (!f32s && p->update_depth > 1) return run_full_to_band_grouped(p, n, A, lda, b, p->update_depth, s);
     float* As = f32s ? p->as_buf : nullptr;
     const int64_t lds = n;
+    // FP64 products on full tiles read Y^T (operands straight into LDS): the
+    // panel's Y is formed transposed for the product that will read it
+    auto use_yt = [&](int64_t mm) { return !f32 && symm_yt_ok(mm, b, lda); };
+    auto form_y = [&](int64_t mm, const double* Uq, hipStream_t st) {
+        if (use_yt(mm)) launch_gemm(false, true, true, b, mm, b, 1.0, p->T, b, Uq, ldq, 0.0, nullptr, 0, p->Yt, b, st);
+        else launch_gemm(false, false, false, mm, b, b, 1.0, Uq, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, st);
+        if (f32s) launch_block_to_f32(mm, b, p->Y, ldq, p->Yf, ldq, st);
+    };
     if (n - b >= b) {
         const int rc = ensure_side_stream(p);
         if (rc) return rc;
         if (f32s) launch_lower_to_f32(n - b, A + b + b * lda, lda, As + b + b * lds, lds, s);
         factor_panel(p, n - b, b, A + b, lda, p->Ub[0], s);
-        launch_gemm(false, false, false, n - b, b, b, 1.0, p->Ub[0], ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, s);
-        if (f32s) launch_block_to_f32(n - b, b, p->Y, ldq, p->Yf, ldq, s);
+        form_y(n - b, p->Ub[0], s);
     }
     for (;; ++k) {
         const int64_t c0 = k * b, r0 = c0 + b, m = n - r0;
@@ -553,6 +564,7 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
         if (p->timing == 1) { ep.a = p->ev(); p->mark(ep.a, s); }
         const int ss = symm_splits(m, b);
         if (f32s) launch_symm_lower_f32s(m, b, A22s, lds, p->Yf, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
+        else if (use_yt(m)) launch_symm_lower_yt(m, b, A22, lda, p->Yt, b, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
         else launch_symm_lower(f32, m, b, A22, lda, p->Y, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
         if (p->timing == 1) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_symm.push_back(ep); }
         // Z = U^T W ; M = T^T Z ; V = 1/2 U M - W
@@ -603,8 +615,7 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
             }
             double* Un = p->Ub[cur ^ 1];
             factor_panel(p, mn, b, A22 + b, lda, Un, p->side);
-            launch_gemm(false, false, false, mn, b, b, 1.0, Un, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, p->side);
-            if (f32s) launch_block_to_f32(mn, b, p->Y, ldq, p->Yf, ldq, p->side);
+            form_y(mn, Un, p->side);
             e = hipEventRecord(p->ev_join, p->side);
             if (e != hipSuccess) return hip_fail(e);
             if (p->upd) e = hipStreamWaitEvent(s, p->ev_ujoin, 0);

@@ -545,6 +545,138 @@ __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(BM
             }
 }
 
+// The same product for full FP64 tiles (m a multiple of 128, nb = 128, lda
+// even), reading Y transposed: Yt = Y^T (nb x m, ld ldyt, a multiple of 2),
+// so that a k-row of the Y tile is 128 contiguous doubles.  Operands that are
+// contiguous along the tile's fast index go from memory straight into LDS
+// (16-byte buffer loads with an LDS destination, lane l's two doubles at the
+// window base + 16 l, one load per k-row; wave w moves rows 2w and 2w + 1):
+// Yt in every chunk and the A tile in the chunks below the diagonal block.
+// The diagonal block (element-wise choice of the entry or its mirror) and
+// the chunks above it (the mirror, k contiguous) still pass A through
+// registers.  The two LDS buffers are separate objects and each segment runs
+// its chunks in pairs, so a load into one buffer is seen not to alias the
+// other buffer's reads; the products and their order are those of
+// symm_lower_kernel.
+constexpr int SYMM_DL_NT = 512;
+
+__global__ __launch_bounds__(SYMM_DL_NT) __attribute__((amdgpu_waves_per_eu(4))) void symm_lower_dl_kernel(
+    int64_t m, int64_t kchunk, const double* __restrict__ A, int64_t lda, const double* __restrict__ Yt,
+    int64_t ldyt, double* W, int64_t ldw, int64_t slice_stride) {
+    constexpr int BM = 128, BN = 128;
+    typedef TileEngine<double, BM, BN, 2, 4, 2, false> E;
+    typedef TileMap<BM, E::NT, false> MAi;   // row fastest
+    typedef TileMap<BM, E::NT, true> MAk;    // k fastest
+    static_assert(MAi::E == MAk::E && E::NT == SYMM_DL_NT && SBR_BK == 16, "tile shape");
+    __shared__ __align__(16) double As0[SBR_BK * E::LDA], As1[SBR_BK * E::LDA];
+    __shared__ __align__(16) double Bs0[SBR_BK * E::LDB], Bs1[SBR_BK * E::LDB];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave % 2, wn = wave / 2;
+    const int64_t i0 = (int64_t)blockIdx.x * BM;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;   // kchunk and m are multiples of SBR_BK
+    const int64_t kend = (kbeg + kchunk < m) ? kbeg + kchunk : m;
+    E eng;
+    eng.zero();
+    constexpr uint32_t SA = sizeof(double);
+    const uint32_t lda32 = (uint32_t)lda;
+    const uint32_t spanD = (uint32_t)((BM + (int64_t)(SBR_BK - 1) * lda) * SA);
+    const uint32_t spanM = (uint32_t)((SBR_BK + (int64_t)(BM - 1) * lda) * SA);
+    const uint32_t spanS = (uint32_t)((m + (int64_t)BM * lda) * SA);
+    const uint32_t spanY = (uint32_t)((BN + (int64_t)(SBR_BK - 1) * ldyt) * SA);
+    // per-lane byte offsets of the straight-to-LDS loads: rows 2 lane, 2 lane + 1
+    // of k-rows 2 wave and 2 wave + 1 (the second one ld further)
+    const uint32_t ly = (uint32_t)((2 * lane + (int64_t)(2 * wave) * ldyt) * SA);
+    const uint32_t la = (uint32_t)((2 * lane + (int64_t)(2 * wave) * lda) * SA);
+    const uint32_t ldyb = (uint32_t)(ldyt * SA), ldab = (uint32_t)(lda * SA);
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    double ra[MAi::E];
+    // MODE 0: below the diagonal block (A straight to LDS); 1: the diagonal
+    // block (element-wise, registers); 2: above it (the mirror, registers)
+    auto issue = [&](auto mode, int64_t k0, double* as, double* bs) {
+        constexpr int MODE = decltype(mode)::value;
+        const __amdgpu_buffer_rsrc_t ry = sbr_buffer(Yt + k0 * ldyt, spanY);
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ry, (lds_ptr)(bs + (2 * wave + kk) * E::LDB), 16,
+                                                     ly + kk * ldyb, 0, 0, 0);
+        if constexpr (MODE == 0) {
+            const __amdgpu_buffer_rsrc_t rs = sbr_buffer(A + i0 + k0 * lda, spanD);
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr)(as + (2 * wave + kk) * E::LDA), 16,
+                                                         la + kk * ldab, 0, 0, 0);
+        } else if constexpr (MODE == 1) {
+            const int64_t d0 = i0 < k0 ? i0 : k0;
+            const __amdgpu_buffer_rsrc_t rs = sbr_buffer(A + d0 + d0 * lda, spanS);
+#pragma unroll
+            for (int e = 0; e < MAi::E; ++e) {
+                int i, k;
+                MAi::coords(t, e, i, k);
+                const uint32_t r = (uint32_t)(i0 + i - d0), c = (uint32_t)(k0 + k - d0);
+                const uint32_t off = (r >= c) ? r + c * lda32 : c + r * lda32;
+                ra[e] = sbr_buffer_load(rs, off * SA, double());
+            }
+        } else {
+            const __amdgpu_buffer_rsrc_t rs = sbr_buffer(A + k0 + i0 * lda, spanM);
+#pragma unroll
+            for (int e = 0; e < MAk::E; ++e) {
+                int i, k;
+                MAk::coords(t, e, i, k);
+                ra[e] = sbr_buffer_load(rs, ((uint32_t)k + (uint32_t)i * lda32) * SA, double());
+            }
+        }
+    };
+    auto store = [&](auto mode, double* as) {
+        constexpr int MODE = decltype(mode)::value;
+        if constexpr (MODE != 0) {
+#pragma unroll
+            for (int e = 0; e < MAi::E; ++e) {
+                int i, k;
+                if constexpr (MODE == 2) MAk::coords(t, e, i, k);
+                else MAi::coords(t, e, i, k);
+                as[k * E::LDA + i] = ra[e];
+            }
+        }
+    };
+    auto segment = [&](auto mode, int64_t ka, int64_t kb) {
+        if (ka >= kb) return;
+        const int64_t nch = (kb - ka) / SBR_BK;
+        issue(mode, ka, As0, Bs0);
+        store(mode, As0);
+        __syncthreads();
+        for (int64_t c = 0; c + 1 < nch; c += 2) {
+            issue(mode, ka + (c + 1) * SBR_BK, As1, Bs1);   // last read before the previous barrier
+            eng.chunk_fenced(As0, Bs0, wm, wn, lane);
+            store(mode, As1);
+            __syncthreads();
+            const bool more = c + 2 < nch;
+            if (more) issue(mode, ka + (c + 2) * SBR_BK, As0, Bs0);
+            eng.chunk_fenced(As1, Bs1, wm, wn, lane);
+            if (more) store(mode, As0);
+            __syncthreads();
+        }
+        if (nch & 1) {   // the last chunk is in the first buffer
+            eng.chunk_fenced(As0, Bs0, wm, wn, lane);
+            __syncthreads();
+        }
+    };
+    const int64_t dlo = i0, dhi = i0 + BM;   // the diagonal block's columns
+    segment(std::integral_constant<int, 0>(), kbeg, kend < dlo ? kend : dlo);
+    segment(std::integral_constant<int, 1>(), kbeg > dlo ? kbeg : dlo, kend < dhi ? kend : dhi);
+    segment(std::integral_constant<int, 2>(), kbeg > dhi ? kbeg : dhi, kend);
+    double* Wo = W + (int64_t)blockIdx.z * slice_stride;
+#pragma unroll
+    for (int tn = 0; tn < E::TN; ++tn)
+#pragma unroll
+        for (int tm = 0; tm < E::TM; ++tm)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + E::row_of(wm, tm, lane);
+                const int64_t j = E::col_of(wn, tn, lane, r);
+                Wo[i + j * ldw] = eng.acc[tn][tm][r];
+            }
+}
+
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 template <typename CT, bool TA, bool TB, bool FAST>
@@ -778,6 +910,29 @@ void launch_symm_lower(bool f32, int64_t m, int64_t nb, const double* A, int64_t
     if (f32) symm_dispatch<float, double>(m, nb, kchunk, splits, A, lda, Y, ldy, part, m, m * nb, s);
     else symm_dispatch<double, double>(m, nb, kchunk, splits, A, lda, Y, ldy, part, m, m * nb, s);
     reduce_slices(m, nb, splits, part, 1.0, 0.0, nullptr, 0, W, ldw, s);
+}
+
+bool symm_yt_ok(int64_t m, int64_t nb, int64_t lda) {
+    return m >= 2048 && m % 128 == 0 && nb == 128 && (lda & 1) == 0 &&
+           (m + 128 * lda) * (int64_t)sizeof(double) < (int64_t)SBR_BUF_OOB;
+}
+
+void launch_symm_lower_yt(int64_t m, int64_t nb, const double* A, int64_t lda, const double* Yt, int64_t ldyt,
+                          double* W, int64_t ldw, double* part, int splits, hipStream_t s) {
+    if (m <= 0 || nb <= 0) return;
+    const bool split = splits > 1 && part != nullptr;
+    int64_t kchunk = m;
+    if (split) {
+        kchunk = (m + splits - 1) / splits;
+        kchunk = (kchunk + SBR_BK - 1) / SBR_BK * SBR_BK;
+    }
+    dim3 g(cdiv(m, 128), 1, split ? splits : 1);
+    if (split) {
+        symm_lower_dl_kernel<<<g, SYMM_DL_NT, 0, s>>>(m, kchunk, A, lda, Yt, ldyt, part, m, m * nb);
+        reduce_slices(m, nb, splits, part, 1.0, 0.0, nullptr, 0, W, ldw, s);
+    } else {
+        symm_lower_dl_kernel<<<g, SYMM_DL_NT, 0, s>>>(m, kchunk, A, lda, Yt, ldyt, W, ldw, 0);
+    }
 }
 
 // ---- FP32-storage form: the trailing matrix lives in an FP32 copy

@@ -124,6 +124,31 @@ def test_eigvalsh_lda_larger_than_n(sbr, oracle_mod, n, b0, lda):
     assert err <= 1e-11 * _norm2(ref)
 
 
+@pytest.mark.parametrize("n", [2432, 4096])
+def test_full_tile_product_paths_agree(sbr, oracle_mod, n):
+    # b0 = 128 and trailing orders that are multiples of 128: with an even
+    # leading dimension the FP64 W = A22 Y reads Y^T and moves its operands
+    # straight into LDS, with an odd one it passes them through registers;
+    # the products and their order are the same, so the eigenvalues must be
+    # the same bit for bit, and right
+    print("full-tile product paths", n, flush=True)
+    A = si.gaussian_symmetric(n, si.make_rng(si.CFG_SMALL, 12))
+    ref = oracle_mod.eigvalsh(A)
+    ws = []
+    for lda in (n, n + 1):
+        X = torch.zeros((n, lda), dtype=torch.float64, device="cuda")
+        X[:, :n] = torch.from_numpy(A).cuda()
+        plan = sbr.Plan(n)
+        w = sbr.eigvalsh(X[:, :n], b0=128, plan=plan, overwrite=True)
+        torch.cuda.synchronize()
+        assert plan.status() == 0
+        ws.append(w.cpu().numpy())
+    assert np.array_equal(ws[0], ws[1])
+    err = np.max(np.abs(ws[0] - ref))
+    print("n %d: max err %.3e" % (n, err / _norm2(ref)), flush=True)
+    assert err <= 1e-11 * _norm2(ref)
+
+
 @pytest.mark.parametrize("b", [2, 4, 8, 16, 32, 64, 128])
 def test_band_halve_wide_ldband(sbr, oracle_mod, b):
     n = 600
