@@ -494,57 +494,69 @@ __global__ __launch_bounds__(REC_NT) void reconstruct_kernel(int b, const double
     }
 }
 
-// The same reconstruction for b = 64 by one wavefront with the block in
-// registers: lane r holds row r (LU and T phases) or column r (the inverse
-// of W1).  Every cross-lane operand is a readlane with a compile-time lane
-// index (the loops are fully unrolled), so no step waits on a barrier or an
-// LDS round trip; the arithmetic and its order are those of
-// reconstruct_kernel.
+// The same reconstruction for b = 64 with the block in registers: lane r
+// holds row r (LU and T phases) or column r (the inverse of W1).  Every
+// cross-lane operand is a readlane with a compile-time lane index (the loops
+// are fully unrolled), so no step waits on a barrier or an LDS round trip;
+// the arithmetic and its order are those of reconstruct_kernel.  Wavefront
+// 0 factors; then it forms T while wavefront 1, which receives the factors
+// through LDS, forms W1^{-1} (both need only the LU factors).
 __device__ __forceinline__ double lane_value(double x, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
     return __hiloint2double(hi, lo);
 }
 
-__global__ __launch_bounds__(64) void reconstruct64_kernel(const double* __restrict__ Q, int64_t ldq, double* U,
-                                                           int64_t ldu, double* T, int64_t ldt, double* W1inv,
-                                                           double* S) {
+__global__ __launch_bounds__(128) void reconstruct64_kernel(const double* __restrict__ Q, int64_t ldq, double* U,
+                                                            int64_t ldu, double* T, int64_t ldt, double* W1inv,
+                                                            double* S) {
     constexpr int B = 64;
-    const int r = threadIdx.x;
+    __shared__ double lu[B * B];   // the LU factors, column-major (row r, column c at c B + r)
+    __shared__ double pvs[B];
+    const int wv = threadIdx.x >> 6, r = threadIdx.x & 63;
     double a[B];
-#pragma unroll
-    for (int c = 0; c < B; ++c) a[c] = Q[r + (int64_t)c * ldq];
-    // ---- LU of Q1 - S without pivoting: the pivot of step i is the current
-    // diagonal entry less s_i = -sgn; rows below take the multiplier
     double sr = 0.0, pr = 0.0;             // this row's sign and pivot
+    if (wv == 0) {
 #pragma unroll
-    for (int i = 0; i < B; ++i) {
-        const double aii = lane_value(a[i], i);
-        const double si = (aii >= 0.0) ? -1.0 : 1.0;
-        const double piv = aii - si;
-        if (r == i) {
-            sr = si;
-            pr = piv;
+        for (int c = 0; c < B; ++c) a[c] = Q[r + (int64_t)c * ldq];
+        // ---- LU of Q1 - S without pivoting: the pivot of step i is the
+        // current diagonal entry less s_i = -sgn; rows below take the multiplier
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const double aii = lane_value(a[i], i);
+            const double si = (aii >= 0.0) ? -1.0 : 1.0;
+            const double piv = aii - si;
+            if (r == i) {
+                sr = si;
+                pr = piv;
+            }
+            const bool below = r > i;
+            const double l = a[i] / piv;
+            const double lm = below ? l : 0.0;
+#pragma unroll
+            for (int c = i + 1; c < B; ++c) a[c] -= lm * lane_value(a[c], i);
+            a[i] = below ? l : a[i];
         }
-        const bool below = r > i;
-        const double l = a[i] / piv;
-        const double lm = below ? l : 0.0;
 #pragma unroll
-        for (int c = i + 1; c < B; ++c) a[c] -= lm * lane_value(a[c], i);
-        a[i] = below ? l : a[i];
+        for (int c = 0; c < B; ++c) lu[c * B + r] = a[c];
+        pvs[r] = pr;
     }
-    // ---- U1 (unit lower) out, S out
+    __syncthreads();
+    if (wv == 0) {
+        // ---- U1 (unit lower) out, S out
 #pragma unroll
-    for (int c = 0; c < B; ++c) U[r + (int64_t)c * ldu] = (r > c) ? a[c] : (r == c ? 1.0 : 0.0);
-    S[r] = sr;
-    // ---- T from T U1^T = M, M = -W1 S (upper), row r: right-looking over
-    // the columns j, t[j'] -= t[j] U1[j'][j] for j' > j
-    {
+        for (int c = 0; c < B; ++c) U[r + (int64_t)c * ldu] = (r > c) ? a[c] : (r == c ? 1.0 : 0.0);
+        S[r] = sr;
+        // ---- T from T U1^T = M, M = -W1 S (upper), row r: right-looking
+        // over the columns j, t[j'] -= t[j] U1[j'][j] for j' > j
+        // (s_j = +-1: the products by s_j are sign flips, written as such so
+        // that the only product of an update is t[j] U1[j'][j], which the
+        // compiler then always fuses into the update's FMA)
         double t[B];
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-            const double sj = lane_value(sr, j);
-            t[j] = (j > r) ? -a[j] * sj : (j == r ? -pr * sj : 0.0);
+            const bool pos = lane_value(sr, j) > 0.0;
+            t[j] = (j > r) ? (pos ? -a[j] : a[j]) : (j == r ? (pos ? -pr : pr) : 0.0);
         }
 #pragma unroll
         for (int j = 0; j + 1 < B; ++j)
@@ -552,10 +564,12 @@ __global__ __launch_bounds__(64) void reconstruct64_kernel(const double* __restr
             for (int jp = j + 1; jp < B; ++jp) t[jp] -= t[j] * lane_value(a[j], jp);
 #pragma unroll
         for (int j = 0; j < B; ++j) T[r + (int64_t)j * ldt] = (r <= j) ? t[j] : 0.0;
-    }
-    // ---- W1^{-1} (upper), column r: bottom-up x[i] = rhs[i] / W1[i][i],
-    // rhs[q] -= W1[q][i] x[i] for q < i, rhs = e_r
-    {
+    } else {
+        // ---- W1^{-1} (upper), column r: bottom-up x[i] = rhs[i] / W1[i][i],
+        // rhs[q] -= W1[q][i] x[i] for q < i, rhs = e_r (W1[q][i]: lane q's a[i])
+#pragma unroll
+        for (int c = 0; c < B; ++c) a[c] = lu[c * B + r];
+        pr = pvs[r];
         const double inv_r = 1.0 / pr;
         double x[B];
 #pragma unroll
@@ -801,7 +815,7 @@ void launch_reconstruct(int b, const double* Q, int64_t ldq, double* U, int64_t 
                         double* W1inv, double* S, hipStream_t s) {
     const size_t shm = (size_t)b * (b + 1) * sizeof(double);
     if (b == 64) {
-        reconstruct64_kernel<<<1, 64, 0, s>>>(Q, ldq, U, ldu, T, ldt, W1inv, S);
+        reconstruct64_kernel<<<1, 128, 0, s>>>(Q, ldq, U, ldu, T, ldt, W1inv, S);
         return;
     }
     reconstruct_kernel<<<1, REC_NT, shm, s>>>(b, Q, ldq, U, ldu, T, ldt, W1inv, S);
