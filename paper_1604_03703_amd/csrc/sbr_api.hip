@@ -538,13 +538,21 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
     if (!f32s && p->update_depth > 1) return run_full_to_band_grouped(p, n, A, lda, b, p->update_depth, s);
     float* As = f32s ? p->as_buf : nullptr;
     const int64_t lds = n;
-    // FP64 products on full tiles read Y^T (operands straight into LDS): the
-    // panel's Y is formed transposed for the product that will read it
-    auto use_yt = [&](int64_t mm) { return !f32 && symm_yt_ok(mm, b, lda); };
+    // products on full tiles read Y^T (operands straight into LDS): the
+    // panel's Y is formed transposed for the product that will read it (in
+    // the FP32-storage form then rounded to an FP32 copy of Y^T, ld b)
+    auto use_yt = [&](int64_t mm) {
+        if (f32s) return symm_yt_ok(mm, b, lds, (int64_t)sizeof(float));
+        return !f32 && symm_yt_ok(mm, b, lda, (int64_t)sizeof(double));
+    };
     auto form_y = [&](int64_t mm, const double* Uq, hipStream_t st) {
-        if (use_yt(mm)) launch_gemm(false, true, true, b, mm, b, 1.0, p->T, b, Uq, ldq, 0.0, nullptr, 0, p->Yt, b, st);
-        else launch_gemm(false, false, false, mm, b, b, 1.0, Uq, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, st);
-        if (f32s) launch_block_to_f32(mm, b, p->Y, ldq, p->Yf, ldq, st);
+        if (use_yt(mm)) {
+            launch_gemm(false, true, true, b, mm, b, 1.0, p->T, b, Uq, ldq, 0.0, nullptr, 0, p->Yt, b, st);
+            if (f32s) launch_block_to_f32(b, mm, p->Yt, b, p->Yf, b, st);
+        } else {
+            launch_gemm(false, false, false, mm, b, b, 1.0, Uq, ldq, p->T, b, 0.0, nullptr, 0, p->Y, ldq, st);
+            if (f32s) launch_block_to_f32(mm, b, p->Y, ldq, p->Yf, ldq, st);
+        }
     };
     if (n - b >= b) {
         const int rc = ensure_side_stream(p);
@@ -563,7 +571,9 @@ int run_full_to_band(sbr_plan_t p, int64_t n, double* A, int64_t lda, int b, boo
         EventPair ep;
         if (p->timing == 1) { ep.a = p->ev(); p->mark(ep.a, s); }
         const int ss = symm_splits(m, b);
-        if (f32s) launch_symm_lower_f32s(m, b, A22s, lds, p->Yf, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
+        if (f32s && use_yt(m))
+            launch_symm_lower_yt_f32s(m, b, A22s, lds, p->Yf, b, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
+        else if (f32s) launch_symm_lower_f32s(m, b, A22s, lds, p->Yf, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
         else if (use_yt(m)) launch_symm_lower_yt(m, b, A22, lda, p->Yt, b, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
         else launch_symm_lower(f32, m, b, A22, lda, p->Y, ldq, p->W, ldq, ss > 1 ? p->part : nullptr, ss, s);
         if (p->timing == 1) { ep.b = p->ev(); p->mark(ep.b, s); p->ev_symm.push_back(ep); }

@@ -545,31 +545,38 @@ __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(BM
             }
 }
 
-// The same product for full FP64 tiles (m a multiple of 128, nb = 128, lda
-// even), reading Y transposed: Yt = Y^T (nb x m, ld ldyt, a multiple of 2),
-// so that a k-row of the Y tile is 128 contiguous doubles.  Operands that are
-// contiguous along the tile's fast index go from memory straight into LDS
-// (16-byte buffer loads with an LDS destination, lane l's two doubles at the
-// window base + 16 l, one load per k-row; wave w moves rows 2w and 2w + 1):
-// Yt in every chunk and the A tile in the chunks below the diagonal block.
-// The diagonal block (element-wise choice of the entry or its mirror) and
-// the chunks above it (the mirror, k contiguous) still pass A through
-// registers.  The two LDS buffers are separate objects and each segment runs
-// its chunks in pairs, so a load into one buffer is seen not to alias the
-// other buffer's reads; the products and their order are those of
-// symm_lower_kernel.
+// The same product for full tiles (m a multiple of 128, nb = 128), reading Y
+// transposed: Yt = Y^T (nb x m, ld ldyt = 128), so that a k-row of the Y tile
+// is 128 contiguous elements.  Operands that are contiguous along the tile's
+// fast index go from memory straight into LDS (16-byte buffer loads with an
+// LDS destination, lane l's bytes at the window base + 16 l): Yt in every
+// chunk and the A tile in the chunks below the diagonal block.  FP64 (CT = ST
+// = double): one load moves one 128-element k-row, wave w moves rows 2w and
+// 2w + 1 of each operand; the LDS rows keep their padding (130 doubles).
+// FP32 (the FP32-MFMA form, CT = ST = float, A the FP32 copy of the trailing
+// matrix): one load moves rows 2w (lanes 0-31) and 2w + 1 (lanes 32-63), so
+// the LDS rows are unpadded (128 floats).  The diagonal block (element-wise
+// choice of the entry or its mirror) and the chunks above it (the mirror, k
+// contiguous) still pass A through registers.  The two LDS buffers are
+// separate objects and each segment runs its chunks in pairs, so a load into
+// one buffer is seen not to alias the other buffer's reads; the products and
+// their order are those of symm_lower_kernel.
 constexpr int SYMM_DL_NT = 512;
 
+template <typename CT>
 __global__ __launch_bounds__(SYMM_DL_NT) __attribute__((amdgpu_waves_per_eu(4))) void symm_lower_dl_kernel(
-    int64_t m, int64_t kchunk, const double* __restrict__ A, int64_t lda, const double* __restrict__ Yt,
-    int64_t ldyt, double* W, int64_t ldw, int64_t slice_stride) {
+    int64_t m, int64_t kchunk, const CT* __restrict__ A, int64_t lda, const CT* __restrict__ Yt, int64_t ldyt,
+    double* W, int64_t ldw, int64_t slice_stride) {
     constexpr int BM = 128, BN = 128;
-    typedef TileEngine<double, BM, BN, 2, 4, 2, false> E;
+    constexpr bool F64 = sizeof(CT) == 8;
+    constexpr int PADL = F64 ? 2 : 0;
+    typedef TileEngine<CT, BM, BN, 2, 4, PADL, false> E;
     typedef TileMap<BM, E::NT, false> MAi;   // row fastest
     typedef TileMap<BM, E::NT, true> MAk;    // k fastest
     static_assert(MAi::E == MAk::E && E::NT == SYMM_DL_NT && SBR_BK == 16, "tile shape");
-    __shared__ __align__(16) double As0[SBR_BK * E::LDA], As1[SBR_BK * E::LDA];
-    __shared__ __align__(16) double Bs0[SBR_BK * E::LDB], Bs1[SBR_BK * E::LDB];
+    static_assert(F64 || E::LDA * sizeof(CT) == 512, "FP32 rows of 512 bytes, two per load");
+    __shared__ __align__(16) CT As0[SBR_BK * E::LDA], As1[SBR_BK * E::LDA];
+    __shared__ __align__(16) CT Bs0[SBR_BK * E::LDB], Bs1[SBR_BK * E::LDB];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave % 2, wn = wave / 2;
     const int64_t i0 = (int64_t)blockIdx.x * BM;
@@ -577,32 +584,35 @@ __global__ __launch_bounds__(SYMM_DL_NT) __attribute__((amdgpu_waves_per_eu(4)))
     const int64_t kend = (kbeg + kchunk < m) ? kbeg + kchunk : m;
     E eng;
     eng.zero();
-    constexpr uint32_t SA = sizeof(double);
+    constexpr uint32_t SA = sizeof(CT);
     const uint32_t lda32 = (uint32_t)lda;
     const uint32_t spanD = (uint32_t)((BM + (int64_t)(SBR_BK - 1) * lda) * SA);
     const uint32_t spanM = (uint32_t)((SBR_BK + (int64_t)(BM - 1) * lda) * SA);
     const uint32_t spanS = (uint32_t)((m + (int64_t)BM * lda) * SA);
     const uint32_t spanY = (uint32_t)((BN + (int64_t)(SBR_BK - 1) * ldyt) * SA);
-    // per-lane byte offsets of the straight-to-LDS loads: rows 2 lane, 2 lane + 1
-    // of k-rows 2 wave and 2 wave + 1 (the second one ld further)
-    const uint32_t ly = (uint32_t)((2 * lane + (int64_t)(2 * wave) * ldyt) * SA);
-    const uint32_t la = (uint32_t)((2 * lane + (int64_t)(2 * wave) * lda) * SA);
+    // per-lane byte offsets of the straight-to-LDS loads (k-row 2 wave first)
+    constexpr int EPL = 16 / sizeof(CT);   // elements a lane moves
+    const int li = F64 ? EPL * lane : EPL * (lane & 31);
+    const int lk = F64 ? 0 : (lane >> 5);
+    const uint32_t ly = (uint32_t)((li + (int64_t)(2 * wave + lk) * ldyt) * SA);
+    const uint32_t la = (uint32_t)((li + (int64_t)(2 * wave + lk) * lda) * SA);
     const uint32_t ldyb = (uint32_t)(ldyt * SA), ldab = (uint32_t)(lda * SA);
+    constexpr int NLD = F64 ? 2 : 1;   // loads per operand and wave
     typedef __attribute__((address_space(3))) void* lds_ptr;
-    double ra[MAi::E];
+    CT ra[MAi::E];
     // MODE 0: below the diagonal block (A straight to LDS); 1: the diagonal
     // block (element-wise, registers); 2: above it (the mirror, registers)
-    auto issue = [&](auto mode, int64_t k0, double* as, double* bs) {
+    auto issue = [&](auto mode, int64_t k0, CT* as, CT* bs) {
         constexpr int MODE = decltype(mode)::value;
         const __amdgpu_buffer_rsrc_t ry = sbr_buffer(Yt + k0 * ldyt, spanY);
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk)
+        for (int kk = 0; kk < NLD; ++kk)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(ry, (lds_ptr)(bs + (2 * wave + kk) * E::LDB), 16,
                                                      ly + kk * ldyb, 0, 0, 0);
         if constexpr (MODE == 0) {
             const __amdgpu_buffer_rsrc_t rs = sbr_buffer(A + i0 + k0 * lda, spanD);
 #pragma unroll
-            for (int kk = 0; kk < 2; ++kk)
+            for (int kk = 0; kk < NLD; ++kk)
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr)(as + (2 * wave + kk) * E::LDA), 16,
                                                          la + kk * ldab, 0, 0, 0);
         } else if constexpr (MODE == 1) {
@@ -614,7 +624,7 @@ __global__ __launch_bounds__(SYMM_DL_NT) __attribute__((amdgpu_waves_per_eu(4)))
                 MAi::coords(t, e, i, k);
                 const uint32_t r = (uint32_t)(i0 + i - d0), c = (uint32_t)(k0 + k - d0);
                 const uint32_t off = (r >= c) ? r + c * lda32 : c + r * lda32;
-                ra[e] = sbr_buffer_load(rs, off * SA, double());
+                ra[e] = sbr_buffer_load(rs, off * SA, CT());
             }
         } else {
             const __amdgpu_buffer_rsrc_t rs = sbr_buffer(A + k0 + i0 * lda, spanM);
@@ -622,11 +632,11 @@ __global__ __launch_bounds__(SYMM_DL_NT) __attribute__((amdgpu_waves_per_eu(4)))
             for (int e = 0; e < MAk::E; ++e) {
                 int i, k;
                 MAk::coords(t, e, i, k);
-                ra[e] = sbr_buffer_load(rs, ((uint32_t)k + (uint32_t)i * lda32) * SA, double());
+                ra[e] = sbr_buffer_load(rs, ((uint32_t)k + (uint32_t)i * lda32) * SA, CT());
             }
         }
     };
-    auto store = [&](auto mode, double* as) {
+    auto store = [&](auto mode, CT* as) {
         constexpr int MODE = decltype(mode)::value;
         if constexpr (MODE != 0) {
 #pragma unroll
@@ -673,7 +683,7 @@ __global__ __launch_bounds__(SYMM_DL_NT) __attribute__((amdgpu_waves_per_eu(4)))
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = i0 + E::row_of(wm, tm, lane);
                 const int64_t j = E::col_of(wn, tn, lane, r);
-                Wo[i + j * ldw] = eng.acc[tn][tm][r];
+                Wo[i + j * ldw] = (double)eng.acc[tn][tm][r];
             }
 }
 
@@ -912,13 +922,15 @@ void launch_symm_lower(bool f32, int64_t m, int64_t nb, const double* A, int64_t
     reduce_slices(m, nb, splits, part, 1.0, 0.0, nullptr, 0, W, ldw, s);
 }
 
-bool symm_yt_ok(int64_t m, int64_t nb, int64_t lda) {
-    return m >= 2048 && m % 128 == 0 && nb == 128 && (lda & 1) == 0 &&
-           (m + 128 * lda) * (int64_t)sizeof(double) < (int64_t)SBR_BUF_OOB;
+bool symm_yt_ok(int64_t m, int64_t nb, int64_t lda, int64_t elem) {
+    // 16-byte aligned columns of A (lda a multiple of 16 / elem), 32-bit offsets
+    return m >= 2048 && m % 128 == 0 && nb == 128 && (lda * elem) % 16 == 0 &&
+           (m + 128 * lda) * elem < (int64_t)SBR_BUF_OOB;
 }
 
-void launch_symm_lower_yt(int64_t m, int64_t nb, const double* A, int64_t lda, const double* Yt, int64_t ldyt,
-                          double* W, int64_t ldw, double* part, int splits, hipStream_t s) {
+template <typename CT>
+void symm_yt_go(int64_t m, int64_t nb, const CT* A, int64_t lda, const CT* Yt, int64_t ldyt, double* W,
+                int64_t ldw, double* part, int splits, hipStream_t s) {
     if (m <= 0 || nb <= 0) return;
     const bool split = splits > 1 && part != nullptr;
     int64_t kchunk = m;
@@ -928,11 +940,21 @@ void launch_symm_lower_yt(int64_t m, int64_t nb, const double* A, int64_t lda, c
     }
     dim3 g(cdiv(m, 128), 1, split ? splits : 1);
     if (split) {
-        symm_lower_dl_kernel<<<g, SYMM_DL_NT, 0, s>>>(m, kchunk, A, lda, Yt, ldyt, part, m, m * nb);
+        symm_lower_dl_kernel<CT><<<g, SYMM_DL_NT, 0, s>>>(m, kchunk, A, lda, Yt, ldyt, part, m, m * nb);
         reduce_slices(m, nb, splits, part, 1.0, 0.0, nullptr, 0, W, ldw, s);
     } else {
-        symm_lower_dl_kernel<<<g, SYMM_DL_NT, 0, s>>>(m, kchunk, A, lda, Yt, ldyt, W, ldw, 0);
+        symm_lower_dl_kernel<CT><<<g, SYMM_DL_NT, 0, s>>>(m, kchunk, A, lda, Yt, ldyt, W, ldw, 0);
     }
+}
+
+void launch_symm_lower_yt(int64_t m, int64_t nb, const double* A, int64_t lda, const double* Yt, int64_t ldyt,
+                          double* W, int64_t ldw, double* part, int splits, hipStream_t s) {
+    symm_yt_go<double>(m, nb, A, lda, Yt, ldyt, W, ldw, part, splits, s);
+}
+
+void launch_symm_lower_yt_f32s(int64_t m, int64_t nb, const float* A, int64_t lda, const float* Yt, int64_t ldyt,
+                               double* W, int64_t ldw, double* part, int splits, hipStream_t s) {
+    symm_yt_go<float>(m, nb, A, lda, Yt, ldyt, W, ldw, part, splits, s);
 }
 
 // ---- FP32-storage form: the trailing matrix lives in an FP32 copy

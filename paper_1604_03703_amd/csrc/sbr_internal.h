@@ -55,11 +55,15 @@ void launch_lower_to_f32(int64_t m, const double* A, int64_t lda, float* As, int
 void launch_cols_to_f64(int64_t m, int64_t nc, const float* As, int64_t lds, double* A, int64_t lda, hipStream_t s);
 void launch_symm_lower(bool f32, int64_t m, int64_t nb, const double* A, int64_t lda, const double* Y,
                        int64_t ldy, double* W, int64_t ldw, double* part, int splits, hipStream_t s);
-// FP64 W = A Y from Yt = Y^T (nb x m, ld ldyt even) for full 128 x 128 tiles:
-// whether (m, nb, lda) qualify, and the launch (same splits and partials).
-bool symm_yt_ok(int64_t m, int64_t nb, int64_t lda);
+// W = A Y from Yt = Y^T (nb x m, ld ldyt = 128) for full 128 x 128 tiles:
+// whether (m, nb, lda) qualify for elements of elem bytes, and the launches
+// (same splits and partials): FP64, and the FP32-storage form (A the FP32
+// copy, Yt an FP32 copy of Y^T).
+bool symm_yt_ok(int64_t m, int64_t nb, int64_t lda, int64_t elem);
 void launch_symm_lower_yt(int64_t m, int64_t nb, const double* A, int64_t lda, const double* Yt, int64_t ldyt,
                           double* W, int64_t ldw, double* part, int splits, hipStream_t s);
+void launch_symm_lower_yt_f32s(int64_t m, int64_t nb, const float* A, int64_t lda, const float* Yt, int64_t ldyt,
+                               double* W, int64_t ldw, double* part, int splits, hipStream_t s);
 
 // ---- sbr_tsqr.hip ---------------------------------------------------------
 // TSQR tree over an m x b panel (m >= b): leaves of b rows (the last one takes
