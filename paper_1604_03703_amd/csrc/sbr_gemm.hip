@@ -227,15 +227,17 @@ __device__ __forceinline__ void lower_tile_banded(int64_t x, int64_t T, int64_t&
 // ST: storage type of C (double, or float for the FP32-storage form); OT:
 // type of U and V (double, or FP32 copies of them in the FP32 form, half the
 // bytes per operand).
-// DL (FP64, 128 x 128 tiles on 8 waves, every tile inside the matrix, ldu
-// even; the launcher checks): operands go from memory straight into LDS
-// (16-byte buffer loads with an LDS destination; lane l's two doubles land at
-// the window base + 16 l, so one load moves one 128-row k-column of a tile).
-// Wave w moves k-columns 2w and 2w + 1 of both operands; the loads of chunk
-// c + 1 run behind the products of chunk c, and each wave waits for its own
-// loads before the chunk's closing barrier.  The two buffers are separate LDS
-// objects and the chunk loop runs in pairs, so a load into one buffer is seen
-// not to alias the reads of the other.
+// DL (128 x 128 tiles on 8 waves, every tile inside the matrix, columns of U
+// and V 16-byte aligned, CT = OT; the launcher checks): operands go from
+// memory straight into LDS (16-byte buffer loads with an LDS destination,
+// lane l's bytes at the window base + 16 l).  Wave w moves k-columns 2w and
+// 2w + 1 of both operands: FP64, one load per 128-row k-column (LDS rows
+// padded to 130); FP32, one load for both columns (lanes 0-31 and 32-63;
+// LDS rows unpadded, 128 floats).  The loads of chunk c + 1 run behind the
+// products of chunk c, and each wave waits for its own loads before the
+// chunk's closing barrier.  The two buffers are separate LDS objects and the
+// chunk loop runs in pairs, so a load into one buffer is seen not to alias
+// the reads of the other.
 template <typename CT, int BM, int WM, int WN, int PAD = 2, typename ST = double, bool FAST = true,
           typename OT = double, bool DL = false>
 __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
@@ -244,9 +246,9 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     typedef TileEngine<CT, BM, BM, WM, WN, PAD, false> E;
     typedef TileMap<BM, E::NT, false> MA;   // row fastest (column-major U, V)
     typedef TileMap<BM, E::NT, false> MB;
-    static_assert(!DL || (FAST && std::is_same<CT, double>::value && std::is_same<OT, double>::value && BM == 128 &&
-                          WM * WN == 8 && SBR_BK == 16),
-                  "direct LDS loads: FP64 128 x 128 tiles on 8 waves");
+    static_assert(!DL || (FAST && std::is_same<CT, OT>::value && BM == 128 && WM * WN == 8 && SBR_BK == 16 &&
+                          (sizeof(CT) == 8 ? PAD == 2 : PAD == 0)),
+                  "direct LDS loads: 128 x 128 tiles on 8 waves");
     const int64_t x = xcd_logical_tile(blockIdx.x, ntiles);
     int64_t I, J;
     if (jt == 0) {
@@ -268,8 +270,13 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
     if constexpr (DL) {
         __shared__ __align__(16) CT As0[SBR_BK * E::LDA], As1[SBR_BK * E::LDA];
         __shared__ __align__(16) CT Bs0[SBR_BK * E::LDB], Bs1[SBR_BK * E::LDB];
-        const uint32_t la = (uint32_t)(((i0 + 2 * lane) + (int64_t)(2 * wave) * ldu) * SO);
-        const uint32_t lb = (uint32_t)(((j0 + 2 * lane) + (int64_t)(2 * wave) * ldu) * SO);
+        constexpr bool F64 = sizeof(CT) == 8;
+        constexpr int EPL = 16 / (int)sizeof(CT);   // elements a lane moves
+        constexpr int NLD = F64 ? 2 : 1;            // loads per operand and wave
+        const int li = F64 ? EPL * lane : EPL * (lane & 31);
+        const int lk = F64 ? 0 : (lane >> 5);
+        const uint32_t la = (uint32_t)(((i0 + li) + (int64_t)(2 * wave + lk) * ldu) * SO);
+        const uint32_t lb = (uint32_t)(((j0 + li) + (int64_t)(2 * wave + lk) * ldu) * SO);
         const uint32_t ldub = (uint32_t)(ldu * SO);
         auto dload = [&](int64_t k0, CT* as, CT* bs) {
             const OT* pa = (k0 < K) ? U + k0 * ldu : V + (k0 - K) * ldu;
@@ -277,7 +284,7 @@ __global__ __launch_bounds__(64 * WM * WN) void syr2k_lower_kernel(
             const __amdgpu_buffer_rsrc_t rsa = sbr_buffer(pa, span);
             const __amdgpu_buffer_rsrc_t rsb = sbr_buffer(pb, span);
 #pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
+            for (int kk = 0; kk < NLD; ++kk) {
                 const int k = 2 * wave + kk;
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(
                     rsa, (__attribute__((address_space(3))) void*)(as + k * E::LDA), 16, la + kk * ldub, 0, 0, 0);
@@ -847,11 +854,12 @@ void syr2k_go(int64_t nt, int64_t m, int64_t nc, int64_t jt, int64_t K, const OT
               const OT* V, int64_t ldv, ST* C, int64_t ldc, hipStream_t s) {
     const bool fast = (ldu == ldv) && (K % SBR_BK == 0) &&
                       (m + (int64_t)(SBR_BK - 1) * ldu) * (int64_t)sizeof(OT) < (int64_t)SBR_BUF_OOB;
-    if constexpr (std::is_same<CT, double>::value && std::is_same<OT, double>::value && BM == 128 && WM * WN == 8) {
+    if constexpr (std::is_same<CT, OT>::value && BM == 128 && WM * WN == 8) {
         // every tile inside the matrix (full lower tiles only) and 16-byte
         // aligned columns: operands straight into LDS
-        if (fast && jt == 0 && m % BM == 0 && (ldu & 1) == 0) {
-            syr2k_lower_kernel<CT, BM, WM, WN, 2, ST, true, OT, true><<<(unsigned)nt, 64 * WM * WN, 0, s>>>(
+        if (fast && jt == 0 && m % BM == 0 && (ldu * (int64_t)sizeof(OT)) % 16 == 0) {
+            constexpr int PADL = sizeof(CT) == 8 ? 2 : 0;
+            syr2k_lower_kernel<CT, BM, WM, WN, PADL, ST, true, OT, true><<<(unsigned)nt, 64 * WM * WN, 0, s>>>(
                 m, nc, jt, K, U, ldu, V, ldv, C, ldc, nt);
             return;
         }
