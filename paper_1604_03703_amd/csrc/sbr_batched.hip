@@ -18,7 +18,8 @@
 //     b = 2h -> h, teams of 2h lanes each chasing one sweep (the team chase of
 //     the small-bandwidth path) in the lag-3 order: chase (i, j) runs after
 //     chase (i, j-1) and after sweep i-1 has finished chase j + 2.  The band
-//     lives in a per-matrix global buffer with ld 2b + 1.
+//     lives in a per-matrix global buffer with ld 2b + 1; the halvings
+//     h = 2 and 1 move it into LDS first and chase it there.
 //   * batched_bisect_kernel: one wavefront per matrix, d and e^2 in LDS, each
 //     lane bisecting up to 8 eigenvalue indices in lockstep.
 #include <float.h>
@@ -327,12 +328,20 @@ __global__ __launch_bounds__(BF_NT) void batched_f2b_kernel(const BatchDesc* __r
 }
 
 // ---------------------------------------------------------------------------
-// Band halvings: one wavefront per matrix, S = 64 / 2h teams.
+// Band halvings: one wavefront per matrix, S = 64 / 2h teams.  LB: the
+// matrix's band (n x (2b + 1) doubles, b = 2h) is moved into LDS when the
+// wavefront takes the matrix, chased there, and the h + 1 diagonals the next
+// stage needs are written out at the end; otherwise the chases work on the
+// band in its global buffer.  The chases are the same either way.
 
 template <int H>
+constexpr int batched_band_lds_doubles() { return sbr::BATCH_NMAX * (4 * H + 1); }
+
+template <int H, bool LB>
 __global__ __launch_bounds__(64) void batched_band_kernel(const BatchDesc* __restrict__ desc, int count,
                                                           int* ticket) {
     constexpr int TEAM = 2 * H, S = 64 / TEAM, H2 = 2 * H, LDW = 4 * H + 1;
+    extern __shared__ double bsm[];   // LB: the band, ld LDW
     __shared__ double scr_all[S * team_chase_scratch<H>()];
     __shared__ int psweep[S], pdone[S];
     __shared__ int mat_sh;
@@ -352,14 +361,19 @@ __global__ __launch_bounds__(64) void batched_band_kernel(const BatchDesc* __res
         // stage index s = log2(b0 / b): even stages work in bandA, odd in bandB
         int stage = 0;
         for (int bb = b0; bb > 2 * H; bb >>= 1) ++stage;
-        double* band = (stage & 1) ? dm.bandB : dm.bandA;
+        double* const gband = (stage & 1) ? dm.bandB : dm.bandA;
         double* next = (stage & 1) ? dm.bandA : dm.bandB;
+        double* const band = LB ? bsm : gband;
         if (stage == 0) {
             // the lower band of the dense A (after full-to-band), headroom zero
             for (int64_t idx = t; idx < (int64_t)n * LDW; idx += 64) {
                 const int d = (int)(idx % LDW), c = (int)(idx / LDW);
                 band[idx] = (d <= H2 && c + d < n) ? dm.A[(c + d) + (int64_t)c * dm.lda] : 0.0;
             }
+        } else if (LB) {
+            for (int64_t idx = t; idx < (int64_t)n * LDW; idx += 64) band[idx] = gband[idx];
+        }
+        if (stage == 0 || LB) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             team_sync<64>();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -655,10 +669,18 @@ void launch_batched(const BatchDesc* desc, int count, int max_b0, bool f32, int*
     else
         batched_f2b_kernel<false><<<gf, BF_NT, BF_TOTAL * sizeof(double), s>>>(desc, count, tickets + 0, scratch);
     const int gb = count < 4096 ? count : 4096;
-    if (max_b0 >= 16) batched_band_kernel<8><<<gb, 64, 0, s>>>(desc, count, tickets + 1);
-    if (max_b0 >= 8) batched_band_kernel<4><<<gb, 64, 0, s>>>(desc, count, tickets + 2);
-    if (max_b0 >= 4) batched_band_kernel<2><<<gb, 64, 0, s>>>(desc, count, tickets + 3);
-    if (max_b0 >= 2) batched_band_kernel<1><<<gb, 64, 0, s>>>(desc, count, tickets + 4);
+    // the last two halvings chase their band in LDS (20 and 37 KB at n = 512,
+    // 8 and 4 matrices a CU); the bands of h = 4 and 8 (70 and 135 KB) would
+    // leave 2 and 1 matrices a CU, which measured slower than chasing in the
+    // global buffer with 16
+    if (max_b0 >= 16) batched_band_kernel<8, false><<<gb, 64, 0, s>>>(desc, count, tickets + 1);
+    if (max_b0 >= 8) batched_band_kernel<4, false><<<gb, 64, 0, s>>>(desc, count, tickets + 2);
+    if (max_b0 >= 4)
+        batched_band_kernel<2, true><<<gb, 64, batched_band_lds_doubles<2>() * sizeof(double), s>>>(desc, count,
+                                                                                                  tickets + 3);
+    if (max_b0 >= 2)
+        batched_band_kernel<1, true><<<gb, 64, batched_band_lds_doubles<1>() * sizeof(double), s>>>(desc, count,
+                                                                                                  tickets + 4);
     const int gs = count < 8192 ? count : 8192;
     batched_bisect_kernel<<<gs, BB_NT, 0, s>>>(desc, count, tickets + 5);
 }
@@ -666,6 +688,7 @@ void launch_batched(const BatchDesc* desc, int count, int max_b0, bool f32, int*
 int init_batched_attributes() {
     hipError_t e = hipFuncSetAttribute((const void*)batched_f2b_kernel<false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, BF_TOTAL * (int)sizeof(double));
+
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)batched_f2b_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 BF_TOTAL * (int)sizeof(double));
