@@ -337,8 +337,10 @@ __global__ __launch_bounds__(BF_NT) void batched_f2b_kernel(const BatchDesc* __r
 template <int H>
 constexpr int batched_band_lds_doubles() { return sbr::BATCH_NMAX * (4 * H + 1); }
 
+// h = 8: two waves a SIMD (the register budget spills 76 values to scratch;
+// 50.9 against 53.5 ms per 4096 matrices with one wave a SIMD and no spills).
 template <int H, bool LB>
-__global__ __launch_bounds__(64) void batched_band_kernel(const BatchDesc* __restrict__ desc, int count,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(H == 8 ? 2 : 1))) void batched_band_kernel(const BatchDesc* __restrict__ desc, int count,
                                                           int* ticket) {
     constexpr int TEAM = 2 * H, S = 64 / TEAM, H2 = 2 * H, LDW = 4 * H + 1;
     extern __shared__ double bsm[];   // LB: the band, ld LDW
