@@ -235,14 +235,24 @@ __global__ __launch_bounds__(BF_NT) __attribute__((amdgpu_waves_per_eu(4))) void
                 if (I < nI) {
                     const int row = I * 16 + li;
                     Acc acc = zacc<Acc>();
-#pragma unroll 4
-                    for (int k0 = 0; k0 < m; k0 += 4) {
-                        const int col = k0 + lk;
-                        double bv = 0.0;
-                        if (row < m && col < m)
-                            bv = (row >= col) ? A22[row + (int64_t)col * lda] : A22[col + (int64_t)row * lda];
-                        const double av = (col < m) ? Us[col + li * BF_LDU] : 0.0;
-                        acc = mmx(av, bv, acc);
+                    // 32 columns of A22 a batch: their loads are in flight
+                    // together, then the batch's products in column order
+                    for (int k0 = 0; k0 < m; k0 += 32) {
+                        double bv[8];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int col = k0 + 4 * j + lk;
+                            double v = 0.0;
+                            if (row < m && col < m)
+                                v = (row >= col) ? A22[row + (int64_t)col * lda] : A22[col + (int64_t)row * lda];
+                            bv[j] = v;
+                        }
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int col = k0 + 4 * j + lk;
+                            const double av = (col < m) ? Us[col + li * BF_LDU] : 0.0;
+                            acc = mmx(av, bv[j], acc);
+                        }
                     }
 #pragma unroll
                     for (int r4 = 0; r4 < 4; ++r4)
@@ -303,6 +313,14 @@ __global__ __launch_bounds__(BF_NT) __attribute__((amdgpu_waves_per_eu(4))) void
                 while ((I + 1) * (I + 2) / 2 <= x) ++I;
                 const int J = x - I * (I + 1) / 2;
                 const int ri = I * 16 + li, rj = J * 16 + li;
+                // the tile's old entries are loaded first, so that their
+                // round trip overlaps the operand loads and the products
+                double old[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int cj = J * 16 + ocol(r);
+                    old[r] = (ri < m && cj <= ri) ? A22[ri + (int64_t)cj * lda] : 0.0;
+                }
                 Acc acc = zacc<Acc>();
 #pragma unroll
                 for (int k0 = 0; k0 < 32; k0 += 4) {
@@ -321,7 +339,7 @@ __global__ __launch_bounds__(BF_NT) __attribute__((amdgpu_waves_per_eu(4))) void
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int cj = J * 16 + ocol(r);
-                        if (cj <= ri) A22[ri + (int64_t)cj * lda] += acc[r];
+                        if (cj <= ri) A22[ri + (int64_t)cj * lda] = old[r] + acc[r];
                     }
                 }
             }
