@@ -268,11 +268,20 @@ __global__ __launch_bounds__(BF_NT) __attribute__((amdgpu_waves_per_eu(4))) void
                 const int kb = (m + 3) / 4;
                 const int ka = w * kb, ke = (ka + kb < m) ? ka + kb : m;
                 Acc acc = zacc<Acc>();
-                for (int k0 = ka; k0 < ke; k0 += 4) {
-                    const int k = k0 + lk;
-                    const double wv = (k < ke) ? Wg[k + li * BF_MP] : 0.0;
-                    const double ub = (k < ke) ? Us[k + li * BF_LDU] : 0.0;
-                    acc = mmx(wv, ub, acc);
+                // W rows in batches of 32, loads in flight together
+                for (int k0 = ka; k0 < ke; k0 += 32) {
+                    double wv[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int k = k0 + 4 * j + lk;
+                        wv[j] = (k < ke) ? Wg[k + li * BF_MP] : 0.0;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int k = k0 + 4 * j + lk;
+                        const double ub = (k < ke) ? Us[k + li * BF_LDU] : 0.0;
+                        acc = mmx(wv[j], ub, acc);
+                    }
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) Zp[w * 256 + li + ocol(r) * 16] = acc[r];
@@ -305,41 +314,55 @@ __global__ __launch_bounds__(BF_NT) __attribute__((amdgpu_waves_per_eu(4))) void
             }
             __syncthreads();
 
-            // ---- 7. A22 += U V^T + V U^T, lower tiles: [U_I, V_I] [V_J, U_J]^T
+            // ---- 7. A22 += U V^T + V U^T, lower tiles: [U_I, V_I] [V_J, U_J]^T.
+            // Two tiles at a time (x and x + 8 of the wave's share): the old
+            // entries and the V operands of both are loaded before the first
+            // product, so their round trips overlap.
             const int ntl = nI * (nI + 1) / 2;
-            for (int x = w; x < ntl; x += BF_NW) {
-                int I = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-                while (I * (I + 1) / 2 > x) --I;
-                while ((I + 1) * (I + 2) / 2 <= x) ++I;
-                const int J = x - I * (I + 1) / 2;
-                const int ri = I * 16 + li, rj = J * 16 + li;
-                // the tile's old entries are loaded first, so that their
-                // round trip overlaps the operand loads and the products
-                double old[4];
+            for (int x0 = w; x0 < ntl; x0 += 2 * BF_NW) {
+                int ri[2], rj[2], Jt[2];
+                bool ok[2];
+                double old[2][4], vj[2][4], vi[2][4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int cj = J * 16 + ocol(r);
-                    old[r] = (ri < m && cj <= ri) ? A22[ri + (int64_t)cj * lda] : 0.0;
-                }
-                Acc acc = zacc<Acc>();
-#pragma unroll
-                for (int k0 = 0; k0 < 32; k0 += 4) {
-                    const int k = k0 + lk;
-                    double av, bv;
-                    if (k0 < 16) {
-                        av = Vg[rj + k * BF_MP];
-                        bv = Us[ri + k * BF_LDU];
-                    } else {
-                        av = Us[rj + (k - 16) * BF_LDU];
-                        bv = Vg[ri + (k - 16) * BF_MP];
+                for (int p = 0; p < 2; ++p) {
+                    const int x = x0 + p * BF_NW;
+                    ok[p] = x < ntl;
+                    int I = 0, J = 0;
+                    if (ok[p]) {
+                        I = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+                        while (I * (I + 1) / 2 > x) --I;
+                        while ((I + 1) * (I + 2) / 2 <= x) ++I;
+                        J = x - I * (I + 1) / 2;
                     }
-                    acc = mmx(av, bv, acc);
-                }
-                if (ri < m) {
+                    ri[p] = I * 16 + li;
+                    rj[p] = J * 16 + li;
+                    Jt[p] = J;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int cj = J * 16 + ocol(r);
-                        if (cj <= ri) A22[ri + (int64_t)cj * lda] = old[r] + acc[r];
+                        old[p][r] = (ok[p] && ri[p] < m && cj <= ri[p]) ? A22[ri[p] + (int64_t)cj * lda] : 0.0;
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const int k = 4 * kk + lk;
+                        vj[p][kk] = ok[p] ? Vg[rj[p] + k * BF_MP] : 0.0;
+                        vi[p][kk] = ok[p] ? Vg[ri[p] + k * BF_MP] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    if (!ok[p]) continue;
+                    Acc acc = zacc<Acc>();
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) acc = mmx(vj[p][kk], Us[ri[p] + (4 * kk + lk) * BF_LDU], acc);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) acc = mmx(Us[rj[p] + (4 * kk + lk) * BF_LDU], vi[p][kk], acc);
+                    if (ri[p] < m) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int cj = Jt[p] * 16 + ocol(r);
+                            if (cj <= ri[p]) A22[ri[p] + (int64_t)cj * lda] = old[p][r] + acc[r];
+                        }
                     }
                 }
             }
