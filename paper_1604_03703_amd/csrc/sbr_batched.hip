@@ -81,8 +81,8 @@ __device__ __forceinline__ double sum32(double v) {
 // F32: the trailing update (W, Z, V and the A22 update) on FP32 MFMA with
 // FP32 accumulation, the results added into the FP64 matrix; the panel QR,
 // tau, U^T U and T stay FP64.
-// Two work-groups a CU (two waves a SIMD: the register budget spills 86
-// values to scratch; 48.4 against 50.9 ms per 4096 matrices with one
+// Two work-groups a CU (two waves a SIMD: the register budget spills about
+// 100 values to scratch; 41.4 against 42.8 ms per 4096 matrices with one
 // work-group a CU and no spills).
 template <bool F32>
 __global__ __launch_bounds__(BF_NT) __attribute__((amdgpu_waves_per_eu(4))) void batched_f2b_kernel(const BatchDesc* __restrict__ desc, int count,
