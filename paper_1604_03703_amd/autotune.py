@@ -7,8 +7,13 @@ number of panels of the full-to-band step but adds a halving stage).  For
 every size bucket this module times the captured batched launch on a batch of
 synthetic matrices of that bucket (SCF-like: sorted diagonal in [-20, 5],
 off-diagonal N(0, 0.1^2) exp(-|i-j|/20), symmetrised) with each candidate b,
-and stores the winner per bucket in tuning/batched.json, keyed by the device
-architecture and the precision form:
+and keeps the fastest per bucket.  The phases of a batched call run as
+separate kernels over the whole batch, so bucket times measured alone do not
+add up to the time of a mixed batch: the per-bucket choice is then refined on
+a batch whose orders span every bucket, one bucket at a time (each other
+candidate tried with the other buckets' bands fixed, a change kept when the
+whole batch gets faster), largest bucket first.  The result is stored in
+tuning/batched.json, keyed by the device architecture and the precision form:
 
     {"gfx950": {"fp64": {"buckets": [{"n_max": 48, "band": 8, "ms": {...}}, ...]}}}
 
@@ -107,6 +112,62 @@ def time_batch(sbr, mats, band: int, precision: str, reps: int, warmup: int) -> 
     return 1e3 * ts[len(ts) // 2]
 
 
+def time_batch_table(sbr, mats, table, precision: str, reps: int, warmup: int) -> float:
+    """Median ms of one replay of the captured batched launch with the band
+    table `table` ((n_max, band) pairs); inputs restored between replays."""
+    plan = sbr.Plan(max(int(m.shape[0]) for m in mats), len(mats), precision)
+    plan.set_batch_bands(table)
+    work = [torch.empty_like(m) for m in mats]
+    ws = [torch.empty(m.shape[0], dtype=torch.float64, device=m.device) for m in mats]
+    call = sbr.BatchedSolve(work, 0, precision, plan, ws)
+    ts = []
+    for it in range(warmup + reps):
+        for w_, m in zip(work, mats):
+            w_.copy_(m)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        call.run()
+        torch.cuda.synchronize()
+        if it >= warmup:
+            ts.append(time.perf_counter() - t0)
+    del call
+    plan.close()
+    ts.sort()
+    return 1e3 * ts[len(ts) // 2]
+
+
+def refine_mixed(sbr, rec: list, precision: str, count: int, reps: int, warmup: int, candidates=CANDIDATES,
+                 lo: int = 32, log=print) -> dict:
+    """Coordinate descent of the bucket bands on one mixed batch (orders
+    uniform in [lo, largest bucket], the SCF-like size mix); updates rec in
+    place, returns a summary."""
+    mats = scf_batch(count, lo, int(rec[-1]["n_max"]), seed=1704)
+    bands = [int(r["band"]) for r in rec]
+
+    def run(bs):
+        return time_batch_table(sbr, mats, [(int(r["n_max"]), b) for r, b in zip(rec, bs)], precision, reps, warmup)
+
+    start = best = run(bands)
+    log("mixed batch, per-bucket choice %s: %.3f ms (%d matrices)" % (bands, start, count))
+    for k in reversed(range(len(rec))):
+        tried = {str(bands[k]): round(best, 4)}
+        for c in candidates:
+            if c == bands[k]:
+                continue
+            trial = list(bands)
+            trial[k] = c
+            t = run(trial)
+            tried[str(c)] = round(t, 4)
+            log("mixed batch, bucket n <= %d at b = %d: %.3f ms" % (rec[k]["n_max"], c, t))
+            if t < best:
+                best, bands = t, trial
+        rec[k]["band"] = bands[k]
+        rec[k]["mixed_ms"] = tried
+    del mats
+    return {"count": count, "orders": [lo, int(rec[-1]["n_max"])], "ms_per_bucket_choice": round(start, 4),
+            "ms": round(best, 4)}
+
+
 def tune(precision="fp64", count: int = 1024, reps: int = 5, warmup: int = 2, path: str = DB,
          buckets=BUCKETS, candidates=CANDIDATES, log=print) -> dict:
     import paper_1604_03703_amd as sbr
@@ -124,9 +185,10 @@ def tune(precision="fp64", count: int = 1024, reps: int = 5, warmup: int = 2, pa
                     "ms": {str(b): round(t, 4) for b, t in ms.items()}})
         lo = hi + 1
         del mats
+    mixed = refine_mixed(sbr, rec, precision, 4 * count, reps, warmup, candidates, log=log)
     db = _load_db(path)
     db.setdefault(arch, {})["fp64" if precision in ("fp64", 0) else "fp32_mfma"] = {
-        "buckets": rec, "candidates": list(candidates), "reps": reps,
+        "buckets": rec, "candidates": list(candidates), "reps": reps, "mixed": mixed,
         "input": "SCF-like: sorted diagonal U[-20, 5], off-diagonal N(0, 0.1^2) exp(-|i-j|/20)",
     }
     os.makedirs(os.path.dirname(path), exist_ok=True)
