@@ -136,33 +136,53 @@ def time_batch_table(sbr, mats, table, precision: str, reps: int, warmup: int) -
     return 1e3 * ts[len(ts) // 2]
 
 
+def coordinate_descent(bands: list, candidates, run, log=None):
+    """One pass of coordinate descent over the buckets, last (largest) first:
+    for bucket k every other candidate is timed with the other buckets fixed
+    (`run(bands) -> ms`), and a change is kept when it is faster than the
+    best so far.  Returns (bands, best ms, start ms, the times tried per
+    bucket as {band: ms})."""
+    bands = list(bands)
+    start = best = run(bands)
+    tried_all = [None] * len(bands)
+    for k in reversed(range(len(bands))):
+        cur = bands[k]                # the band the bucket had when its turn came
+        tried = {str(cur): round(best, 4)}
+        for c in candidates:
+            if c == cur:
+                continue
+            trial = list(bands)
+            trial[k] = c
+            t = run(trial)
+            tried[str(c)] = round(t, 4)
+            if log:
+                log(k, c, t)
+            if t < best:
+                best, bands = t, trial
+        tried_all[k] = tried
+    return bands, best, start, tried_all
+
+
 def refine_mixed(sbr, rec: list, precision: str, count: int, reps: int, warmup: int, candidates=CANDIDATES,
                  lo: int = 32, log=print) -> dict:
     """Coordinate descent of the bucket bands on one mixed batch (orders
     uniform in [lo, largest bucket], the SCF-like size mix); updates rec in
     place, returns a summary."""
     mats = scf_batch(count, lo, int(rec[-1]["n_max"]), seed=1704)
-    bands = [int(r["band"]) for r in rec]
 
     def run(bs):
         return time_batch_table(sbr, mats, [(int(r["n_max"]), b) for r, b in zip(rec, bs)], precision, reps, warmup)
 
-    start = best = run(bands)
-    log("mixed batch, per-bucket choice %s: %.3f ms (%d matrices)" % (bands, start, count))
-    for k in reversed(range(len(rec))):
-        tried = {str(bands[k]): round(best, 4)}
-        for c in candidates:
-            if c == bands[k]:
-                continue
-            trial = list(bands)
-            trial[k] = c
-            t = run(trial)
-            tried[str(c)] = round(t, 4)
-            log("mixed batch, bucket n <= %d at b = %d: %.3f ms" % (rec[k]["n_max"], c, t))
-            if t < best:
-                best, bands = t, trial
-        rec[k]["band"] = bands[k]
-        rec[k]["mixed_ms"] = tried
+    def note(k, c, t):
+        log("mixed batch, bucket n <= %d at b = %d: %.3f ms" % (rec[k]["n_max"], c, t))
+
+    first = [int(r["band"]) for r in rec]
+    bands, best, start, tried = coordinate_descent(first, candidates, run, note)
+    log("mixed batch (%d matrices): per-bucket choice %s %.3f ms, refined %s %.3f ms"
+        % (count, first, start, bands, best))
+    for r, b, t in zip(rec, bands, tried):
+        r["band"] = b
+        r["mixed_ms"] = t
     del mats
     return {"count": count, "orders": [lo, int(rec[-1]["n_max"])], "ms_per_bucket_choice": round(start, 4),
             "ms": round(best, 4)}

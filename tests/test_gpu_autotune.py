@@ -39,6 +39,38 @@ def test_tuning_database_is_well_formed():
             assert prev >= 512
 
 
+def test_coordinate_descent_separable_and_coupled():
+    from paper_1604_03703_amd.autotune import coordinate_descent
+    cands = (4, 8, 16)
+    w = {4: [3.0, 1.0, 2.0], 8: [1.0, 2.0, 1.5], 16: [2.0, 3.0, 1.0]}   # per bucket, per band
+
+    # separable cost: one pass reaches the brute-force optimum from any start
+    def sep(bands):
+        return sum(w[b][k] for k, b in enumerate(bands))
+
+    full = min(itertools.product(cands, repeat=3), key=sep)
+    for start in itertools.product(cands, repeat=3):
+        calls = []
+        bands, best, t0, tried = coordinate_descent(list(start), cands, lambda b: calls.append(tuple(b)) or sep(b))
+        assert bands == list(full) and best == sep(full) and t0 == sep(start)
+        # the start, then each other candidate once per bucket, last bucket first
+        assert calls[0] == tuple(start) and len(calls) == 1 + 3 * 2
+        assert [c for c in calls[1:3]] == [tuple(start[:2]) + (c,) for c in cands if c != start[2]]
+        for k, t in enumerate(tried):
+            assert t[str(bands[k])] == min(t.values())
+
+    # coupled cost (a phase paid once for the whole batch if any bucket uses
+    # b = 16): from [8, 8, 8] the pass moves the last bucket to 16 only if
+    # that pays for the shared phase, and then the others follow
+    def coupled(bands):
+        return sep(bands) + (1.2 if 16 in bands else 0.0)
+
+    bands, best, _, _ = coordinate_descent([8, 8, 8], cands, coupled)
+    # bucket 2: 16 gives 1 + 2 + 1 + 1.2 = 5.2 < 4.5? no -> stays 8 (4.5);
+    # bucket 1: 4 gives 1 + 1 + 1.5 = 3.5; bucket 0: 8 stays (1 is its best)
+    assert bands == [8, 4, 8] and best == coupled([8, 4, 8]) == 3.5
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("table", ["tuned", [(64, 4), (200, 8), (512, 16)], [(512, 16)], [(100, 16), (512, 4)]])
 def test_batched_with_band_table(oracle_mod, table):
